@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of windowed beamspace MVDR on one MI355X: (target, subband) beams per second.
+
+A step is one pass of the whole path over one batch of synthetic array data already resident
+in HBM: window placement and steering, FFT channelizer, zero-padded spatial FFT with the
+window gather, and per-pair covariance / Cholesky / solve / apply.  The chosen form (fused
+kernels replayed from a HIP graph) is timed, and reported beside the plain per-stage FP32
+form, full-dimensional element-space MVDR on the same GPU, and the FP64 CPU oracle.
+
+Workload (default): N=256 elements, M=512-point spatial FFT, K=128 subbands, W=9, L=256
+training and Lt=256 test snapshots, 8 targets, 3 wideband jammers (INR 20-40 dB), seeded.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "(target,subband) MVDR beams/s at ≤0.1 dB SINR loss vs FP64; chosen vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def cpu_baseline_leg(scene, x32, budget_s=10.0):
+    """Time the FP64 oracle on the same workload on the host (one thread); also returns its
+    result, which the validity check below compares the GPU weights with."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    cfg = scene.cfg
+    sin_az = [math.sin(a) for a in scene.target_az]
+    x128 = x32.astype(np.complex128)
+    passes, t_total, ref = 0, 0.0, None
+    with threadpool_limits(limits=1):
+        while passes == 0 or t_total < budget_s:
+            t0 = time.perf_counter()
+            ref = oracle.windowed_mvdr(x128, M=cfg.M, K=cfg.K, L=cfg.L, Lt=cfg.Lt, sin_az=sin_az,
+                                       win=scene.win, delta=cfg.delta, beta=cfg.beta, dl=cfg.dl,
+                                       half_bin=cfg.half_bin)
+            t_total += time.perf_counter() - t0
+            passes += 1
+    beams = cfg.T * cfg.K
+    res = dict(value=beams * passes / t_total, unit="beams/s", cores=1, kind="oracle",
+               sample=f"whole workload ({beams} pairs), {passes} pass(es), {t_total:.1f} s, "
+                      f"numpy/scipy complex128 on 1 host thread")
+    return res, ref
+
+
+def sinr_check(scene, ref, weights):
+    import oracle
+    cfg = scene.cfg
+    ratio = oracle.subband_freq_ratio(cfg.K, cfg.beta, cfg.half_bin)
+    worst_loss, worst_err = 0.0, 0.0
+    for k in range(cfg.K):
+        Rin_e = oracle.interference_covariance(cfg.N, np.sin(scene.jammer_az), scene.jammer_inr,
+                                               ratio[k], cfg.dl, cfg.noise_var)
+        for t in range(cfg.T):
+            W = int(scene.win[t])
+            bins = oracle.window_bins(int(ref["start"][t, k]), W, cfg.M)
+            D = np.exp(-2j * np.pi * np.outer(bins.astype(np.float64), np.arange(cfg.N)) / cfg.M)
+            D /= math.sqrt(cfg.M)
+            Rin = D @ Rin_e @ D.conj().T
+            wo = ref["w"][t, k, :W]
+            wg = weights[t, k, :W]
+            worst_loss = max(worst_loss, abs(oracle.sinr_loss_db(wg, wo, ref["a"][t, k, :W], Rin)))
+            worst_err = max(worst_err, oracle.rel_weight_error(wg, wo))
+    return worst_loss, worst_err
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="gpu", help="scene config name (default: gpu)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-full", action="store_true", help="skip full-dimensional MVDR")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the path is measured on one GPU's share of the "
+              f"work (--gpus {args.gpus} requested)", file=sys.stderr)
+        return 2
+
+    import torch
+    import scenes
+    import paper_2508_11790_amd as wb
+
+    torch.cuda.set_device(0)
+    cfg = scenes.config_by_name(args.workload)
+    log(f"workload {cfg.name}: generating scene")
+    sc = scenes.make_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    x = torch.from_numpy(x32).cuda()
+    T, K = cfg.T, cfg.K
+    wmax = int(sc.win.max())
+    plan = wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, T, wmax, beta=cfg.beta,
+                   d_over_lambda=cfg.dl, half_bin=cfg.half_bin)
+    dev = x.device
+    out = torch.empty((T, K, cfg.Lt), dtype=torch.complex64, device=dev)
+    wts = torch.empty((T, K, wmax), dtype=torch.complex64, device=dev)
+    info = torch.empty((T, K), dtype=torch.int32, device=dev)
+    az, win, delta = sc.target_az, sc.win, cfg.delta
+
+    def step(form):
+        return lambda: plan.beamform(x, az, win, delta, form=form, out=out, weights=wts,
+                                     info=info, want_starts=False)
+
+    log("timing chosen form (fused kernels, HIP graph replay)")
+    ms_chosen = timed_steps(torch, step("graph"), args.steps, args.warmup)
+    assert int(info.abs().sum()) == 0
+    w_chosen = wts.cpu().numpy().astype(np.complex128)
+    log("timing plain per-stage FP32 form")
+    ms_plain = timed_steps(torch, step("plain"), args.steps, args.warmup)
+    w_plain = wts.cpu().numpy().astype(np.complex128)
+    ms_full = None
+    if not args.no_full:
+        log("timing full-dimensional element-space MVDR")
+        nfs = max(2, min(args.steps // 20, 20))
+        ms_full = timed_steps(torch, lambda: plan.full_mvdr(x, az, delta, want_weights=False),
+                              nfs, 2)
+
+    log("per-kernel times (HIP events)")
+    st = plan.stage_times(x, az, win, delta, reps=max(20, args.steps // 4))
+    sumW = int(np.sum(win))
+    B, S = cfg.B, cfg.B * cfg.K
+    bytes_per = {
+        "channelize": 2.0 * cfg.N * S * 8,
+        "beamspace": cfg.N * S * 8 + K * B * sumW * 8,
+        "mvdr": K * B * sumW * 8 + T * K * cfg.Lt * 8 + T * K * wmax * 8,
+    }
+    kern = max(bytes_per, key=lambda n: st[n])
+    achieved = bytes_per[kern] / (st[kern] * 1e-3) / 1e9
+    roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    bytes_per_launch=bytes_per[kern], ms_per_launch=st[kern],
+                    stage_ms={k: round(v, 5) for k, v in st.items()},
+                    stage_gbs={n: round(bytes_per[n] / (st[n] * 1e-3) / 1e9, 1) for n in bytes_per})
+
+    beams = T * K
+    result = {
+        "metric": METRIC,
+        "value": beams / (ms_chosen * 1e-3),
+        "unit": "beams/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_chosen,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 FFTs, f64 covariance/solve",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: ULA N={cfg.N}, M={cfg.M}, K={cfg.K}, W={wmax}, "
+                               f"L={cfg.L}, Lt={cfg.Lt}, T={T}, {cfg.n_jammers} jammers",
+                   "form": "fused + HIP graph", "pairs_per_step": beams},
+        "plain": {"value": beams / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                  "form": "per-stage FP32 kernels, full beamspace in HBM, no graph"},
+        "full_dim": (None if ms_full is None else
+                     {"value": beams / (ms_full * 1e-3), "ms_per_step": ms_full,
+                      "form": f"element-space {cfg.N}x{cfg.N} MVDR per subband, FP64"}),
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("CPU oracle leg")
+        cpu, ref = cpu_baseline_leg(sc, x32)
+        result["cpu_baseline"] = cpu
+        loss_c, err_c = sinr_check(sc, ref, w_chosen)
+        loss_p, err_p = sinr_check(sc, ref, w_plain)
+        result["validity"] = {"chosen_max_sinr_loss_db": loss_c, "chosen_max_rel_weight_err": err_c,
+                              "plain_max_sinr_loss_db": loss_p, "plain_max_rel_weight_err": err_p,
+                              "bar_db": 0.1, "valid": bool(loss_c <= 0.1 and loss_p <= 0.1)}
+    else:
+        result["cpu_baseline"] = None
+    plan.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,160 @@
+/*
+ * wbmvdr.h -- C ABI of the windowed beamspace MVDR library for AMD MI355X (gfx950).
+ *
+ * The library implements the per-subband windowed beamspace MVDR beamformer of
+ * "Scaling Wideband Massive MIMO Radar via Beamspace Dimension Reduction"
+ * (Noroozi, Han, Tang, Zhang, Madhow), for a uniform linear array:
+ *
+ *   element samples x[e][t]          (Sec. II-A, Eq. 9: y[n] per subband)
+ *     -> FFT channelizer into K subbands               (Sec. III-A, Fig. 2)
+ *     -> zero-padded M-point spatial DFT (beamspace)   (Sec. III-B, Eq. 14-17)
+ *     -> W-bin window around each target's beam bin   (Sec. III-B, Eq. 18-19)
+ *     -> loaded W x W sample covariance               (Sec. II-B Eq. 11, Sec. III-C)
+ *     -> MVDR correlator c = R^-1 a / (a^H R^-1 a)     (Eq. 13, Eq. 20)
+ *     -> beam output c^H y on the test snapshots       (Sec. II-B, below Eq. 13)
+ *
+ * and, as the comparison, full-dimensional element-space MVDR (Sec. II-B, Eq. 11-13).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Complex data are interleaved float pairs (wbm_c32, identical to torch.complex64)
+ *   or double pairs (wbm_c64).  Array pointers documented as "device" must be HIP
+ *   device memory; "host" pointers are read synchronously before the call returns.
+ *   The caller owns every array it passes; the plan owns its workspace.
+ * - Every call validates its arguments before anything is enqueued and returns a
+ *   wbm_status; no exception crosses the ABI.  On failure nothing was enqueued and
+ *   wbm_last_error() returns a message (thread-local).
+ * - Work is enqueued on the given HIP stream (NULL = default stream) and the call
+ *   returns without waiting; synchronise the stream before reading outputs.
+ * - Numerical failure of one (target, subband) solve does not fail the call: its
+ *   info entry is set to j > 0 (the Cholesky pivot j-1 was not positive/finite),
+ *   and its outputs are zero.
+ * - A plan is not thread safe; independent plans may be used concurrently.
+ *
+ * Shapes (ULA, paper's 2-D names in brackets): N elements [N = N_z N_x], M-point
+ * spatial DFT [M = M_z M_x], K subbands [the paper's L], L training and Lt test
+ * snapshots (blocks of K samples) per subband [n_t], T targets [the paper's K],
+ * window widths W_t <= w_max <= 64 [W = W_z W_x].  B = L + Lt, S = B * K.
+ */
+#ifndef WBMVDR_H
+#define WBMVDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } wbm_c32;
+typedef struct { double re, im; } wbm_c64;
+
+typedef enum {
+  WBM_OK = 0,
+  WBM_ERR_ARG = 1,          /* null pointer / value out of range */
+  WBM_ERR_SHAPE = 2,        /* sizes inconsistent with the plan */
+  WBM_ERR_NOMEM = 3,        /* device or pinned allocation failed */
+  WBM_ERR_HIP = 4,          /* a HIP runtime call failed (text in wbm_last_error) */
+  WBM_ERR_UNSUPPORTED = 5   /* valid request the library does not implement */
+} wbm_status;
+
+/* wbm_config.flags */
+#define WBM_HALF_BIN 1      /* subband centres of Eq. 1: f_c + ((l - 1/2)/K) f_s (pre-twiddle
+                               exp(-j pi tau / K) on every block); default: plain FFT bins */
+
+/* form argument of wbm_beamform */
+#define WBM_FORM_PLAIN 0    /* per-stage kernels, FP32 arithmetic, one launch per stage, full
+                               beamspace written to HBM and gathered per pair */
+#define WBM_FORM_FUSED 1    /* beamspace FFT writes only the windows; one fused per-pair
+                               covariance -> Cholesky -> solve -> apply launch; FP64
+                               accumulation of the covariance and FP64 Cholesky */
+#define WBM_FORM_GRAPH 2    /* WBM_FORM_FUSED with the launch sequence replayed from a
+                               HIP graph (captured on first use for a given argument set) */
+
+typedef struct {
+  int32_t n_elem;           /* N >= 1 */
+  int32_t m_fft;            /* M: power of two, N <= M <= 8192 */
+  int32_t k_sub;            /* K: power of two, 2 <= K <= 8192 */
+  int32_t l_train;          /* L >= 1 training snapshots per subband */
+  int32_t l_test;           /* Lt >= 0 test snapshots per subband */
+  int32_t max_targets;      /* T_max >= 1: capacity for targets per call */
+  int32_t w_max;            /* 1 <= w_max <= 64, <= M: largest window width */
+  int32_t flags;            /* WBM_HALF_BIN or 0 */
+  double beta;              /* fractional bandwidth f_s / f_c, 0 <= beta < 2 */
+  double d_over_lambda;     /* element spacing over the centre wavelength (0.5) */
+} wbm_config;
+
+typedef struct wbm_plan wbm_plan;
+
+/* Create a plan: validates cfg, allocates the device workspace for the largest
+ * problem cfg allows (channelized and beamspace buffers, tables).  *out receives
+ * the plan, or NULL on failure. */
+wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out);
+/* Free a plan and its workspace (synchronises the device first).  NULL is a no-op. */
+wbm_status wbm_plan_destroy(wbm_plan* plan);
+/* Bytes of device workspace the plan holds. */
+int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
+
+/* Windowed beamspace MVDR for every (target, subband) pair (Sec. III, Eq. 11-20).
+ *   x       device [N][S] wbm_c32: element samples, time contiguous per element.
+ *   az_rad  host [T] azimuth of each target from broadside (radians), Eq. 2.
+ *   win     host [T] window width W_t per target, 1 <= W_t <= w_max.
+ *   T       number of targets, 1 <= T <= max_targets.
+ *   loading diagonal loading delta >= 0 added to the 1/L-scaled covariance.
+ *   form    WBM_FORM_PLAIN / WBM_FORM_FUSED / WBM_FORM_GRAPH.
+ *   out     device [T][K][Lt] wbm_c32: beam outputs c^H y on test snapshots L..L+Lt-1.
+ *   weights device [T][K][w_max] wbm_c32 or NULL: correlators c~ in window-bin order
+ *           (bins (s + i) mod M, i < W_t), zero padded to w_max.
+ *   starts  device [T][K] int32 or NULL: first window bin s of every pair (may be
+ *           negative; the bins are taken mod M).
+ *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's Cholesky failed.
+ *   stream  hipStream_t or NULL. */
+wbm_status wbm_beamform(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
+                        const int32_t* win, int32_t T, double loading, int32_t form,
+                        wbm_c32* out, wbm_c32* weights, int32_t* starts, int32_t* info,
+                        void* stream);
+
+/* Stage: FFT channelizer (Sec. III-A).  x device [N][S] -> X device [K][B][N],
+ * X[k][b][e] = K^-1/2 sum_tau x[e][bK + tau] h[tau] exp(-j 2 pi tau k / K),
+ * h = 1 or exp(-j pi tau / K) with WBM_HALF_BIN. */
+wbm_status wbm_channelize(wbm_plan* plan, const wbm_c32* x, wbm_c32* X, void* stream);
+
+/* Stage: zero-padded spatial DFT (Eq. 14-17).  X device [K][B][N] -> Y device [K][M][B],
+ * Y[k][m][b] = M^-1/2 sum_{e<N} X[k][b][e] exp(-j 2 pi m e / M). */
+wbm_status wbm_beamspace(wbm_plan* plan, const wbm_c32* X, wbm_c32* Y, void* stream);
+
+/* Stage: window placement and windowed steering (Eq. 18-19; a~ = S D a below Eq. 20).
+ *   starts device [T][K] int32: s = floor(u - (W_t-1)/2 + 1/2), u = M (d/lambda) sin(az) f_k/f_c
+ *          evaluated in IEEE double as ((M * dl) * sin(az)) * ratio, ratio = 1 + (beta*(ks+h))/K,
+ *          ks the signed bin index, h = 1/2 with WBM_HALF_BIN else 0.
+ *   abar   device [T][K][w_max] wbm_c64: a~_i = M^-1/2 sum_{e<N} e^{j Omega e} e^{-j 2 pi m_i e / M}. */
+wbm_status wbm_steer(wbm_plan* plan, const double* az_rad, const int32_t* win, int32_t T,
+                     int32_t* starts, wbm_c64* abar, void* stream);
+
+/* Full-dimensional element-space MVDR per subband (Sec. II-B, Eq. 11-13): the
+ * comparison method.  R = (1/L) sum_{b<L} X_b X_b^H + loading I_N (N x N, FP64
+ * accumulation), c_t = R^-1 a_t / (a_t^H R^-1 a_t) with a_t the element steering
+ * vector of target t at the subband centre (Eq. 7-8), out = c_t^H X_b for the Lt
+ * test blocks.  N <= 4096.
+ *   out device [T][K][Lt]; weights device [T][K][N] or NULL; info device [K] or NULL. */
+wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad, int32_t T,
+                         double loading, wbm_c32* out, wbm_c32* weights, int32_t* info,
+                         void* stream);
+
+/* Per-stage timing of the fused sequence (same arguments as wbm_beamform with
+ * form = WBM_FORM_FUSED, outputs go to plan-internal scratch): runs it `reps` times on
+ * `stream` with HIP events around every kernel and writes the average milliseconds of
+ * steer, channelize, windowed beamspace and fused MVDR to stage_ms (host [4]).  Blocks
+ * until the stream has drained. */
+wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
+                           const int32_t* win, int32_t T, double loading, int32_t reps,
+                           double* stage_ms, void* stream);
+
+const char* wbm_status_str(wbm_status s);
+const char* wbm_last_error(void);
+/* Library version string. */
+const char* wbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WBMVDR_H */

@@ -216,7 +216,8 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
                   sin_az: Sequence[float], win: Sequence[int], delta: float,
                   beta: float = 0.2, dl: float = 0.5, half_bin: bool = False,
                   subbands: Optional[Sequence[int]] = None,
-                  X: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+                  X: Optional[np.ndarray] = None,
+                  return_windows: bool = False) -> Dict[str, np.ndarray]:
     """Windowed beamspace MVDR for every (target, subband) pair (Fig. 2, Sec. III).
 
     Steps per subband k: channelize (Sec. III-A) -> beamspace rows of the
@@ -225,7 +226,8 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
 
     Returns dict with ``start`` [T, nk] int64, ``u`` [T, nk], ``w`` [T, nk, Wmax]
     (zero padded), ``a`` [T, nk, Wmax] (windowed steering), ``z`` [T, nk, Lt],
-    ``R`` list-of-lists of the loaded covariances, ``subbands``.
+    ``R`` list-of-lists of the loaded covariances, ``subbands``, and with
+    ``return_windows`` ``Yw`` list-of-lists of the windowed snapshots [W, L + Lt].
     """
     N = x.shape[0]
     T = len(sin_az)
@@ -245,6 +247,7 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
     a_out = np.zeros((T, nk, Wmax), dtype=np.complex128)
     z_out = np.zeros((T, nk, Lt), dtype=np.complex128)
     Rs = [[None] * nk for _ in range(T)]
+    Yws = [[None] * nk for _ in range(T)] if return_windows else None
     for ik, k in enumerate(ks):
         Xk = X[:, :L + Lt, kcol[k]]
         Yk = beamspace(Xk, M)                                                 # [M, B]
@@ -262,7 +265,12 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
             a_out[t, ik, :W] = a
             z_out[t, ik] = beam_output(w, Yw[:, L:L + Lt])
             Rs[t][ik] = R
-    return dict(start=start, u=upos, w=w_out, a=a_out, z=z_out, R=Rs, subbands=np.asarray(ks))
+            if return_windows:
+                Yws[t][ik] = Yw
+    out = dict(start=start, u=upos, w=w_out, a=a_out, z=z_out, R=Rs, subbands=np.asarray(ks))
+    if return_windows:
+        out["Yw"] = Yws
+    return out
 
 
 def full_mvdr(x: np.ndarray, *, K: int, L: int, Lt: int, sin_az: Sequence[float], delta: float,

@@ -1,0 +1,565 @@
+// C ABI of the windowed beamspace MVDR library: argument validation, plan / workspace
+// management, per-call target description upload and the launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "wbm_launch.h"
+#include "wbmvdr.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+wbm_status fail(wbm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+wbm_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return WBM_ERR_HIP;
+}
+
+#define WBM_HIP(call, what)                  \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+struct GraphKey {
+  const void* x = nullptr;
+  void* out = nullptr;
+  void* weights = nullptr;
+  void* info = nullptr;
+  int T = 0, sumW = 0;
+  double loading = 0.0;
+  bool valid = false;
+  bool operator==(const GraphKey& o) const {
+    return valid && o.valid && x == o.x && out == o.out && weights == o.weights && info == o.info &&
+           T == o.T && sumW == o.sumW && loading == o.loading;
+  }
+};
+
+}  // namespace
+
+struct wbm_plan {
+  wbm_config cfg;
+  int B = 0;
+  int64_t S = 0;
+  int logTB = 0, TB = 0, nbt = 0;
+  int device = 0;
+  // tables
+  float2* twK = nullptr;
+  float2* twM = nullptr;
+  float2* hb = nullptr;
+  // per-call target description: device copy + pinned staging
+  unsigned char* desc_dev = nullptr;
+  unsigned char* desc_host = nullptr;
+  size_t desc_bytes = 0;
+  hipEvent_t desc_evt = nullptr;
+  bool desc_evt_recorded = false;
+  wbm::DevDesc dd{};
+  // workspace
+  float2* X = nullptr;       // [K][B][N]
+  float2* Yw = nullptr;      // [K][nbt][T_max*w_max][TB]
+  float2* Y = nullptr;       // [K][M][B]      (plain form, allocated on first use)
+  float2* R32 = nullptr;     // [T_max*K][w_max^2] (plain form)
+  float2* w32 = nullptr;     // [T_max*K][w_max]   (plain form)
+  int* starts = nullptr;     // [T_max][K]
+  double2* abar = nullptr;   // [T_max][K][w_max]
+  double2* fullR = nullptr;  // [nk_full][N][N] (full-dimensional MVDR, first use)
+  double2* fullW = nullptr;  // [nk_full][T_max][N]
+  int* full_info = nullptr;  // [K]
+  int nk_full = 0;
+  int64_t ws_bytes = 0;
+  // graph replay of the fused sequence
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  GraphKey gkey;
+  // scratch outputs of wbm_stage_times
+  float2* prof_out = nullptr;
+  float2* prof_w = nullptr;
+  int* prof_info = nullptr;
+};
+
+namespace {
+
+template <typename T>
+wbm_status dev_alloc(wbm_plan* p, T** ptr, size_t count, const char* what) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(WBM_ERR_NOMEM, std::string("hipMalloc failed for ") + what + " (" +
+                                   std::to_string(sizeof(T) * count) + " bytes)");
+  }
+  *ptr = static_cast<T*>(q);
+  p->ws_bytes += (int64_t)(sizeof(T) * count);
+  return WBM_OK;
+}
+
+wbm_status upload_twiddles(float2* dst, int n, double sign_frac) {
+  // dst[q] = exp(-2 pi i q / n) (sign_frac = 1) or the half-bin pre-twiddle exp(-i pi q / n)
+  std::vector<float2> h(n);
+  for (int q = 0; q < n; ++q) {
+    const double ang = -2.0 * M_PI * (double)q / (double)n * sign_frac;
+    h[q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  WBM_HIP(hipMemcpy(dst, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice), "twiddle upload");
+  return WBM_OK;
+}
+
+// Validate the per-call targets and upload their description; returns sumW.
+wbm_status upload_desc(wbm_plan* p, const double* az_rad, const int32_t* win, int T,
+                       hipStream_t st, int* sumW_out) {
+  const wbm_config& c = p->cfg;
+  if (!az_rad) return fail(WBM_ERR_ARG, "az_rad is NULL");
+  if (T < 1 || T > c.max_targets)
+    return fail(WBM_ERR_SHAPE, "T=" + std::to_string(T) + " outside [1, max_targets=" +
+                                   std::to_string(c.max_targets) + "]");
+  for (int t = 0; t < T; ++t) {
+    if (!std::isfinite(az_rad[t])) return fail(WBM_ERR_ARG, "az_rad[" + std::to_string(t) + "] not finite");
+    if (win) {
+      const int W = win[t];
+      if (W < 1 || W > c.w_max)
+        return fail(WBM_ERR_ARG, "win[" + std::to_string(t) + "]=" + std::to_string(W) +
+                                     " outside [1, w_max=" + std::to_string(c.w_max) + "]");
+    }
+  }
+  if (p->desc_evt_recorded) {
+    WBM_HIP(hipEventSynchronize(p->desc_evt), "descriptor staging wait");
+  }
+  const int Tm = c.max_targets;
+  double* sin_az = reinterpret_cast<double*>(p->desc_host);
+  int* wv = reinterpret_cast<int*>(p->desc_host + sizeof(double) * Tm);
+  int* woff = wv + Tm;
+  int* rowtab = woff + Tm;
+  int sumW = 0;
+  for (int t = 0; t < T; ++t) {
+    sin_az[t] = std::sin(az_rad[t]);
+    const int W = win ? win[t] : c.w_max;
+    wv[t] = W;
+    woff[t] = sumW;
+    for (int i = 0; i < W; ++i) rowtab[sumW + i] = (t << 8) | i;
+    sumW += W;
+  }
+  WBM_HIP(hipMemcpyAsync(p->desc_dev, p->desc_host, p->desc_bytes, hipMemcpyHostToDevice, st),
+          "descriptor upload");
+  WBM_HIP(hipEventRecord(p->desc_evt, st), "descriptor event");
+  p->desc_evt_recorded = true;
+  *sumW_out = sumW;
+  return WBM_OK;
+}
+
+wbm_status ensure_plain(wbm_plan* p) {
+  if (p->Y) return WBM_OK;
+  const wbm_config& c = p->cfg;
+  wbm_status s = dev_alloc(p, &p->Y, (size_t)c.k_sub * c.m_fft * p->B, "beamspace Y");
+  if (s) return s;
+  const size_t pairs = (size_t)c.max_targets * c.k_sub;
+  s = dev_alloc(p, &p->R32, pairs * c.w_max * c.w_max, "plain covariances");
+  if (s) return s;
+  return dev_alloc(p, &p->w32, pairs * c.w_max, "plain weights");
+}
+
+wbm::PairArgs pair_args(const wbm_plan* p, int T, int sumW, double loading) {
+  wbm::PairArgs a;
+  a.T = T;
+  a.K = p->cfg.k_sub;
+  a.M = p->cfg.m_fft;
+  a.L = p->cfg.l_train;
+  a.Lt = p->cfg.l_test;
+  a.B = p->B;
+  a.wmax = p->cfg.w_max;
+  a.logTB = p->logTB;
+  a.nbt = p->nbt;
+  a.sumW = sumW;
+  a.delta = loading;
+  return a;
+}
+
+wbm::SteerArgs steer_args(const wbm_plan* p, int T) {
+  wbm::SteerArgs a;
+  a.T = T;
+  a.K = p->cfg.k_sub;
+  a.M = p->cfg.m_fft;
+  a.N = p->cfg.n_elem;
+  a.wmax = p->cfg.w_max;
+  a.half_bin = (p->cfg.flags & WBM_HALF_BIN) ? 1 : 0;
+  a.beta = p->cfg.beta;
+  a.dl = p->cfg.d_over_lambda;
+  return a;
+}
+
+// Steer -> channelize -> windowed beamspace -> fused MVDR on stream st.
+hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
+                         float2* out, float2* wout, int* info, hipStream_t st) {
+  const wbm_config& c = p->cfg;
+  hipError_t e = wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st);
+  if (e != hipSuccess) return e;
+  e = wbm::launch_channelize(x, p->X, c.n_elem, c.k_sub, p->B, p->twK,
+                             (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st);
+  if (e != hipSuccess) return e;
+  e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
+                            p->dd.rowtab, sumW, p->starts, st);
+  if (e != hipSuccess) return e;
+  return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), p->dd, p->Yw, p->starts, p->abar,
+                                out, wout, info, st);
+}
+
+wbm_status check_plan(const wbm_plan* p) {
+  if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return WBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wbm_version(void) { return "wbmvdr 0.1 (gfx950)"; }
+
+const char* wbm_last_error(void) { return g_err.c_str(); }
+
+const char* wbm_status_str(wbm_status s) {
+  switch (s) {
+    case WBM_OK: return "ok";
+    case WBM_ERR_ARG: return "invalid argument";
+    case WBM_ERR_SHAPE: return "shape mismatch";
+    case WBM_ERR_NOMEM: return "out of memory";
+    case WBM_ERR_HIP: return "HIP runtime error";
+    case WBM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+int64_t wbm_plan_workspace_bytes(const wbm_plan* p) { return p ? p->ws_bytes : 0; }
+
+wbm_status wbm_plan_destroy(wbm_plan* p) {
+  if (!p) return WBM_OK;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->desc_evt) (void)hipEventDestroy(p->desc_evt);
+  if (p->desc_host) (void)hipHostFree(p->desc_host);
+  void* bufs[] = {p->twK, p->twM, p->hb, p->desc_dev, p->X, p->Yw, p->Y, p->R32,
+                  p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
+                  p->prof_out, p->prof_w, p->prof_info};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  delete p;
+  return WBM_OK;
+}
+
+wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
+  if (!out) return fail(WBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(WBM_ERR_ARG, "cfg is NULL");
+  const wbm_config& c = *cfg;
+  if (c.n_elem < 1) return fail(WBM_ERR_ARG, "n_elem must be >= 1");
+  if (!is_pow2(c.m_fft) || c.m_fft < c.n_elem || c.m_fft > 8192)
+    return fail(WBM_ERR_ARG, "m_fft must be a power of two with n_elem <= m_fft <= 8192");
+  if (!is_pow2(c.k_sub) || c.k_sub < 2 || c.k_sub > 8192)
+    return fail(WBM_ERR_ARG, "k_sub must be a power of two in [2, 8192]");
+  if (c.l_train < 1 || c.l_test < 0) return fail(WBM_ERR_ARG, "need l_train >= 1 and l_test >= 0");
+  if (c.max_targets < 1 || c.max_targets > (1 << 20)) return fail(WBM_ERR_ARG, "max_targets out of range");
+  if (c.w_max < 1 || c.w_max > 64 || c.w_max > c.m_fft)
+    return fail(WBM_ERR_ARG, "w_max must be in [1, min(64, m_fft)]");
+  if (!(c.beta >= 0.0 && c.beta < 2.0)) return fail(WBM_ERR_ARG, "beta must be in [0, 2)");
+  if (!(c.d_over_lambda > 0.0 && std::isfinite(c.d_over_lambda)))
+    return fail(WBM_ERR_ARG, "d_over_lambda must be positive");
+  if (c.flags & ~WBM_HALF_BIN) return fail(WBM_ERR_ARG, "unknown flags");
+  const int64_t B = (int64_t)c.l_train + c.l_test;
+  if (B > 65535) return fail(WBM_ERR_ARG, "l_train + l_test must be <= 65535");
+
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(WBM_ERR_HIP, "no HIP device available");
+  }
+  wbm_plan* p = new wbm_plan();
+  p->cfg = c;
+  (void)hipGetDevice(&p->device);
+  p->B = (int)B;
+  p->S = B * c.k_sub;
+  p->logTB = wbm::beamspace_tile_log(c.m_fft, p->B);
+  p->TB = 1 << p->logTB;
+  p->nbt = (p->B + p->TB - 1) / p->TB;
+
+  auto bail = [&](wbm_status s) {
+    std::string keep = g_err;
+    wbm_plan_destroy(p);
+    g_err = keep;
+    return s;
+  };
+  wbm_status s;
+  if ((s = dev_alloc(p, &p->twK, c.k_sub, "twiddles K"))) return bail(s);
+  if ((s = dev_alloc(p, &p->twM, c.m_fft, "twiddles M"))) return bail(s);
+  if ((s = dev_alloc(p, &p->hb, c.k_sub, "half-bin twiddles"))) return bail(s);
+  if ((s = upload_twiddles(p->twK, c.k_sub, 1.0))) return bail(s);
+  if ((s = upload_twiddles(p->twM, c.m_fft, 1.0))) return bail(s);
+  if ((s = upload_twiddles(p->hb, c.k_sub, 0.5))) return bail(s);
+
+  const int Tm = c.max_targets;
+  p->desc_bytes = sizeof(double) * Tm + sizeof(int) * (size_t)Tm * (3 + c.w_max);
+  if ((s = dev_alloc(p, &p->desc_dev, p->desc_bytes, "descriptor"))) return bail(s);
+  if (hipHostMalloc((void**)&p->desc_host, p->desc_bytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(WBM_ERR_NOMEM, "pinned descriptor allocation failed"));
+  }
+  std::memset(p->desc_host, 0, p->desc_bytes);
+  if (hipEventCreateWithFlags(&p->desc_evt, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(WBM_ERR_HIP, "hipEventCreate failed"));
+  p->dd.sin_az = reinterpret_cast<const double*>(p->desc_dev);
+  p->dd.win = reinterpret_cast<const int*>(p->desc_dev + sizeof(double) * Tm);
+  p->dd.woff = p->dd.win + Tm;
+  p->dd.rowtab = p->dd.woff + Tm;
+
+  const size_t NS = (size_t)c.n_elem * p->S;
+  if ((s = dev_alloc(p, &p->X, NS, "channelized X"))) return bail(s);
+  if ((s = dev_alloc(p, &p->Yw, (size_t)c.k_sub * p->nbt * p->TB * (size_t)Tm * c.w_max, "windows Yw")))
+    return bail(s);
+  if ((s = dev_alloc(p, &p->starts, (size_t)Tm * c.k_sub, "starts"))) return bail(s);
+  if ((s = dev_alloc(p, &p->abar, (size_t)Tm * c.k_sub * c.w_max, "steering"))) return bail(s);
+  if ((s = dev_alloc(p, &p->full_info, (size_t)c.k_sub, "full info"))) return bail(s);
+
+  he = wbm::set_fft_attributes();
+  if (he == hipSuccess) he = wbm::set_pair_attributes();
+  if (he == hipSuccess) he = wbm::set_full_attributes();
+  if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute"));
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(WBM_ERR_HIP, "capture stream creation failed"));
+  *out = p;
+  return WBM_OK;
+}
+
+wbm_status wbm_steer(wbm_plan* p, const double* az_rad, const int32_t* win, int32_t T,
+                     int32_t* starts, wbm_c64* abar, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!starts || !abar) return fail(WBM_ERR_ARG, "starts / abar is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
+  WBM_HIP(wbm::launch_steer(steer_args(p, T), p->dd, starts, reinterpret_cast<double2*>(abar), st),
+          "steer launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_channelize(wbm_plan* p, const wbm_c32* x, wbm_c32* X, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!x || !X) return fail(WBM_ERR_ARG, "x / X is NULL");
+  const wbm_config& c = p->cfg;
+  WBM_HIP(wbm::launch_channelize(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(X),
+                                 c.n_elem, c.k_sub, p->B, p->twK,
+                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr,
+                                 static_cast<hipStream_t>(stream)),
+          "channelize launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beamspace(wbm_plan* p, const wbm_c32* X, wbm_c32* Y, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!X || !Y) return fail(WBM_ERR_ARG, "X / Y is NULL");
+  const wbm_config& c = p->cfg;
+  WBM_HIP(wbm::launch_beamspace(reinterpret_cast<const float2*>(X), reinterpret_cast<float2*>(Y),
+                                nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM, nullptr, 0,
+                                nullptr, static_cast<hipStream_t>(stream)),
+          "beamspace launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, const int32_t* win,
+                        int32_t T, double loading, int32_t form, wbm_c32* out, wbm_c32* weights,
+                        int32_t* starts, int32_t* info, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x) return fail(WBM_ERR_ARG, "x is NULL");
+  if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
+  if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
+  if (form != WBM_FORM_PLAIN && form != WBM_FORM_FUSED && form != WBM_FORM_GRAPH)
+    return fail(WBM_ERR_ARG, "unknown form");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
+  float2* o = reinterpret_cast<float2*>(out);
+  float2* w = reinterpret_cast<float2*>(weights);
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  if (form == WBM_FORM_PLAIN) {
+    if ((s = ensure_plain(p))) return s;
+    WBM_HIP(wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st), "steer launch");
+    WBM_HIP(wbm::launch_channelize(xx, p->X, c.n_elem, c.k_sub, p->B, p->twK,
+                                   (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st),
+            "channelize launch");
+    WBM_HIP(wbm::launch_beamspace(p->X, p->Y, nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
+                                  nullptr, 0, nullptr, st),
+            "beamspace launch");
+    WBM_HIP(wbm::launch_mvdr_plain(pair_args(p, T, sumW, loading), p->dd, p->Y, p->starts, p->abar,
+                                   p->R32, p->w32, o, w, info, st),
+            "plain MVDR launch");
+  } else if (form == WBM_FORM_FUSED) {
+    WBM_HIP(enqueue_fused(p, xx, T, sumW, loading, o, w, info, st), "fused launch");
+  } else {
+    GraphKey key;
+    key.x = x;
+    key.out = out;
+    key.weights = weights;
+    key.info = info;
+    key.T = T;
+    key.sumW = sumW;
+    key.loading = loading;
+    key.valid = true;
+    if (!(key == p->gkey)) {
+      if (p->gexec) {
+        WBM_HIP(hipGraphExecDestroy(p->gexec), "graph destroy");
+        p->gexec = nullptr;
+      }
+      p->gkey.valid = false;
+      hipGraph_t g = nullptr;
+      WBM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      hipError_t le = enqueue_fused(p, xx, T, sumW, loading, o, w, info, p->cap_stream);
+      hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
+      if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "launch during capture");
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "end capture");
+      hipError_t ie = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        p->gexec = nullptr;
+        return hip_fail(ie, "graph instantiate");
+      }
+      p->gkey = key;
+    }
+    WBM_HIP(hipGraphLaunch(p->gexec, st), "graph launch");
+  }
+  if (starts) {
+    WBM_HIP(hipMemcpyAsync(starts, p->starts, sizeof(int) * (size_t)T * c.k_sub,
+                           hipMemcpyDeviceToDevice, st),
+            "starts copy");
+  }
+  return WBM_OK;
+}
+
+wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
+                           const int32_t* win, int32_t T, double loading, int32_t reps,
+                           double* stage_ms, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x || !stage_ms) return fail(WBM_ERR_ARG, "x / stage_ms is NULL");
+  if (reps < 1) return fail(WBM_ERR_ARG, "reps must be >= 1");
+  if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
+  const size_t pairs = (size_t)c.max_targets * c.k_sub;
+  if (!p->prof_out) {
+    if ((s = dev_alloc(p, &p->prof_out, pairs * (size_t)c.l_test, "profile outputs"))) return s;
+    if ((s = dev_alloc(p, &p->prof_w, pairs * (size_t)c.w_max, "profile weights"))) return s;
+    if ((s = dev_alloc(p, &p->prof_info, pairs, "profile info"))) return s;
+  }
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
+  double acc[4] = {0, 0, 0, 0};
+  hipError_t e = hipSuccess;
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess)
+      e = wbm::launch_channelize(xx, p->X, c.n_elem, c.k_sub, p->B, p->twK,
+                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess)
+      e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
+                                p->dd.rowtab, sumW, p->starts, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], st);
+    if (e == hipSuccess)
+      e = wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), p->dd, p->Yw, p->starts, p->abar,
+                                 p->prof_out, p->prof_w, p->prof_info, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      acc[i] += ms;
+    }
+  }
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  if (e != hipSuccess) return hip_fail(e, "stage timing");
+  for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i] / reps;
+  return WBM_OK;
+}
+
+wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, int32_t T,
+                         double loading, wbm_c32* out, wbm_c32* weights, int32_t* info,
+                         void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x) return fail(WBM_ERR_ARG, "x is NULL");
+  if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
+  if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
+  if (c.n_elem > 4096) return fail(WBM_ERR_UNSUPPORTED, "full-dimensional MVDR supports N <= 4096");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, nullptr, T, st, &sumW))) return s;
+  const size_t NN = (size_t)c.n_elem * c.n_elem;
+  if (!p->fullR) {
+    const size_t budget = (size_t)8 << 30;
+    size_t nk = budget / (sizeof(double2) * NN);
+    if (nk < 1) nk = 1;
+    if (nk > (size_t)c.k_sub) nk = c.k_sub;
+    p->nk_full = (int)nk;
+    if ((s = dev_alloc(p, &p->fullR, nk * NN, "full covariance"))) return s;
+    if ((s = dev_alloc(p, &p->fullW, nk * (size_t)c.max_targets * c.n_elem, "full weights"))) return s;
+  }
+  WBM_HIP(wbm::launch_channelize(reinterpret_cast<const float2*>(x), p->X, c.n_elem, c.k_sub, p->B,
+                                 p->twK, (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st),
+          "channelize launch");
+  int* inf = info ? info : p->full_info;
+  for (int k0 = 0; k0 < c.k_sub; k0 += p->nk_full) {
+    wbm::FullArgs a;
+    a.N = c.n_elem;
+    a.K = c.k_sub;
+    a.L = c.l_train;
+    a.Lt = c.l_test;
+    a.B = p->B;
+    a.T = T;
+    a.k0 = k0;
+    a.nk = std::min(p->nk_full, c.k_sub - k0);
+    a.delta = loading;
+    a.beta = c.beta;
+    a.dl = c.d_over_lambda;
+    a.half_bin = (c.flags & WBM_HALF_BIN) ? 1 : 0;
+    WBM_HIP(wbm::launch_full_mvdr(a, p->dd, p->X, p->fullR, p->fullW,
+                                  reinterpret_cast<float2*>(out), reinterpret_cast<float2*>(weights),
+                                  inf, st),
+            "full MVDR launch");
+  }
+  return WBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,438 @@
+// Window placement / windowed steering, and the per-(target, subband) reduced-dimension MVDR
+// kernels for gfx950: loaded W x W sample covariance (Eq. 11), Cholesky factorisation, the
+// two triangular solves giving c = R^-1 a / (a^H R^-1 a) (Eq. 13 / Eq. 20) and the beam
+// output c^H y on the test snapshots.
+//
+// Fused form: one workgroup per pair runs everything; the covariance accumulates exact
+// FP32 x FP32 products in FP64 and the Cholesky / solves run in FP64 (window covariances of
+// strong interferers reach condition numbers ~1e6, where FP32 accumulation loses the weights).
+// Plain form: the same steps as three FP32 launches with R and c in HBM, gathering the window
+// rows from the full beamspace.
+#include <math.h>
+
+#include "wbm_dev.h"
+#include "wbm_launch.h"
+
+namespace wbm {
+
+template <typename T>
+struct C2 {
+  T x, y;
+};
+template <typename T>
+__device__ __forceinline__ C2<T> c2(T a, T b) {
+  C2<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+
+constexpr int kPairThreads = 256;   // 4 wave64 per pair
+constexpr int kCH = 64;             // snapshots per LDS chunk of the covariance
+constexpr int kEPT = 9;             // ceil(64*65/2 / 256) lower-triangle entries per thread
+
+// ------------------------------------------------------------------------------------------
+// Window geometry in IEEE double with no contraction, so that the integer start is the same
+// as a host evaluation of the same expression.
+__device__ __forceinline__ void window_geom(double M, double dl, double sin_az, double beta,
+                                            double ksh, double K, int W, double* u_out,
+                                            int* s_out) {
+#pragma clang fp contract(off)
+  const double ratio = 1.0 + (beta * ksh) / K;
+  const double u = ((M * dl) * sin_az) * ratio;
+  const double c = u - 0.5 * (double)(W - 1);
+  *s_out = (int)floor(c + 0.5);
+  *u_out = u;
+}
+
+// One thread per (t, k, i < wmax): start s of the pair and a~_i = M^-1/2 sum_e e^{j psi e},
+// psi = 2 pi (u - (s + i)) / M, by the Dirichlet closed form with sinpi/sincospi in FP64.
+__global__ void k_steer(SteerArgs a, DevDesc d, int* __restrict__ starts,
+                        double2* __restrict__ abar) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)a.T * a.K * a.wmax;
+  if (idx >= total) return;
+  const int i = (int)(idx % a.wmax);
+  const int64_t pk = idx / a.wmax;
+  const int k = (int)(pk % a.K), t = (int)(pk / a.K);
+  const int W = d.win[t];
+  const int ks = (k < a.K / 2) ? k : k - a.K;
+  const double ksh = (double)ks + (a.half_bin ? 0.5 : 0.0);
+  double u;
+  int s;
+  window_geom((double)a.M, a.dl, d.sin_az[t], a.beta, ksh, (double)a.K, W, &u, &s);
+  if (i == 0) starts[t * a.K + k] = s;
+  double2 out = make_double2(0.0, 0.0);
+  if (i < W) {
+    const double xx = (u - (double)(s + i)) / (double)a.M;
+    const double num = sinpi((double)a.N * xx), den = sinpi(xx);
+    double mag = (den == 0.0) ? (double)a.N : num / den;
+    mag /= sqrt((double)a.M);
+    double sp, cp;
+    sincospi((double)(a.N - 1) * xx, &sp, &cp);
+    out = make_double2(mag * cp, mag * sp);
+  }
+  abar[idx] = out;
+}
+
+hipError_t launch_steer(const SteerArgs& a, const DevDesc& d, int* starts, double2* abar,
+                        hipStream_t s) {
+  const int64_t total = (int64_t)a.T * a.K * a.wmax;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_steer, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, a, d,
+                     starts, abar);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Row e of the packed lower triangle -> (i, j), j <= i.
+__device__ __forceinline__ void tri_index(int e, int& i, int& j) {
+  int ii = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
+  while (ii * (ii + 1) / 2 > e) --ii;
+  i = ii;
+  j = e - ii * (ii + 1) / 2;
+}
+
+// Snapshot b of window row i of pair (t, k).
+template <bool WINDOWED>
+__device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const PairArgs& a, int k,
+                                         int woff, int s, int i, int b) {
+  if constexpr (WINDOWED) {
+    const int TB = 1 << a.logTB;
+    return src[(((int64_t)k * a.nbt + (b >> a.logTB)) * a.sumW + woff + i) * TB + (b & (TB - 1))];
+  } else {
+    return src[((int64_t)k * a.M + ((s + i) & (a.M - 1))) * a.B + b];
+  }
+}
+
+// R (LDS, row stride RS, lower triangle) = (1/L) sum_{b<L} y_b y_b^H + delta I, accumulated
+// in ACC.  ys is an LDS scratch of W x kCH float2 that may alias R.
+template <typename ACC, bool WINDOWED>
+__device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& a, int k, int W,
+                                int woff, int s, float2* ys, C2<ACC>* R, int RS) {
+  const int tid = threadIdx.x;
+  const int nE = W * (W + 1) / 2;
+  int S = 1;
+  if (nE < kPairThreads) {
+    S = kPairThreads / nE;
+    S = 1 << (31 - __clz(S));
+    if (S > 64) S = 64;
+  }
+  const int groups = kPairThreads / S;
+  const int g = tid / S, sl = tid & (S - 1);
+  C2<ACC> acc[kEPT];
+  int ei[kEPT], ej[kEPT];
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {
+    acc[q] = c2<ACC>(0, 0);
+    const int e = g + q * groups;
+    ei[q] = -1;
+    ej[q] = 0;
+    if (e < nE) tri_index(e, ei[q], ej[q]);
+  }
+  for (int c0 = 0; c0 < a.L; c0 += kCH) {
+    __syncthreads();
+    for (int idx = tid; idx < W * kCH; idx += kPairThreads) {
+      const int i = idx / kCH, bb = idx - i * kCH;
+      const int b = c0 + bb;
+      float2 v = make_float2(0.f, 0.f);
+      if (b < a.L) v = load_y<WINDOWED>(src, a, k, woff, s, i, b);
+      ys[idx] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q) {
+      if (ei[q] >= 0) {
+        const float2* yi = ys + ei[q] * kCH;
+        const float2* yj = ys + ej[q] * kCH;
+        ACC ax = acc[q].x, ay = acc[q].y;
+        for (int bb = sl; bb < kCH; bb += S) {
+          const float2 u = yi[bb], v = yj[bb];
+          const ACC ux = u.x, uy = u.y, vx = v.x, vy = v.y;
+          ax += ux * vx + uy * vy;   // y_i conj(y_j)
+          ay += uy * vx - ux * vy;
+        }
+        acc[q] = c2<ACC>(ax, ay);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kEPT; ++q) {
+    for (int off = S >> 1; off > 0; off >>= 1) {
+      acc[q].x += __shfl_xor(acc[q].x, off);
+      acc[q].y += __shfl_xor(acc[q].y, off);
+    }
+  }
+  __syncthreads();   // ys (may alias R) no longer read
+  const ACC invL = (ACC)1 / (ACC)a.L;
+  if (sl == 0) {
+#pragma unroll
+    for (int q = 0; q < kEPT; ++q) {
+      if (ei[q] >= 0) {
+        C2<ACC> r = c2<ACC>(acc[q].x * invL, acc[q].y * invL);
+        if (ei[q] == ej[q]) {
+          r.x += (ACC)a.delta;
+          r.y = 0;
+        }
+        R[ei[q] * RS + ej[q]] = r;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// In-LDS right-looking Cholesky R = G G^H (lower), G's diagonal in diag[], strictly lower part
+// overwriting R.  Returns 0, or j + 1 when pivot j is not positive and finite (uniform).
+template <typename T>
+__device__ int chol_lds(C2<T>* R, int RS, T* diag, int W) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < W; ++j) {
+    const T d = R[j * RS + j].x;
+    if (!(d > (T)0) || !(d < (T)INFINITY)) return j + 1;
+    const T dj = sqrt(d);
+    const T inv = (T)1 / dj;
+    if (tid == 0) diag[j] = dj;
+    for (int i = j + 1 + tid; i < W; i += kPairThreads) {
+      C2<T> v = R[i * RS + j];
+      R[i * RS + j] = c2<T>(v.x * inv, v.y * inv);
+    }
+    __syncthreads();
+    const int nT = W - j - 1;
+    const int cnt = nT * (nT + 1) / 2;
+    for (int e = tid; e < cnt; e += kPairThreads) {
+      int ii, cc;
+      tri_index(e, ii, cc);
+      const int i = j + 1 + ii, c = j + 1 + cc;
+      const C2<T> gi = R[i * RS + j], gc = R[c * RS + j];
+      C2<T> r = R[i * RS + c];
+      r.x -= gi.x * gc.x + gi.y * gc.y;   // g_i conj(g_c)
+      r.y -= gi.y * gc.x - gi.x * gc.y;
+      R[i * RS + c] = r;
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Wave 0 solves G v = a, q = v^H v, G^H x = v, w = x / q (one lane per row, W <= 64) and
+// stores w in wv[] (LDS).  Caller syncs afterwards.
+template <typename T>
+__device__ void solve_lds(const C2<T>* R, int RS, const T* diag, int W,
+                          const double2* __restrict__ abar_p, C2<T>* wv) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  C2<T> v = c2<T>(0, 0);
+  if (lane < W) {
+    const double2 av = abar_p[lane];
+    v = c2<T>((T)av.x, (T)av.y);
+  }
+  for (int j = 0; j < W; ++j) {
+    const T dinv = (T)1 / diag[j];
+    const T vx = __shfl(v.x, j) * dinv, vy = __shfl(v.y, j) * dinv;
+    if (lane == j) {
+      v = c2<T>(vx, vy);
+    } else if (lane > j && lane < W) {
+      const C2<T> g = R[lane * RS + j];
+      v.x -= g.x * vx - g.y * vy;
+      v.y -= g.x * vy + g.y * vx;
+    }
+  }
+  T q = v.x * v.x + v.y * v.y;
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  C2<T> x = v;
+  for (int j = W - 1; j >= 0; --j) {
+    const T dinv = (T)1 / diag[j];
+    const T xx = __shfl(x.x, j) * dinv, xy = __shfl(x.y, j) * dinv;
+    if (lane == j) {
+      x = c2<T>(xx, xy);
+    } else if (lane < j) {
+      const C2<T> g = R[j * RS + lane];   // (G^H)[lane][j] = conj(G[j][lane])
+      x.x -= g.x * xx + g.y * xy;
+      x.y -= g.x * xy - g.y * xx;
+    }
+  }
+  const T qinv = (T)1 / q;
+  if (lane < W) wv[lane] = c2<T>(x.x * qinv, x.y * qinv);
+}
+
+struct PairLds {
+  int RS;
+  size_t r_off, diag_off, wv_off, total;
+};
+
+template <typename T>
+__host__ __device__ inline PairLds pair_lds_layout(int wmax) {
+  PairLds p;
+  p.RS = wmax + 1;
+  size_t rbytes = sizeof(C2<T>) * (size_t)wmax * p.RS;
+  size_t ybytes = sizeof(float2) * (size_t)wmax * kCH;
+  size_t big = rbytes > ybytes ? rbytes : ybytes;
+  big = (big + 15) & ~(size_t)15;
+  p.r_off = 0;
+  p.diag_off = big;
+  p.wv_off = big + ((sizeof(T) * 64 + 15) & ~(size_t)15);
+  p.total = p.wv_off + sizeof(C2<T>) * 64;
+  return p;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused form: one workgroup per pair p = k * T + t.
+__global__ __launch_bounds__(kPairThreads) void k_mvdr_fused(
+    PairArgs a, DevDesc d, const float2* __restrict__ Yw, const int* __restrict__ starts,
+    const double2* __restrict__ abar, float2* __restrict__ out, float2* __restrict__ wout,
+    int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PairLds lay = pair_lds_layout<double>(a.wmax);
+  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r_off);
+  float2* ys = reinterpret_cast<float2*>(smem + lay.r_off);
+  double* diag = reinterpret_cast<double*>(smem + lay.diag_off);
+  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv_off);
+
+  const int p = blockIdx.x;
+  const int k = p / a.T, t = p - k * a.T;
+  const int W = d.win[t], woff = d.woff[t];
+  const int s = starts[t * a.K + k];
+  const int64_t pair = (int64_t)t * a.K + k;
+
+  pair_covariance<double, true>(Yw, a, k, W, woff, s, ys, R, lay.RS);
+  const int fail = chol_lds<double>(R, lay.RS, diag, W);
+  if (!fail) solve_lds<double>(R, lay.RS, diag, W, abar + pair * a.wmax, wv);
+  __syncthreads();
+  for (int l = threadIdx.x; l < a.Lt; l += kPairThreads) {
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = 0; i < W; ++i) {
+        const float2 y = load_y<true>(Yw, a, k, woff, s, i, a.L + l);
+        const C2<double> w = wv[i];
+        zx += w.x * (double)y.x + w.y * (double)y.y;    // conj(w) y
+        zy += w.x * (double)y.y - w.y * (double)y.x;
+      }
+    }
+    out[pair * a.Lt + l] = make_float2((float)zx, (float)zy);
+  }
+  if (wout) {
+    for (int i = threadIdx.x; i < a.wmax; i += kPairThreads) {
+      float2 v = make_float2(0.f, 0.f);
+      if (!fail && i < W) v = make_float2((float)wv[i].x, (float)wv[i].y);
+      wout[pair * a.wmax + i] = v;
+    }
+  }
+  if (info && threadIdx.x == 0) info[pair] = fail;
+}
+
+hipError_t launch_mvdr_fused(const PairArgs& a, const DevDesc& d, const float2* Yw,
+                             const int* starts, const double2* abar, float2* out, float2* wout,
+                             int* info, hipStream_t s) {
+  const PairLds lay = pair_lds_layout<double>(a.wmax);
+  hipLaunchKernelGGL(k_mvdr_fused, dim3(a.T * a.K), dim3(kPairThreads), lay.total, s, a, d, Yw,
+                     starts, abar, out, wout, info);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Plain form, FP32 throughout, three launches.
+__global__ __launch_bounds__(kPairThreads) void k_plain_cov(PairArgs a, DevDesc d,
+                                                            const float2* __restrict__ Y,
+                                                            const int* __restrict__ starts,
+                                                            float2* __restrict__ R32) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PairLds lay = pair_lds_layout<float>(a.wmax);
+  C2<float>* R = reinterpret_cast<C2<float>*>(smem + lay.r_off);
+  float2* ys = reinterpret_cast<float2*>(smem + lay.r_off);
+  const int p = blockIdx.x;
+  const int k = p / a.T, t = p - k * a.T;
+  const int W = d.win[t];
+  const int s = starts[t * a.K + k];
+  const int64_t pair = (int64_t)t * a.K + k;
+  pair_covariance<float, false>(Y, a, k, W, 0, s, ys, R, lay.RS);
+  float2* dst = R32 + pair * a.wmax * a.wmax;
+  for (int e = threadIdx.x; e < W * W; e += kPairThreads) {
+    const int i = e / W, j = e - i * W;
+    if (j <= i) dst[i * a.wmax + j] = make_float2(R[i * lay.RS + j].x, R[i * lay.RS + j].y);
+  }
+}
+
+__global__ __launch_bounds__(kPairThreads) void k_plain_solve(PairArgs a, DevDesc d,
+                                                              const float2* __restrict__ R32,
+                                                              const double2* __restrict__ abar,
+                                                              float2* __restrict__ w32,
+                                                              int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const PairLds lay = pair_lds_layout<float>(a.wmax);
+  C2<float>* R = reinterpret_cast<C2<float>*>(smem + lay.r_off);
+  float* diag = reinterpret_cast<float*>(smem + lay.diag_off);
+  C2<float>* wv = reinterpret_cast<C2<float>*>(smem + lay.wv_off);
+  const int p = blockIdx.x;
+  const int k = p / a.T, t = p - k * a.T;
+  const int W = d.win[t];
+  const int64_t pair = (int64_t)t * a.K + k;
+  const float2* src = R32 + pair * a.wmax * a.wmax;
+  for (int e = threadIdx.x; e < W * W; e += kPairThreads) {
+    const int i = e / W, j = e - i * W;
+    if (j <= i) R[i * lay.RS + j] = c2<float>(src[i * a.wmax + j].x, src[i * a.wmax + j].y);
+  }
+  __syncthreads();
+  const int fail = chol_lds<float>(R, lay.RS, diag, W);
+  if (!fail) solve_lds<float>(R, lay.RS, diag, W, abar + pair * a.wmax, wv);
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.wmax; i += kPairThreads) {
+    float2 v = make_float2(0.f, 0.f);
+    if (!fail && i < W) v = make_float2(wv[i].x, wv[i].y);
+    w32[pair * a.wmax + i] = v;
+  }
+  if (info && threadIdx.x == 0) info[pair] = fail;
+}
+
+__global__ __launch_bounds__(kPairThreads) void k_plain_apply(PairArgs a, DevDesc d,
+                                                              const float2* __restrict__ Y,
+                                                              const int* __restrict__ starts,
+                                                              const float2* __restrict__ w32,
+                                                              float2* __restrict__ out,
+                                                              float2* __restrict__ wout) {
+  __shared__ float2 wv[64];
+  const int p = blockIdx.x;
+  const int k = p / a.T, t = p - k * a.T;
+  const int W = d.win[t];
+  const int s = starts[t * a.K + k];
+  const int64_t pair = (int64_t)t * a.K + k;
+  if (threadIdx.x < a.wmax) {
+    wv[threadIdx.x] = w32[pair * a.wmax + threadIdx.x];
+    if (wout) wout[pair * a.wmax + threadIdx.x] = w32[pair * a.wmax + threadIdx.x];
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < a.Lt; l += kPairThreads) {
+    float zx = 0.f, zy = 0.f;
+    for (int i = 0; i < W; ++i) {
+      const float2 y = load_y<false>(Y, a, k, 0, s, i, a.L + l);
+      const float2 w = wv[i];
+      zx += w.x * y.x + w.y * y.y;
+      zy += w.x * y.y - w.y * y.x;
+    }
+    out[pair * a.Lt + l] = make_float2(zx, zy);
+  }
+}
+
+hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* Y,
+                             const int* starts, const double2* abar, float2* R32, float2* w32,
+                             float2* out, float2* wout, int* info, hipStream_t s) {
+  const PairLds lay = pair_lds_layout<float>(a.wmax);
+  const dim3 grid(a.T * a.K), blk(kPairThreads);
+  hipLaunchKernelGGL(k_plain_cov, grid, blk, lay.total, s, a, d, Y, starts, R32);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_plain_solve, grid, blk, lay.total, s, a, d, R32, abar, w32, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_plain_apply, grid, blk, 0, s, a, d, Y, starts, w32, out, wout);
+  return hipGetLastError();
+}
+
+}  // namespace wbm
+
+namespace wbm {
+hipError_t set_pair_attributes() {
+  return hipFuncSetAttribute((const void*)k_mvdr_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             96 * 1024);
+}
+}  // namespace wbm

@@ -1,0 +1,68 @@
+// Host-side launchers of the gfx950 kernels (internal to the library; the public
+// interface is include/wbmvdr.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wbm {
+
+// Per-call description of the targets, uploaded to the device before the kernels run.
+struct DevDesc {
+  const double* sin_az;   // [T]
+  const int* win;         // [T]
+  const int* woff;        // [T] first window row of target t (prefix sum of win)
+  const int* rowtab;      // [sumW] window row r -> (t << 8) | i
+};
+
+// Time-DFT channelizer: x [N][B*K] -> X [K][B][N].
+hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, const float2* twK,
+                             const float2* hb, hipStream_t s);
+// log2 of the snapshots per beamspace tile for M, B.
+int beamspace_tile_log(int M, int B);
+// Zero-padded spatial DFT: X [K][B][N] -> Y [K][M][B] (if Y) and windows Yw (if Yw).
+hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
+                            const float2* twM, const int* rowtab, int sumW, const int* starts,
+                            hipStream_t s);
+
+struct SteerArgs {
+  int T, K, M, N, wmax, half_bin;
+  double beta, dl;
+};
+// Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
+hipError_t launch_steer(const SteerArgs& a, const DevDesc& d, int* starts, double2* abar,
+                        hipStream_t s);
+
+struct PairArgs {
+  int T, K, M, L, Lt, B, wmax;
+  int logTB, nbt, sumW;          // windowed layout (fused form)
+  double delta;
+};
+// Fused per-pair covariance (FP64 accumulation) -> Cholesky (FP64) -> solve -> apply,
+// reading the window rows written by the beamspace kernel.
+hipError_t launch_mvdr_fused(const PairArgs& a, const DevDesc& d, const float2* Yw,
+                             const int* starts, const double2* abar, float2* out, float2* wout,
+                             int* info, hipStream_t s);
+// Plain per-stage FP32 form reading the full beamspace Y [K][M][B]: gather + covariance,
+// Cholesky + solve, apply -- three launches with R and w in HBM.
+hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* Y,
+                             const int* starts, const double2* abar, float2* R32, float2* w32,
+                             float2* out, float2* wout, int* info, hipStream_t s);
+
+struct FullArgs {
+  int N, K, L, Lt, B, T, k0, nk;  // subbands k0 .. k0 + nk - 1
+  double delta, beta, dl;
+  int half_bin;
+};
+// Full-dimensional element-space MVDR for subbands k0..k0+nk-1 (R workspace [nk][N][N] FP64).
+hipError_t launch_full_mvdr(const FullArgs& a, const DevDesc& d, const float2* X, double2* R,
+                            double2* wtmp, float2* out, float2* wout, int* info, hipStream_t s);
+
+
+
+}  // namespace wbm
+
+namespace wbm {
+hipError_t set_fft_attributes();
+hipError_t set_pair_attributes();
+hipError_t set_full_attributes();
+}  // namespace wbm

@@ -1,0 +1,89 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI and compare it
+with the FP64 oracle on the same complex64 input."""
+
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+
+import oracle
+
+EPS32 = 2.0 ** -24
+
+
+def log(msg: str) -> None:
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def weight_tol(kappa: float, plain: bool = False) -> float:
+    """Relative weight tolerance against the FP64 oracle.
+
+    The library stores channelized and beamspace snapshots in FP32; rounding every snapshot
+    to FP32 perturbs the windowed covariance so that the MVDR weights move by about
+    0.5 eps32 sqrt(kappa) (measured on in-window jammers at 30-50 dB INR).  The fused form
+    (FP64 accumulation and Cholesky) must stay within 8 eps32 sqrt(kappa), floor 1e-5.  The
+    plain form forms the covariance and solves in FP32, whose rounding moves the weights by
+    about eps32 kappa; its bound is 4 eps32 kappa, floor 1e-5.
+    """
+    if plain:
+        return max(1e-5, 4.0 * EPS32 * kappa)
+    return max(1e-5, 8.0 * EPS32 * math.sqrt(kappa))
+
+
+def windowed_interference(scene, k, bins, ratio):
+    cfg = scene.cfg
+    Rin = oracle.interference_covariance(cfg.N, np.sin(scene.jammer_az), scene.jammer_inr,
+                                         ratio, cfg.dl, cfg.noise_var)
+    D = np.exp(-2j * np.pi * np.outer(np.asarray(bins, dtype=np.float64), np.arange(cfg.N)) / cfg.M)
+    D /= math.sqrt(cfg.M)
+    return D @ Rin @ D.conj().T
+
+
+def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.1,
+                     check_sinr=True):
+    """Check GPU outputs ``res`` (tensors) against oracle dict ``ref`` (windowed_mvdr with
+    return_windows).  Returns a dict of error statistics."""
+    cfg = scene.cfg
+    T, K = len(scene.win), cfg.K
+    ks = list(range(K)) if subbands is None else list(subbands)
+    starts = res["starts"].cpu().numpy()
+    w_g = res["weights"].cpu().numpy().astype(np.complex128)
+    z_g = res["out"].cpu().numpy().astype(np.complex128)
+    info = res["info"].cpu().numpy()
+    ratio = oracle.subband_freq_ratio(K, cfg.beta, cfg.half_bin)
+    assert np.all(info[:, ks] == 0), "Cholesky failures reported"
+    assert np.array_equal(starts[:, ks], ref["start"]), "window starts differ"
+    worst_w, worst_ratio, worst_z, worst_loss = 0.0, 0.0, 0.0, 0.0
+    for ik, k in enumerate(ks):
+        for t in range(T):
+            W = int(scene.win[t])
+            wo = ref["w"][t, ik, :W]
+            wg = w_g[t, k, :W]
+            assert np.all(w_g[t, k, W:] == 0), "weights not zero padded"
+            R = ref["R"][t][ik]
+            kappa = float(np.linalg.cond(R))
+            err = oracle.rel_weight_error(wg, wo)
+            tol = weight_tol(kappa, plain)
+            assert err <= tol, f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
+            worst_w = max(worst_w, err)
+            worst_ratio = max(worst_ratio, err / tol)
+            # apply step: GPU output vs the GPU's own weights on the oracle's test snapshots
+            Yt = ref["Yw"][t][ik][:, cfg.L:cfg.L + cfg.Lt]
+            if cfg.Lt:
+                zc = wg.conj() @ Yt
+                scale = np.linalg.norm(wg) * np.max(np.linalg.norm(Yt, axis=0))
+                dz = float(np.max(np.abs(z_g[t, k] - zc)) / scale)
+                assert dz <= 2e-6, f"pair t={t} k={k}: output error {dz:.3e}"
+                worst_z = max(worst_z, dz)
+            if check_sinr and scene.jammer_az.size:
+                bins = oracle.window_bins(int(ref["start"][t, ik]), W, cfg.M)
+                Rin = windowed_interference(scene, k, bins, ratio[k])
+                a = ref["a"][t, ik, :W]
+                loss = abs(oracle.sinr_loss_db(wg, wo, a, Rin))
+                assert loss <= sinr_bar_db, f"pair t={t} k={k}: SINR loss {loss:.3e} dB"
+                worst_loss = max(worst_loss, loss)
+    return dict(max_weight_err=worst_w, max_err_over_tol=worst_ratio, max_out_err=worst_z,
+                max_sinr_loss_db=worst_loss)

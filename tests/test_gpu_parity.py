@@ -1,0 +1,281 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle on the same
+seeded complex64 inputs -- stage by stage, end to end, and on edge cases."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_helpers import compare_beamform, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    _t.cuda.set_device(0)
+    return _t
+
+
+@pytest.fixture(scope="module")
+def wb():
+    import paper_2508_11790_amd as _wb
+    return _wb
+
+
+def _plan(wb, cfg, scene):
+    return wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, len(scene.win), int(max(scene.win)),
+                   beta=cfg.beta, d_over_lambda=cfg.dl, half_bin=cfg.half_bin)
+
+
+def _x32(scene):
+    return scene.x.astype(np.complex64)
+
+
+def _oracle(scene, x32, subbands=None, windows=True):
+    cfg = scene.cfg
+    return oracle.windowed_mvdr(x32.astype(np.complex128), M=cfg.M, K=cfg.K, L=cfg.L, Lt=cfg.Lt,
+                                sin_az=[math.sin(a) for a in scene.target_az], win=scene.win,
+                                delta=cfg.delta, beta=cfg.beta, dl=cfg.dl, half_bin=cfg.half_bin,
+                                subbands=subbands, return_windows=windows)
+
+
+# ----------------------------------------------------------------------------- stages
+
+@pytest.mark.parametrize("half_bin", [False, True])
+@pytest.mark.parametrize("shape", [(16, 32, 16, 64, 64), (20, 32, 8, 37, 11), (256, 512, 128, 256, 256),
+                                   (4, 4, 2, 3, 1)])
+def test_channelizer_and_beamspace_stages(torch, wb, shape, half_bin):
+    N, M, K, L, Lt = shape
+    log(f"stage case N={N} M={M} K={K} L={L} Lt={Lt} half_bin={half_bin}")
+    rng = np.random.default_rng(N + K)
+    B = L + Lt
+    x = (rng.standard_normal((N, B * K)) + 1j * rng.standard_normal((N, B * K))).astype(np.complex64)
+    plan = wb.Plan(N, M, K, L, Lt, 1, 1, half_bin=half_bin)
+    X_g = plan.channelize(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    X_o = oracle.channelize(x.astype(np.complex128), K, half_bin)            # [N, B, K]
+    d = np.max(np.abs(X_g.cpu().numpy().transpose(2, 1, 0) - X_o)) / np.max(np.abs(X_o))
+    assert d < 2e-6, d
+    # beamspace fed with the oracle's X rounded to complex64
+    X32 = X_o.astype(np.complex64)
+    Y_g = plan.beamspace(torch.from_numpy(np.ascontiguousarray(X32.transpose(2, 1, 0))).cuda())
+    torch.cuda.synchronize()
+    Y_o = oracle.beamspace(X32.astype(np.complex128), M)                   # [M, B, K]
+    d = np.max(np.abs(Y_g.cpu().numpy().transpose(1, 2, 0) - Y_o)) / np.max(np.abs(Y_o))
+    assert d < 2e-6, d
+    plan.close()
+
+
+@pytest.mark.parametrize("half_bin", [False, True])
+@pytest.mark.parametrize("N,M,K,wmax", [(16, 32, 16, 5), (256, 512, 128, 9), (1024, 2048, 256, 33),
+                                        (4096, 8192, 512, 64), (7, 8, 4, 8)])
+def test_window_starts_bit_exact_and_steering(torch, wb, N, M, K, wmax, half_bin):
+    log(f"steer case N={N} M={M} K={K} wmax={wmax}")
+    rng = np.random.default_rng(N)
+    T = 48
+    az = np.deg2rad(rng.uniform(-89, 89, size=T))
+    az[:6] = np.deg2rad([0.0, 30.0, -30.0, 90.0, -90.0, 10.0])
+    win = rng.integers(1, wmax + 1, size=T).astype(np.int32)
+    win[:4] = [wmax, 1, 2, min(4, wmax)]
+    plan = wb.Plan(N, M, K, 1, 1, T, wmax, half_bin=half_bin)
+    starts, abar = plan.steer(az, win)
+    torch.cuda.synchronize()
+    starts = starts.cpu().numpy()
+    abar = abar.cpu().numpy()
+    ratio = oracle.subband_freq_ratio(K, 0.2, half_bin)
+    for t in range(T):
+        s_az = math.sin(az[t])
+        for k in range(K):
+            u = oracle.beam_position(s_az, ratio[k], M, 0.5)
+            s = oracle.window_start(u, int(win[t]))
+            assert starts[t, k] == s, (t, k, u)
+        for k in (0, K // 2, K - 1, 1):
+            bins = oracle.window_bins(int(starts[t, k]), int(win[t]), M)
+            a = oracle.beamspace_steering(N, M, oracle.spatial_frequency(s_az, ratio[k], 0.5), bins)
+            assert np.max(np.abs(abar[t, k, :win[t]] - a)) < 1e-11 * max(1.0, N / math.sqrt(M))
+            assert np.all(abar[t, k, win[t]:] == 0)
+    plan.close()
+
+
+# ----------------------------------------------------------------------------- end to end
+
+@pytest.mark.parametrize("form", ["plain", "fused", "graph"])
+@pytest.mark.parametrize("half_bin", [False, True])
+def test_small_config_end_to_end(torch, wb, form, half_bin):
+    cfg = scenes.SMALL.replace(half_bin=half_bin)
+    log(f"small end-to-end form={form} half_bin={half_bin}")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
+    torch.cuda.synchronize()
+    st = compare_beamform(sc, ref, res, plain=(form == "plain"))
+    log(f"  {st}")
+    assert st["max_weight_err"] < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_gpu_config_all_pairs(torch, wb, form):
+    cfg = scenes.GPU
+    log(f"gpu config (N=256 M=512 K=128 W=9 L=256) all 1024 pairs form={form}")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
+    torch.cuda.synchronize()
+    st = compare_beamform(sc, ref, res, plain=(form == "plain"))
+    log(f"  {st}")
+    assert st["max_weight_err"] < 1e-5       # seeded scene: every window is well conditioned
+    plan.close()
+
+
+def test_batch_config_full_size_sampled_subbands(torch, wb):
+    cfg = scenes.BATCH
+    log("batch config (N=1024 M=2048 K=256 L=512, W in {5,9,17,33}, 64 targets): generating")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    plan = _plan(wb, cfg, sc)
+    xd = torch.from_numpy(x32).cuda()
+    res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form="fused")
+    torch.cuda.synchronize()
+    ks = [0, 1, 77, 128, 200, 255]
+    log("  oracle on sampled subbands")
+    ref = _oracle(sc, x32, subbands=ks)
+    st = compare_beamform(sc, ref, res, subbands=ks)
+    log(f"  {st}")
+    del xd
+    plan.close()
+
+
+def test_graph_replays_match_eager(torch, wb):
+    cfg = scenes.GPU
+    sc = scenes.make_scene(cfg)
+    x = torch.from_numpy(_x32(sc)).cuda()
+    plan = _plan(wb, cfg, sc)
+    eager = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    e_out = eager["out"].clone()
+    e_w = eager["weights"].clone()
+    out = torch.empty_like(e_out)
+    w = torch.empty_like(e_w)
+    for rep in range(4):
+        out.zero_()
+        w.zero_()
+        plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="graph", out=out, weights=w)
+        torch.cuda.synchronize()
+        assert torch.equal(out, e_out), rep
+        assert torch.equal(w, e_w), rep
+        # eager work between replays
+        plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+        torch.cuda.synchronize()
+    plan.close()
+
+
+# ----------------------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("case", [
+    dict(N=20, M=32, K=8, L=37, Lt=11, W=(4, 1, 32, 7)),       # ragged snapshots, even W, W = M
+    dict(N=5, M=8, K=2, L=9, Lt=3, W=(8, 3)),                   # tiny, full window
+    dict(N=33, M=64, K=4, L=70, Lt=0, W=(5, 6)),                # no test snapshots
+    dict(N=16, M=16, K=16, L=40, Lt=40, W=(16,)),               # M = N (unitary D)
+])
+def test_edge_shapes(torch, wb, case):
+    W = case["W"]
+    T = len(W)
+    log(f"edge case {case}")
+    cfg = scenes.SceneConfig(name="edge", N=case["N"], M=case["M"], K=case["K"], L=case["L"],
+                             Lt=case["Lt"], T=T, W=None, W_choices=(1,), n_jammers=1,
+                             target_az_deg=tuple(np.linspace(-40, 50, T)),
+                             target_snr_db=(0.0,) * T, jammer_az_deg=(-70.0,),
+                             jammer_inr_db=(25.0,), seed=11)
+    sc = scenes.make_scene(cfg)
+    sc.win = np.asarray(W, dtype=np.int32)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    for form in ("plain", "fused"):
+        res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        compare_beamform(sc, ref, res, plain=(form == "plain"))
+    plan.close()
+
+
+def test_identity_windowed_equals_full_dimensional(torch, wb):
+    # W = M = N: the windowed beamspace MVDR equals element-space MVDR (Eq. 13 vs Eq. 20-21)
+    cfg = scenes.SMALL.replace(M=16, W=16)
+    sc = scenes.make_scene(cfg)
+    x = torch.from_numpy(_x32(sc)).cuda()
+    plan = _plan(wb, cfg, sc)
+    bm = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    fm = plan.full_mvdr(x, sc.target_az, cfg.delta)
+    torch.cuda.synchronize()
+    zb, zf = bm["out"].cpu().numpy(), fm["out"].cpu().numpy()
+    assert np.max(np.abs(zb - zf)) < 1e-4 * np.max(np.abs(zf))
+    assert int(fm["info"].abs().sum()) == 0
+    plan.close()
+
+
+def test_rejects_bad_targets(torch, wb):
+    plan = wb.Plan(16, 32, 16, 64, 64, 2, 5)
+    x = torch.zeros((16, 128 * 16), dtype=torch.complex64, device="cuda")
+    with pytest.raises(wb.WbmError):
+        plan.beamform(x, [0.1, 0.2, 0.3], [5, 5, 5], 10.0)          # T > max_targets
+    with pytest.raises(wb.WbmError):
+        plan.beamform(x, [0.1], [6], 10.0)                           # W > w_max
+    with pytest.raises(wb.WbmError):
+        plan.beamform(x, [float("nan")], [5], 10.0)
+    with pytest.raises(wb.WbmError):
+        plan.beamform(x, [0.1], [5], -1.0)
+    plan.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "fused"])
+def test_zero_loading_singular_reports_info(torch, wb, form):
+    # silent input and no loading: the window covariance is 0, the first pivot fails (info = 1)
+    plan = wb.Plan(16, 32, 4, 3, 2, 1, 9)
+    x = torch.zeros((16, 5 * 4), dtype=torch.complex64, device="cuda")
+    res = plan.beamform(x, [0.2], [9], 0.0, form=form)
+    torch.cuda.synchronize()
+    assert np.all(res["info"].cpu().numpy() == 1)
+    assert np.all(res["out"].cpu().numpy() == 0)
+    assert np.all(res["weights"].cpu().numpy() == 0)
+    plan.close()
+
+
+@pytest.mark.parametrize("name,subbands", [("small", None), ("gpu", [0, 5, 64, 127])])
+def test_full_dimensional_mvdr_matches_oracle(torch, wb, name, subbands):
+    cfg = scenes.config_by_name(name)
+    log(f"full-dimensional MVDR, {name} config")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    plan = _plan(wb, cfg, sc)
+    res = plan.full_mvdr(torch.from_numpy(x32).cuda(), sc.target_az, cfg.delta)
+    torch.cuda.synchronize()
+    assert int(res["info"].abs().sum()) == 0
+    ks = list(range(cfg.K)) if subbands is None else subbands
+    X = oracle.channelize_bins(x32, cfg.K, ks, cfg.half_bin)
+    ref = oracle.full_mvdr(x32, K=cfg.K, L=cfg.L, Lt=cfg.Lt, sin_az=[math.sin(a) for a in sc.target_az],
+                           delta=cfg.delta, beta=cfg.beta, dl=cfg.dl, half_bin=cfg.half_bin,
+                           subbands=ks, X=None)
+    w_g = res["weights"].cpu().numpy().astype(np.complex128)
+    z_g = res["out"].cpu().numpy().astype(np.complex128)
+    worst = 0.0
+    for ik, k in enumerate(ks):
+        R = oracle.sample_covariance(X[:, :cfg.L, ik], cfg.delta)
+        kappa = float(np.linalg.cond(R))
+        for t in range(cfg.T):
+            err = oracle.rel_weight_error(w_g[t, k], ref["w"][t, ik])
+            tol = max(1e-5, 8 * 2.0 ** -24 * math.sqrt(kappa))
+            assert err <= tol, (t, k, err, tol, kappa)
+            worst = max(worst, err)
+            zc = w_g[t, k].conj() @ X[:, cfg.L:, ik]
+            scale = np.linalg.norm(w_g[t, k]) * np.max(np.linalg.norm(X[:, cfg.L:, ik], axis=0))
+            assert np.max(np.abs(z_g[t, k] - zc)) <= 2e-6 * scale
+    log(f"  max weight error {worst:.3e}")
+    plan.close()
