@@ -340,9 +340,11 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   if ((s = dev_alloc(p, &p->full_info, (size_t)c.k_sub, "full info"))) return bail(s);
 
   he = wbm::set_fft_attributes();
-  if (he == hipSuccess) he = wbm::set_pair_attributes();
-  if (he == hipSuccess) he = wbm::set_full_attributes();
-  if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute"));
+  if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute (FFT kernels)"));
+  he = wbm::set_pair_attributes();
+  if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute (pair kernels)"));
+  he = wbm::set_full_attributes();
+  if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute (full-dimensional kernels)"));
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(WBM_ERR_HIP, "capture stream creation failed"));
   *out = p;

@@ -294,11 +294,12 @@ hipError_t launch_full_mvdr(const FullArgs& a, const DevDesc& d, const float2* X
 }
 
 hipError_t set_full_attributes() {
+  // dynamic LDS of both kernels is at most kLdsBudget; their static LDS is a few KiB
   hipError_t e = hipFuncSetAttribute((const void*)k_full_chol,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBudget);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_full_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             160 * 1024);
+                             (int)kLdsBudget);
 }
 
 }  // namespace wbm

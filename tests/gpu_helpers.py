@@ -18,19 +18,30 @@ def log(msg: str) -> None:
     sys.stdout.flush()
 
 
-def weight_tol(kappa: float, plain: bool = False) -> float:
-    """Relative weight tolerance against the FP64 oracle.
+def snapshot_dynamic_range(scene) -> float:
+    """sqrt(total element-space snapshot power / noise power) = sqrt(1 + N sum INR / sigma^2)."""
+    cfg = scene.cfg
+    return math.sqrt(1.0 + cfg.N * float(np.sum(scene.jammer_inr)) / cfg.noise_var)
 
-    The library stores channelized and beamspace snapshots in FP32; rounding every snapshot
-    to FP32 perturbs the windowed covariance so that the MVDR weights move by about
-    0.5 eps32 sqrt(kappa) (measured on in-window jammers at 30-50 dB INR).  The fused form
-    (FP64 accumulation and Cholesky) must stay within 8 eps32 sqrt(kappa), floor 1e-5.  The
-    plain form forms the covariance and solves in FP32, whose rounding moves the weights by
-    about eps32 kappa; its bound is 4 eps32 kappa, floor 1e-5.
+
+def weight_tol(kappa: float, plain: bool = False, dr: float = 1.0) -> float:
+    """Relative weight tolerance against the FP64 oracle, derived from the FP32 arithmetic.
+
+    * Rounding every stored snapshot to FP32 perturbs the windowed covariance so that the
+      MVDR weights move by about 0.5 eps32 sqrt(kappa) (measured with in-window jammers at
+      30-50 dB INR): bound 8 eps32 sqrt(kappa).
+    * FP32 FFT arithmetic leaves errors of order eps32 times the whole snapshot's norm in
+      every bin, so low-power window bins see strong jammers' rounding: the weights move by
+      about 0.05 eps32 DR, DR the snapshot dynamic range (measured at N = 256 and 1024):
+      bound 0.5 eps32 DR.
+    * The plain form also forms the covariance and solves in FP32, which moves the weights
+      by about eps32 kappa: bound 4 eps32 kappa.
+    The floor is the 1e-5 relative weight error the method is held to.
     """
+    base = max(1e-5, 0.5 * EPS32 * dr)
     if plain:
-        return max(1e-5, 4.0 * EPS32 * kappa)
-    return max(1e-5, 8.0 * EPS32 * math.sqrt(kappa))
+        return max(base, 4.0 * EPS32 * kappa)
+    return max(base, 8.0 * EPS32 * math.sqrt(kappa))
 
 
 def windowed_interference(scene, k, bins, ratio):
@@ -43,7 +54,7 @@ def windowed_interference(scene, k, bins, ratio):
 
 
 def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.1,
-                     check_sinr=True):
+                     check_sinr=True, fp32_fft=True):
     """Check GPU outputs ``res`` (tensors) against oracle dict ``ref`` (windowed_mvdr with
     return_windows).  Returns a dict of error statistics."""
     cfg = scene.cfg
@@ -57,6 +68,7 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
     assert np.all(info[:, ks] == 0), "Cholesky failures reported"
     assert np.array_equal(starts[:, ks], ref["start"]), "window starts differ"
     worst_w, worst_ratio, worst_z, worst_loss = 0.0, 0.0, 0.0, 0.0
+    dr = snapshot_dynamic_range(scene) if fp32_fft else 1.0
     for ik, k in enumerate(ks):
         for t in range(T):
             W = int(scene.win[t])
@@ -66,17 +78,19 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
             R = ref["R"][t][ik]
             kappa = float(np.linalg.cond(R))
             err = oracle.rel_weight_error(wg, wo)
-            tol = weight_tol(kappa, plain)
+            tol = weight_tol(kappa, plain, dr)
             assert err <= tol, f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
             worst_w = max(worst_w, err)
             worst_ratio = max(worst_ratio, err / tol)
-            # apply step: GPU output vs the GPU's own weights on the oracle's test snapshots
+            # apply step: GPU output vs the GPU's own weights on the oracle's test snapshots.
+            # The GPU's snapshots carry the FP32 rounding of two FFTs (~1e-6 of |y|), so the
+            # bound is 1e-5 ||w|| max ||y||; a wrong index or conjugation gives O(1).
             Yt = ref["Yw"][t][ik][:, cfg.L:cfg.L + cfg.Lt]
             if cfg.Lt:
                 zc = wg.conj() @ Yt
                 scale = np.linalg.norm(wg) * np.max(np.linalg.norm(Yt, axis=0))
                 dz = float(np.max(np.abs(z_g[t, k] - zc)) / scale)
-                assert dz <= 2e-6, f"pair t={t} k={k}: output error {dz:.3e}"
+                assert dz <= 1e-5, f"pair t={t} k={k}: output error {dz:.3e}"
                 worst_z = max(worst_z, dz)
             if check_sinr and scene.jammer_az.size:
                 bins = oracle.window_bins(int(ref["start"][t, ik]), W, cfg.M)
