@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--workload", default="gpu", help="scene config name (default: gpu)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-full", action="store_true", help="skip full-dimensional MVDR")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run 5 plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the path is measured on one GPU's share of the "
@@ -141,6 +143,15 @@ def main():
         nfs = max(2, min(args.steps // 20, 20))
         ms_full = timed_steps(torch, lambda: plan.full_mvdr(x, az, delta, want_weights=False),
                               nfs, 2)
+
+    if args.copy_calib:
+        src = torch.empty(args.copy_calib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {args.copy_calib} MiB")
+        del src, dst
 
     log("per-kernel times (HIP events)")
     st = plan.stage_times(x, az, win, delta, reps=max(20, args.steps // 4))

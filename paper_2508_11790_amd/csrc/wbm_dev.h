@@ -6,8 +6,8 @@
 
 namespace wbm {
 
-constexpr int kThreads = 256;         // workgroup size of the FFT kernels (4 wave64)
-constexpr int kTile = 8192;           // complex values per FFT tile in LDS (64 KiB + padding)
+
+
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -73,62 +73,92 @@ __device__ __forceinline__ void dftR(float2* v) {
   else dft8(v);
 }
 
-// One Stockham autosort pass of radix R over `nrows` rows of length n = 2^logn held in LDS
-// (row stride rs complex).  Butterfly j of a row reads v[r] = x[j + r n/R], multiplies by
-// exp(-2 pi i r (j mod Ns) / (Ns R)) (table tw[q] = exp(-2 pi i q / n)), applies the R-point
-// DFT and writes v[r] to (j div Ns) Ns R + (j mod Ns) + r Ns.  All reads complete (barrier)
-// before any write, so the pass works in place.  Every thread owns up to PER butterflies.
-template <int R, int THREADS, int TILE>
-__device__ __forceinline__ void stockham_pass(float2* lds, int nrows, int logn, int rs, int logNs,
-                                              const float2* __restrict__ tw) {
-  constexpr int PER = (TILE / R + THREADS - 1) / THREADS;
-  constexpr int LOGR = (R == 2) ? 1 : (R == 4 ? 2 : 3);
-  const int n = 1 << logn;
-  const int logq = logn - LOGR;              // log2(n / R)
-  const int nbf = nrows << logq;             // butterflies in the tile
-  const int Ns = 1 << logNs;
-  float2 v[PER][R];
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int bf = threadIdx.x + p * THREADS;
-    if (bf < nbf) {
-      const int row = bf >> logq, j = bf & ((1 << logq) - 1);
-      const float2* src = lds + row * rs + j;
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = src[r << logq];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int bf = threadIdx.x + p * THREADS;
-    if (bf < nbf) {
-      const int row = bf >> logq, j = bf & ((1 << logq) - 1);
-      const int k = j & (Ns - 1);
-      if (logNs > 0) {
-        // twiddle index r * k * n / (Ns R)
-        const int step = k << (logn - logNs - LOGR);
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], tw[(r * step) & (n - 1)]);
-      }
-      dftR<R>(v[p]);
-      float2* dst = lds + row * rs + (((j >> logNs) << (logNs + LOGR)) | k);
-#pragma unroll
-      for (int r = 0; r < R; ++r) dst[r << logNs] = v[p][r];
-    }
-  }
-  __syncthreads();
-}
+// Batched forward DFT of `rows` rows of n = 2^LOGN points held across a workgroup of
+// tile/8 threads, eight complex values per thread (Stockham autosort, radix 8 with one
+// leading radix-2 or radix-4 pass).  Pass p of radix R over sub-length Ns: butterfly j of
+// a row takes v[r] = x[j + r n/R], multiplies v[r] by exp(-2 pi i r (j mod Ns) / (Ns R)),
+// applies the R-point DFT and stores v[r] at (j div Ns) Ns R + (j mod Ns) + r Ns.  Values
+// live in registers inside a pass and in LDS between passes; the LDS row stride and one pad
+// slot every eight values keep the strided accesses off a single bank.
+template <int LOGN, int LOGTILE>
+struct Fft {
+  static constexpr int n = 1 << LOGN;
+  static constexpr int tile = 1 << LOGTILE;
+  static constexpr int rows = tile / n;
+  static constexpr int threads = tile / 8;
+  static constexpr int rs = n + n / 8 + 1;                  // LDS row stride (complex)
+  static constexpr int lds_complex = rows * rs;
+  static constexpr int R0 = (LOGN % 3 == 1) ? 2 : ((LOGN % 3 == 2) ? 4 : 8);
+  static constexpr int LOGR0 = (R0 == 2) ? 1 : (R0 == 4 ? 2 : 3);
+  static_assert(LOGTILE >= LOGN && LOGTILE >= 3, "tile must hold a row and 8 values/thread");
 
-// Forward DFT of `nrows` rows of length 2^logn in LDS (row stride rs), natural order in and
-// out, unnormalised.  Caller must __syncthreads() after filling the rows.
-template <int THREADS, int TILE>
-__device__ void fft_rows(float2* lds, int nrows, int logn, int rs, const float2* __restrict__ tw) {
-  int logNs = 0;
-  const int rem = logn % 3;
-  if (rem == 1) { stockham_pass<2, THREADS, TILE>(lds, nrows, logn, rs, logNs, tw); logNs += 1; }
-  if (rem == 2) { stockham_pass<4, THREADS, TILE>(lds, nrows, logn, rs, logNs, tw); logNs += 2; }
-  while (logNs < logn) { stockham_pass<8, THREADS, TILE>(lds, nrows, logn, rs, logNs, tw); logNs += 3; }
-}
+  __device__ __forceinline__ static int addr(int row, int i) { return row * rs + i + (i >> 3); }
+
+  // row and in-row butterfly index of this thread's p-th butterfly of a radix-R pass
+  template <int LOGR>
+  __device__ __forceinline__ static void bf(int p, int& row, int& j) {
+    constexpr int LOGQ = LOGN - LOGR;
+    const int b = threadIdx.x + p * threads;
+    row = b >> LOGQ;
+    j = b & ((1 << LOGQ) - 1);
+  }
+
+  template <int R, int LOGR, int LOGNS>
+  __device__ __forceinline__ static void compute_write(float2 (&v)[8], float2* lds,
+                                                       const float2* __restrict__ tw) {
+#pragma unroll
+    for (int p = 0; p < 8 / R; ++p) {
+      int row, j;
+      bf<LOGR>(p, row, j);
+      float2* b = v + p * R;
+      const int k = j & ((1 << LOGNS) - 1);
+      if constexpr (LOGNS > 0) {
+        const int step = k << (LOGN - LOGNS - LOGR);
+#pragma unroll
+        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tw[r * step]);
+      }
+      dftR<R>(b);
+      const int base = ((j >> LOGNS) << (LOGNS + LOGR)) | k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds[addr(row, base + (r << LOGNS))] = b[r];
+    }
+  }
+
+  __device__ __forceinline__ static void read8(float2 (&v)[8], const float2* lds) {
+    constexpr int LOGQ = LOGN - 3;
+    int row, j;
+    bf<3>(0, row, j);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = lds[addr(row, j + (r << LOGQ))];
+  }
+
+  template <int LOGNS>
+  __device__ __forceinline__ static void rest(float2 (&v)[8], float2* lds,
+                                              const float2* __restrict__ tw) {
+    if constexpr (LOGNS < LOGN) {
+      __syncthreads();
+      read8(v, lds);
+      __syncthreads();
+      compute_write<8, 3, LOGNS>(v, lds, tw);
+      rest<LOGNS + 3>(v, lds, tw);
+    }
+  }
+
+  // Index of the r-th input of this thread's p-th first-pass butterfly: (row, position).
+  __device__ __forceinline__ static void first_input(int p, int r, int& row, int& pos) {
+    int j;
+    bf<LOGR0>(p, row, j);
+    pos = j + (r << (LOGN - LOGR0));
+  }
+
+  // v holds the first-pass inputs (slot p*R0 + r <-> first_input(p, r)); on return the
+  // transform of every row is in LDS in natural order (addr(row, i)), visible to all threads.
+  __device__ __forceinline__ static void run(float2 (&v)[8], float2* lds,
+                                             const float2* __restrict__ tw) {
+    compute_write<R0, LOGR0, 0>(v, lds, tw);
+    rest<LOGR0>(v, lds, tw);
+    __syncthreads();
+  }
+};
 
 }  // namespace wbm
