@@ -4,8 +4,12 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
+#include <sys/stat.h>
 #include <vector>
 
 #include "wbm_launch.h"
@@ -44,12 +48,13 @@ struct GraphKey {
   void* out = nullptr;
   void* weights = nullptr;
   void* info = nullptr;
+  void* starts = nullptr;
   int T = 0, sumW = 0;
   double loading = 0.0;
   bool valid = false;
   bool operator==(const GraphKey& o) const {
     return valid && o.valid && x == o.x && out == o.out && weights == o.weights && info == o.info &&
-           T == o.T && sumW == o.sumW && loading == o.loading;
+           starts == o.starts && T == o.T && sumW == o.sumW && loading == o.loading;
   }
 };
 
@@ -59,7 +64,10 @@ struct wbm_plan {
   wbm_config cfg;
   int B = 0;
   int64_t S = 0;
-  int logTB = 0, TB = 0, nbt = 0;
+  int logTB = 0, TB = 0, nbt = 0;     // beamspace tile (snapshots per workgroup) of the fused form
+  int chan_logtile = 12, beam_logtile = 12;
+  int pair_threads = 256;             // threads per (target, subband) pair of the fused MVDR
+  bool tuned = false;
   int device = 0;
   // tables
   float2* twK = nullptr;
@@ -175,6 +183,18 @@ wbm_status ensure_plain(wbm_plan* p) {
   return dev_alloc(p, &p->w32, pairs * c.w_max, "plain weights");
 }
 
+// scratch outputs for timing runs (autotuner, wbm_stage_times)
+wbm_status ensure_prof(wbm_plan* p) {
+  if (p->prof_out) return WBM_OK;
+  const wbm_config& c = p->cfg;
+  const size_t pairs = (size_t)c.max_targets * c.k_sub;
+  wbm_status s;
+  if ((s = dev_alloc(p, &p->prof_out, pairs * (size_t)(c.l_test ? c.l_test : 1), "timing outputs")))
+    return s;
+  if ((s = dev_alloc(p, &p->prof_w, pairs * (size_t)c.w_max, "timing weights"))) return s;
+  return dev_alloc(p, &p->prof_info, pairs, "timing info");
+}
+
 wbm::PairArgs pair_args(const wbm_plan* p, int T, int sumW, double loading) {
   wbm::PairArgs a;
   a.T = T;
@@ -191,33 +211,205 @@ wbm::PairArgs pair_args(const wbm_plan* p, int T, int sumW, double loading) {
   return a;
 }
 
-wbm::SteerArgs steer_args(const wbm_plan* p, int T) {
-  wbm::SteerArgs a;
-  a.T = T;
-  a.K = p->cfg.k_sub;
-  a.M = p->cfg.m_fft;
-  a.N = p->cfg.n_elem;
-  a.wmax = p->cfg.w_max;
-  a.half_bin = (p->cfg.flags & WBM_HALF_BIN) ? 1 : 0;
-  a.beta = p->cfg.beta;
-  a.dl = p->cfg.d_over_lambda;
-  return a;
+wbm::WindowGeom geom(const wbm_plan* p, int T) {
+  wbm::WindowGeom g;
+  g.T = T;
+  g.K = p->cfg.k_sub;
+  g.M = p->cfg.m_fft;
+  g.N = p->cfg.n_elem;
+  g.half_bin = (p->cfg.flags & WBM_HALF_BIN) ? 1 : 0;
+  g.beta = p->cfg.beta;
+  g.dl = p->cfg.d_over_lambda;
+  g.sin_az = p->dd.sin_az;
+  g.win = p->dd.win;
+  return g;
 }
 
-// Steer -> channelize -> windowed beamspace -> fused MVDR on stream st.
-hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
-                         float2* out, float2* wout, int* info, hipStream_t st) {
+void set_beam_tile(wbm_plan* p, int logtile) {
+  p->beam_logtile = logtile;
+  p->logTB = wbm::beamspace_tile_log(p->cfg.m_fft, logtile);
+  p->TB = 1 << p->logTB;
+  p->nbt = (p->B + p->TB - 1) / p->TB;
+}
+
+hipError_t enqueue_channelize(wbm_plan* p, const float2* x, hipStream_t st) {
   const wbm_config& c = p->cfg;
-  hipError_t e = wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st);
+  return wbm::launch_channelize(x, p->X, c.n_elem, c.k_sub, p->B, p->twK,
+                                (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, p->chan_logtile, st);
+}
+
+hipError_t enqueue_beamspace_windows(wbm_plan* p, int T, int sumW, hipStream_t st) {
+  const wbm_config& c = p->cfg;
+  return wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
+                               p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st);
+}
+
+// Channelize -> windowed beamspace -> fused MVDR on stream st (the beamspace and pair
+// kernels place the windows themselves).
+hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
+                         float2* out, float2* wout, int* starts, int* info, hipStream_t st) {
+  hipError_t e = enqueue_channelize(p, x, st);
   if (e != hipSuccess) return e;
-  e = wbm::launch_channelize(x, p->X, c.n_elem, c.k_sub, p->B, p->twK,
-                             (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st);
+  e = enqueue_beamspace_windows(p, T, sumW, st);
   if (e != hipSuccess) return e;
-  e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
-                            p->dd.rowtab, sumW, p->starts, st);
+  return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, out,
+                                wout, starts, info, p->pair_threads, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// FFT tile autotuner: times every supported tile size of the channelizer and the windowed
+// beamspace kernel on the plan's own shape (HIP events, best of 3 after one warm-up launch)
+// and keeps the fastest.  Results are cached in a JSON file keyed by device and shape
+// ($WBM_AUTOTUNE_CACHE, default ~/.cache/wbmvdr/autotune.json); WBM_AUTOTUNE=0 disables
+// tuning (tile 2^12).
+
+std::string tune_key(const wbm_plan* p) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch = arch.substr(0, colon);
+  const wbm_config& c = p->cfg;
+  std::ostringstream os;
+  os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max;
+  return os.str();
+}
+
+std::string cache_path() {
+  const char* env = std::getenv("WBM_AUTOTUNE_CACHE");
+  if (env && *env) return env;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/wbmvdr/autotune.json";
+}
+
+// The cache file is a flat JSON object {"key": [chan_logtile, beam_logtile, pair_threads], ...}.
+bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr) {
+  std::ifstream f(cache_path());
+  if (!f) return false;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string txt = ss.str();
+  const std::string pat = "\"" + key + "\": [";
+  const size_t pos = txt.find(pat);
+  if (pos == std::string::npos) return false;
+  int a = 0, b = 0, c = 0;
+  if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d", &a, &b, &c) != 3) return false;
+  if (!wbm::fft_logtile_supported(a) || !wbm::fft_logtile_supported(b)) return false;
+  if (c != 64 && c != 256) return false;
+  *chan = a;
+  *beam = b;
+  *thr = c;
+  return true;
+}
+
+void cache_store(const std::string& key, int chan, int beam, int thr) {
+  const std::string path = cache_path();
+  std::string txt;
+  {
+    std::ifstream f(path);
+    if (f) {
+      std::stringstream ss;
+      ss << f.rdbuf();
+      txt = ss.str();
+    }
+  }
+  const size_t open = txt.find('{'), close = txt.rfind('}');
+  std::string body = (open != std::string::npos && close != std::string::npos && close > open)
+                         ? txt.substr(open + 1, close - open - 1) : std::string();
+  while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
+  std::ostringstream os;
+  os << "{" << body << (body.empty() ? "" : ",") << "\n  \"" << key << "\": [" << chan << ", "
+     << beam << ", " << thr << "]\n}\n";
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    for (size_t i = 1; i <= dir.size(); ++i)
+      if (i == dir.size() || dir[i] == '/') mkdir(dir.substr(0, i).c_str(), 0755);
+  }
+  std::ofstream out(path);
+  if (out) out << os.str();
+}
+
+template <class F>
+hipError_t time_best(F launch, hipStream_t st, float* best_ms) {
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
-  return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), p->dd, p->Yw, p->starts, p->abar,
-                                out, wout, info, st);
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  *best_ms = 1e30f;
+  for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+    e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && r > 0 && ms < *best_ms) *best_ms = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e;
+}
+
+hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loading,
+                    hipStream_t st) {
+  p->tuned = true;
+  const char* env = std::getenv("WBM_AUTOTUNE");
+  if (env && std::strcmp(env, "0") == 0) return hipSuccess;
+  const std::string key = tune_key(p);
+  int chan = 12, beam = 12, thr = 256;
+  if (cache_lookup(key, &chan, &beam, &thr)) {
+    p->chan_logtile = chan;
+    set_beam_tile(p, beam);
+    p->pair_threads = thr;
+    return hipSuccess;
+  }
+  float best_c = 1e30f, best_b = 1e30f;
+  for (int lt = 11; lt <= 13; ++lt) {
+    float ms;
+    p->chan_logtile = lt;
+    hipError_t e = time_best([&]() { return enqueue_channelize(p, x, st); }, st, &ms);
+    if (e != hipSuccess) return e;
+    if (ms < best_c) {
+      best_c = ms;
+      chan = lt;
+    }
+    set_beam_tile(p, lt);
+    e = time_best([&]() { return enqueue_beamspace_windows(p, T, sumW, st); }, st, &ms);
+    if (e != hipSuccess) return e;
+    if (ms < best_b) {
+      best_b = ms;
+      beam = lt;
+    }
+  }
+  p->chan_logtile = chan;
+  set_beam_tile(p, beam);
+  // threads per pair of the fused MVDR kernel, on the windows the chosen tile wrote
+  hipError_t e = enqueue_beamspace_windows(p, T, sumW, st);
+  if (e != hipSuccess) return e;
+  float best_p = 1e30f;
+  const wbm::PairArgs pa = pair_args(p, T, sumW, loading);
+  for (int thr_c : {256, 64}) {
+    if (thr_c == 64 && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
+    float ms;
+    e = time_best([&]() {
+      return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
+                                    p->prof_info, thr_c, st);
+    }, st, &ms);
+    if (e != hipSuccess) return e;
+    if (ms < best_p) {
+      best_p = ms;
+      thr = thr_c;
+    }
+  }
+  p->pair_threads = thr;
+  cache_store(key, chan, beam, thr);
+  return hipSuccess;
 }
 
 wbm_status check_plan(const wbm_plan* p) {
@@ -298,9 +490,7 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   (void)hipGetDevice(&p->device);
   p->B = (int)B;
   p->S = B * c.k_sub;
-  p->logTB = wbm::beamspace_tile_log(c.m_fft, p->B);
-  p->TB = 1 << p->logTB;
-  p->nbt = (p->B + p->TB - 1) / p->TB;
+  set_beam_tile(p, 12);
 
   auto bail = [&](wbm_status s) {
     std::string keep = g_err;
@@ -333,7 +523,10 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
 
   const size_t NS = (size_t)c.n_elem * p->S;
   if ((s = dev_alloc(p, &p->X, NS, "channelized X"))) return bail(s);
-  if ((s = dev_alloc(p, &p->Yw, (size_t)c.k_sub * p->nbt * p->TB * (size_t)Tm * c.w_max, "windows Yw")))
+  // room for the snapshot padding of the largest beamspace tile the autotuner may pick
+  const size_t tb_max = (size_t)1 << wbm::beamspace_tile_log(c.m_fft, 13);
+  const size_t b_pad = ((size_t)p->B + tb_max - 1) / tb_max * tb_max;
+  if ((s = dev_alloc(p, &p->Yw, (size_t)c.k_sub * b_pad * (size_t)Tm * c.w_max, "windows Yw")))
     return bail(s);
   if ((s = dev_alloc(p, &p->starts, (size_t)Tm * c.k_sub, "starts"))) return bail(s);
   if ((s = dev_alloc(p, &p->abar, (size_t)Tm * c.k_sub * c.w_max, "steering"))) return bail(s);
@@ -359,7 +552,7 @@ wbm_status wbm_steer(wbm_plan* p, const double* az_rad, const int32_t* win, int3
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
-  WBM_HIP(wbm::launch_steer(steer_args(p, T), p->dd, starts, reinterpret_cast<double2*>(abar), st),
+  WBM_HIP(wbm::launch_steer(geom(p, T), p->cfg.w_max, starts, reinterpret_cast<double2*>(abar), st),
           "steer launch");
   return WBM_OK;
 }
@@ -371,7 +564,7 @@ wbm_status wbm_channelize(wbm_plan* p, const wbm_c32* x, wbm_c32* X, void* strea
   const wbm_config& c = p->cfg;
   WBM_HIP(wbm::launch_channelize(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(X),
                                  c.n_elem, c.k_sub, p->B, p->twK,
-                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr,
+                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, p->chan_logtile,
                                  static_cast<hipStream_t>(stream)),
           "channelize launch");
   return WBM_OK;
@@ -384,7 +577,7 @@ wbm_status wbm_beamspace(wbm_plan* p, const wbm_c32* X, wbm_c32* Y, void* stream
   const wbm_config& c = p->cfg;
   WBM_HIP(wbm::launch_beamspace(reinterpret_cast<const float2*>(X), reinterpret_cast<float2*>(Y),
                                 nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM, nullptr, 0,
-                                nullptr, static_cast<hipStream_t>(stream)),
+                                geom(p, 0), p->beam_logtile, static_cast<hipStream_t>(stream)),
           "beamspace launch");
   return WBM_OK;
 }
@@ -406,26 +599,34 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
   float2* o = reinterpret_cast<float2*>(out);
   float2* w = reinterpret_cast<float2*>(weights);
   const float2* xx = reinterpret_cast<const float2*>(x);
+  if (form != WBM_FORM_PLAIN && !p->tuned) {
+    if ((s = ensure_prof(p))) return s;
+    WBM_HIP(autotune(p, xx, T, sumW, loading, st), "autotune");
+  }
   if (form == WBM_FORM_PLAIN) {
     if ((s = ensure_plain(p))) return s;
-    WBM_HIP(wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st), "steer launch");
-    WBM_HIP(wbm::launch_channelize(xx, p->X, c.n_elem, c.k_sub, p->B, p->twK,
-                                   (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st),
-            "channelize launch");
+    WBM_HIP(wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st), "steer launch");
+    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
     WBM_HIP(wbm::launch_beamspace(p->X, p->Y, nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
-                                  nullptr, 0, nullptr, st),
+                                  nullptr, 0, geom(p, T), 12, st),
             "beamspace launch");
     WBM_HIP(wbm::launch_mvdr_plain(pair_args(p, T, sumW, loading), p->dd, p->Y, p->starts, p->abar,
                                    p->R32, p->w32, o, w, info, st),
             "plain MVDR launch");
+    if (starts) {
+      WBM_HIP(hipMemcpyAsync(starts, p->starts, sizeof(int) * (size_t)T * c.k_sub,
+                             hipMemcpyDeviceToDevice, st),
+              "starts copy");
+    }
   } else if (form == WBM_FORM_FUSED) {
-    WBM_HIP(enqueue_fused(p, xx, T, sumW, loading, o, w, info, st), "fused launch");
+    WBM_HIP(enqueue_fused(p, xx, T, sumW, loading, o, w, starts, info, st), "fused launch");
   } else {
     GraphKey key;
     key.x = x;
     key.out = out;
     key.weights = weights;
     key.info = info;
+    key.starts = starts;
     key.T = T;
     key.sumW = sumW;
     key.loading = loading;
@@ -438,7 +639,7 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
       p->gkey.valid = false;
       hipGraph_t g = nullptr;
       WBM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-      hipError_t le = enqueue_fused(p, xx, T, sumW, loading, o, w, info, p->cap_stream);
+      hipError_t le = enqueue_fused(p, xx, T, sumW, loading, o, w, starts, info, p->cap_stream);
       hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
       if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -455,11 +656,6 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
     }
     WBM_HIP(hipGraphLaunch(p->gexec, st), "graph launch");
   }
-  if (starts) {
-    WBM_HIP(hipMemcpyAsync(starts, p->starts, sizeof(int) * (size_t)T * c.k_sub,
-                           hipMemcpyDeviceToDevice, st),
-            "starts copy");
-  }
   return WBM_OK;
 }
 
@@ -475,32 +671,24 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
-  const size_t pairs = (size_t)c.max_targets * c.k_sub;
-  if (!p->prof_out) {
-    if ((s = dev_alloc(p, &p->prof_out, pairs * (size_t)c.l_test, "profile outputs"))) return s;
-    if ((s = dev_alloc(p, &p->prof_w, pairs * (size_t)c.w_max, "profile weights"))) return s;
-    if ((s = dev_alloc(p, &p->prof_info, pairs, "profile info"))) return s;
-  }
+  if ((s = ensure_prof(p))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
+  if (!p->tuned) WBM_HIP(autotune(p, xx, T, sumW, loading, st), "autotune");
   hipEvent_t ev[5];
   for (int i = 0; i < 5; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
   double acc[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
   for (int r = 0; r < reps && e == hipSuccess; ++r) {
     e = hipEventRecord(ev[0], st);
-    if (e == hipSuccess) e = wbm::launch_steer(steer_args(p, T), p->dd, p->starts, p->abar, st);
+    if (e == hipSuccess) e = wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess)
-      e = wbm::launch_channelize(xx, p->X, c.n_elem, c.k_sub, p->B, p->twK,
-                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st);
+    if (e == hipSuccess) e = enqueue_channelize(p, xx, st);
     if (e == hipSuccess) e = hipEventRecord(ev[2], st);
-    if (e == hipSuccess)
-      e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
-                                p->dd.rowtab, sumW, p->starts, st);
+    if (e == hipSuccess) e = enqueue_beamspace_windows(p, T, sumW, st);
     if (e == hipSuccess) e = hipEventRecord(ev[3], st);
     if (e == hipSuccess)
-      e = wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), p->dd, p->Yw, p->starts, p->abar,
-                                 p->prof_out, p->prof_w, p->prof_info, st);
+      e = wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw,
+                                 p->prof_out, p->prof_w, nullptr, p->prof_info, p->pair_threads, st);
     if (e == hipSuccess) e = hipEventRecord(ev[4], st);
     if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
     for (int i = 0; i < 4 && e == hipSuccess; ++i) {
@@ -538,9 +726,7 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
     if ((s = dev_alloc(p, &p->fullR, nk * NN, "full covariance"))) return s;
     if ((s = dev_alloc(p, &p->fullW, nk * (size_t)c.max_targets * c.n_elem, "full weights"))) return s;
   }
-  WBM_HIP(wbm::launch_channelize(reinterpret_cast<const float2*>(x), p->X, c.n_elem, c.k_sub, p->B,
-                                 p->twK, (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, st),
-          "channelize launch");
+  WBM_HIP(enqueue_channelize(p, reinterpret_cast<const float2*>(x), st), "channelize launch");
   int* inf = info ? info : p->full_info;
   for (int k0 = 0; k0 < c.k_sub; k0 += p->nk_full) {
     wbm::FullArgs a;

@@ -8,23 +8,26 @@
 
 namespace wbm {
 
-constexpr int kLogTileMin = 12;   // 4096 complex per workgroup tile (n <= 4096)
-
-__host__ __device__ constexpr int fft_logtile(int logn) {
-  return logn > kLogTileMin ? logn : kLogTileMin;
+// A workgroup transforms one tile of 2^LOGTILE complex values (rows of n = 2^LOGN points),
+// eight values per thread.  LOGTILE is chosen per shape by the plan's autotuner among
+// kLogTiles (clamped to at least LOGN).
+__host__ __device__ constexpr int fft_tile(int logn, int logtile) {
+  return logtile > logn ? logtile : logn;
 }
-__host__ __device__ constexpr int fft_threads(int logn) { return (1 << fft_logtile(logn)) / 8; }
+__host__ __device__ constexpr int fft_threads(int logn, int logtile) {
+  return (1 << fft_tile(logn, logtile)) / 8;
+}
 
 // x [N][S] (S = B*K) -> X [K][B][N].  Workgroup = (TE = tile/K elements, block b).  Rows
 // e >= N are zero-filled and not written.  Optional pre-twiddle hb[tau] (half-bin centres).
 // Output scaled by K^-1/2 (unitary DFT).
-template <int LOGK>
-__global__ __launch_bounds__(fft_threads(LOGK)) void k_channelize(
+template <int LOGK, int LOGT>
+__global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
     const float2* __restrict__ x, float2* __restrict__ X, int N, int B, int64_t S,
     const float2* __restrict__ twK, const float2* __restrict__ hb, float scale) {
-  using F = Fft<LOGK, fft_logtile(LOGK)>;
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT)>;
   constexpr int K = F::n, TE = F::rows;
-  constexpr int LOGTE = fft_logtile(LOGK) - LOGK;
+  constexpr int LOGTE = fft_tile(LOGK, LOGT) - LOGK;
   __shared__ float2 lds[F::lds_complex];
   const int e0 = blockIdx.x * TE;
   const int b = blockIdx.y;
@@ -55,18 +58,23 @@ __global__ __launch_bounds__(fft_threads(LOGK)) void k_channelize(
 // X [K][B][N] -> beamspace of a tile of TB = tile/M snapshots of subband k (zero padded to M):
 //   full  : Y [K][M][B]                                         (stage output), and/or
 //   window: Yw [K][nbt][sumW][TB], row r = window row (t, i) of target t, bin (s_tk + i) mod M.
-// Workgroup = (snapshot tile j, subband k).
-template <int LOGM>
-__global__ __launch_bounds__(fft_threads(LOGM)) void k_beamspace(
+// Workgroup = (snapshot tile j, subband k).  With windows, the first T threads place the
+// targets' windows for subband k (same FP64 evaluation as the steering kernel) into LDS.
+template <int LOGM, int LOGT>
+__global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
     const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int N, int B,
     int K, const float2* __restrict__ twM, float scale, const int* __restrict__ rowtab, int sumW,
-    const int* __restrict__ starts) {
-  using F = Fft<LOGM, fft_logtile(LOGM)>;
+    WindowGeom g) {
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
   constexpr int M = F::n, TB = F::rows;
-  constexpr int LOGTB = fft_logtile(LOGM) - LOGM;
+  constexpr int LOGTB = fft_tile(LOGM, LOGT) - LOGM;
   __shared__ float2 lds[F::lds_complex];
+  extern __shared__ int s_start[];                       // [T] window starts of subband k
   const int j = blockIdx.x, k = blockIdx.y;
   const int b0 = j * TB;
+  if (Yw) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) s_start[t] = window_start(g, t, k);
+  }
   float2 v[8];
 #pragma unroll
   for (int p = 0; p < 8 / F::R0; ++p) {
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(fft_threads(LOGM)) void k_beamspace(
     for (int idx = threadIdx.x; idx < tot; idx += F::threads) {
       const int r = idx >> LOGTB, b = idx & (TB - 1);
       const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-      const int m = (starts[t * K + k] + i) & (M - 1);
+      const int m = (s_start[t] + i) & (M - 1);
       dst[idx] = cscale(lds[F::addr(b, m)], scale);
     }
   }
@@ -107,57 +115,82 @@ static int ilog2(int v) {
   return l;
 }
 
-template <int LOGK>
+template <int LOGK, int LOGT>
 static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const float2* twK,
                               const float2* hb, hipStream_t s) {
-  using F = Fft<LOGK, fft_logtile(LOGK)>;
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT)>;
   dim3 grid((N + F::rows - 1) / F::rows, B);
-  hipLaunchKernelGGL(k_channelize<LOGK>, grid, dim3(F::threads), 0, s, x, X, N, B,
+  hipLaunchKernelGGL((k_channelize<LOGK, LOGT>), grid, dim3(F::threads), 0, s, x, X, N, B,
                      (int64_t)B * F::n, twK, hb, 1.0f / sqrtf((float)F::n));
   return hipGetLastError();
 }
 
-template <int LOGM>
+template <int LOGM, int LOGT>
 static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
-                              const float2* twM, const int* rowtab, int sumW, const int* starts,
-                              hipStream_t s) {
-  using F = Fft<LOGM, fft_logtile(LOGM)>;
+                              const float2* twM, const int* rowtab, int sumW,
+                              const WindowGeom& g, hipStream_t s) {
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
   dim3 grid((B + F::rows - 1) / F::rows, K);
-  hipLaunchKernelGGL(k_beamspace<LOGM>, grid, dim3(F::threads), 0, s, X, Y, Yw, N, B, K, twM,
-                     1.0f / sqrtf((float)F::n), rowtab, sumW, starts);
+  const size_t shm = Yw ? sizeof(int) * (size_t)g.T : 0;
+  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), grid, dim3(F::threads), shm, s, X, Y, Yw, N, B,
+                     K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g);
   return hipGetLastError();
 }
 
-#define WBM_LOG_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13)
+#define WBM_LOG_CASES(M, T) \
+  M(1, T) M(2, T) M(3, T) M(4, T) M(5, T) M(6, T) M(7, T) M(8, T) M(9, T) M(10, T) M(11, T) \
+  M(12, T) M(13, T)
+
+int fft_tile_log(int logn, int logtile) { return fft_tile(logn, logtile); }
+
+bool fft_logtile_supported(int logtile) { return logtile >= 11 && logtile <= 13; }
 
 hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, const float2* twK,
-                             const float2* hb, hipStream_t s) {
-  switch (ilog2(K)) {
-#define C(L) \
-  case L:    \
-    return chan_launch<L>(x, X, N, B, twK, hb, s);
-    WBM_LOG_CASES(C)
-#undef C
+                             const float2* hb, int logtile, hipStream_t s) {
+  const int lk = ilog2(K);
+#define C(L, T)                                     \
+  case L:                                           \
+    return chan_launch<L, T>(x, X, N, B, twK, hb, s);
+  switch (logtile) {
+    case 11:
+      switch (lk) { WBM_LOG_CASES(C, 11) }
+      break;
+    case 12:
+      switch (lk) { WBM_LOG_CASES(C, 12) }
+      break;
+    case 13:
+      switch (lk) { WBM_LOG_CASES(C, 13) }
+      break;
   }
+#undef C
   return hipErrorInvalidValue;
 }
 
-int beamspace_tile_log(int M, int /*B*/) { return fft_logtile(ilog2(M)) - ilog2(M); }
+int beamspace_tile_log(int M, int logtile) { return fft_tile(ilog2(M), logtile) - ilog2(M); }
 
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
-                            const float2* twM, const int* rowtab, int sumW, const int* starts,
-                            hipStream_t s) {
-  switch (ilog2(M)) {
-#define C(L) \
-  case L:    \
-    return beam_launch<L>(X, Y, Yw, N, B, K, twM, rowtab, sumW, starts, s);
-    WBM_LOG_CASES(C)
-#undef C
+                            const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
+                            int logtile, hipStream_t s) {
+  const int lm = ilog2(M);
+#define C(L, T)                                                          \
+  case L:                                                                \
+    return beam_launch<L, T>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, s);
+  switch (logtile) {
+    case 11:
+      switch (lm) { WBM_LOG_CASES(C, 11) }
+      break;
+    case 12:
+      switch (lm) { WBM_LOG_CASES(C, 12) }
+      break;
+    case 13:
+      switch (lm) { WBM_LOG_CASES(C, 13) }
+      break;
   }
+#undef C
   return hipErrorInvalidValue;
 }
 
-// The FFT kernels use static LDS only (at most 8192 * 9/8 + 8 complex = 72 KiB).
+// Static LDS is at most 8192 * 9/8 + 8 complex = 72 KiB; the beamspace kernel adds T ints.
 hipError_t set_fft_attributes() { return hipSuccess; }
 
 }  // namespace wbm

@@ -3,9 +3,11 @@
 // two triangular solves giving c = R^-1 a / (a^H R^-1 a) (Eq. 13 / Eq. 20) and the beam
 // output c^H y on the test snapshots.
 //
-// Fused form: one workgroup per pair runs everything; the covariance accumulates exact
-// FP32 x FP32 products in FP64 and the Cholesky / solves run in FP64 (window covariances of
-// strong interferers reach condition numbers ~1e6, where FP32 accumulation loses the weights).
+// Fused form: one workgroup per pair runs everything, placing its window and evaluating its
+// steering vector itself; the covariance accumulates exact FP32 x FP32 products in FP64 and
+// the Cholesky / solves run in FP64 (window covariances next to strong interferers reach
+// condition numbers ~1e6, where FP32 accumulation loses the weights).  Windows up to 40 bins
+// run one wave64 per pair; wider windows run four waves per pair.
 // Plain form: the same steps as three FP32 launches with R and c in HBM, gathering the window
 // rows from the full beamspace.
 #include <math.h>
@@ -27,59 +29,31 @@ __device__ __forceinline__ C2<T> c2(T a, T b) {
   return r;
 }
 
-constexpr int kPairThreads = 256;   // 4 wave64 per pair
-constexpr int kCH = 64;             // snapshots per LDS chunk of the covariance
-constexpr int kEPT = 9;             // ceil(64*65/2 / 256) lower-triangle entries per thread
+constexpr int kCH = 64;        // snapshots per LDS chunk of the covariance
+constexpr int kWaveWMax = 40;  // widest window of the one-wave kernel
 
 // ------------------------------------------------------------------------------------------
-// Window geometry in IEEE double with no contraction, so that the integer start is the same
-// as a host evaluation of the same expression.
-__device__ __forceinline__ void window_geom(double M, double dl, double sin_az, double beta,
-                                            double ksh, double K, int W, double* u_out,
-                                            int* s_out) {
-#pragma clang fp contract(off)
-  const double ratio = 1.0 + (beta * ksh) / K;
-  const double u = ((M * dl) * sin_az) * ratio;
-  const double c = u - 0.5 * (double)(W - 1);
-  *s_out = (int)floor(c + 0.5);
-  *u_out = u;
-}
-
-// One thread per (t, k, i < wmax): start s of the pair and a~_i = M^-1/2 sum_e e^{j psi e},
-// psi = 2 pi (u - (s + i)) / M, by the Dirichlet closed form with sinpi/sincospi in FP64.
-__global__ void k_steer(SteerArgs a, DevDesc d, int* __restrict__ starts,
+// One thread per (t, k, i < wmax): start s of the pair and its windowed steering vector.
+__global__ void k_steer(WindowGeom g, int wmax, int* __restrict__ starts,
                         double2* __restrict__ abar) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)a.T * a.K * a.wmax;
+  const int64_t total = (int64_t)g.T * g.K * wmax;
   if (idx >= total) return;
-  const int i = (int)(idx % a.wmax);
-  const int64_t pk = idx / a.wmax;
-  const int k = (int)(pk % a.K), t = (int)(pk / a.K);
-  const int W = d.win[t];
-  const int ks = (k < a.K / 2) ? k : k - a.K;
-  const double ksh = (double)ks + (a.half_bin ? 0.5 : 0.0);
+  const int i = (int)(idx % wmax);
+  const int64_t pk = idx / wmax;
+  const int k = (int)(pk % g.K), t = (int)(pk / g.K);
   double u;
   int s;
-  window_geom((double)a.M, a.dl, d.sin_az[t], a.beta, ksh, (double)a.K, W, &u, &s);
-  if (i == 0) starts[t * a.K + k] = s;
-  double2 out = make_double2(0.0, 0.0);
-  if (i < W) {
-    const double xx = (u - (double)(s + i)) / (double)a.M;
-    const double num = sinpi((double)a.N * xx), den = sinpi(xx);
-    double mag = (den == 0.0) ? (double)a.N : num / den;
-    mag /= sqrt((double)a.M);
-    double sp, cp;
-    sincospi((double)(a.N - 1) * xx, &sp, &cp);
-    out = make_double2(mag * cp, mag * sp);
-  }
-  abar[idx] = out;
+  window_of(g, t, k, &u, &s);
+  if (i == 0) starts[t * g.K + k] = s;
+  abar[idx] = (i < g.win[t]) ? window_steering(g, u, s, i) : make_double2(0.0, 0.0);
 }
 
-hipError_t launch_steer(const SteerArgs& a, const DevDesc& d, int* starts, double2* abar,
+hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar,
                         hipStream_t s) {
-  const int64_t total = (int64_t)a.T * a.K * a.wmax;
+  const int64_t total = (int64_t)g.T * g.K * wmax;
   const int bs = 256;
-  hipLaunchKernelGGL(k_steer, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, a, d,
+  hipLaunchKernelGGL(k_steer, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, g, wmax,
                      starts, abar);
   return hipGetLastError();
 }
@@ -107,24 +81,25 @@ __device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const P
 }
 
 // R (LDS, row stride RS, lower triangle) = (1/L) sum_{b<L} y_b y_b^H + delta I, accumulated
-// in ACC.  ys is an LDS scratch of W x kCH float2 that may alias R.
-template <typename ACC, bool WINDOWED>
+// in ACC by THREADS threads, up to EPT lower-triangle entries per thread (W(W+1)/2 <=
+// EPT * THREADS).  ys is an LDS scratch of W x kCH float2 that may alias R.
+template <typename ACC, bool WINDOWED, int THREADS, int EPT>
 __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& a, int k, int W,
                                 int woff, int s, float2* ys, C2<ACC>* R, int RS) {
   const int tid = threadIdx.x;
   const int nE = W * (W + 1) / 2;
   int S = 1;
-  if (nE < kPairThreads) {
-    S = kPairThreads / nE;
+  if (nE < THREADS) {
+    S = THREADS / nE;
     S = 1 << (31 - __clz(S));
     if (S > 64) S = 64;
   }
-  const int groups = kPairThreads / S;
+  const int groups = THREADS / S;
   const int g = tid / S, sl = tid & (S - 1);
-  C2<ACC> acc[kEPT];
-  int ei[kEPT], ej[kEPT];
+  C2<ACC> acc[EPT];
+  int ei[EPT], ej[EPT];
 #pragma unroll
-  for (int q = 0; q < kEPT; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     acc[q] = c2<ACC>(0, 0);
     const int e = g + q * groups;
     ei[q] = -1;
@@ -133,7 +108,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
   }
   for (int c0 = 0; c0 < a.L; c0 += kCH) {
     __syncthreads();
-    for (int idx = tid; idx < W * kCH; idx += kPairThreads) {
+    for (int idx = tid; idx < W * kCH; idx += THREADS) {
       const int i = idx / kCH, bb = idx - i * kCH;
       const int b = c0 + bb;
       float2 v = make_float2(0.f, 0.f);
@@ -142,7 +117,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kEPT; ++q) {
+    for (int q = 0; q < EPT; ++q) {
       if (ei[q] >= 0) {
         const float2* yi = ys + ei[q] * kCH;
         const float2* yj = ys + ej[q] * kCH;
@@ -158,7 +133,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
     }
   }
 #pragma unroll
-  for (int q = 0; q < kEPT; ++q) {
+  for (int q = 0; q < EPT; ++q) {
     for (int off = S >> 1; off > 0; off >>= 1) {
       acc[q].x += __shfl_xor(acc[q].x, off);
       acc[q].y += __shfl_xor(acc[q].y, off);
@@ -168,7 +143,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
   const ACC invL = (ACC)1 / (ACC)a.L;
   if (sl == 0) {
 #pragma unroll
-    for (int q = 0; q < kEPT; ++q) {
+    for (int q = 0; q < EPT; ++q) {
       if (ei[q] >= 0) {
         C2<ACC> r = c2<ACC>(acc[q].x * invL, acc[q].y * invL);
         if (ei[q] == ej[q]) {
@@ -184,7 +159,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
 
 // In-LDS right-looking Cholesky R = G G^H (lower), G's diagonal in diag[], strictly lower part
 // overwriting R.  Returns 0, or j + 1 when pivot j is not positive and finite (uniform).
-template <typename T>
+template <typename T, int THREADS>
 __device__ int chol_lds(C2<T>* R, int RS, T* diag, int W) {
   const int tid = threadIdx.x;
   for (int j = 0; j < W; ++j) {
@@ -193,14 +168,14 @@ __device__ int chol_lds(C2<T>* R, int RS, T* diag, int W) {
     const T dj = sqrt(d);
     const T inv = (T)1 / dj;
     if (tid == 0) diag[j] = dj;
-    for (int i = j + 1 + tid; i < W; i += kPairThreads) {
+    for (int i = j + 1 + tid; i < W; i += THREADS) {
       C2<T> v = R[i * RS + j];
       R[i * RS + j] = c2<T>(v.x * inv, v.y * inv);
     }
     __syncthreads();
     const int nT = W - j - 1;
     const int cnt = nT * (nT + 1) / 2;
-    for (int e = tid; e < cnt; e += kPairThreads) {
+    for (int e = tid; e < cnt; e += THREADS) {
       int ii, cc;
       tri_index(e, ii, cc);
       const int i = j + 1 + ii, c = j + 1 + cc;
@@ -218,15 +193,12 @@ __device__ int chol_lds(C2<T>* R, int RS, T* diag, int W) {
 // Wave 0 solves G v = a, q = v^H v, G^H x = v, w = x / q (one lane per row, W <= 64) and
 // stores w in wv[] (LDS).  Caller syncs afterwards.
 template <typename T>
-__device__ void solve_lds(const C2<T>* R, int RS, const T* diag, int W,
-                          const double2* __restrict__ abar_p, C2<T>* wv) {
+__device__ void solve_lds(const C2<T>* R, int RS, const T* diag, int W, const double2* av,
+                          C2<T>* wv) {
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
   C2<T> v = c2<T>(0, 0);
-  if (lane < W) {
-    const double2 av = abar_p[lane];
-    v = c2<T>((T)av.x, (T)av.y);
-  }
+  if (lane < W) v = c2<T>((T)av[lane].x, (T)av[lane].y);
   for (int j = 0; j < W; ++j) {
     const T dinv = (T)1 / diag[j];
     const T vx = __shfl(v.x, j) * dinv, vy = __shfl(v.y, j) * dinv;
@@ -258,7 +230,7 @@ __device__ void solve_lds(const C2<T>* R, int RS, const T* diag, int W,
 
 struct PairLds {
   int RS;
-  size_t r_off, diag_off, wv_off, total;
+  size_t r_off, diag_off, wv_off, av_off, total;
 };
 
 template <typename T>
@@ -272,34 +244,43 @@ __host__ __device__ inline PairLds pair_lds_layout(int wmax) {
   p.r_off = 0;
   p.diag_off = big;
   p.wv_off = big + ((sizeof(T) * 64 + 15) & ~(size_t)15);
-  p.total = p.wv_off + sizeof(C2<T>) * 64;
+  p.av_off = p.wv_off + sizeof(C2<T>) * 64;
+  p.total = p.av_off + sizeof(double2) * 64;
   return p;
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused form: one workgroup per pair p = k * T + t.
-__global__ __launch_bounds__(kPairThreads) void k_mvdr_fused(
-    PairArgs a, DevDesc d, const float2* __restrict__ Yw, const int* __restrict__ starts,
-    const double2* __restrict__ abar, float2* __restrict__ out, float2* __restrict__ wout,
-    int* __restrict__ info) {
+// Fused form: one workgroup of THREADS per pair p = k * T + t.
+template <int THREADS, int EPT>
+__global__ __launch_bounds__(THREADS) void k_mvdr_fused(PairArgs a, WindowGeom g, DevDesc d,
+                                                        const float2* __restrict__ Yw,
+                                                        float2* __restrict__ out,
+                                                        float2* __restrict__ wout,
+                                                        int* __restrict__ starts_out,
+                                                        int* __restrict__ info) {
   extern __shared__ __align__(16) unsigned char smem[];
   const PairLds lay = pair_lds_layout<double>(a.wmax);
   C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r_off);
   float2* ys = reinterpret_cast<float2*>(smem + lay.r_off);
   double* diag = reinterpret_cast<double*>(smem + lay.diag_off);
   C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv_off);
+  double2* av = reinterpret_cast<double2*>(smem + lay.av_off);
 
   const int p = blockIdx.x;
   const int k = p / a.T, t = p - k * a.T;
   const int W = d.win[t], woff = d.woff[t];
-  const int s = starts[t * a.K + k];
   const int64_t pair = (int64_t)t * a.K + k;
+  double u;
+  int s;
+  window_of(g, t, k, &u, &s);
+  if (threadIdx.x < W) av[threadIdx.x] = window_steering(g, u, s, threadIdx.x);
+  if (starts_out && threadIdx.x == 0) starts_out[pair] = s;
 
-  pair_covariance<double, true>(Yw, a, k, W, woff, s, ys, R, lay.RS);
-  const int fail = chol_lds<double>(R, lay.RS, diag, W);
-  if (!fail) solve_lds<double>(R, lay.RS, diag, W, abar + pair * a.wmax, wv);
+  pair_covariance<double, true, THREADS, EPT>(Yw, a, k, W, woff, s, ys, R, lay.RS);
+  const int fail = chol_lds<double, THREADS>(R, lay.RS, diag, W);
+  if (!fail) solve_lds<double>(R, lay.RS, diag, W, av, wv);
   __syncthreads();
-  for (int l = threadIdx.x; l < a.Lt; l += kPairThreads) {
+  for (int l = threadIdx.x; l < a.Lt; l += THREADS) {
     double zx = 0.0, zy = 0.0;
     if (!fail) {
       for (int i = 0; i < W; ++i) {
@@ -312,7 +293,7 @@ __global__ __launch_bounds__(kPairThreads) void k_mvdr_fused(
     out[pair * a.Lt + l] = make_float2((float)zx, (float)zy);
   }
   if (wout) {
-    for (int i = threadIdx.x; i < a.wmax; i += kPairThreads) {
+    for (int i = threadIdx.x; i < a.wmax; i += THREADS) {
       float2 v = make_float2(0.f, 0.f);
       if (!fail && i < W) v = make_float2((float)wv[i].x, (float)wv[i].y);
       wout[pair * a.wmax + i] = v;
@@ -321,21 +302,43 @@ __global__ __launch_bounds__(kPairThreads) void k_mvdr_fused(
   if (info && threadIdx.x == 0) info[pair] = fail;
 }
 
-hipError_t launch_mvdr_fused(const PairArgs& a, const DevDesc& d, const float2* Yw,
-                             const int* starts, const double2* abar, float2* out, float2* wout,
-                             int* info, hipStream_t s) {
+template <int THREADS, int EPT>
+static hipError_t fused_launch(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                               const float2* Yw, float2* out, float2* wout, int* starts,
+                               int* info, hipStream_t s) {
   const PairLds lay = pair_lds_layout<double>(a.wmax);
-  hipLaunchKernelGGL(k_mvdr_fused, dim3(a.T * a.K), dim3(kPairThreads), lay.total, s, a, d, Yw,
-                     starts, abar, out, wout, info);
+  hipLaunchKernelGGL((k_mvdr_fused<THREADS, EPT>), dim3(a.T * a.K), dim3(THREADS), lay.total, s,
+                     a, g, d, Yw, out, wout, starts, info);
   return hipGetLastError();
+}
+
+bool mvdr_wave_supported(int wmax) { return wmax <= kWaveWMax; }
+
+hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                             int threads, hipStream_t s) {
+  const int nE = a.wmax * (a.wmax + 1) / 2;
+  if (threads == 64 && a.wmax <= kWaveWMax) {
+    // one wave64 per pair; entries per lane = ceil(nE / 64)
+    const int ept = (nE + 63) / 64;
+    if (ept <= 1) return fused_launch<64, 1>(a, g, d, Yw, out, wout, starts, info, s);
+    if (ept <= 2) return fused_launch<64, 2>(a, g, d, Yw, out, wout, starts, info, s);
+    if (ept <= 3) return fused_launch<64, 3>(a, g, d, Yw, out, wout, starts, info, s);
+    if (ept <= 5) return fused_launch<64, 5>(a, g, d, Yw, out, wout, starts, info, s);
+    if (ept <= 9) return fused_launch<64, 9>(a, g, d, Yw, out, wout, starts, info, s);
+    return fused_launch<64, 13>(a, g, d, Yw, out, wout, starts, info, s);
+  }
+  return fused_launch<256, 9>(a, g, d, Yw, out, wout, starts, info, s);
 }
 
 // ------------------------------------------------------------------------------------------
 // Plain form, FP32 throughout, three launches.
-__global__ __launch_bounds__(kPairThreads) void k_plain_cov(PairArgs a, DevDesc d,
-                                                            const float2* __restrict__ Y,
-                                                            const int* __restrict__ starts,
-                                                            float2* __restrict__ R32) {
+constexpr int kPlainThreads = 256;
+
+__global__ __launch_bounds__(kPlainThreads) void k_plain_cov(PairArgs a, DevDesc d,
+                                                             const float2* __restrict__ Y,
+                                                             const int* __restrict__ starts,
+                                                             float2* __restrict__ R32) {
   extern __shared__ __align__(16) unsigned char smem[];
   const PairLds lay = pair_lds_layout<float>(a.wmax);
   C2<float>* R = reinterpret_cast<C2<float>*>(smem + lay.r_off);
@@ -345,19 +348,19 @@ __global__ __launch_bounds__(kPairThreads) void k_plain_cov(PairArgs a, DevDesc 
   const int W = d.win[t];
   const int s = starts[t * a.K + k];
   const int64_t pair = (int64_t)t * a.K + k;
-  pair_covariance<float, false>(Y, a, k, W, 0, s, ys, R, lay.RS);
+  pair_covariance<float, false, kPlainThreads, 9>(Y, a, k, W, 0, s, ys, R, lay.RS);
   float2* dst = R32 + pair * a.wmax * a.wmax;
-  for (int e = threadIdx.x; e < W * W; e += kPairThreads) {
+  for (int e = threadIdx.x; e < W * W; e += kPlainThreads) {
     const int i = e / W, j = e - i * W;
     if (j <= i) dst[i * a.wmax + j] = make_float2(R[i * lay.RS + j].x, R[i * lay.RS + j].y);
   }
 }
 
-__global__ __launch_bounds__(kPairThreads) void k_plain_solve(PairArgs a, DevDesc d,
-                                                              const float2* __restrict__ R32,
-                                                              const double2* __restrict__ abar,
-                                                              float2* __restrict__ w32,
-                                                              int* __restrict__ info) {
+__global__ __launch_bounds__(kPlainThreads) void k_plain_solve(PairArgs a, DevDesc d,
+                                                               const float2* __restrict__ R32,
+                                                               const double2* __restrict__ abar,
+                                                               float2* __restrict__ w32,
+                                                               int* __restrict__ info) {
   extern __shared__ __align__(16) unsigned char smem[];
   const PairLds lay = pair_lds_layout<float>(a.wmax);
   C2<float>* R = reinterpret_cast<C2<float>*>(smem + lay.r_off);
@@ -368,15 +371,15 @@ __global__ __launch_bounds__(kPairThreads) void k_plain_solve(PairArgs a, DevDes
   const int W = d.win[t];
   const int64_t pair = (int64_t)t * a.K + k;
   const float2* src = R32 + pair * a.wmax * a.wmax;
-  for (int e = threadIdx.x; e < W * W; e += kPairThreads) {
+  for (int e = threadIdx.x; e < W * W; e += kPlainThreads) {
     const int i = e / W, j = e - i * W;
     if (j <= i) R[i * lay.RS + j] = c2<float>(src[i * a.wmax + j].x, src[i * a.wmax + j].y);
   }
   __syncthreads();
-  const int fail = chol_lds<float>(R, lay.RS, diag, W);
+  const int fail = chol_lds<float, kPlainThreads>(R, lay.RS, diag, W);
   if (!fail) solve_lds<float>(R, lay.RS, diag, W, abar + pair * a.wmax, wv);
   __syncthreads();
-  for (int i = threadIdx.x; i < a.wmax; i += kPairThreads) {
+  for (int i = threadIdx.x; i < a.wmax; i += kPlainThreads) {
     float2 v = make_float2(0.f, 0.f);
     if (!fail && i < W) v = make_float2(wv[i].x, wv[i].y);
     w32[pair * a.wmax + i] = v;
@@ -384,12 +387,12 @@ __global__ __launch_bounds__(kPairThreads) void k_plain_solve(PairArgs a, DevDes
   if (info && threadIdx.x == 0) info[pair] = fail;
 }
 
-__global__ __launch_bounds__(kPairThreads) void k_plain_apply(PairArgs a, DevDesc d,
-                                                              const float2* __restrict__ Y,
-                                                              const int* __restrict__ starts,
-                                                              const float2* __restrict__ w32,
-                                                              float2* __restrict__ out,
-                                                              float2* __restrict__ wout) {
+__global__ __launch_bounds__(kPlainThreads) void k_plain_apply(PairArgs a, DevDesc d,
+                                                               const float2* __restrict__ Y,
+                                                               const int* __restrict__ starts,
+                                                               const float2* __restrict__ w32,
+                                                               float2* __restrict__ out,
+                                                               float2* __restrict__ wout) {
   __shared__ float2 wv[64];
   const int p = blockIdx.x;
   const int k = p / a.T, t = p - k * a.T;
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(kPairThreads) void k_plain_apply(PairArgs a, DevDes
     if (wout) wout[pair * a.wmax + threadIdx.x] = w32[pair * a.wmax + threadIdx.x];
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < a.Lt; l += kPairThreads) {
+  for (int l = threadIdx.x; l < a.Lt; l += kPlainThreads) {
     float zx = 0.f, zy = 0.f;
     for (int i = 0; i < W; ++i) {
       const float2 y = load_y<false>(Y, a, k, 0, s, i, a.L + l);
@@ -417,7 +420,7 @@ hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* 
                              const int* starts, const double2* abar, float2* R32, float2* w32,
                              float2* out, float2* wout, int* info, hipStream_t s) {
   const PairLds lay = pair_lds_layout<float>(a.wmax);
-  const dim3 grid(a.T * a.K), blk(kPairThreads);
+  const dim3 grid(a.T * a.K), blk(kPlainThreads);
   hipLaunchKernelGGL(k_plain_cov, grid, blk, lay.total, s, a, d, Y, starts, R32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -428,11 +431,12 @@ hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* 
   return hipGetLastError();
 }
 
-}  // namespace wbm
-
-namespace wbm {
 hipError_t set_pair_attributes() {
-  return hipFuncSetAttribute((const void*)k_mvdr_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             96 * 1024);
+  hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_fused<256, 9>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_mvdr_fused<64, 13>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
 }
+
 }  // namespace wbm

@@ -30,6 +30,53 @@ __device__ __forceinline__ double2 dcmulc(double2 a, double2 b) {
 __device__ __forceinline__ double2 dscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
 // ---------------------------------------------------------------------------------------------
+// Window placement (Eq. 18): u = M (d/lambda) sin(az) f_k/f_c, s = floor(u - (W-1)/2 + 1/2),
+// evaluated in IEEE double with no contraction so that every kernel (and a host evaluation
+// of the same expression) takes the same integer decision.
+struct WindowGeom {
+  int T, K, M, N, half_bin;
+  double beta, dl;
+  const double* sin_az;   // [T]
+  const int* win;         // [T]
+};
+
+__device__ __forceinline__ void window_geom(double M, double dl, double sin_az, double beta,
+                                            double ksh, double K, int W, double* u_out,
+                                            int* s_out) {
+#pragma clang fp contract(off)
+  const double ratio = 1.0 + (beta * ksh) / K;
+  const double u = ((M * dl) * sin_az) * ratio;
+  const double c = u - 0.5 * (double)(W - 1);
+  *s_out = (int)floor(c + 0.5);
+  *u_out = u;
+}
+
+__device__ __forceinline__ void window_of(const WindowGeom& g, int t, int k, double* u, int* s) {
+  const int ks = (k < g.K / 2) ? k : k - g.K;
+  const double ksh = (double)ks + (g.half_bin ? 0.5 : 0.0);
+  window_geom((double)g.M, g.dl, g.sin_az[t], g.beta, ksh, (double)g.K, g.win[t], u, s);
+}
+
+__device__ __forceinline__ int window_start(const WindowGeom& g, int t, int k) {
+  double u;
+  int s;
+  window_of(g, t, k, &u, &s);
+  return s;
+}
+
+// Windowed steering a~_i = M^-1/2 sum_{e<N} e^{j psi e}, psi = 2 pi (u - (s + i)) / M, by the
+// Dirichlet closed form with sinpi / sincospi in FP64.
+__device__ __forceinline__ double2 window_steering(const WindowGeom& g, double u, int s, int i) {
+  const double xx = (u - (double)(s + i)) / (double)g.M;
+  const double num = sinpi((double)g.N * xx), den = sinpi(xx);
+  double mag = (den == 0.0) ? (double)g.N : num / den;
+  mag /= sqrt((double)g.M);
+  double sp, cp;
+  sincospi((double)(g.N - 1) * xx, &sp, &cp);
+  return make_double2(mag * cp, mag * sp);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Small DFTs in registers, forward sign: X[k] = sum_r v[r] exp(-2 pi i r k / R).
 
 __device__ __forceinline__ void dft2(float2* v) {

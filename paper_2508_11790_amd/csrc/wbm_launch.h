@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wbm_dev.h"
+
 namespace wbm {
 
 // Per-call description of the targets, uploaded to the device before the kernels run.
@@ -14,34 +16,35 @@ struct DevDesc {
   const int* rowtab;      // [sumW] window row r -> (t << 8) | i
 };
 
+// FFT tile sizes the kernels are built for (log2 complex per workgroup tile).
+bool fft_logtile_supported(int logtile);
+// log2 of the snapshots per beamspace tile for M and a tile size.
+int beamspace_tile_log(int M, int logtile);
+
 // Time-DFT channelizer: x [N][B*K] -> X [K][B][N].
 hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, const float2* twK,
-                             const float2* hb, hipStream_t s);
-// log2 of the snapshots per beamspace tile for M, B.
-int beamspace_tile_log(int M, int B);
-// Zero-padded spatial DFT: X [K][B][N] -> Y [K][M][B] (if Y) and windows Yw (if Yw).
+                             const float2* hb, int logtile, hipStream_t s);
+// Zero-padded spatial DFT: X [K][B][N] -> Y [K][M][B] (if Y) and windows Yw (if Yw; the
+// kernel places the windows of subband k itself from g).
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
-                            const float2* twM, const int* rowtab, int sumW, const int* starts,
-                            hipStream_t s);
+                            const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
+                            int logtile, hipStream_t s);
 
-struct SteerArgs {
-  int T, K, M, N, wmax, half_bin;
-  double beta, dl;
-};
 // Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
-hipError_t launch_steer(const SteerArgs& a, const DevDesc& d, int* starts, double2* abar,
-                        hipStream_t s);
+hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar, hipStream_t s);
 
 struct PairArgs {
   int T, K, M, L, Lt, B, wmax;
   int logTB, nbt, sumW;          // windowed layout (fused form)
   double delta;
 };
-// Fused per-pair covariance (FP64 accumulation) -> Cholesky (FP64) -> solve -> apply,
-// reading the window rows written by the beamspace kernel.
-hipError_t launch_mvdr_fused(const PairArgs& a, const DevDesc& d, const float2* Yw,
-                             const int* starts, const double2* abar, float2* out, float2* wout,
-                             int* info, hipStream_t s);
+// Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
+// solve -> apply, reading the window rows written by the beamspace kernel.
+// threads = 64 (one wave per pair, windows up to 40 bins) or 256 (four waves per pair).
+hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                             int threads, hipStream_t s);
+bool mvdr_wave_supported(int wmax);
 // Plain per-stage FP32 form reading the full beamspace Y [K][M][B]: gather + covariance,
 // Cholesky + solve, apply -- three launches with R and w in HBM.
 hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* Y,
@@ -57,12 +60,8 @@ struct FullArgs {
 hipError_t launch_full_mvdr(const FullArgs& a, const DevDesc& d, const float2* X, double2* R,
                             double2* wtmp, float2* out, float2* wout, int* info, hipStream_t s);
 
-
-
-}  // namespace wbm
-
-namespace wbm {
 hipError_t set_fft_attributes();
 hipError_t set_pair_attributes();
 hipError_t set_full_attributes();
+
 }  // namespace wbm
