@@ -149,6 +149,80 @@ wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_ra
                            const int32_t* win, int32_t T, double loading, int32_t reps,
                            double* stage_ms, void* stream);
 
+/* ------------------------------------------------------------------------------------
+ * Loading / window predictor.  The paper fixes the diagonal loading and the window width;
+ * this library adds a small network that picks both per (target, subband) pair from the
+ * pair's beamspace power profile, trained on sweeps of the fixed method scored by output
+ * SINR.  The fixed method stays the fallback.
+ *   Network: 64 -> 128 -> 128 -> 2 multilayer perceptron, GELU (exact erf) after both
+ *   hidden layers.  Parameters: one device array of WBM_MLP_PARAMS FP32 values in the order
+ *   W1 [128][64], b1 [128], W2 [128][128], b2 [128], W3 [2][128], b3 [2] (row-major, out x in),
+ *   used rounded to BF16 (round to nearest even) with FP32 activations and accumulation.
+ *   Input: log10(P_j / sigma^2 + 1e-30), P_j the mean power over the L training snapshots of
+ *   beamspace bin c - 32 + j (mod M), j < 64, c = floor(u + 1/2) the target's beam bin.
+ *   Outputs: out0 = ln(delta / sigma^2), out1 = log2(W - 1); decision delta = sigma^2 *
+ *   exp(clamp(out0, ln 0.1, ln 1e4)), W = 2^clamp(rint(out1), 2, 5) + 1 in {5, 9, 17, 33}. */
+#define WBM_MLP_PARAMS 25090
+#define WBM_PROFILE_BINS 64
+
+/* Training power profiles of every pair: feat device [T][K][64] float (the network input).
+ * noise_power = sigma^2 > 0. */
+wbm_status wbm_profiles(wbm_plan* plan, const wbm_c32* x, const double* az_rad, int32_t T,
+                        double noise_power, float* feat, void* stream);
+
+/* Windowed MVDR with a window width and a loading per pair.  Target t's window of win[t]
+ * bins (host, as in wbm_beamform) is gathered once; pair (t, k) uses its centred sub-window
+ * of pair_win[t][k] bins (device int32; same parity as win[t], else the full window) and the
+ * loading pair_loading[t][k] (device float, >= 0).  Outputs as in wbm_beamform. */
+wbm_status wbm_beamform_pairs(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
+                              const int32_t* win, int32_t T, const int32_t* pair_win,
+                              const float* pair_loading, wbm_c32* out, wbm_c32* weights,
+                              int32_t* starts, int32_t* info, void* stream);
+
+/* Learned form: profiles -> network -> per-pair (delta, W) -> windowed MVDR, one call.
+ * Needs w_max >= 33.  params device [WBM_MLP_PARAMS].  A pair whose network output is not
+ * finite uses fallback_win / fallback_loading (odd fallback_win <= 33).  pair_win,
+ * pair_loading (device [T][K], may be NULL) receive the decisions; fallback (device [T][K]
+ * int32, may be NULL) is 1 where the fallback was used. */
+wbm_status wbm_beamform_learned(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
+                                int32_t T, const float* params, double noise_power,
+                                int32_t fallback_win, double fallback_loading, wbm_c32* out,
+                                wbm_c32* weights, int32_t* pair_win, float* pair_loading,
+                                int32_t* fallback, int32_t* starts, int32_t* info,
+                                void* stream);
+
+/* Output SINR of weights (device [T][K][w_max], window-bin order starting at starts[t][k],
+ * width pair_win[t][k] or win[t] if pair_win is NULL) against the exact covariance of white
+ * noise sigma^2 plus J white jammers (host jam_az [J] radians, jam_inr [J] linear per
+ * element): |w^H a~|^2 / (w^H (S D R_in D^H S^T) w).  sinr device [T][K] float. */
+wbm_status wbm_sinr(wbm_plan* plan, const double* az_rad, const int32_t* win, int32_t T,
+                    const wbm_c32* weights, const int32_t* pair_win, const int32_t* starts,
+                    const double* jam_az, const double* jam_inr, int32_t J, double noise_power,
+                    float* sinr, void* stream);
+
+typedef struct wbm_mlp wbm_mlp;
+/* Network workspace for batches of up to max_batch samples. */
+wbm_status wbm_mlp_create(int32_t max_batch, wbm_mlp** out);
+wbm_status wbm_mlp_destroy(wbm_mlp* mlp);
+/* out device [n][2] = network(in device [n][64]). */
+wbm_status wbm_mlp_forward(wbm_mlp* mlp, const float* params, const float* in, int32_t n,
+                           float* out, void* stream);
+/* grad device [WBM_MLP_PARAMS] and loss device [1] of the mean squared error over the n
+ * samples and both outputs against target device [n][2]; deterministic reduction order. */
+wbm_status wbm_mlp_grad(wbm_mlp* mlp, const float* params, const float* in, const float* target,
+                        int32_t n, float* grad, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on params with moment
+ * arrays m, v (device [WBM_MLP_PARAMS]). */
+wbm_status wbm_mlp_adam(wbm_mlp* mlp, float* params, float* m, float* v, const float* grad,
+                        int32_t step, double lr, void* stream);
+/* Labels of a sweep: sinr device [nd * nw][npairs] (row c = id * nw + iw for loading
+ * deltas[id] and width widths[iw], host arrays) -> label device [npairs][2] =
+ * (ln(delta / sigma^2), log2(W - 1)) of the best SINR; ties go to the smaller width, then to
+ * the larger loading.  nd, nw <= 64. */
+wbm_status wbm_sweep_labels(wbm_mlp* mlp, const float* sinr, int32_t npairs, const double* deltas,
+                            int32_t nd, const int32_t* widths, int32_t nw, double noise_power,
+                            float* label, void* stream);
+
 const char* wbm_status_str(wbm_status s);
 const char* wbm_last_error(void);
 /* Library version string. */

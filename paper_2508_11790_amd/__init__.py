@@ -17,7 +17,10 @@ import numpy as np
 from . import _lib
 from ._lib import FORM_FUSED, FORM_GRAPH, FORM_PLAIN, WbmError  # noqa: F401
 
-__all__ = ["Plan", "WbmError", "FORM_PLAIN", "FORM_FUSED", "FORM_GRAPH", "version"]
+__all__ = ["Plan", "Mlp", "WbmError", "FORM_PLAIN", "FORM_FUSED", "FORM_GRAPH", "version",
+           "MLP_PARAMS"]
+
+MLP_PARAMS = _lib.MLP_PARAMS
 
 _FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH}
 
@@ -179,6 +182,77 @@ class Plan:
                                                _stream(stream)))
         return dict(zip(self.STAGES, ms.tolist()))
 
+    # ------------------------------------------------------------------ loading / window predictor
+    def profiles(self, x, az_rad, noise_power: float = 1.0, stream=None):
+        """Network input of every pair: [T, K, 64] float32 log10 training power profile."""
+        torch = _torch()
+        self._x(x)
+        az, _, T = self._targets(az_rad, None)
+        feat = torch.empty((T, self.K, 64), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().wbm_profiles(self._h, _ptr(x), az.ctypes.data, T, float(noise_power),
+                                            _ptr(feat), _stream(stream)))
+        return feat
+
+    def beamform_pairs(self, x, az_rad, win, pair_win, pair_loading, out=None, weights=None,
+                       starts=None, info=None, stream=None):
+        """Windowed MVDR with a window width (int32 [T, K]) and loading (float32 [T, K]) per
+        pair; win [T] is the window gathered per target (sub-windows are centred in it)."""
+        torch = _torch()
+        self._x(x)
+        az, w, T = self._targets(az_rad, win)
+        dev = self.device
+        _check_tensor(pair_win, "pair_win", (T, self.K), torch.int32, dev)
+        _check_tensor(pair_loading, "pair_loading", (T, self.K), torch.float32, dev)
+        out = torch.empty((T, self.K, self.Lt), dtype=torch.complex64, device=dev) if out is None else out
+        weights = (torch.empty((T, self.K, self.w_max), dtype=torch.complex64, device=dev)
+                   if weights is None else weights)
+        starts = torch.empty((T, self.K), dtype=torch.int32, device=dev) if starts is None else starts
+        info = torch.empty((T, self.K), dtype=torch.int32, device=dev) if info is None else info
+        _lib.check(_lib.load().wbm_beamform_pairs(
+            self._h, _ptr(x), az.ctypes.data, None if w is None else w.ctypes.data, T,
+            _ptr(pair_win), _ptr(pair_loading), _ptr(out), _ptr(weights), _ptr(starts), _ptr(info),
+            _stream(stream)))
+        return dict(out=out, weights=weights, starts=starts, info=info)
+
+    def beamform_learned(self, x, az_rad, params, noise_power: float = 1.0, fallback_win: int = 9,
+                         fallback_loading: float = 10.0, stream=None):
+        """Learned form: per-pair (loading, window) from the network, then windowed MVDR."""
+        torch = _torch()
+        self._x(x)
+        az, _, T = self._targets(az_rad, None)
+        dev = self.device
+        _check_tensor(params, "params", (MLP_PARAMS,), torch.float32, dev)
+        out = torch.empty((T, self.K, self.Lt), dtype=torch.complex64, device=dev)
+        weights = torch.empty((T, self.K, self.w_max), dtype=torch.complex64, device=dev)
+        pair_win = torch.empty((T, self.K), dtype=torch.int32, device=dev)
+        pair_loading = torch.empty((T, self.K), dtype=torch.float32, device=dev)
+        fallback = torch.empty((T, self.K), dtype=torch.int32, device=dev)
+        starts = torch.empty((T, self.K), dtype=torch.int32, device=dev)
+        info = torch.empty((T, self.K), dtype=torch.int32, device=dev)
+        _lib.check(_lib.load().wbm_beamform_learned(
+            self._h, _ptr(x), az.ctypes.data, T, _ptr(params), float(noise_power), int(fallback_win),
+            float(fallback_loading), _ptr(out), _ptr(weights), _ptr(pair_win), _ptr(pair_loading),
+            _ptr(fallback), _ptr(starts), _ptr(info), _stream(stream)))
+        return dict(out=out, weights=weights, pair_win=pair_win, pair_loading=pair_loading,
+                    fallback=fallback, starts=starts, info=info)
+
+    def sinr(self, az_rad, win, weights, starts, jam_az, jam_inr, noise_power: float = 1.0,
+             pair_win=None, stream=None):
+        """Output SINR [T, K] of weights against the exact noise + jammer covariance."""
+        torch = _torch()
+        az, w, T = self._targets(az_rad, win)
+        ja = np.ascontiguousarray(np.asarray(jam_az, dtype=np.float64).ravel())
+        ji = np.ascontiguousarray(np.asarray(jam_inr, dtype=np.float64).ravel())
+        if ja.size != ji.size:
+            raise ValueError("jam_az and jam_inr must have the same length")
+        out = torch.empty((T, self.K), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().wbm_sinr(
+            self._h, az.ctypes.data, None if w is None else w.ctypes.data, T, _ptr(weights),
+            _ptr(pair_win), _ptr(starts), ja.ctypes.data if ja.size else None,
+            ji.ctypes.data if ji.size else None, int(ja.size), float(noise_power), _ptr(out),
+            _stream(stream)))
+        return out
+
     def full_mvdr(self, x, az_rad, loading: float, want_weights: bool = True, stream=None):
         """Full-dimensional element-space MVDR per subband: out [T, K, Lt], weights [T, K, N],
         info [K]."""
@@ -193,3 +267,65 @@ class Plan:
                                              _ptr(out), _ptr(weights), _ptr(info),
                                              _stream(stream)))
         return dict(out=out, weights=weights, info=info)
+
+
+class Mlp:
+    """Workspace of the loading / window predictor network (64 -> 128 -> 128 -> 2, GELU)."""
+
+    def __init__(self, max_batch: int):
+        lib = _lib.load()
+        h = C.c_void_p()
+        _lib.check(lib.wbm_mlp_create(int(max_batch), C.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+        self.device = _torch().device("cuda", _torch().cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().wbm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, params, inp, stream=None):
+        torch = _torch()
+        n = int(inp.shape[0])
+        _check_tensor(params, "params", (MLP_PARAMS,), torch.float32, self.device)
+        _check_tensor(inp, "in", (n, 64), torch.float32, self.device)
+        out = torch.empty((n, 2), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().wbm_mlp_forward(self._h, _ptr(params), _ptr(inp), n, _ptr(out),
+                                               _stream(stream)))
+        return out
+
+    def grad(self, params, inp, target, grad=None, loss=None, stream=None):
+        torch = _torch()
+        n = int(inp.shape[0])
+        _check_tensor(params, "params", (MLP_PARAMS,), torch.float32, self.device)
+        _check_tensor(inp, "in", (n, 64), torch.float32, self.device)
+        _check_tensor(target, "target", (n, 2), torch.float32, self.device)
+        grad = torch.empty((MLP_PARAMS,), dtype=torch.float32, device=self.device) if grad is None else grad
+        loss = torch.empty((1,), dtype=torch.float32, device=self.device) if loss is None else loss
+        _lib.check(_lib.load().wbm_mlp_grad(self._h, _ptr(params), _ptr(inp), _ptr(target), n,
+                                            _ptr(grad), _ptr(loss), _stream(stream)))
+        return grad, loss
+
+    def adam(self, params, m, v, grad, step: int, lr: float, stream=None):
+        _lib.check(_lib.load().wbm_mlp_adam(self._h, _ptr(params), _ptr(m), _ptr(v), _ptr(grad),
+                                            int(step), float(lr), _stream(stream)))
+
+    def sweep_labels(self, sinr, deltas, widths, noise_power: float = 1.0, stream=None):
+        """sinr [len(deltas) * len(widths), npairs] -> label [npairs, 2]."""
+        torch = _torch()
+        d = np.ascontiguousarray(np.asarray(deltas, dtype=np.float64))
+        w = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+        npairs = int(sinr.shape[1])
+        _check_tensor(sinr, "sinr", (d.size * w.size, npairs), torch.float32, self.device)
+        label = torch.empty((npairs, 2), dtype=torch.float32, device=self.device)
+        _lib.check(_lib.load().wbm_sweep_labels(self._h, _ptr(sinr), npairs, d.ctypes.data, d.size,
+                                                w.ctypes.data, w.size, float(noise_power),
+                                                _ptr(label), _stream(stream)))
+        return label

@@ -32,7 +32,11 @@ class WbmError(RuntimeError):
 
 EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes", "wbm_beamform",
            "wbm_channelize", "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times",
-           "wbm_status_str", "wbm_last_error", "wbm_version")
+           "wbm_profiles", "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr",
+           "wbm_mlp_create", "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
+           "wbm_sweep_labels", "wbm_status_str", "wbm_last_error", "wbm_version")
+MLP_PARAMS = 25090
+PROFILE_BINS = 64
 
 _lib = None
 
@@ -56,13 +60,26 @@ def load() -> C.CDLL:
     lib.wbm_steer.argtypes = [P, P, P, I32, P, P, P]
     lib.wbm_full_mvdr.argtypes = [P, P, P, I32, D, P, P, P, P]
     lib.wbm_stage_times.argtypes = [P, P, P, P, I32, D, I32, P, P]
+    lib.wbm_profiles.argtypes = [P, P, P, I32, D, P, P]
+    lib.wbm_beamform_pairs.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P]
+    lib.wbm_beamform_learned.argtypes = [P, P, P, I32, P, D, I32, D, P, P, P, P, P, P, P, P]
+    lib.wbm_sinr.argtypes = [P, P, P, I32, P, P, P, P, P, I32, D, P, P]
+    lib.wbm_mlp_create.argtypes = [I32, C.POINTER(P)]
+    lib.wbm_mlp_destroy.argtypes = [P]
+    lib.wbm_mlp_forward.argtypes = [P, P, P, I32, P, P]
+    lib.wbm_mlp_grad.argtypes = [P, P, P, P, I32, P, P, P]
+    lib.wbm_mlp_adam.argtypes = [P, P, P, P, P, I32, D, P]
+    lib.wbm_sweep_labels.argtypes = [P, P, I32, P, I32, P, I32, D, P, P]
     lib.wbm_status_str.argtypes = [I32]
     lib.wbm_status_str.restype = C.c_char_p
     lib.wbm_last_error.argtypes = []
     lib.wbm_last_error.restype = C.c_char_p
     lib.wbm_version.restype = C.c_char_p
     for name in ("wbm_plan_create", "wbm_plan_destroy", "wbm_beamform", "wbm_channelize",
-                 "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times"):
+                 "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times", "wbm_profiles",
+                 "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr", "wbm_mlp_create",
+                 "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
+                 "wbm_sweep_labels"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

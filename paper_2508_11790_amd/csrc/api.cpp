@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "wbm_launch.h"
+#include "wbm_learned.h"
 #include "wbmvdr.h"
 
 namespace {
@@ -101,6 +102,29 @@ struct wbm_plan {
   float2* prof_out = nullptr;
   float2* prof_w = nullptr;
   int* prof_info = nullptr;
+  // loading / window predictor buffers (first use)
+  float* pprof = nullptr;    // [K][G][T_max][64] power-profile partials
+  float* feat = nullptr;     // [T_max][K][64]
+  float* nnout = nullptr;    // [T_max][K][2]
+  int* pw = nullptr;         // [T_max][K]
+  float* pdelta = nullptr;   // [T_max][K]
+  int prof_G = 0;
+  // jammer list for SINR scoring: device + pinned staging
+  double* jam_dev = nullptr;
+  double* jam_host = nullptr;
+  hipEvent_t jam_evt = nullptr;
+  bool jam_evt_recorded = false;
+};
+
+struct wbm_mlp {
+  int max_batch = 0;
+  float* part = nullptr;       // [workgroups][params]
+  float* loss_part = nullptr;  // [workgroups]
+  unsigned char* tab_dev = nullptr;   // label sweep tables: 64 floats + 64 ints
+  unsigned char* tab_host = nullptr;
+  hipEvent_t tab_evt = nullptr;
+  bool tab_evt_recorded = false;
+  int device = 0;
 };
 
 namespace {
@@ -449,9 +473,12 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->desc_evt) (void)hipEventDestroy(p->desc_evt);
   if (p->desc_host) (void)hipHostFree(p->desc_host);
+  if (p->jam_evt) (void)hipEventDestroy(p->jam_evt);
+  if (p->jam_host) (void)hipHostFree(p->jam_host);
   void* bufs[] = {p->twK, p->twM, p->hb, p->desc_dev, p->X, p->Yw, p->Y, p->R32,
                   p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
-                  p->prof_out, p->prof_w, p->prof_info};
+                  p->prof_out, p->prof_w, p->prof_info, p->pprof, p->feat, p->nnout,
+                  p->pw, p->pdelta, p->jam_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -747,6 +774,303 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
                                   inf, st),
             "full MVDR launch");
   }
+  return WBM_OK;
+}
+
+// ============================================================================================
+// Loading / window predictor
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxJam = 64;
+constexpr double kLearnedWin = 33.0;
+
+wbm_status ensure_learned(wbm_plan* p) {
+  if (p->pprof) return WBM_OK;
+  const wbm_config& c = p->cfg;
+  const size_t pairs = (size_t)c.max_targets * c.k_sub;
+  const int nbt_max = wbm::beamspace_tiles(c.m_fft, p->B, 11);
+  int G = (1024 + c.k_sub - 1) / c.k_sub;
+  if (G > 16) G = 16;
+  if (G < 1) G = 1;
+  p->prof_G = G;
+  (void)nbt_max;
+  wbm_status s;
+  if ((s = dev_alloc(p, &p->pprof, (size_t)c.k_sub * 16 * c.max_targets * 64, "profile partials")))
+    return s;
+  if ((s = dev_alloc(p, &p->feat, pairs * 64, "features"))) return s;
+  if ((s = dev_alloc(p, &p->nnout, pairs * 2, "network outputs"))) return s;
+  if ((s = dev_alloc(p, &p->pw, pairs, "pair windows"))) return s;
+  return dev_alloc(p, &p->pdelta, pairs, "pair loadings");
+}
+
+// Channelize + beamspace (windows if Yw) + profile partials -> features (into feat).
+hipError_t enqueue_profiles(wbm_plan* p, const float2* x, int T, int sumW, bool windows,
+                            float noise, float* feat, hipStream_t st) {
+  const wbm_config& c = p->cfg;
+  hipError_t e = enqueue_channelize(p, x, st);
+  if (e != hipSuccess) return e;
+  const int nbt = wbm::beamspace_tiles(c.m_fft, p->B, p->beam_logtile);
+  const int G = p->prof_G < nbt ? p->prof_G : nbt;
+  e = wbm::launch_beamspace(p->X, nullptr, windows ? p->Yw : nullptr, c.n_elem, c.m_fft, p->B,
+                            c.k_sub, p->twM, p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st,
+                            p->pprof, c.l_train, G);
+  if (e != hipSuccess) return e;
+  return wbm::launch_features(p->pprof, T, c.k_sub, G, c.l_train, noise, feat, st);
+}
+
+wbm_status check_mlp(const wbm_mlp* m) {
+  if (!m) return fail(WBM_ERR_ARG, "mlp is NULL");
+  hipError_t e = hipSetDevice(m->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return WBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wbm_status wbm_profiles(wbm_plan* p, const wbm_c32* x, const double* az_rad, int32_t T,
+                        double noise_power, float* feat, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!x || !feat) return fail(WBM_ERR_ARG, "x / feat is NULL");
+  if (!(noise_power > 0.0 && std::isfinite(noise_power)))
+    return fail(WBM_ERR_ARG, "noise_power must be positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, nullptr, T, st, &sumW))) return s;
+  if ((s = ensure_learned(p))) return s;
+  WBM_HIP(enqueue_profiles(p, reinterpret_cast<const float2*>(x), T, sumW, false,
+                           (float)noise_power, feat, st),
+          "profile launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beamform_pairs(wbm_plan* p, const wbm_c32* x, const double* az_rad,
+                              const int32_t* win, int32_t T, const int32_t* pair_win,
+                              const float* pair_loading, wbm_c32* out, wbm_c32* weights,
+                              int32_t* starts, int32_t* info, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x) return fail(WBM_ERR_ARG, "x is NULL");
+  if (!pair_win || !pair_loading) return fail(WBM_ERR_ARG, "pair_win / pair_loading is NULL");
+  if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  if (!p->tuned) {
+    if ((s = ensure_prof(p))) return s;
+    WBM_HIP(autotune(p, xx, T, sumW, 0.0, st), "autotune");
+  }
+  WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
+  WBM_HIP(enqueue_beamspace_windows(p, T, sumW, st), "beamspace launch");
+  wbm::PairArgs a = pair_args(p, T, sumW, 0.0);
+  a.pw = pair_win;
+  a.pdelta = pair_loading;
+  WBM_HIP(wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, reinterpret_cast<float2*>(out),
+                                 reinterpret_cast<float2*>(weights), starts, info, p->pair_threads,
+                                 st),
+          "pair MVDR launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beamform_learned(wbm_plan* p, const wbm_c32* x, const double* az_rad,
+                                int32_t T, const float* params, double noise_power,
+                                int32_t fallback_win, double fallback_loading, wbm_c32* out,
+                                wbm_c32* weights, int32_t* pair_win, float* pair_loading,
+                                int32_t* fallback, int32_t* starts, int32_t* info,
+                                void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x || !params) return fail(WBM_ERR_ARG, "x / params is NULL");
+  if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
+  if (c.w_max < (int)kLearnedWin) return fail(WBM_ERR_SHAPE, "the learned form needs w_max >= 33");
+  if (fallback_win < 1 || fallback_win > (int)kLearnedWin || (fallback_win & 1) == 0)
+    return fail(WBM_ERR_ARG, "fallback_win must be odd and <= 33");
+  if (!(fallback_loading >= 0.0 && std::isfinite(fallback_loading)))
+    return fail(WBM_ERR_ARG, "fallback_loading must be finite and >= 0");
+  if (!(noise_power > 0.0 && std::isfinite(noise_power)))
+    return fail(WBM_ERR_ARG, "noise_power must be positive");
+  if (T < 1 || T > c.max_targets) return fail(WBM_ERR_SHAPE, "T outside [1, max_targets]");
+  std::vector<int32_t> win(T, (int)kLearnedWin);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win.data(), T, st, &sumW))) return s;
+  if ((s = ensure_learned(p))) return s;
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  if (!p->tuned) {
+    if ((s = ensure_prof(p))) return s;
+    WBM_HIP(autotune(p, xx, T, sumW, fallback_loading, st), "autotune");
+  }
+  const int n = T * c.k_sub;
+  int* pw = pair_win ? pair_win : p->pw;
+  float* pd = pair_loading ? pair_loading : p->pdelta;
+  WBM_HIP(enqueue_profiles(p, xx, T, sumW, true, (float)noise_power, p->feat, st), "profiles");
+  WBM_HIP(wbm::launch_mlp_forward(params, p->feat, n, p->nnout, st), "network forward");
+  WBM_HIP(wbm::launch_decide(p->nnout, n, (float)noise_power, (float)fallback_loading,
+                             fallback_win, pw, pd, fallback, st),
+          "decision");
+  wbm::PairArgs a = pair_args(p, T, sumW, fallback_loading);
+  a.pw = pw;
+  a.pdelta = pd;
+  WBM_HIP(wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, reinterpret_cast<float2*>(out),
+                                 reinterpret_cast<float2*>(weights), starts, info, p->pair_threads,
+                                 st),
+          "pair MVDR launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_sinr(wbm_plan* p, const double* az_rad, const int32_t* win, int32_t T,
+                    const wbm_c32* weights, const int32_t* pair_win, const int32_t* starts,
+                    const double* jam_az, const double* jam_inr, int32_t J, double noise_power,
+                    float* sinr, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!weights || !starts || !sinr) return fail(WBM_ERR_ARG, "weights / starts / sinr is NULL");
+  if (J < 0 || J > kMaxJam) return fail(WBM_ERR_ARG, "J outside [0, 64]");
+  if (J > 0 && (!jam_az || !jam_inr)) return fail(WBM_ERR_ARG, "jam_az / jam_inr is NULL");
+  if (!(noise_power > 0.0 && std::isfinite(noise_power)))
+    return fail(WBM_ERR_ARG, "noise_power must be positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
+  if (!p->jam_dev) {
+    if ((s = dev_alloc(p, &p->jam_dev, 2 * kMaxJam, "jammer list"))) return s;
+    if (hipHostMalloc((void**)&p->jam_host, sizeof(double) * 2 * kMaxJam, hipHostMallocDefault) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return fail(WBM_ERR_NOMEM, "pinned jammer staging allocation failed");
+    }
+    WBM_HIP(hipEventCreateWithFlags(&p->jam_evt, hipEventDisableTiming), "event create");
+  }
+  if (p->jam_evt_recorded) WBM_HIP(hipEventSynchronize(p->jam_evt), "jammer staging wait");
+  for (int j = 0; j < J; ++j) {
+    if (!std::isfinite(jam_az[j]) || !(jam_inr[j] >= 0.0))
+      return fail(WBM_ERR_ARG, "jammer " + std::to_string(j) + " not finite / negative INR");
+    p->jam_host[j] = std::sin(jam_az[j]);
+    p->jam_host[kMaxJam + j] = jam_inr[j];
+  }
+  WBM_HIP(hipMemcpyAsync(p->jam_dev, p->jam_host, sizeof(double) * 2 * kMaxJam,
+                         hipMemcpyHostToDevice, st),
+          "jammer upload");
+  WBM_HIP(hipEventRecord(p->jam_evt, st), "jammer event");
+  p->jam_evt_recorded = true;
+  WBM_HIP(wbm::launch_sinr(geom(p, T), reinterpret_cast<const float2*>(weights), p->cfg.w_max,
+                           pair_win, starts, p->jam_dev, p->jam_dev + kMaxJam, J, noise_power, sinr,
+                           st),
+          "SINR launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_mlp_create(int32_t max_batch, wbm_mlp** out) {
+  if (!out) return fail(WBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > (1 << 24)) return fail(WBM_ERR_ARG, "max_batch out of range");
+  wbm_mlp* m = new wbm_mlp();
+  m->max_batch = max_batch;
+  (void)hipGetDevice(&m->device);
+  const int nwg = wbm::mlp_backward_workgroups(max_batch);
+  auto bail = [&](const char* what) {
+    (void)hipGetLastError();
+    wbm_mlp_destroy(m);
+    return fail(WBM_ERR_NOMEM, what);
+  };
+  if (hipMalloc((void**)&m->part, sizeof(float) * (size_t)nwg * wbm::mlp_param_count()) != hipSuccess)
+    return bail("gradient partials allocation failed");
+  if (hipMalloc((void**)&m->loss_part, sizeof(float) * (size_t)nwg) != hipSuccess)
+    return bail("loss partials allocation failed");
+  if (hipMalloc((void**)&m->tab_dev, 512) != hipSuccess) return bail("table allocation failed");
+  if (hipHostMalloc((void**)&m->tab_host, 512, hipHostMallocDefault) != hipSuccess)
+    return bail("pinned table allocation failed");
+  if (hipEventCreateWithFlags(&m->tab_evt, hipEventDisableTiming) != hipSuccess)
+    return bail("event creation failed");
+  *out = m;
+  return WBM_OK;
+}
+
+wbm_status wbm_mlp_destroy(wbm_mlp* m) {
+  if (!m) return WBM_OK;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  if (m->tab_evt) (void)hipEventDestroy(m->tab_evt);
+  if (m->tab_host) (void)hipHostFree(m->tab_host);
+  if (m->tab_dev) (void)hipFree(m->tab_dev);
+  if (m->part) (void)hipFree(m->part);
+  if (m->loss_part) (void)hipFree(m->loss_part);
+  delete m;
+  return WBM_OK;
+}
+
+wbm_status wbm_mlp_forward(wbm_mlp* m, const float* params, const float* in, int32_t n,
+                           float* out, void* stream) {
+  wbm_status s = check_mlp(m);
+  if (s) return s;
+  if (!params || !in || !out) return fail(WBM_ERR_ARG, "params / in / out is NULL");
+  if (n < 0) return fail(WBM_ERR_ARG, "n < 0");
+  WBM_HIP(wbm::launch_mlp_forward(params, in, n, out, static_cast<hipStream_t>(stream)), "forward");
+  return WBM_OK;
+}
+
+wbm_status wbm_mlp_grad(wbm_mlp* m, const float* params, const float* in, const float* target,
+                        int32_t n, float* grad, float* loss, void* stream) {
+  wbm_status s = check_mlp(m);
+  if (s) return s;
+  if (!params || !in || !target || !grad) return fail(WBM_ERR_ARG, "NULL argument");
+  if (n < 1 || n > m->max_batch) return fail(WBM_ERR_SHAPE, "n outside [1, max_batch]");
+  WBM_HIP(wbm::launch_mlp_backward(params, in, target, n, m->part, m->loss_part, grad, loss,
+                                   static_cast<hipStream_t>(stream)),
+          "backward");
+  return WBM_OK;
+}
+
+wbm_status wbm_mlp_adam(wbm_mlp* m, float* params, float* mom, float* var, const float* grad,
+                        int32_t step, double lr, void* stream) {
+  wbm_status s = check_mlp(m);
+  if (s) return s;
+  if (!params || !mom || !var || !grad) return fail(WBM_ERR_ARG, "NULL argument");
+  if (step < 1) return fail(WBM_ERR_ARG, "step must be >= 1");
+  if (!(lr > 0.0 && std::isfinite(lr))) return fail(WBM_ERR_ARG, "lr must be positive");
+  const double c1 = 1.0 - std::pow(0.9, step), c2 = 1.0 - std::pow(0.999, step);
+  WBM_HIP(wbm::launch_adam(params, mom, var, grad, (float)lr, 0.9f, 0.999f, 1e-8f, (float)c1,
+                           (float)c2, static_cast<hipStream_t>(stream)),
+          "adam");
+  return WBM_OK;
+}
+
+wbm_status wbm_sweep_labels(wbm_mlp* m, const float* sinr, int32_t npairs, const double* deltas,
+                            int32_t nd, const int32_t* widths, int32_t nw, double noise_power,
+                            float* label, void* stream) {
+  wbm_status s = check_mlp(m);
+  if (s) return s;
+  if (!sinr || !deltas || !widths || !label) return fail(WBM_ERR_ARG, "NULL argument");
+  if (nd < 1 || nd > 64 || nw < 1 || nw > 64) return fail(WBM_ERR_ARG, "nd, nw must be in [1, 64]");
+  if (npairs < 1) return fail(WBM_ERR_ARG, "npairs < 1");
+  if (!(noise_power > 0.0)) return fail(WBM_ERR_ARG, "noise_power must be positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (m->tab_evt_recorded) WBM_HIP(hipEventSynchronize(m->tab_evt), "table staging wait");
+  float* fd = reinterpret_cast<float*>(m->tab_host);
+  int* iw = reinterpret_cast<int*>(m->tab_host + 256);
+  for (int i = 0; i < nd; ++i) {
+    if (!(deltas[i] > 0.0)) return fail(WBM_ERR_ARG, "deltas must be positive");
+    fd[i] = (float)deltas[i];
+  }
+  for (int i = 0; i < nw; ++i) {
+    if (widths[i] < 2) return fail(WBM_ERR_ARG, "widths must be >= 2");
+    iw[i] = widths[i];
+  }
+  WBM_HIP(hipMemcpyAsync(m->tab_dev, m->tab_host, 512, hipMemcpyHostToDevice, st), "table upload");
+  WBM_HIP(hipEventRecord(m->tab_evt, st), "table event");
+  m->tab_evt_recorded = true;
+  WBM_HIP(wbm::launch_label(sinr, npairs, reinterpret_cast<const float*>(m->tab_dev), nd,
+                            reinterpret_cast<const int*>(m->tab_dev + 256), nw, (float)noise_power,
+                            label, st),
+          "label launch");
   return WBM_OK;
 }
 

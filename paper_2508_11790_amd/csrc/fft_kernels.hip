@@ -55,57 +55,93 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
   }
 }
 
-// X [K][B][N] -> beamspace of a tile of TB = tile/M snapshots of subband k (zero padded to M):
+// X [K][B][N] -> beamspace of tiles of TB = tile/M snapshots of subband k (zero padded to M):
 //   full  : Y [K][M][B]                                         (stage output), and/or
-//   window: Yw [K][nbt][sumW][TB], row r = window row (t, i) of target t, bin (s_tk + i) mod M.
-// Workgroup = (snapshot tile j, subband k).  With windows, the first T threads place the
-// targets' windows for subband k (same FP64 evaluation as the steering kernel) into LDS.
+//   window: Yw [K][nbt][sumW][TB], row r = window row (t, i) of target t, bin (s_tk + i) mod M,
+//   prof  : per-target training power profile partials [K][gridDim.x][T][64]: sum over this
+//           workgroup's training snapshots (b < L) of |Y|^2 at bins c_tk - 32 .. c_tk + 31
+//           (mod M), c_tk = floor(u_tk + 1/2) the target's beam bin.
+// Workgroup = (first snapshot tile, subband k); it loops over tiles j, j + gridDim.x, ...
+// With windows or profiles the first threads place the targets of subband k (same FP64
+// evaluation as the steering kernel) into LDS.
 template <int LOGM, int LOGT>
 __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
     const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int N, int B,
     int K, const float2* __restrict__ twM, float scale, const int* __restrict__ rowtab, int sumW,
-    WindowGeom g) {
+    WindowGeom g, float* __restrict__ prof, int L) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
   constexpr int M = F::n, TB = F::rows;
   constexpr int LOGTB = fft_tile(LOGM, LOGT) - LOGM;
   __shared__ float2 lds[F::lds_complex];
-  extern __shared__ int s_start[];                       // [T] window starts of subband k
-  const int j = blockIdx.x, k = blockIdx.y;
-  const int b0 = j * TB;
-  if (Yw) {
-    for (int t = threadIdx.x; t < g.T; t += F::threads) s_start[t] = window_start(g, t, k);
-  }
-  float2 v[8];
-#pragma unroll
-  for (int p = 0; p < 8 / F::R0; ++p) {
-#pragma unroll
-    for (int r = 0; r < F::R0; ++r) {
-      int row, e;
-      F::first_input(p, r, row, e);
-      float2 val = make_float2(0.f, 0.f);
-      if (e < N && b0 + row < B) val = X[((int64_t)k * B + b0 + row) * N + e];
-      v[p * F::R0 + r] = val;
+  extern __shared__ int s_dyn[];
+  int* s_start = s_dyn;                                    // [T] window starts of subband k
+  int* s_center = s_dyn + g.T;                             // [T] beam bins (profile centre)
+  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);  // [T][64] profile sums
+  const int k = blockIdx.y;
+  const int nbt = (B + TB - 1) / TB;
+  if (Yw || prof) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) {
+      double u;
+      int s;
+      window_of(g, t, k, &u, &s);
+      s_start[t] = s;
+      if (prof) s_center[t] = (int)floor(u + 0.5);
     }
+    if (prof)
+      for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
   }
-  F::run(v, lds, twM);
-  if (Y) {
+  for (int j = blockIdx.x; j < nbt; j += gridDim.x) {
+    const int b0 = j * TB;
+    float2 v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = threadIdx.x + q * F::threads;
-      const int m = idx >> LOGTB, b = idx & (TB - 1);
-      if (b0 + b < B) Y[((int64_t)k * M + m) * B + b0 + b] = cscale(lds[F::addr(b, m)], scale);
+    for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        int row, e;
+        F::first_input(p, r, row, e);
+        float2 val = make_float2(0.f, 0.f);
+        if (e < N && b0 + row < B) val = X[((int64_t)k * B + b0 + row) * N + e];
+        v[p * F::R0 + r] = val;
+      }
     }
+    F::run(v, lds, twM);
+    if (Y) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int idx = threadIdx.x + q * F::threads;
+        const int m = idx >> LOGTB, b = idx & (TB - 1);
+        if (b0 + b < B) Y[((int64_t)k * M + m) * B + b0 + b] = cscale(lds[F::addr(b, m)], scale);
+      }
+    }
+    if (Yw) {
+      float2* dst = Yw + ((int64_t)k * nbt + j) * sumW * TB;
+      const int tot = sumW * TB;
+      for (int idx = threadIdx.x; idx < tot; idx += F::threads) {
+        const int r = idx >> LOGTB, b = idx & (TB - 1);
+        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+        const int m = (s_start[t] + i) & (M - 1);
+        dst[idx] = cscale(lds[F::addr(b, m)], scale);
+      }
+    }
+    if (prof && b0 < L) {
+      const int nb = min(TB, L - b0);
+      // each thread owns the same (t, bin) entries on every tile: no synchronisation needed
+      for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) {
+        const int t = idx >> 6, jj = idx & 63;
+        const int m = (s_center[t] - 32 + jj) & (M - 1);
+        float acc = 0.f;
+        for (int b = 0; b < nb; ++b) {
+          const float2 y = cscale(lds[F::addr(b, m)], scale);
+          acc += y.x * y.x + y.y * y.y;
+        }
+        s_acc[idx] += acc;
+      }
+    }
+    __syncthreads();   // the next tile's first pass overwrites lds
   }
-  if (Yw) {
-    const int nbt = (B + TB - 1) / TB;
-    float2* dst = Yw + ((int64_t)k * nbt + j) * sumW * TB;
-    const int tot = sumW * TB;
-    for (int idx = threadIdx.x; idx < tot; idx += F::threads) {
-      const int r = idx >> LOGTB, b = idx & (TB - 1);
-      const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-      const int m = (s_start[t] + i) & (M - 1);
-      dst[idx] = cscale(lds[F::addr(b, m)], scale);
-    }
+  if (prof) {
+    float* dst = prof + ((int64_t)k * gridDim.x + blockIdx.x) * g.T * 64;
+    for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) dst[idx] = s_acc[idx];
   }
 }
 
@@ -128,12 +164,17 @@ static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const fl
 template <int LOGM, int LOGT>
 static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
                               const float2* twM, const int* rowtab, int sumW,
-                              const WindowGeom& g, hipStream_t s) {
+                              const WindowGeom& g, float* prof, int L, int G, hipStream_t s) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
-  dim3 grid((B + F::rows - 1) / F::rows, K);
-  const size_t shm = Yw ? sizeof(int) * (size_t)g.T : 0;
+  const int nbt = (B + F::rows - 1) / F::rows;
+  const int gx = prof ? G : nbt;
+  if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
+  dim3 grid(gx, K);
+  size_t shm = 0;
+  if (Yw || prof) shm = sizeof(int) * 2 * (size_t)g.T;
+  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
   hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), grid, dim3(F::threads), shm, s, X, Y, Yw, N, B,
-                     K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g);
+                     K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L);
   return hipGetLastError();
 }
 
@@ -168,13 +209,18 @@ hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, co
 
 int beamspace_tile_log(int M, int logtile) { return fft_tile(ilog2(M), logtile) - ilog2(M); }
 
+int beamspace_tiles(int M, int B, int logtile) {
+  const int tb = 1 << beamspace_tile_log(M, logtile);
+  return (B + tb - 1) / tb;
+}
+
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
                             const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
-                            int logtile, hipStream_t s) {
+                            int logtile, hipStream_t s, float* prof, int L, int G) {
   const int lm = ilog2(M);
-#define C(L, T)                                                          \
-  case L:                                                                \
-    return beam_launch<L, T>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, s);
+#define C(LG, T)                                                                     \
+  case LG:                                                                           \
+    return beam_launch<LG, T>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, prof, L, G, s);
   switch (logtile) {
     case 11:
       switch (lm) { WBM_LOG_CASES(C, 11) }
@@ -190,7 +236,21 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
   return hipErrorInvalidValue;
 }
 
-// Static LDS is at most 8192 * 9/8 + 8 complex = 72 KiB; the beamspace kernel adds T ints.
-hipError_t set_fft_attributes() { return hipSuccess; }
+// Static LDS is at most 8192 * 9/8 + 8 complex = 72 KiB; the beamspace kernel adds 8 + 256
+// bytes per target (window starts, beam bins, profile sums).
+hipError_t set_fft_attributes() {
+#define A(LG, T)                                                                          \
+  {                                                                                       \
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LG, T>,                   \
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,        \
+                                       T == 13 ? 80 * 1024 : 64 * 1024);                  \
+    if (e != hipSuccess) return e;                                                        \
+  }
+  WBM_LOG_CASES(A, 11)
+  WBM_LOG_CASES(A, 12)
+  WBM_LOG_CASES(A, 13)
+#undef A
+  return hipSuccess;
+}
 
 }  // namespace wbm

@@ -85,7 +85,7 @@ __device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const P
 // EPT * THREADS).  ys is an LDS scratch of W x kCH float2 that may alias R.
 template <typename ACC, bool WINDOWED, int THREADS, int EPT>
 __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& a, int k, int W,
-                                int woff, int s, float2* ys, C2<ACC>* R, int RS) {
+                                int woff, int s, float2* ys, C2<ACC>* R, int RS, double delta) {
   const int tid = threadIdx.x;
   const int nE = W * (W + 1) / 2;
   int S = 1;
@@ -147,7 +147,7 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
       if (ei[q] >= 0) {
         C2<ACC> r = c2<ACC>(acc[q].x * invL, acc[q].y * invL);
         if (ei[q] == ej[q]) {
-          r.x += (ACC)a.delta;
+          r.x += (ACC)delta;
           r.y = 0;
         }
         R[ei[q] * RS + ej[q]] = r;
@@ -268,15 +268,26 @@ __global__ __launch_bounds__(THREADS) void k_mvdr_fused(PairArgs a, WindowGeom g
 
   const int p = blockIdx.x;
   const int k = p / a.T, t = p - k * a.T;
-  const int W = d.win[t], woff = d.woff[t];
+  int W = d.win[t], woff = d.woff[t];
   const int64_t pair = (int64_t)t * a.K + k;
   double u;
   int s;
   window_of(g, t, k, &u, &s);
+  if (a.pw) {
+    // centred sub-window: for widths of equal parity the start moves by the half difference
+    const int Wp = a.pw[pair];
+    if (Wp >= 1 && Wp <= W && ((W - Wp) & 1) == 0) {
+      const int off = (W - Wp) >> 1;
+      woff += off;
+      s += off;
+      W = Wp;
+    }
+  }
+  const double delta = a.pdelta ? (double)a.pdelta[pair] : a.delta;
   if (threadIdx.x < W) av[threadIdx.x] = window_steering(g, u, s, threadIdx.x);
   if (starts_out && threadIdx.x == 0) starts_out[pair] = s;
 
-  pair_covariance<double, true, THREADS, EPT>(Yw, a, k, W, woff, s, ys, R, lay.RS);
+  pair_covariance<double, true, THREADS, EPT>(Yw, a, k, W, woff, s, ys, R, lay.RS, delta);
   const int fail = chol_lds<double, THREADS>(R, lay.RS, diag, W);
   if (!fail) solve_lds<double>(R, lay.RS, diag, W, av, wv);
   __syncthreads();
@@ -348,7 +359,7 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_cov(PairArgs a, DevDesc
   const int W = d.win[t];
   const int s = starts[t * a.K + k];
   const int64_t pair = (int64_t)t * a.K + k;
-  pair_covariance<float, false, kPlainThreads, 9>(Y, a, k, W, 0, s, ys, R, lay.RS);
+  pair_covariance<float, false, kPlainThreads, 9>(Y, a, k, W, 0, s, ys, R, lay.RS, a.delta);
   float2* dst = R32 + pair * a.wmax * a.wmax;
   for (int e = threadIdx.x; e < W * W; e += kPlainThreads) {
     const int i = e / W, j = e - i * W;

@@ -25,10 +25,15 @@ int beamspace_tile_log(int M, int logtile);
 hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, const float2* twK,
                              const float2* hb, int logtile, hipStream_t s);
 // Zero-padded spatial DFT: X [K][B][N] -> Y [K][M][B] (if Y) and windows Yw (if Yw; the
-// kernel places the windows of subband k itself from g).
+// kernel places the windows of subband k itself from g).  With prof, G workgroups per
+// subband each loop over snapshot tiles and write training power-profile partials
+// prof [K][G][T][64] (64 bins centred on each target's beam bin, snapshots b < L).
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
                             const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
-                            int logtile, hipStream_t s);
+                            int logtile, hipStream_t s, float* prof = nullptr, int L = 0,
+                            int G = 0);
+// Snapshot tiles of the beamspace kernel for M, B at a tile size.
+int beamspace_tiles(int M, int B, int logtile);
 
 // Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
 hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar, hipStream_t s);
@@ -37,6 +42,10 @@ struct PairArgs {
   int T, K, M, L, Lt, B, wmax;
   int logTB, nbt, sumW;          // windowed layout (fused form)
   double delta;
+  // optional per-pair window width [T][K] (a sub-window of the gathered one, same parity)
+  // and per-pair loading [T][K]; nullptr = the target's window / delta
+  const int* pw = nullptr;
+  const float* pdelta = nullptr;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
 // solve -> apply, reading the window rows written by the beamspace kernel.
