@@ -173,6 +173,12 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
   size_t shm = 0;
   if (Yw || prof) shm = sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
+  if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
+    // beyond the default 64 KiB per workgroup: ask for exactly the dynamic part
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LOGM, LOGT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), grid, dim3(F::threads), shm, s, X, Y, Yw, N, B,
                      K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L);
   return hipGetLastError();
@@ -237,20 +243,8 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
 }
 
 // Static LDS is at most 8192 * 9/8 + 8 complex = 72 KiB; the beamspace kernel adds 8 + 256
-// bytes per target (window starts, beam bins, profile sums).
-hipError_t set_fft_attributes() {
-#define A(LG, T)                                                                          \
-  {                                                                                       \
-    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LG, T>,                   \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,        \
-                                       T == 13 ? 80 * 1024 : 64 * 1024);                  \
-    if (e != hipSuccess) return e;                                                        \
-  }
-  WBM_LOG_CASES(A, 11)
-  WBM_LOG_CASES(A, 12)
-  WBM_LOG_CASES(A, 13)
-#undef A
-  return hipSuccess;
-}
+// bytes per target (window starts, beam bins, profile sums), requested at launch when the
+// total passes 64 KiB.
+hipError_t set_fft_attributes() { return hipSuccess; }
 
 }  // namespace wbm

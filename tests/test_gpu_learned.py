@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import scenes
-from gpu_helpers import log
+from gpu_helpers import log, snapshot_dynamic_range, weight_tol
 from oracle import learned as olearned
 from oracle import mlp as omlp
 
@@ -87,7 +87,9 @@ def test_pair_windows_and_loadings_match_oracle(torch, wb):
             ref = _pair_oracle(x128, cfg, _sin(sc)[t], k, W, d)
             assert starts[t, k] == ref["start"][0, 0]
             err = oracle.rel_weight_error(w[t, k, :W], ref["w"][0, 0, :W])
-            assert err < 1e-5, (t, k, W, d, err)
+            kappa = float(np.linalg.cond(ref["R"][0][0]))
+            tol = weight_tol(kappa, False, snapshot_dynamic_range(sc))
+            assert err <= tol, (t, k, W, d, err, tol)
             assert np.all(w[t, k, W:] == 0)
             bins = oracle.window_bins(int(starts[t, k]), W, cfg.M)
             s_ref = olearned.pair_sinr(w[t, k, :W], ref["a"][0, 0, :W], bins, cfg.N, cfg.M,
