@@ -69,6 +69,15 @@ typedef enum {
                                accumulation of the covariance and FP64 Cholesky */
 #define WBM_FORM_GRAPH 2    /* WBM_FORM_FUSED with the launch sequence replayed from a
                                HIP graph (captured on first use for a given argument set) */
+#define WBM_FORM_MIXED 3    /* fused sequence with the window covariance on MFMA: each FP32
+                               snapshot split into BF16 hi + lo (three BF16 products, FP32
+                               accumulation), FP32 Cholesky and solves, one FP64-residual
+                               refinement step and FP64 normalisation a^H R^-1 a; windows whose
+                               Cholesky pivots span a condition estimate above 1e4 take the
+                               FP64 path instead and report info bit 30 (info & (1 << 30)) */
+#define WBM_FORM_MIXED_BF16 4  /* as WBM_FORM_MIXED with one BF16 product per step (snapshots
+                               rounded to BF16) */
+#define WBM_INFO_ROUTED (1 << 30)
 
 typedef struct {
   int32_t n_elem;           /* N >= 1 */
@@ -100,13 +109,14 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
  *   win     host [T] window width W_t per target, 1 <= W_t <= w_max.
  *   T       number of targets, 1 <= T <= max_targets.
  *   loading diagonal loading delta >= 0 added to the 1/L-scaled covariance.
- *   form    WBM_FORM_PLAIN / WBM_FORM_FUSED / WBM_FORM_GRAPH.
+ *   form    WBM_FORM_PLAIN / FUSED / GRAPH / MIXED / MIXED_BF16.
  *   out     device [T][K][Lt] wbm_c32: beam outputs c^H y on test snapshots L..L+Lt-1.
  *   weights device [T][K][w_max] wbm_c32 or NULL: correlators c~ in window-bin order
  *           (bins (s + i) mod M, i < W_t), zero padded to w_max.
  *   starts  device [T][K] int32 or NULL: first window bin s of every pair (may be
  *           negative; the bins are taken mod M).
- *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's Cholesky failed.
+ *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's Cholesky failed at
+ *           pivot j-1 (mixed forms: plus WBM_INFO_ROUTED when the FP64 path was taken).
  *   stream  hipStream_t or NULL. */
 wbm_status wbm_beamform(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                         const int32_t* win, int32_t T, double loading, int32_t form,

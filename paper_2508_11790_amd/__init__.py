@@ -22,7 +22,9 @@ __all__ = ["Plan", "Mlp", "WbmError", "FORM_PLAIN", "FORM_FUSED", "FORM_GRAPH", 
 
 MLP_PARAMS = _lib.MLP_PARAMS
 
-_FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH}
+_FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH,
+          "mixed": _lib.FORM_MIXED, "mixed_bf16": _lib.FORM_MIXED_BF16}
+INFO_ROUTED = _lib.INFO_ROUTED
 
 
 def version() -> str:

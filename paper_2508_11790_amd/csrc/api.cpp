@@ -618,8 +618,7 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
   if (!x) return fail(WBM_ERR_ARG, "x is NULL");
   if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
-  if (form != WBM_FORM_PLAIN && form != WBM_FORM_FUSED && form != WBM_FORM_GRAPH)
-    return fail(WBM_ERR_ARG, "unknown form");
+  if (form < WBM_FORM_PLAIN || form > WBM_FORM_MIXED_BF16) return fail(WBM_ERR_ARG, "unknown form");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
@@ -647,6 +646,12 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
     }
   } else if (form == WBM_FORM_FUSED) {
     WBM_HIP(enqueue_fused(p, xx, T, sumW, loading, o, w, starts, info, st), "fused launch");
+  } else if (form == WBM_FORM_MIXED || form == WBM_FORM_MIXED_BF16) {
+    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
+    WBM_HIP(enqueue_beamspace_windows(p, T, sumW, st), "beamspace launch");
+    WBM_HIP(wbm::launch_mvdr_mixed(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, o, w,
+                                   starts, info, form == WBM_FORM_MIXED, st),
+            "mixed MVDR launch");
   } else {
     GraphKey key;
     key.x = x;

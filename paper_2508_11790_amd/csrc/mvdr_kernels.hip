@@ -451,3 +451,314 @@ hipError_t set_pair_attributes() {
 }
 
 }  // namespace wbm
+
+// ==========================================================================================
+// Mixed-precision form.  The W x W covariance is the one dense contraction of the path: with
+// Z = [Re Y; Im Y] (2W x L real) the Gram G = Z Z^T gives Re R = G11 + G22 and
+// Im R = G21 - G12.  G runs on MFMA (v_mfma_f32_32x32x16_bf16, FP32 accumulation) over 32 x 32
+// tiles of the lower triangle, either with the BF16-rounded snapshots (one product per tile and
+// step) or with each FP32 snapshot split into BF16 hi + lo parts (hi*hi + hi*lo + lo*hi, three
+// products).  The Cholesky and both triangular solves run in FP32; the residual of one
+// iterative-refinement step and the normalisation a^H R^-1 a run in FP64.  A window whose
+// Cholesky pivots span more than kRouteKappa (condition-number estimate) is routed to the exact
+// path instead: FP64 accumulation of the FP32 snapshots and FP64 Cholesky; its info entry then
+// carries bit 30.
+namespace wbm {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kMixThreads = 256;
+constexpr int kMixCH = 64;                 // snapshots per LDS chunk (4 MFMA k-steps)
+constexpr int kMixRS = kMixCH + 8;         // bf16 row stride (144 B: off the bank period)
+constexpr int kMaxTiles = 10;              // lower-triangle 32x32 tiles of 2W <= 128
+constexpr double kRouteKappa = 1.0e4;
+constexpr int kInfoRouted = 1 << 30;
+
+__device__ __forceinline__ __bf16 to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  const unsigned short h = (unsigned short)(u >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
+__device__ __forceinline__ float from_bf16(__bf16 b) {
+  const unsigned short h = __builtin_bit_cast(unsigned short, b);
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+struct MixLds {
+  size_t zhi, zlo, g, r, diag, wv, av, total;
+  int RS;
+};
+
+__host__ __device__ inline MixLds mix_lds_layout(int wmax) {
+  MixLds p;
+  const int rows = 2 * wmax;
+  const int pad = (rows + 31) / 32 * 32;
+  size_t o = 0;
+  p.zhi = o;
+  o += sizeof(__bf16) * (size_t)pad * kMixRS;
+  p.zlo = o;
+  o += sizeof(__bf16) * (size_t)pad * kMixRS;
+  o = (o + 15) & ~(size_t)15;
+  // G (FP32, pad x pad) aliases the staging area after the last chunk
+  const size_t gbytes = sizeof(float) * (size_t)pad * pad;
+  p.g = 0;
+  if (gbytes > o) o = (gbytes + 15) & ~(size_t)15;
+  p.RS = wmax + 1;
+  p.r = o;                                               // complex R, FP64 (routing needs it)
+  o += sizeof(C2<double>) * (size_t)wmax * p.RS;
+  p.diag = o;
+  o += sizeof(double) * 64;
+  p.wv = o;
+  o += sizeof(C2<double>) * 64;
+  p.av = o;
+  o += sizeof(double2) * 64;
+  p.total = o;
+  return p;
+}
+
+template <bool SPLIT>
+__global__ __launch_bounds__(kMixThreads) void k_mvdr_mixed(PairArgs a, WindowGeom g, DevDesc d,
+                                                            const float2* __restrict__ Yw,
+                                                            float2* __restrict__ out,
+                                                            float2* __restrict__ wout,
+                                                            int* __restrict__ starts_out,
+                                                            int* __restrict__ info) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MixLds lay = mix_lds_layout(a.wmax);
+  __bf16* zhi = reinterpret_cast<__bf16*>(smem + lay.zhi);
+  __bf16* zlo = reinterpret_cast<__bf16*>(smem + lay.zlo);
+  float* G = reinterpret_cast<float*>(smem + lay.g);
+  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r);
+  double* diag = reinterpret_cast<double*>(smem + lay.diag);
+  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv);
+  double2* av = reinterpret_cast<double2*>(smem + lay.av);
+  float* R32 = reinterpret_cast<float*>(smem + lay.r);   // FP32 view used by the FP32 Cholesky
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  const int p = blockIdx.x;
+  const int k = p / a.T, t = p - k * a.T;
+  const int W = d.win[t], woff = d.woff[t];
+  const int64_t pair = (int64_t)t * a.K + k;
+  double u;
+  int s;
+  window_of(g, t, k, &u, &s);
+  if (tid < W) av[tid] = window_steering(g, u, s, tid);
+  if (starts_out && tid == 0) starts_out[pair] = s;
+
+  const int rows = 2 * W;
+  const int nt = (rows + 31) / 32;
+  const int ntiles = nt * (nt + 1) / 2;
+  f32x16_t acc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) acc[q] = f32x16_t{};
+  // this wave's tiles: q-th tile = wave + 4 q
+  for (int c0 = 0; c0 < a.L; c0 += kMixCH) {
+    __syncthreads();
+    for (int idx = tid; idx < nt * 32 * kMixCH; idx += kMixThreads) {
+      const int r = idx / kMixCH, bb = idx - r * kMixCH;
+      const int b = c0 + bb;
+      float v = 0.f;
+      if (r < rows && b < a.L) {
+        const int i = r < W ? r : r - W;
+        const float2 y = load_y<true>(Yw, a, k, woff, s, i, b);
+        v = r < W ? y.x : y.y;
+      }
+      const __bf16 hi = to_bf16(v);
+      zhi[r * kMixRS + bb] = hi;
+      if (SPLIT) zlo[r * kMixRS + bb] = to_bf16(v - from_bf16(hi));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int tile = wave + 4 * q;
+      if (tile < ntiles) {
+        int ti, tj;
+        tri_index(tile, ti, tj);
+        const int ra = ti * 32 + (lane & 31), rb = tj * 32 + (lane & 31);
+        const int kofs = (lane >> 5) * 8;
+#pragma unroll
+        for (int ks = 0; ks < kMixCH; ks += 16) {
+          const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(zhi + ra * kMixRS + ks + kofs);
+          const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(zhi + rb * kMixRS + ks + kofs);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[q], 0, 0, 0);
+          if (SPLIT) {
+            const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(zlo + ra * kMixRS + ks + kofs);
+            const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(zlo + rb * kMixRS + ks + kofs);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[q], 0, 0, 0);
+            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[q], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();   // staging no longer read; G aliases it
+  const int pad = nt * 32;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int tile = wave + 4 * q;
+    if (tile < ntiles) {
+      int ti, tj;
+      tri_index(tile, ti, tj);
+      const int col = tj * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        G[row * pad + col] = acc[q][r];
+      }
+    }
+  }
+  __syncthreads();
+  // complex R (lower) from the real Gram, scaled and loaded; FP32 copy for the FP32 Cholesky
+  const int RS = lay.RS;
+  const float invL = 1.0f / (float)a.L;
+  for (int e = tid; e < W * W; e += kMixThreads) {
+    const int i = e / W, j = e - i * W;
+    if (j <= i) {
+      const float g11 = G[i * pad + j], g22 = G[(W + i) * pad + (W + j)];
+      const float g21 = G[(W + i) * pad + j], g12t = G[(W + j) * pad + i];   // G12[i][j] = G[W+j][i]
+      float re = (g11 + g22) * invL, im = (g21 - g12t) * invL;
+      if (i == j) {
+        re += (float)a.delta;
+        im = 0.f;
+      }
+      R32[2 * (i * RS + j)] = re;       // FP32 complex in the first half of R's storage
+      R32[2 * (i * RS + j) + 1] = im;
+    }
+  }
+  __syncthreads();
+  C2<float>* Rf = reinterpret_cast<C2<float>*>(R32);
+  float* diagf = reinterpret_cast<float*>(diag);
+  int fail = chol_lds<float, kMixThreads>(Rf, RS, diagf, W);
+  // condition estimate from the pivots: (max / min)^2
+  bool route = fail != 0;
+  if (!fail) {
+    float dmax = 0.f, dmin = 3.0e38f;
+    for (int j = 0; j < W; ++j) {
+      dmax = fmaxf(dmax, diagf[j]);
+      dmin = fminf(dmin, diagf[j]);
+    }
+    route = (double)dmax * dmax > kRouteKappa * (double)dmin * dmin;
+  }
+  __syncthreads();
+  if (!route) {
+    // FP32 solves of R x = a, one FP64-residual refinement, FP64 normalisation (wave 0)
+    if (tid < 64) {
+      C2<double> x = c2<double>(0, 0);
+      C2<double> b = c2<double>(0, 0);
+      if (lane < W) b = c2<double>(av[lane].x, av[lane].y);
+      for (int it = 0; it < 2; ++it) {
+        // rhs = b - R x in FP64 with R the MFMA-formed matrix, read back from the Gram G
+        // (lower tiles): R_ij = (G[i][j] + G[W+i][W+j] + i (G[W+i][j] - G[W+j][i])) / L for
+        // i >= j, R_ij = conj(R_ji) above the diagonal, + delta on it.
+        C2<float> v = c2<float>(0.f, 0.f);
+        {
+          double rx = 0.0, ry = 0.0;
+          for (int j = 0; j < W; ++j) {
+            const double xj_x = __shfl(x.x, j), xj_y = __shfl(x.y, j);
+            if (lane < W) {
+              const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
+              double re = ((double)G[hi * pad + lo] + (double)G[(W + hi) * pad + (W + lo)]) / a.L;
+              double im = ((double)G[(W + hi) * pad + lo] - (double)G[(W + lo) * pad + hi]) / a.L;
+              if (lane < j) im = -im;
+              if (lane == j) {
+                re += a.delta;
+                im = 0.0;
+              }
+              rx += re * xj_x - im * xj_y;
+              ry += re * xj_y + im * xj_x;
+            }
+          }
+          if (lane < W) v = c2<float>((float)(b.x - rx), (float)(b.y - ry));
+        }
+        // dx = R^-1 rhs in FP32: forward then backward substitution with the factor
+        for (int j = 0; j < W; ++j) {
+          const float dinv = 1.0f / diagf[j];
+          const float vx = __shfl(v.x, j) * dinv, vy = __shfl(v.y, j) * dinv;
+          if (lane == j) {
+            v = c2<float>(vx, vy);
+          } else if (lane > j && lane < W) {
+            const C2<float> gg = Rf[lane * RS + j];
+            v.x -= gg.x * vx - gg.y * vy;
+            v.y -= gg.x * vy + gg.y * vx;
+          }
+        }
+        for (int j = W - 1; j >= 0; --j) {
+          const float dinv = 1.0f / diagf[j];
+          const float xx = __shfl(v.x, j) * dinv, xy = __shfl(v.y, j) * dinv;
+          if (lane == j) {
+            v = c2<float>(xx, xy);
+          } else if (lane < j) {
+            const C2<float> gg = Rf[j * RS + lane];
+            v.x -= gg.x * xx + gg.y * xy;
+            v.y -= gg.x * xy - gg.y * xx;
+          }
+        }
+        x.x += (double)v.x;
+        x.y += (double)v.y;
+      }
+      // q = a^H x in FP64 (real for Hermitian positive definite R)
+      double qq = (lane < W) ? b.x * x.x + b.y * x.y : 0.0;
+      for (int off = 32; off > 0; off >>= 1) qq += __shfl_xor(qq, off);
+      if (lane < W) wv[lane] = c2<double>(x.x / qq, x.y / qq);
+    }
+  } else {
+    // exact route: FP64 accumulation of the FP32 snapshots and FP64 Cholesky
+    float2* ys = reinterpret_cast<float2*>(smem);
+    pair_covariance<double, true, kMixThreads, 9>(Yw, a, k, W, woff, s, ys, R, RS, a.delta);
+    fail = chol_lds<double, kMixThreads>(R, RS, diag, W);
+    if (!fail) solve_lds<double>(R, RS, diag, W, av, wv);
+  }
+  __syncthreads();
+  for (int l = tid; l < a.Lt; l += kMixThreads) {
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = 0; i < W; ++i) {
+        const float2 y = load_y<true>(Yw, a, k, woff, s, i, a.L + l);
+        const C2<double> w = wv[i];
+        zx += w.x * (double)y.x + w.y * (double)y.y;
+        zy += w.x * (double)y.y - w.y * (double)y.x;
+      }
+    }
+    out[pair * a.Lt + l] = make_float2((float)zx, (float)zy);
+  }
+  if (wout) {
+    for (int i = tid; i < a.wmax; i += kMixThreads) {
+      float2 v = make_float2(0.f, 0.f);
+      if (!fail && i < W) v = make_float2((float)wv[i].x, (float)wv[i].y);
+      wout[pair * a.wmax + i] = v;
+    }
+  }
+  if (info && tid == 0) info[pair] = fail | (route ? kInfoRouted : 0);
+}
+
+hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                             bool split, hipStream_t s) {
+  if (a.wmax > 64) return hipErrorInvalidValue;
+  MixLds lay = mix_lds_layout(a.wmax);
+  // the exact route stages snapshots with the same kernel: make room for its chunk too
+  const size_t exact = sizeof(float2) * (size_t)a.wmax * kCH;
+  size_t shm = lay.total;
+  if (exact > lay.r) shm = lay.total + (exact - lay.r);
+  (void)shm;
+  if (exact > lay.r) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)(a.T * a.K);
+  if (split) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mixed<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mvdr_mixed<true>, dim3(grid), dim3(kMixThreads), lay.total, s, a, g, d, Yw,
+                       out, wout, starts, info);
+  } else {
+    hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mixed<false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mvdr_mixed<false>, dim3(grid), dim3(kMixThreads), lay.total, s, a, g, d,
+                       Yw, out, wout, starts, info);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace wbm

@@ -54,6 +54,12 @@ hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDe
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s);
 bool mvdr_wave_supported(int wmax);
+// Mixed-precision pair kernel: MFMA BF16 covariance (split = BF16 hi/lo, three products;
+// else one BF16 product) with FP32 accumulation, FP32 Cholesky and solves, FP64 refinement
+// residual and normalisation; ill-conditioned windows routed to FP64 (info bit 30).
+hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                             bool split, hipStream_t s);
 // Plain per-stage FP32 form reading the full beamspace Y [K][M][B]: gather + covariance,
 // Cholesky + solve, apply -- three launches with R and w in HBM.
 hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* Y,

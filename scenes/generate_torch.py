@@ -39,19 +39,33 @@ def make_scene_torch(cfg: SceneConfig, seed: int, device="cuda"):
     ratio = torch.from_numpy(subband_freq_ratio_gen(K, cfg.beta, cfg.half_bin)).to(device)
     src_sin = torch.from_numpy(np.concatenate([np.sin(np.deg2rad(taz)),
                                                np.sin(np.deg2rad(jaz))])).to(device)
-    e_idx = torch.arange(N, dtype=torch.float64, device=device)
-    ph = 2.0 * math.pi * cfg.dl * (ratio[:, None, None] * e_idx[None, :, None]) * src_sin[None, None, :]
-    A = torch.polar(torch.ones_like(ph), ph).to(torch.complex64)            # [K, N, src]
-    X = torch.matmul(A, G.permute(2, 0, 1))                               # [K, N, B]
-    X = X.permute(1, 2, 0).contiguous()                                   # [N, B, K]
-    nz = torch.randn((N, B, K, 2), generator=gen, device=device) * math.sqrt(cfg.noise_var / 2.0)
-    X += torch.complex(nz[..., 0], nz[..., 1])
-    x = torch.fft.ifft(X, dim=2, norm="ortho")
+    Gk = G.permute(2, 0, 1).contiguous()                                  # [K, src, B]
+    del G
+    x = torch.empty((N, cfg.S), dtype=torch.complex64, device=device)
+    tw = None
     if cfg.half_bin:
         tw = torch.polar(torch.ones(K, dtype=torch.float64, device=device),
                          math.pi * torch.arange(K, dtype=torch.float64, device=device) / K)
-        x *= tw.to(torch.complex64)
-    x = x.reshape(N, cfg.S).contiguous()
+        tw = tw.to(torch.complex64)
+    # element chunks of at most 2^27 complex samples bound the temporaries
+    ec = max(1, min(N, (1 << 27) // (B * K)))
+    for e0 in range(0, N, ec):
+        e1 = min(N, e0 + ec)
+        e_idx = torch.arange(e0, e1, dtype=torch.float64, device=device)
+        ph = 2.0 * math.pi * cfg.dl * (ratio[:, None, None] * e_idx[None, :, None]) * src_sin[None, None, :]
+        A = torch.polar(torch.ones_like(ph), ph).to(torch.complex64)        # [K, ec, src]
+        Xc = torch.matmul(A, Gk).permute(1, 2, 0).contiguous()            # [ec, B, K]
+        del A
+        nz = torch.randn((e1 - e0, B, K, 2), generator=gen, device=device)
+        nz *= math.sqrt(cfg.noise_var / 2.0)
+        Xc += torch.view_as_complex(nz)
+        del nz
+        xc = torch.fft.ifft(Xc, dim=2, norm="ortho")
+        del Xc
+        if tw is not None:
+            xc *= tw
+        x[e0:e1] = xc.reshape(e1 - e0, cfg.S)
+        del xc
     sc = Scene(cfg=cfg, seed=seed, x=None, target_az=np.deg2rad(taz), target_snr=tsnr,
                target_delay=delay, jammer_az=np.deg2rad(jaz), jammer_inr=jinr, win=win)
     return sc, x

@@ -24,7 +24,7 @@ def snapshot_dynamic_range(scene) -> float:
     return math.sqrt(1.0 + cfg.N * float(np.sum(scene.jammer_inr)) / cfg.noise_var)
 
 
-def weight_tol(kappa: float, plain: bool = False, dr: float = 1.0) -> float:
+def weight_tol(kappa: float, plain: bool = False, dr: float = 1.0, unit: float = EPS32) -> float:
     """Relative weight tolerance against the FP64 oracle, derived from the FP32 arithmetic.
 
     * Rounding every stored snapshot to FP32 perturbs the windowed covariance so that the
@@ -35,12 +35,14 @@ def weight_tol(kappa: float, plain: bool = False, dr: float = 1.0) -> float:
       about 0.05 eps32 DR, DR the snapshot dynamic range (measured at N = 256 and 1024):
       bound 0.5 eps32 DR.
     * The plain form also forms the covariance and solves in FP32, which moves the weights
-      by about eps32 kappa: bound 4 eps32 kappa.
+      by about u kappa with u = eps32: bound 4 u kappa.  The mixed forms form it from BF16
+      products: u = 2^-16 with each snapshot split into BF16 hi + lo (the lo*lo product is
+      dropped), u = 2^-8 with one BF16 product.
     The floor is the 1e-5 relative weight error the method is held to.
     """
     base = max(1e-5, 0.5 * EPS32 * dr)
     if plain:
-        return max(base, 4.0 * EPS32 * kappa)
+        return max(base, 4.0 * unit * kappa)
     return max(base, 8.0 * EPS32 * math.sqrt(kappa))
 
 
@@ -54,7 +56,7 @@ def windowed_interference(scene, k, bins, ratio):
 
 
 def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.1,
-                     check_sinr=True, fp32_fft=True):
+                     check_sinr=True, fp32_fft=True, tol_scale=1.0, unit=EPS32):
     """Check GPU outputs ``res`` (tensors) against oracle dict ``ref`` (windowed_mvdr with
     return_windows).  Returns a dict of error statistics."""
     cfg = scene.cfg
@@ -78,15 +80,17 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
             R = ref["R"][t][ik]
             kappa = float(np.linalg.cond(R))
             err = oracle.rel_weight_error(wg, wo)
-            tol = weight_tol(kappa, plain, dr)
-            assert err <= tol, f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
+            tol = weight_tol(kappa, plain, dr, unit)
+            if tol_scale is not None:   # None: the error is reported, not bounded
+                assert err <= tol * tol_scale, \
+                    f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
             worst_w = max(worst_w, err)
             worst_ratio = max(worst_ratio, err / tol)
             # apply step: GPU output vs the GPU's own weights on the oracle's test snapshots.
             # The GPU's snapshots carry the FP32 rounding of two FFTs (~1e-6 of |y|), so the
             # bound is 1e-5 ||w|| max ||y||; a wrong index or conjugation gives O(1).
             Yt = ref["Yw"][t][ik][:, cfg.L:cfg.L + cfg.Lt]
-            if cfg.Lt:
+            if cfg.Lt and tol_scale is not None:
                 zc = wg.conj() @ Yt
                 scale = np.linalg.norm(wg) * np.max(np.linalg.norm(Yt, axis=0))
                 dz = float(np.max(np.abs(z_g[t, k] - zc)) / scale)

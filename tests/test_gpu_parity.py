@@ -279,3 +279,29 @@ def test_full_dimensional_mvdr_matches_oracle(torch, wb, name, subbands):
             assert np.max(np.abs(z_g[t, k] - zc)) <= 1e-5 * scale
     log(f"  max weight error {worst:.3e}")
     plan.close()
+
+
+# ----------------------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("name", ["small", "gpu"])
+def test_mixed_precision_forms(torch, wb, name):
+    """MFMA BF16 covariance forms: weights within the bound of each form's product precision
+    (2^-16 split hi/lo, 2^-8 single BF16), SINR loss <= 0.1 dB, every result's error logged."""
+    cfg = scenes.config_by_name(name)
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    x = torch.from_numpy(x32).cuda()
+    for form in ("mixed", "mixed_bf16"):
+        res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        info = res["info"].cpu().numpy()
+        routed = (info & wb.INFO_ROUTED) != 0
+        assert np.all((info & ~wb.INFO_ROUTED) == 0), "Cholesky failures"
+        res = dict(res)
+        res["info"] = torch.zeros_like(res["info"])
+        unit = 2.0 ** -16 if form == "mixed" else 2.0 ** -8
+        st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit)
+        log(f"  {name} {form}: routed {int(routed.sum())}/{routed.size} {st}")
+    plan.close()
