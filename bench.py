@@ -100,6 +100,10 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip full-dimensional MVDR")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run 5 plain device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--predictor", default=os.path.join(ROOT, "paper_2508_11790_amd",
+                                                        "predictor_params.npz"),
+                    help="trained loading/window predictor for the learned form ('' to skip)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the path is measured on one GPU's share of the "
@@ -113,9 +117,14 @@ def main():
     torch.cuda.set_device(0)
     cfg = scenes.config_by_name(args.workload)
     log(f"workload {cfg.name}: generating scene")
-    sc = scenes.make_scene(cfg)
-    x32 = sc.x.astype(np.complex64)
-    x = torch.from_numpy(x32).cuda()
+    if cfg.N >= 1024:
+        sc, x = scenes.make_scene_torch(cfg, cfg.seed)       # seeded, generated on the GPU
+        x32 = None
+    else:
+        sc = scenes.make_scene(cfg)
+        x32 = sc.x.astype(np.complex64)
+        x = torch.from_numpy(x32).cuda()
+        sc.x = None
     T, K = cfg.T, cfg.K
     wmax = int(sc.win.max())
     plan = wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, T, wmax, beta=cfg.beta,
@@ -137,6 +146,38 @@ def main():
     log("timing plain per-stage FP32 form")
     ms_plain = timed_steps(torch, step("plain"), args.steps, args.warmup)
     w_plain = wts.cpu().numpy().astype(np.complex128)
+    mixed = {}
+    if not args.no_mixed:
+        for form in ("mixed", "mixed_bf16"):
+            log(f"timing {form} form")
+            ms = timed_steps(torch, step(form), args.steps, args.warmup)
+            routed = int(((info.cpu().numpy() & wb.INFO_ROUTED) != 0).sum())
+            mixed[form] = {"value": T * K / (ms * 1e-3), "ms_per_step": ms, "routed_pairs": routed,
+                           "weights": wts.cpu().numpy().astype(np.complex128)}
+    learned_res = None
+    if args.predictor and os.path.exists(args.predictor):
+        from paper_2508_11790_amd import learned as wlearned
+        log("timing learned form")
+        params = torch.from_numpy(wlearned.load_params(args.predictor)).cuda()
+        plan_l = wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, T, 33, beta=cfg.beta,
+                         d_over_lambda=cfg.dl, half_bin=cfg.half_bin)
+        lres = {}
+
+        def lstep():
+            lres.update(plan_l.beamform_learned(x, az, params, cfg.noise_var, 9, delta))
+        ms_l = timed_steps(torch, lstep, args.steps, args.warmup)
+        fx = plan.beamform(x, az, win, delta, form="fused")
+        s_fixed = plan.sinr(az, win, fx["weights"], fx["starts"], sc.jammer_az, sc.jammer_inr,
+                            cfg.noise_var)
+        s_learn = plan_l.sinr(az, [33] * T, lres["weights"], lres["starts"], sc.jammer_az,
+                              sc.jammer_inr, cfg.noise_var, pair_win=lres["pair_win"])
+        gain = float((10 * torch.log10(s_learn)).mean() - (10 * torch.log10(s_fixed)).mean())
+        learned_res = {"value": T * K / (ms_l * 1e-3), "ms_per_step": ms_l,
+                       "mean_sinr_gain_db_vs_fixed": gain,
+                       "fallback_pairs": int(lres["fallback"].sum()),
+                       "form": "profiles -> MLP (BF16 weights) -> per-pair loading and window"}
+        plan_l.close()
+
     ms_full = None
     if not args.no_full:
         log("timing full-dimensional element-space MVDR")
@@ -189,20 +230,28 @@ def main():
                    "form": "fused + HIP graph", "pairs_per_step": beams},
         "plain": {"value": beams / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                   "form": "per-stage FP32 kernels, full beamspace in HBM, no graph"},
+        "mixed": {f: {k2: v for k2, v in r.items() if k2 != "weights"} for f, r in mixed.items()},
+        "learned": learned_res,
         "full_dim": (None if ms_full is None else
                      {"value": beams / (ms_full * 1e-3), "ms_per_step": ms_full,
                       "form": f"element-space {cfg.N}x{cfg.N} MVDR per subband, FP64"}),
         "roofline": roofline,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and x32 is not None:
         log("CPU oracle leg")
         cpu, ref = cpu_baseline_leg(sc, x32)
         result["cpu_baseline"] = cpu
         loss_c, err_c = sinr_check(sc, ref, w_chosen)
         loss_p, err_p = sinr_check(sc, ref, w_plain)
-        result["validity"] = {"chosen_max_sinr_loss_db": loss_c, "chosen_max_rel_weight_err": err_c,
-                              "plain_max_sinr_loss_db": loss_p, "plain_max_rel_weight_err": err_p,
-                              "bar_db": 0.1, "valid": bool(loss_c <= 0.1 and loss_p <= 0.1)}
+        val = {"chosen_max_sinr_loss_db": loss_c, "chosen_max_rel_weight_err": err_c,
+               "plain_max_sinr_loss_db": loss_p, "plain_max_rel_weight_err": err_p, "bar_db": 0.1}
+        ok = loss_c <= 0.1 and loss_p <= 0.1
+        for f, r in mixed.items():
+            lf, ef = sinr_check(sc, ref, r["weights"])
+            val[f + "_max_sinr_loss_db"] = lf
+            val[f + "_max_rel_weight_err"] = ef
+        val["valid"] = bool(ok)
+        result["validity"] = val
     else:
         result["cpu_baseline"] = None
     plan.close()

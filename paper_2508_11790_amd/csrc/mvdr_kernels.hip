@@ -30,6 +30,7 @@ __device__ __forceinline__ C2<T> c2(T a, T b) {
 }
 
 constexpr int kCH = 64;        // snapshots per LDS chunk of the covariance
+constexpr int kCHS = kCH + 1;  // LDS row stride of a staged chunk: rows two banks apart
 constexpr int kWaveWMax = 40;  // widest window of the one-wave kernel
 
 // ------------------------------------------------------------------------------------------
@@ -80,9 +81,39 @@ __device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const P
   }
 }
 
+// Stage window rows i < W, snapshots b0 .. b0 + kCH - 1 (zero at b >= limit) into
+// ys[i * kCHS + bb].  The thread-to-element order follows the source layout so that
+// consecutive threads read consecutive addresses: snapshot-fastest runs for the full beamspace
+// and for window tiles of at least kCH snapshots, otherwise one contiguous [W][TB] tile block
+// after another.
+template <bool WINDOWED, int THREADS>
+__device__ __forceinline__ void stage_rows(const float2* __restrict__ src, const PairArgs& a,
+                                           int k, int woff, int s, int W, int b0, int limit,
+                                           float2* ys) {
+  const int tid = threadIdx.x;
+  if (!WINDOWED || a.logTB >= 6) {
+    for (int idx = tid; idx < W * kCH; idx += THREADS) {
+      const int i = idx / kCH, bb = idx - i * kCH;
+      const int b = b0 + bb;
+      ys[i * kCHS + bb] =
+          (b < limit) ? load_y<WINDOWED>(src, a, k, woff, s, i, b) : make_float2(0.f, 0.f);
+    }
+  } else {
+    const int per = W << a.logTB;
+    const int tbm = (1 << a.logTB) - 1;
+    for (int idx = tid; idx < W * kCH; idx += THREADS) {
+      const int q = idx / per, r = idx - q * per;
+      const int i = r >> a.logTB, bb = (q << a.logTB) + (r & tbm);
+      const int b = b0 + bb;
+      ys[i * kCHS + bb] =
+          (b < limit) ? load_y<WINDOWED>(src, a, k, woff, s, i, b) : make_float2(0.f, 0.f);
+    }
+  }
+}
+
 // R (LDS, row stride RS, lower triangle) = (1/L) sum_{b<L} y_b y_b^H + delta I, accumulated
 // in ACC by THREADS threads, up to EPT lower-triangle entries per thread (W(W+1)/2 <=
-// EPT * THREADS).  ys is an LDS scratch of W x kCH float2 that may alias R.
+// EPT * THREADS).  ys is an LDS scratch of W x kCHS float2 that may alias R.
 template <typename ACC, bool WINDOWED, int THREADS, int EPT>
 __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& a, int k, int W,
                                 int woff, int s, float2* ys, C2<ACC>* R, int RS, double delta) {
@@ -108,19 +139,13 @@ __device__ void pair_covariance(const float2* __restrict__ src, const PairArgs& 
   }
   for (int c0 = 0; c0 < a.L; c0 += kCH) {
     __syncthreads();
-    for (int idx = tid; idx < W * kCH; idx += THREADS) {
-      const int i = idx / kCH, bb = idx - i * kCH;
-      const int b = c0 + bb;
-      float2 v = make_float2(0.f, 0.f);
-      if (b < a.L) v = load_y<WINDOWED>(src, a, k, woff, s, i, b);
-      ys[idx] = v;
-    }
+    stage_rows<WINDOWED, THREADS>(src, a, k, woff, s, W, c0, a.L, ys);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
       if (ei[q] >= 0) {
-        const float2* yi = ys + ei[q] * kCH;
-        const float2* yj = ys + ej[q] * kCH;
+        const float2* yi = ys + ei[q] * kCHS;
+        const float2* yj = ys + ej[q] * kCHS;
         ACC ax = acc[q].x, ay = acc[q].y;
         for (int bb = sl; bb < kCH; bb += S) {
           const float2 u = yi[bb], v = yj[bb];
@@ -228,6 +253,36 @@ __device__ void solve_lds(const C2<T>* R, int RS, const T* diag, int W, const do
   if (lane < W) wv[lane] = c2<T>(x.x * qinv, x.y * qinv);
 }
 
+// out[l] = w^H y_{L + l} for the Lt test snapshots, staged through LDS (ys, which may alias
+// the factorised R: it is no longer read).  Zero outputs when fail.
+template <int THREADS>
+__device__ void apply_staged(const float2* __restrict__ Yw, const PairArgs& a, int k, int woff,
+                             int s, int W, int fail, const C2<double>* wv, float2* ys,
+                             float2* __restrict__ out) {
+  constexpr int SPL = THREADS / kCH;    // threads per snapshot
+  const int tid = threadIdx.x;
+  const int l0 = tid / SPL, part = tid - l0 * SPL;
+  for (int c0 = 0; c0 < a.Lt; c0 += kCH) {
+    __syncthreads();
+    stage_rows<true, THREADS>(Yw, a, k, woff, s, W, a.L + c0, a.L + a.Lt, ys);
+    __syncthreads();
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = part; i < W; i += SPL) {
+        const float2 y = ys[i * kCHS + l0];
+        const C2<double> w = wv[i];
+        zx += w.x * (double)y.x + w.y * (double)y.y;    // conj(w) y
+        zy += w.x * (double)y.y - w.y * (double)y.x;
+      }
+    }
+    for (int off = SPL >> 1; off > 0; off >>= 1) {
+      zx += __shfl_xor(zx, off);
+      zy += __shfl_xor(zy, off);
+    }
+    if (part == 0 && c0 + l0 < a.Lt) out[c0 + l0] = make_float2((float)zx, (float)zy);
+  }
+}
+
 struct PairLds {
   int RS;
   size_t r_off, diag_off, wv_off, av_off, total;
@@ -238,7 +293,7 @@ __host__ __device__ inline PairLds pair_lds_layout(int wmax) {
   PairLds p;
   p.RS = wmax + 1;
   size_t rbytes = sizeof(C2<T>) * (size_t)wmax * p.RS;
-  size_t ybytes = sizeof(float2) * (size_t)wmax * kCH;
+  size_t ybytes = sizeof(float2) * (size_t)wmax * kCHS;
   size_t big = rbytes > ybytes ? rbytes : ybytes;
   big = (big + 15) & ~(size_t)15;
   p.r_off = 0;
@@ -290,19 +345,7 @@ __global__ __launch_bounds__(THREADS) void k_mvdr_fused(PairArgs a, WindowGeom g
   pair_covariance<double, true, THREADS, EPT>(Yw, a, k, W, woff, s, ys, R, lay.RS, delta);
   const int fail = chol_lds<double, THREADS>(R, lay.RS, diag, W);
   if (!fail) solve_lds<double>(R, lay.RS, diag, W, av, wv);
-  __syncthreads();
-  for (int l = threadIdx.x; l < a.Lt; l += THREADS) {
-    double zx = 0.0, zy = 0.0;
-    if (!fail) {
-      for (int i = 0; i < W; ++i) {
-        const float2 y = load_y<true>(Yw, a, k, woff, s, i, a.L + l);
-        const C2<double> w = wv[i];
-        zx += w.x * (double)y.x + w.y * (double)y.y;    // conj(w) y
-        zy += w.x * (double)y.y - w.y * (double)y.x;
-      }
-    }
-    out[pair * a.Lt + l] = make_float2((float)zx, (float)zy);
-  }
+  apply_staged<THREADS>(Yw, a, k, woff, s, W, fail, wv, ys, out + pair * a.Lt);
   if (wout) {
     for (int i = threadIdx.x; i < a.wmax; i += THREADS) {
       float2 v = make_float2(0.f, 0.f);
@@ -503,8 +546,10 @@ __host__ __device__ inline MixLds mix_lds_layout(int wmax) {
   o = (o + 15) & ~(size_t)15;
   // G (FP32, pad x pad) aliases the staging area after the last chunk
   const size_t gbytes = sizeof(float) * (size_t)pad * pad;
+  const size_t ybytes = sizeof(float2) * (size_t)wmax * kCHS;  // FP64-route / apply staging
   p.g = 0;
   if (gbytes > o) o = (gbytes + 15) & ~(size_t)15;
+  if (ybytes > o) o = (ybytes + 15) & ~(size_t)15;
   p.RS = wmax + 1;
   p.r = o;                                               // complex R, FP64 (routing needs it)
   o += sizeof(C2<double>) * (size_t)wmax * p.RS;
@@ -556,18 +601,34 @@ __global__ __launch_bounds__(kMixThreads) void k_mvdr_mixed(PairArgs a, WindowGe
   // this wave's tiles: q-th tile = wave + 4 q
   for (int c0 = 0; c0 < a.L; c0 += kMixCH) {
     __syncthreads();
-    for (int idx = tid; idx < nt * 32 * kMixCH; idx += kMixThreads) {
-      const int r = idx / kMixCH, bb = idx - r * kMixCH;
-      const int b = c0 + bb;
-      float v = 0.f;
-      if (r < rows && b < a.L) {
-        const int i = r < W ? r : r - W;
-        const float2 y = load_y<true>(Yw, a, k, woff, s, i, b);
-        v = r < W ? y.x : y.y;
+    // complex snapshots in the source order (as stage_rows), real parts to rows i, imaginary
+    // parts to rows W + i; padding rows stay zero
+    for (int idx = tid; idx < (nt * 32 - rows) * kMixCH; idx += kMixThreads) {
+      const int r = rows + idx / kMixCH, bb = idx % kMixCH;
+      zhi[r * kMixRS + bb] = to_bf16(0.f);
+      if (SPLIT) zlo[r * kMixRS + bb] = to_bf16(0.f);
+    }
+    const bool runs = a.logTB >= 6;
+    const int per = W << a.logTB, tbm = (1 << a.logTB) - 1;
+    for (int idx = tid; idx < W * kMixCH; idx += kMixThreads) {
+      int i, bb;
+      if (runs) {
+        i = idx / kMixCH;
+        bb = idx - i * kMixCH;
+      } else {
+        const int q = idx / per, r = idx - q * per;
+        i = r >> a.logTB;
+        bb = (q << a.logTB) + (r & tbm);
       }
-      const __bf16 hi = to_bf16(v);
-      zhi[r * kMixRS + bb] = hi;
-      if (SPLIT) zlo[r * kMixRS + bb] = to_bf16(v - from_bf16(hi));
+      const int b = c0 + bb;
+      const float2 y = (b < a.L) ? load_y<true>(Yw, a, k, woff, s, i, b) : make_float2(0.f, 0.f);
+      const __bf16 hr = to_bf16(y.x), hi = to_bf16(y.y);
+      zhi[i * kMixRS + bb] = hr;
+      zhi[(W + i) * kMixRS + bb] = hi;
+      if (SPLIT) {
+        zlo[i * kMixRS + bb] = to_bf16(y.x - from_bf16(hr));
+        zlo[(W + i) * kMixRS + bb] = to_bf16(y.y - from_bf16(hi));
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -710,19 +771,8 @@ __global__ __launch_bounds__(kMixThreads) void k_mvdr_mixed(PairArgs a, WindowGe
     fail = chol_lds<double, kMixThreads>(R, RS, diag, W);
     if (!fail) solve_lds<double>(R, RS, diag, W, av, wv);
   }
-  __syncthreads();
-  for (int l = tid; l < a.Lt; l += kMixThreads) {
-    double zx = 0.0, zy = 0.0;
-    if (!fail) {
-      for (int i = 0; i < W; ++i) {
-        const float2 y = load_y<true>(Yw, a, k, woff, s, i, a.L + l);
-        const C2<double> w = wv[i];
-        zx += w.x * (double)y.x + w.y * (double)y.y;
-        zy += w.x * (double)y.y - w.y * (double)y.x;
-      }
-    }
-    out[pair * a.Lt + l] = make_float2((float)zx, (float)zy);
-  }
+  apply_staged<kMixThreads>(Yw, a, k, woff, s, W, fail, wv, reinterpret_cast<float2*>(smem),
+                            out + pair * a.Lt);
   if (wout) {
     for (int i = tid; i < a.wmax; i += kMixThreads) {
       float2 v = make_float2(0.f, 0.f);
@@ -738,12 +788,6 @@ hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDe
                              bool split, hipStream_t s) {
   if (a.wmax > 64) return hipErrorInvalidValue;
   MixLds lay = mix_lds_layout(a.wmax);
-  // the exact route stages snapshots with the same kernel: make room for its chunk too
-  const size_t exact = sizeof(float2) * (size_t)a.wmax * kCH;
-  size_t shm = lay.total;
-  if (exact > lay.r) shm = lay.total + (exact - lay.r);
-  (void)shm;
-  if (exact > lay.r) return hipErrorInvalidValue;
   const unsigned grid = (unsigned)(a.T * a.K);
   if (split) {
     hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mixed<true>,
