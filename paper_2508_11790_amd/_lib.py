@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "libwbmvdr.so")
 WBM_HALF_BIN = 1
 FORM_PLAIN, FORM_FUSED, FORM_GRAPH, FORM_MIXED, FORM_MIXED_BF16 = 0, 1, 2, 3, 4
 INFO_ROUTED = 1 << 30
+PAIR_MFMA, PAIR_WAVE, PAIR_BLOCK = 1, 64, 256
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "out of memory",
           4: "HIP runtime error", 5: "unsupported"}
 
@@ -31,7 +32,8 @@ class WbmError(RuntimeError):
         self.status = status
 
 
-EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes", "wbm_beamform",
+EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes",
+           "wbm_plan_set_tuning", "wbm_plan_get_tuning", "wbm_beamform",
            "wbm_channelize", "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times",
            "wbm_profiles", "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr",
            "wbm_mlp_create", "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
@@ -55,6 +57,8 @@ def load() -> C.CDLL:
     lib.wbm_plan_destroy.argtypes = [P]
     lib.wbm_plan_workspace_bytes.argtypes = [P]
     lib.wbm_plan_workspace_bytes.restype = I64
+    lib.wbm_plan_set_tuning.argtypes = [P, I32, I32, I32]
+    lib.wbm_plan_get_tuning.argtypes = [P, P, P, P]
     lib.wbm_beamform.argtypes = [P, P, P, P, I32, D, I32, P, P, P, P, P]
     lib.wbm_channelize.argtypes = [P, P, P, P]
     lib.wbm_beamspace.argtypes = [P, P, P, P]

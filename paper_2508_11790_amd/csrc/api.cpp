@@ -2,6 +2,7 @@
 // management, per-call target description upload and the launch sequences.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -67,7 +68,7 @@ struct wbm_plan {
   int64_t S = 0;
   int logTB = 0, TB = 0, nbt = 0;     // beamspace tile (snapshots per workgroup) of the fused form
   int chan_logtile = 12, beam_logtile = 12;
-  int pair_threads = 256;             // threads per (target, subband) pair of the fused MVDR
+  int pair_threads = WBM_PAIR_MFMA;   // fused MVDR pair kernel: WBM_PAIR_*
   bool tuned = false;
   int device = 0;
   // tables
@@ -179,6 +180,7 @@ wbm_status upload_desc(wbm_plan* p, const double* az_rad, const int32_t* win, in
   int* wv = reinterpret_cast<int*>(p->desc_host + sizeof(double) * Tm);
   int* woff = wv + Tm;
   int* rowtab = woff + Tm;
+  int* torder = rowtab + (size_t)Tm * c.w_max;
   int sumW = 0;
   for (int t = 0; t < T; ++t) {
     sin_az[t] = std::sin(az_rad[t]);
@@ -187,7 +189,11 @@ wbm_status upload_desc(wbm_plan* p, const double* az_rad, const int32_t* win, in
     woff[t] = sumW;
     for (int i = 0; i < W; ++i) rowtab[sumW + i] = (t << 8) | i;
     sumW += W;
+    torder[t] = t;
   }
+  // pair kernels take the widest windows first (longest-processing-time order): workgroups
+  // are handed out in index order, so the expensive pairs start early and spread evenly
+  std::stable_sort(torder, torder + T, [wv](int x, int y) { return wv[x] > wv[y]; });
   WBM_HIP(hipMemcpyAsync(p->desc_dev, p->desc_host, p->desc_bytes, hipMemcpyHostToDevice, st),
           "descriptor upload");
   WBM_HIP(hipEventRecord(p->desc_evt, st), "descriptor event");
@@ -296,7 +302,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max;
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p2";
   return os.str();
 }
 
@@ -307,7 +313,8 @@ std::string cache_path() {
   return std::string(home ? home : "/tmp") + "/.cache/wbmvdr/autotune.json";
 }
 
-// The cache file is a flat JSON object {"key": [chan_logtile, beam_logtile, pair_threads], ...}.
+// The cache file is a flat JSON object {"key": [chan_logtile, beam_logtile, pair_kernel], ...}
+// (pair_kernel: 1 = FP64 matrix-core kernel, 64 / 256 = vector kernel with that many threads).
 bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr) {
   std::ifstream f(cache_path());
   if (!f) return false;
@@ -320,7 +327,7 @@ bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr) {
   int a = 0, b = 0, c = 0;
   if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d", &a, &b, &c) != 3) return false;
   if (!wbm::fft_logtile_supported(a) || !wbm::fft_logtile_supported(b)) return false;
-  if (c != 64 && c != 256) return false;
+  if (c != WBM_PAIR_MFMA && c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK) return false;
   *chan = a;
   *beam = b;
   *thr = c;
@@ -386,7 +393,7 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   const char* env = std::getenv("WBM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
   const std::string key = tune_key(p);
-  int chan = 12, beam = 12, thr = 256;
+  int chan = 12, beam = 12, thr = WBM_PAIR_MFMA;
   if (cache_lookup(key, &chan, &beam, &thr)) {
     p->chan_logtile = chan;
     set_beam_tile(p, beam);
@@ -418,8 +425,8 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   if (e != hipSuccess) return e;
   float best_p = 1e30f;
   const wbm::PairArgs pa = pair_args(p, T, sumW, loading);
-  for (int thr_c : {256, 64}) {
-    if (thr_c == 64 && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
+  for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE}) {
+    if (thr_c == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
     float ms;
     e = time_best([&]() {
       return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
@@ -435,6 +442,8 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   cache_store(key, chan, beam, thr);
   return hipSuccess;
 }
+
+static_assert(WBM_PAIR_MFMA == wbm::kPairMfma, "pair kernel ids");
 
 wbm_status check_plan(const wbm_plan* p) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
@@ -464,6 +473,30 @@ const char* wbm_status_str(wbm_status s) {
 }
 
 int64_t wbm_plan_workspace_bytes(const wbm_plan* p) { return p ? p->ws_bytes : 0; }
+
+wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t pair) {
+  if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
+  if (!wbm::fft_logtile_supported(chan) || !wbm::fft_logtile_supported(beam))
+    return fail(WBM_ERR_ARG, "FFT tile log2 must be 11, 12 or 13");
+  if (pair != WBM_PAIR_MFMA && pair != WBM_PAIR_WAVE && pair != WBM_PAIR_BLOCK)
+    return fail(WBM_ERR_ARG, "pair_kernel must be WBM_PAIR_MFMA, WBM_PAIR_WAVE or WBM_PAIR_BLOCK");
+  if (pair == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max))
+    return fail(WBM_ERR_UNSUPPORTED, "the one-wave pair kernel needs w_max <= 40");
+  p->chan_logtile = chan;
+  set_beam_tile(p, beam);
+  p->pair_threads = pair;
+  p->tuned = true;
+  p->gkey.valid = false;
+  return WBM_OK;
+}
+
+wbm_status wbm_plan_get_tuning(const wbm_plan* p, int32_t* chan, int32_t* beam, int32_t* pair) {
+  if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
+  if (chan) *chan = p->chan_logtile;
+  if (beam) *beam = p->beam_logtile;
+  if (pair) *pair = p->pair_threads;
+  return WBM_OK;
+}
 
 wbm_status wbm_plan_destroy(wbm_plan* p) {
   if (!p) return WBM_OK;
@@ -547,6 +580,7 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   p->dd.win = reinterpret_cast<const int*>(p->desc_dev + sizeof(double) * Tm);
   p->dd.woff = p->dd.win + Tm;
   p->dd.rowtab = p->dd.woff + Tm;
+  p->dd.torder = p->dd.rowtab + (size_t)Tm * c.w_max;
 
   const size_t NS = (size_t)c.n_elem * p->S;
   if ((s = dev_alloc(p, &p->X, NS, "channelized X"))) return bail(s);
@@ -710,7 +744,7 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   for (int i = 0; i < 5; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
   double acc[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
-  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+  for (int r = -1; r < reps && e == hipSuccess; ++r) {   // r = -1: untimed warm-up
     e = hipEventRecord(ev[0], st);
     if (e == hipSuccess) e = wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
@@ -723,7 +757,7 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
                                  p->prof_out, p->prof_w, nullptr, p->prof_info, p->pair_threads, st);
     if (e == hipSuccess) e = hipEventRecord(ev[4], st);
     if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    for (int i = 0; i < 4 && e == hipSuccess && r >= 0; ++i) {
       float ms = 0.f;
       e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
       acc[i] += ms;

@@ -18,9 +18,10 @@ __host__ __device__ constexpr int fft_threads(int logn, int logtile) {
   return (1 << fft_tile(logn, logtile)) / 8;
 }
 
-// x [N][S] (S = B*K) -> X [K][B][N].  Workgroup = (TE = tile/K elements, block b).  Rows
-// e >= N are zero-filled and not written.  Optional pre-twiddle hb[tau] (half-bin centres).
-// Output scaled by K^-1/2 (unitary DFT).
+// x [N][S] (S = B*K) -> X [K][B][N].  Workgroup = (TE = tile/K elements, blocks b =
+// blockIdx.y, blockIdx.y + gridDim.y, ...).  Rows e >= N are zero-filled and not written.
+// Optional pre-twiddle hb[tau] (half-bin centres).  Output scaled by K^-1/2 (unitary DFT).
+// The next block's samples are fetched into registers while the current block is transformed.
 template <int LOGK, int LOGT>
 __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
     const float2* __restrict__ x, float2* __restrict__ X, int N, int B, int64_t S,
@@ -30,28 +31,51 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
   constexpr int LOGTE = fft_tile(LOGK, LOGT) - LOGK;
   __shared__ float2 lds[F::lds_complex];
   const int e0 = blockIdx.x * TE;
-  const int b = blockIdx.y;
-  float2 v[8];
+  float2 tr[F::NPA][7];
+  F::load_twiddles(tr, twK);
+  float2 hv[8];
 #pragma unroll
   for (int p = 0; p < 8 / F::R0; ++p) {
 #pragma unroll
     for (int r = 0; r < F::R0; ++r) {
       int row, tau;
       F::first_input(p, r, row, tau);
-      float2 val = make_float2(0.f, 0.f);
-      if (e0 + row < N) {
-        val = x[(int64_t)(e0 + row) * S + (int64_t)b * K + tau];
-        if (hb) val = cmul(val, hb[tau]);
-      }
-      v[p * F::R0 + r] = val;
+      hv[p * F::R0 + r] = hb ? hb[tau] : make_float2(1.f, 0.f);
     }
   }
-  F::run(v, lds, twK);
+  auto fetch = [&](int b, float2 (&v)[8]) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int idx = threadIdx.x + q * F::threads;
-    const int k = idx >> LOGTE, e = idx & (TE - 1);
-    if (e0 + e < N) X[((int64_t)k * B + b) * N + e0 + e] = cscale(lds[F::addr(e, k)], scale);
+    for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        int row, tau;
+        F::first_input(p, r, row, tau);
+        float2 val = make_float2(0.f, 0.f);
+        if (e0 + row < N) val = x[(int64_t)(e0 + row) * S + (int64_t)b * K + tau];
+        v[p * F::R0 + r] = val;
+      }
+    }
+  };
+  float2 nv[8];
+  int b = blockIdx.y;
+  if (b < B) fetch(b, nv);
+  for (; b < B; b += gridDim.y) {
+    float2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = nv[q];
+    if (b + (int)gridDim.y < B) fetch(b + gridDim.y, nv);
+    if (hb) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = cmul(v[q], hv[q]);
+    }
+    F::run(v, lds, tr);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + q * F::threads;
+      const int k = idx >> LOGTE, e = idx & (TE - 1);
+      if (e0 + e < N) X[((int64_t)k * B + b) * N + e0 + e] = cscale(lds[F::addr(e, k)], scale);
+    }
+    __syncthreads();   // the next block's first pass overwrites lds
   }
 }
 
@@ -61,7 +85,8 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
 //   prof  : per-target training power profile partials [K][gridDim.x][T][64]: sum over this
 //           workgroup's training snapshots (b < L) of |Y|^2 at bins c_tk - 32 .. c_tk + 31
 //           (mod M), c_tk = floor(u_tk + 1/2) the target's beam bin.
-// Workgroup = (first snapshot tile, subband k); it loops over tiles j, j + gridDim.x, ...
+// Workgroup = (first snapshot tile, subband k); it loops over tiles j, j + gridDim.x, ...,
+// fetching the next tile's inputs into registers while the current one is transformed.
 // With windows or profiles the first threads place the targets of subband k (same FP64
 // evaluation as the steering kernel) into LDS.
 template <int LOGM, int LOGT>
@@ -76,23 +101,14 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   extern __shared__ int s_dyn[];
   int* s_start = s_dyn;                                    // [T] window starts of subband k
   int* s_center = s_dyn + g.T;                             // [T] beam bins (profile centre)
-  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);  // [T][64] profile sums
+  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);  // [T][64] profile sums (prof)
+  int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);      // [sumW] bin of window row r (Yw)
   const int k = blockIdx.y;
   const int nbt = (B + TB - 1) / TB;
-  if (Yw || prof) {
-    for (int t = threadIdx.x; t < g.T; t += F::threads) {
-      double u;
-      int s;
-      window_of(g, t, k, &u, &s);
-      s_start[t] = s;
-      if (prof) s_center[t] = (int)floor(u + 0.5);
-    }
-    if (prof)
-      for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
-  }
-  for (int j = blockIdx.x; j < nbt; j += gridDim.x) {
+  float2 tr[F::NPA][7];
+  F::load_twiddles(tr, twM);
+  auto fetch = [&](int j, float2 (&v)[8]) {
     const int b0 = j * TB;
-    float2 v[8];
 #pragma unroll
     for (int p = 0; p < 8 / F::R0; ++p) {
 #pragma unroll
@@ -104,7 +120,34 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
         v[p * F::R0 + r] = val;
       }
     }
-    F::run(v, lds, twM);
+  };
+  float2 nv[8];
+  if ((int)blockIdx.x < nbt) fetch(blockIdx.x, nv);
+  if (Yw || prof) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) {
+      double u;
+      int s;
+      window_of(g, t, k, &u, &s);
+      s_start[t] = s;
+      if (prof) s_center[t] = (int)floor(u + 0.5);
+    }
+    if (prof)
+      for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
+    if (Yw) {
+      __syncthreads();
+      for (int r = threadIdx.x; r < sumW; r += F::threads) {
+        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+        s_bin[r] = (s_start[t] + i) & (M - 1);
+      }
+    }
+  }
+  for (int j = blockIdx.x; j < nbt; j += gridDim.x) {
+    const int b0 = j * TB;
+    float2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = nv[q];
+    if (j + (int)gridDim.x < nbt) fetch(j + gridDim.x, nv);
+    F::run(v, lds, tr);
     if (Y) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -118,9 +161,7 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
       const int tot = sumW * TB;
       for (int idx = threadIdx.x; idx < tot; idx += F::threads) {
         const int r = idx >> LOGTB, b = idx & (TB - 1);
-        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-        const int m = (s_start[t] + i) & (M - 1);
-        dst[idx] = cscale(lds[F::addr(b, m)], scale);
+        dst[idx] = cscale(lds[F::addr(b, s_bin[r])], scale);
       }
     }
     if (prof && b0 < L) {
@@ -151,13 +192,35 @@ static int ilog2(int v) {
   return l;
 }
 
+// Workgroups the device holds at once for a kernel (occupancy x compute units), cached per
+// instantiation; the FFT kernels loop over their tiles with a grid of about this size.
+template <class KERN>
+static int resident_blocks(KERN kernel, int threads, size_t dyn_shm, int* cache) {
+  if (*cache > 0) return *cache;
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, dyn_shm) !=
+          hipSuccess || per_cu < 1 || cus < 1) {
+    (void)hipGetLastError();
+    return 2048;
+  }
+  *cache = per_cu * cus;
+  return *cache;
+}
+
 template <int LOGK, int LOGT>
 static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const float2* twK,
                               const float2* hb, hipStream_t s) {
   using F = Fft<LOGK, fft_tile(LOGK, LOGT)>;
-  dim3 grid((N + F::rows - 1) / F::rows, B);
-  hipLaunchKernelGGL((k_channelize<LOGK, LOGT>), grid, dim3(F::threads), 0, s, x, X, N, B,
-                     (int64_t)B * F::n, twK, hb, 1.0f / sqrtf((float)F::n));
+  static int resident = 0;
+  const int gx = (N + F::rows - 1) / F::rows;
+  const int cap = resident_blocks(k_channelize<LOGK, LOGT>, F::threads, 0, &resident);
+  int gy = (cap + gx - 1) / gx;
+  if (gy > B) gy = B;
+  if (gy < 1) gy = 1;
+  hipLaunchKernelGGL((k_channelize<LOGK, LOGT>), dim3(gx, gy), dim3(F::threads), 0, s, x, X, N,
+                     B, (int64_t)B * F::n, twK, hb, 1.0f / sqrtf((float)F::n));
   return hipGetLastError();
 }
 
@@ -167,20 +230,27 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
                               const WindowGeom& g, float* prof, int L, int G, hipStream_t s) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
   const int nbt = (B + F::rows - 1) / F::rows;
-  const int gx = prof ? G : nbt;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
-  dim3 grid(gx, K);
   size_t shm = 0;
   if (Yw || prof) shm = sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
+  if (Yw) shm += sizeof(int) * (size_t)sumW;
   if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
     // beyond the default 64 KiB per workgroup: ask for exactly the dynamic part
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LOGM, LOGT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), grid, dim3(F::threads), shm, s, X, Y, Yw, N, B,
-                     K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L);
+  int gx = G;
+  if (!prof) {
+    static int resident = 0;
+    const int cap = resident_blocks(k_beamspace<LOGM, LOGT>, F::threads, shm, &resident);
+    gx = (cap + K - 1) / K;
+    if (gx > nbt) gx = nbt;
+    if (gx < 1) gx = 1;
+  }
+  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), dim3(gx, K), dim3(F::threads), shm, s, X, Y, Yw, N,
+                     B, K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L);
   return hipGetLastError();
 }
 

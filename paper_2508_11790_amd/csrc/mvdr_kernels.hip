@@ -1,15 +1,16 @@
 // Window placement / windowed steering, and the per-(target, subband) reduced-dimension MVDR
-// kernels for gfx950: loaded W x W sample covariance (Eq. 11), Cholesky factorisation, the
-// two triangular solves giving c = R^-1 a / (a^H R^-1 a) (Eq. 13 / Eq. 20) and the beam
-// output c^H y on the test snapshots.
+// kernels for gfx950: loaded W x W sample covariance (Eq. 11), its factorisation, the two
+// triangular solves giving c = R^-1 a / (a^H R^-1 a) (Eq. 13 / Eq. 20) and the beam output
+// c^H y on the test snapshots.
 //
-// Fused form: one workgroup per pair runs everything, placing its window and evaluating its
-// steering vector itself; the covariance accumulates exact FP32 x FP32 products in FP64 and
-// the Cholesky / solves run in FP64 (window covariances next to strong interferers reach
-// condition numbers ~1e6, where FP32 accumulation loses the weights).  Windows up to 40 bins
-// run one wave64 per pair; wider windows run four waves per pair.
+// Fused forms: one workgroup per pair runs everything, placing its window and evaluating its
+// steering vector itself; the covariance accumulates exact FP32 x FP32 products in FP64 and the
+// LDL^H factorisation and solves run in FP64 (window covariances next to strong interferers
+// reach condition numbers ~1e6, where FP32 accumulation loses the weights).  Variants: four
+// waves or one wave per pair on the vector units, four waves on the FP64 matrix cores.
 // Plain form: the same steps as three FP32 launches with R and c in HBM, gathering the window
 // rows from the full beamspace.
+// Mixed form (end of file): BF16 matrix-core covariance, FP32 Cholesky, FP64 refinement.
 #include <math.h>
 
 #include "wbm_dev.h"
@@ -67,6 +68,23 @@ __device__ __forceinline__ void tri_index(int e, int& i, int& j) {
   while (ii * (ii + 1) / 2 > e) --ii;
   i = ii;
   j = e - ii * (ii + 1) / 2;
+}
+
+// Workgroup -> (target, subband) of the pair kernels.  Workgroups go round-robin to the eight
+// XCDs (workgroup id mod 8), so with K a multiple of 8 XCD x takes subbands k = x mod 8, all
+// targets of a subband back to back (they read the same window tile blocks through one L2),
+// widest windows first (d.torder); otherwise targets widest first, subbands fastest.  Either
+// way the costly pairs are dispatched first.
+__device__ __forceinline__ void pair_of_block(const PairArgs& a, const DevDesc& d, int& t, int& k) {
+  const int p = blockIdx.x;
+  if ((a.K & 7) == 0) {
+    const int slot = p >> 3;
+    t = d.torder[slot % a.T];
+    k = ((slot / a.T) << 3) + (p & 7);
+  } else {
+    t = d.torder[p / a.K];
+    k = p % a.K;
+  }
 }
 
 // Snapshot b of window row i of pair (t, k).
@@ -304,25 +322,431 @@ __host__ __device__ inline PairLds pair_lds_layout(int wmax) {
   return p;
 }
 
-// ------------------------------------------------------------------------------------------
-// Fused form: one workgroup of THREADS per pair p = k * T + t.
-template <int THREADS, int EPT>
-__global__ __launch_bounds__(THREADS) void k_mvdr_fused(PairArgs a, WindowGeom g, DevDesc d,
-                                                        const float2* __restrict__ Yw,
-                                                        float2* __restrict__ out,
-                                                        float2* __restrict__ wout,
-                                                        int* __restrict__ starts_out,
-                                                        int* __restrict__ info) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const PairLds lay = pair_lds_layout<double>(a.wmax);
-  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r_off);
-  float2* ys = reinterpret_cast<float2*>(smem + lay.r_off);
-  double* diag = reinterpret_cast<double*>(smem + lay.diag_off);
-  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv_off);
-  double2* av = reinterpret_cast<double2*>(smem + lay.av_off);
+bool mvdr_wave_supported(int wmax) { return wmax <= kWaveWMax; }
 
-  const int p = blockIdx.x;
-  const int k = p / a.T, t = p - k * a.T;
+hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                            const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                            hipStream_t s);
+hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                              int threads, hipStream_t s);
+
+hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                             int threads, hipStream_t s) {
+  if (threads == kPairMfma) return launch_mvdr_mfma(a, g, d, Yw, out, wout, starts, info, s);
+  if (threads == 256 || (threads == 64 && a.wmax <= kWaveWMax))
+    return launch_mvdr_vector(a, g, d, Yw, out, wout, starts, info, threads, s);
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused pair kernels, second generation.  One workgroup of TH threads per (target, subband)
+// pair, in chunks of CH = TH / 4 training snapshots staged through LDS, the next chunk already
+// in flight in registers (after the last training chunk, the first test chunk), each thread's
+// chunk elements mapped once per pair:
+//   - vector form (TH = 256: four waves per pair; TH = 64: one wave per pair, more pairs per
+//     CU): the loaded covariance on the FP64 vector units, a thread owning a BS x BS block of
+//     the lower triangle and an interleaved slice of the chunk's snapshots;
+//   - matrix-core form (TH = 256): with Z = [Re Y; Im Y] (2W x L) the real Gram G = Z Z^T
+//     carries the covariance, Re R_ij = G_ij + G_{W+i,W+j}, Im R_ij = G_{W+i,j} - G_{W+j,i};
+//     G's lower 16 x 16 tiles accumulate on v_mfma_f64_16x16x4f64, the four waves splitting
+//     tiles (TG groups) and snapshot steps (4 / TG slices, summed in slice order).
+// Either way the FP32 snapshots' products are exact in FP64 and every sum is FP64; results
+// are deterministic.  Then an LDL^H factorisation (one barrier per column), the solves of
+// Eq. 13 / Eq. 20 in FP64 on one wave, and the beam outputs on the test snapshots.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kXRSP = 64 + 4;   // float row stride of the matrix-core form's staged planes:
+                                // an operand's 16 rows x 4 steps hit distinct banks
+
+// Register budgets for windows up to WCAP bins and TH threads: Gram tiles per wave (matrix
+// cores), staged elements per thread and chunk, covariance entries per thread (matrix cores).
+template <int WCAP, int TH>
+struct XCap {
+  static constexpr int CH = TH / 4;
+  static constexpr int kMaxT = WCAP <= 40 ? 4 : 9;
+  static constexpr int kPre = (WCAP * CH + TH - 1) / TH;
+  static constexpr int kEnt = (WCAP * (WCAP + 1) / 2 + TH - 1) / TH;
+};
+
+struct XLds {
+  size_t region, diag, wv, av, red, total;
+  int RS;
+};
+
+// LDS of the pair kernels: one region reused by the staged chunks, the Gram tiles (matrix
+// cores) and the complex R, then the pivots, weights, steering vector and the apply's partial
+// sums.
+template <bool MF, int TH>
+__host__ __device__ inline XLds x_lds_layout(int wmax) {
+  constexpr int CH = TH / 4;
+  XLds p;
+  p.RS = wmax + 1;
+  const size_t r = sizeof(C2<double>) * (size_t)wmax * p.RS;          // complex R (lower)
+  size_t big = r;
+  if (MF) {
+    const int pad = (2 * wmax + 15) / 16 * 16;
+    const int nt = pad / 16;
+    const size_t z = sizeof(float) * (size_t)pad * kXRSP;              // staged chunk planes
+    const size_t gram = sizeof(double) * 256 * (size_t)(nt * (nt + 1) / 2);
+    if (z > big) big = z;
+    if (gram > big) big = gram;
+  } else {
+    const size_t zf = sizeof(float2) * (size_t)((wmax + 3) / 4 * 4) * (CH + 1);
+    if (zf > big) big = zf;
+  }
+  p.region = 0;
+  p.diag = (big + 15) & ~(size_t)15;
+  p.wv = p.diag + sizeof(double) * 64;
+  p.av = p.wv + sizeof(C2<double>) * 64;
+  p.red = p.av + sizeof(double2) * 64;
+  p.total = p.red + sizeof(double2) * 4 * CH;
+  return p;
+}
+
+// Tile groups for ntiles lower tiles: the fewest MFMAs on the busiest wave, ties to more
+// groups (fewer slices to sum), at most maxt tiles per wave.
+__device__ __forceinline__ int mfma_tile_groups(int ntiles, int maxt) {
+  int best = 4;
+  float cost = 1e30f;
+  for (int tg = 1; tg <= 4; tg <<= 1) {
+    const int per = (ntiles + tg - 1) / tg;
+    if (per > maxt) continue;
+    const float c = (float)per * (float)tg * 0.25f;   // per / (4 / tg)
+    if (c <= cost) {
+      cost = c;
+      best = tg;
+    }
+  }
+  return best;
+}
+
+// Element e of a chunk of W rows x CH snapshots in source order -> (row, snapshot): snapshot
+// runs when a window tile block holds at least CH snapshots, else one contiguous [W][TB] block
+// after another.
+template <int CH>
+__device__ __forceinline__ void chunk_elem(const PairArgs& a, int W, int e, int& i, int& bb) {
+  if ((1 << a.logTB) >= CH) {
+    i = e / CH;
+    bb = e - i * CH;
+  } else {
+    const int per = W << a.logTB;
+    const int q = e / per, r = e - q * per;
+    i = r >> a.logTB;
+    bb = (q << a.logTB) + (r & ((1 << a.logTB) - 1));
+  }
+}
+
+// This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end, and
+// their offsets from the chunk's first element in the window layout (valid when chunks start
+// at multiples of CH: then a chunk never splits a tile block differently).  The mapping is the
+// same for every chunk.
+template <int PRE, int TH>
+__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off) {
+  constexpr int CH = TH / 4;
+  const int TB = 1 << a.logTB;
+#pragma unroll
+  for (int m = 0; m < PRE; ++m) {
+    const int e = threadIdx.x + m * TH;
+    map[m] = -1;
+    off[m] = 0;
+    if (e < W * CH) {
+      int i, bb;
+      chunk_elem<CH>(a, W, e, i, bb);
+      map[m] = (i << 8) | bb;
+      off[m] = ((bb >> a.logTB) * a.sumW + i) * TB + (bb & (TB - 1));
+    }
+  }
+}
+
+// Snapshots c0 + (mapped snapshot) of the window rows (zero at b >= lim) into registers.  With
+// aligned chunks (c0 a multiple of CH) one add per element; otherwise the full address.
+template <int PRE>
+__device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const PairArgs& a,
+                                            int k, int woff, const int* map, const int* off,
+                                            bool aligned, int c0, int lim, float2* pre) {
+  const int TB = 1 << a.logTB;
+  const float2* base = Yw + (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
+  if (aligned) {
+    const float2* cb = base + (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1));
+    const int rem = lim - c0;
+#pragma unroll
+    for (int m = 0; m < PRE; ++m) {
+      pre[m] = make_float2(0.f, 0.f);
+      if (map[m] >= 0 && (map[m] & 255) < rem) pre[m] = cb[off[m]];
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < PRE; ++m) {
+      pre[m] = make_float2(0.f, 0.f);
+      const int i = map[m] >> 8, b = c0 + (map[m] & 255);
+      if (map[m] >= 0 && b < lim)
+        pre[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
+    }
+  }
+}
+
+// Registers -> LDS planes (matrix cores): real parts in rows i, imaginary parts in rows W + i.
+template <int PRE>
+__device__ __forceinline__ void store_planes(int W, const int* map, const float2* pre, float* z) {
+#pragma unroll
+  for (int m = 0; m < PRE; ++m) {
+    if (map[m] >= 0) {
+      const int o = (map[m] >> 8) * kXRSP + (map[m] & 255);
+      z[o] = pre[m].x;
+      z[o + W * kXRSP] = pre[m].y;
+    }
+  }
+}
+
+// Registers -> LDS complex rows, zf[i * RSF + snapshot].
+template <int PRE, int RSF>
+__device__ __forceinline__ void store_rows(const int* map, const float2* pre, float2* zf) {
+#pragma unroll
+  for (int m = 0; m < PRE; ++m) {
+    if (map[m] >= 0) zf[(map[m] >> 8) * RSF + (map[m] & 255)] = pre[m];
+  }
+}
+
+struct GramArgs {
+  int W, woff, k, ntiles, TG, tg, kq, lane;
+  bool aligned;
+};
+
+// Matrix-core Gram (TH = 256, CH = 64) into the tile-packed P[tile][16][16] (FP64): NT tiles
+// per wave (tile tg + q TG; past ntiles a stand-in tile whose sum is dropped), snapshot steps
+// split over KS = 4 / TG slices.  NT is a compile-time count so that no MFMA sits under a
+// branch.
+template <int NT, int PRE>
+__device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const PairArgs& a,
+                                          const GramArgs& ga, const int* map, const int* off,
+                                          float2* pre, float* z, double* P) {
+  constexpr int CH = 64;
+  const int KS = 4 / ga.TG;
+  int ra[NT], rb[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    int tile = ga.tg + q * ga.TG, ti, tj;
+    if (tile >= ga.ntiles) tile = 0;
+    tri_index(tile, ti, tj);
+    // lane's snapshots in a chunk: 16 consecutive ones from (lane >> 4) * 16, step s using
+    // the s-th (A and B agree, so the sum over the chunk is the same)
+    ra[q] = (ti * 16 + (ga.lane & 15)) * kXRSP + ((ga.lane >> 4) << 4);
+    rb[q] = (tj * 16 + (ga.lane & 15)) * kXRSP + ((ga.lane >> 4) << 4);
+  }
+  f64x4_t acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < a.L; c0 += CH) {
+    __syncthreads();   // previous chunk consumed
+    store_planes<PRE>(ga.W, map, pre, z);
+    __syncthreads();
+    if (c0 + CH < a.L)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+    else if (a.Lt > 0)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+    for (int sb = ga.kq; sb < CH / 16; sb += KS) {
+      float4 A[NT], Bv[NT];
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        A[q] = *reinterpret_cast<const float4*>(z + ra[q] + 4 * sb);
+        Bv[q] = *reinterpret_cast<const float4*>(z + rb[q] + 4 * sb);
+      }
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[q].x, (double)Bv[q].x, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[q].y, (double)Bv[q].y, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[q].z, (double)Bv[q].z, acc[q], 0, 0, 0);
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)A[q].w, (double)Bv[q].w, acc[q], 0, 0, 0);
+      }
+    }
+  }
+  for (int sl = 0; sl < KS; ++sl) {
+    __syncthreads();
+    if (ga.kq == sl) {
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int tile = ga.tg + q * ga.TG;
+        if (tile < ga.ntiles) {
+          double* dst = P + (size_t)tile * 256 + ga.lane;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dst[r * 64] = (sl == 0 ? 0.0 : dst[r * 64]) + acc[q][r];
+        }
+      }
+    }
+  }
+}
+
+// Vector Gram: R_ij = (1/L) sum_b y_ib conj(y_jb) (+ delta on the diagonal), i >= j, into R
+// (LDS, row stride RS).  A thread owns a BS x BS block of the lower triangle and a slice of S
+// interleaved snapshots (S a power of two; the S slices of a block on consecutive lanes,
+// summed by shuffles in a fixed order).  Requires nblk <= TH.
+template <int BS, int PRE, int TH>
+__device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const PairArgs& a,
+                                         const GramArgs& ga, const int* map, const int* off,
+                                         float2* pre, float2* zf, C2<double>* R, int RS,
+                                         double delta) {
+  constexpr int CH = TH / 4, RSF = CH + 1;
+  const int W = ga.W;
+  const int nb = (W + BS - 1) / BS, nblk = nb * (nb + 1) / 2;
+  int S = 1;
+  while (2 * S * nblk <= TH && S < CH) S *= 2;
+  const int tid = threadIdx.x;
+  const int blk = tid / S, sg = tid & (S - 1);
+  const bool act = blk < nblk;
+  int bi = 0, bj = 0;
+  if (act) tri_index(blk, bi, bj);
+  const float2* yr0 = zf + bi * BS * RSF;
+  const float2* yc0 = zf + bj * BS * RSF;
+  double ax[BS][BS], ay[BS][BS];
+#pragma unroll
+  for (int u = 0; u < BS; ++u)
+#pragma unroll
+    for (int v = 0; v < BS; ++v) ax[u][v] = ay[u][v] = 0.0;
+  for (int c0 = 0; c0 < a.L; c0 += CH) {
+    __syncthreads();   // previous chunk consumed
+    store_rows<PRE, RSF>(map, pre, zf);
+    __syncthreads();
+    if (c0 + CH < a.L)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+    else if (a.Lt > 0)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+    if (act) {
+      for (int bb = sg; bb < CH; bb += S) {
+        double rx[BS], ry[BS], cx[BS], cy[BS];
+#pragma unroll
+        for (int u = 0; u < BS; ++u) {
+          const float2 yr = yr0[u * RSF + bb], yc = yc0[u * RSF + bb];
+          rx[u] = yr.x;
+          ry[u] = yr.y;
+          cx[u] = yc.x;
+          cy[u] = yc.y;
+        }
+#pragma unroll
+        for (int u = 0; u < BS; ++u)
+#pragma unroll
+          for (int v = 0; v < BS; ++v) {   // y_i conj(y_j), two FMAs per part
+            ax[u][v] = fma(rx[u], cx[v], ax[u][v]);
+            ax[u][v] = fma(ry[u], cy[v], ax[u][v]);
+            ay[u][v] = fma(ry[u], cx[v], ay[u][v]);
+            ay[u][v] = fma(-rx[u], cy[v], ay[u][v]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < BS; ++u)
+#pragma unroll
+    for (int v = 0; v < BS; ++v)
+      for (int off = S >> 1; off > 0; off >>= 1) {
+        ax[u][v] += __shfl_xor(ax[u][v], off);
+        ay[u][v] += __shfl_xor(ay[u][v], off);
+      }
+  __syncthreads();   // staging no longer read: R aliases it
+  const double invL = 1.0 / (double)a.L;
+  if (act && sg == 0) {
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+      for (int v = 0; v < BS; ++v) {
+        const int i = bi * BS + u, j = bj * BS + v;
+        if (i < W && j <= i) {
+          C2<double> r = c2<double>(ax[u][v] * invL, ay[u][v] * invL);
+          if (i == j) {
+            r.x += delta;
+            r.y = 0.0;
+          }
+          R[i * RS + j] = r;
+        }
+      }
+  }
+  __syncthreads();
+}
+
+// In-LDS LDL^H factorisation R = L D L^H (L unit lower) by TH threads on a G x G grid
+// (G = 16 or 8), one barrier per column: column j keeps l_ij d_j below the diagonal, d_j on
+// it.  Returns 0, or j + 1 when pivot d_j is not positive and finite (uniform).
+template <int TH>
+__device__ int ldl_lds(C2<double>* R, int RS, int W) {
+  constexpr int G = TH >= 256 ? 16 : 8;
+  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
+  for (int j = 0; j < W; ++j) {
+    const double d = R[j * RS + j].x;
+    if (!(d > 0.0) || !(d < INFINITY)) return j + 1;
+    const double inv = 1.0 / d;
+    for (int i = j + 1 + ty; i < W; i += G) {
+      const C2<double> gi = R[i * RS + j];
+      const double lx = gi.x * inv, ly = gi.y * inv;   // l_ij
+      for (int c = j + 1 + tx; c <= i; c += G) {
+        const C2<double> gc = R[c * RS + j];            // l_cj d_j
+        C2<double> r = R[i * RS + c];
+        r.x = fma(-lx, gc.x, fma(-ly, gc.y, r.x));      // - l_ij conj(l_cj) d_j
+        r.y = fma(-ly, gc.x, fma(lx, gc.y, r.y));
+        R[i * RS + c] = r;
+      }
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// Wave 0: y = L^-1 a, q = a^H R^-1 a = sum |y_i|^2 / d_i, x = L^-H D^-1 y, w = x / q into wv[]
+// (one lane per row, W <= 64).  Caller syncs afterwards.
+__device__ void ldl_solve(const C2<double>* R, int RS, int W, const double2* av,
+                          C2<double>* wv) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  const double invd = (lane < W) ? 1.0 / R[lane * RS + lane].x : 0.0;
+  C2<double> y = c2<double>(0.0, 0.0);
+  if (lane < W) y = c2<double>(av[lane].x, av[lane].y);
+  for (int j = 0; j < W; ++j) {
+    const double ivj = __shfl(invd, j);
+    const double yx = __shfl(y.x, j) * ivj, yy = __shfl(y.y, j) * ivj;   // y_j / d_j
+    if (lane > j && lane < W) {
+      const C2<double> g = R[lane * RS + j];                              // l_ij d_j
+      y.x -= g.x * yx - g.y * yy;
+      y.y -= g.x * yy + g.y * yx;
+    }
+  }
+  double q = (y.x * y.x + y.y * y.y) * invd;
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  C2<double> x = c2<double>(y.x * invd, y.y * invd);
+  for (int j = W - 1; j >= 0; --j) {
+    const double xx = __shfl(x.x, j), xy = __shfl(x.y, j);               // x_j, final
+    if (lane < j) {
+      const C2<double> g = R[j * RS + lane];                              // l_ji d_i
+      x.x -= (g.x * xx + g.y * xy) * invd;                                // conj(l_ji) x_j
+      x.y -= (g.x * xy - g.y * xx) * invd;
+    }
+  }
+  const double qinv = 1.0 / q;
+  if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
+}
+
+template <int WCAP, bool MF, int TH>
+__device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom& g,
+                                            const DevDesc& d, const float2* __restrict__ Yw,
+                                            float2* __restrict__ out, float2* __restrict__ wout,
+                                            int* __restrict__ starts_out, int* __restrict__ info) {
+  using Cap = XCap<WCAP, TH>;
+  constexpr int CH = Cap::CH, PRE = Cap::kPre, RSF = CH + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const XLds lay = x_lds_layout<MF, TH>(a.wmax);
+  float* z = reinterpret_cast<float*>(smem + lay.region);
+  float2* zf = reinterpret_cast<float2*>(smem + lay.region);
+  double* P = reinterpret_cast<double*>(smem + lay.region);
+  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.region);
+  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv);
+  double2* av = reinterpret_cast<double2*>(smem + lay.av);
+  double2* red = reinterpret_cast<double2*>(smem + lay.red);
+  // the wave index is uniform per wave: readfirstlane lets the compiler branch on it with
+  // scalar instructions
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  int t, k;
+  pair_of_block(a, d, t, k);
   int W = d.win[t], woff = d.woff[t];
   const int64_t pair = (int64_t)t * a.K + k;
   double u;
@@ -339,50 +763,213 @@ __global__ __launch_bounds__(THREADS) void k_mvdr_fused(PairArgs a, WindowGeom g
     }
   }
   const double delta = a.pdelta ? (double)a.pdelta[pair] : a.delta;
-  if (threadIdx.x < W) av[threadIdx.x] = window_steering(g, u, s, threadIdx.x);
-  if (starts_out && threadIdx.x == 0) starts_out[pair] = s;
 
-  pair_covariance<double, true, THREADS, EPT>(Yw, a, k, W, woff, s, ys, R, lay.RS, delta);
-  const int fail = chol_lds<double, THREADS>(R, lay.RS, diag, W);
-  if (!fail) solve_lds<double>(R, lay.RS, diag, W, av, wv);
-  apply_staged<THREADS>(Yw, a, k, woff, s, W, fail, wv, ys, out + pair * a.Lt);
+  int map[PRE], off[PRE];
+  chunk_map<PRE, TH>(a, W, map, off);
+  const bool aligned = (a.L % CH) == 0;
+  float2 pre[PRE];
+  fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
+  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, u, s, i);
+  if (starts_out && tid == 0) starts_out[pair] = s;
+
+  if constexpr (!MF) {
+    GramArgs ga{W, woff, k, 0, 0, 0, 0, lane, aligned};
+    if constexpr (TH >= 256) {
+      // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
+      if (WCAP <= 44 || W <= 44)
+        gram_vec<2, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+      else if constexpr (WCAP > 44)
+        gram_vec<4, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+    } else {
+      // one wave: 4 x 4 blocks (at most 55 blocks for 40 bins)
+      gram_vec<4, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+    }
+  } else {
+    static_assert(!MF || TH == 256, "the matrix-core form runs four waves");
+    constexpr int kXMaxT = Cap::kMaxT, kXEnt = Cap::kEnt;
+    const int rows = 2 * W;
+    const int nt = (rows + 15) >> 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int TG = mfma_tile_groups(ntiles, kXMaxT);
+    const int NT = (ntiles + TG - 1) / TG;   // tiles per wave, the same on every wave
+    // rows 2W .. 16 nt - 1 stay zero for the whole loop
+    for (int e = tid; e < (nt * 16 - rows) * CH; e += TH)
+      z[(rows + e / CH) * kXRSP + (e % CH)] = 0.f;
+    GramArgs ga{W, woff, k, ntiles, TG, wave % TG, wave / TG, lane, aligned};
+    switch (NT) {
+#define WBM_GRAM_CASE(n) \
+  case n:                \
+    if constexpr (n <= kXMaxT) gram_mfma<n, PRE>(Yw, a, ga, map, off, pre, z, P); \
+    break;
+      WBM_GRAM_CASE(1) WBM_GRAM_CASE(2) WBM_GRAM_CASE(3) WBM_GRAM_CASE(4) WBM_GRAM_CASE(5)
+      WBM_GRAM_CASE(6) WBM_GRAM_CASE(7) WBM_GRAM_CASE(8) WBM_GRAM_CASE(9)
+#undef WBM_GRAM_CASE
+    }
+    __syncthreads();
+    // complex R (lower), scaled and loaded; read into registers, then written over P
+    const int nE = W * (W + 1) / 2;
+    const double invL = 1.0 / (double)a.L;
+    C2<double> rv[kXEnt];
+    int ri[kXEnt], rj[kXEnt];
+    auto gram = [&](int r, int c) -> double {
+      const int ti = r >> 4, tj = c >> 4;
+      return P[(size_t)(ti * (ti + 1) / 2 + tj) * 256 + (r & 15) * 16 + (c & 15)];
+    };
+#pragma unroll
+    for (int q = 0; q < kXEnt; ++q) {
+      const int e = tid + q * TH;
+      ri[q] = -1;
+      rj[q] = 0;
+      rv[q] = c2<double>(0.0, 0.0);
+      if (e < nE) {
+        int i, j;
+        tri_index(e, i, j);
+        ri[q] = i;
+        rj[q] = j;
+        double re = (gram(i, j) + gram(W + i, W + j)) * invL;
+        double im = (gram(W + i, j) - gram(W + j, i)) * invL;
+        if (i == j) {
+          re += delta;
+          im = 0.0;
+        }
+        rv[q] = c2<double>(re, im);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kXEnt; ++q)
+      if (ri[q] >= 0) R[ri[q] * lay.RS + rj[q]] = rv[q];
+    __syncthreads();
+  }
+
+  const int fail = ldl_lds<TH>(R, lay.RS, W);
+  if (!fail) ldl_solve(R, lay.RS, W, av, wv);
+  // beam outputs on the test snapshots, CH at a time: thread (row group q = tid / CH, snapshot
+  // l = tid % CH) sums window rows i = q mod 4, then the four partials are added in order
+  const int rg = tid / CH, ls = tid % CH;
+  float2* o = out + pair * a.Lt;
+  const int nch = (a.Lt + CH - 1) / CH;
+  for (int c = 0; c < nch; ++c) {
+    __syncthreads();   // R / the previous chunk no longer read
+    if constexpr (MF)
+      store_planes<PRE>(W, map, pre, z);
+    else
+      store_rows<PRE, RSF>(map, pre, zf);
+    __syncthreads();
+    if (c + 1 < nch)
+      fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt, pre);
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = rg; i < W; i += 4) {
+        double yr, yi;
+        if constexpr (MF) {
+          yr = z[i * kXRSP + ls];
+          yi = z[(W + i) * kXRSP + ls];
+        } else {
+          const float2 y = zf[i * RSF + ls];
+          yr = y.x;
+          yi = y.y;
+        }
+        const C2<double> w = wv[i];
+        zx = fma(w.x, yr, fma(w.y, yi, zx));     // conj(w) y
+        zy = fma(w.x, yi, fma(-w.y, yr, zy));
+      }
+    }
+    red[rg * CH + ls] = make_double2(zx, zy);
+    __syncthreads();
+    const int l = c * CH + tid;
+    if (tid < CH && l < a.Lt) {
+      double2 acc = red[tid];
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        acc.x += red[q * CH + tid].x;
+        acc.y += red[q * CH + tid].y;
+      }
+      o[l] = make_float2((float)acc.x, (float)acc.y);
+    }
+  }
   if (wout) {
-    for (int i = threadIdx.x; i < a.wmax; i += THREADS) {
+    for (int i = tid; i < a.wmax; i += TH) {
       float2 v = make_float2(0.f, 0.f);
       if (!fail && i < W) v = make_float2((float)wv[i].x, (float)wv[i].y);
       wout[pair * a.wmax + i] = v;
     }
   }
-  if (info && threadIdx.x == 0) info[pair] = fail;
+  if (info && tid == 0) info[pair] = fail;
 }
 
-template <int THREADS, int EPT>
-static hipError_t fused_launch(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
-                               const float2* Yw, float2* out, float2* wout, int* starts,
-                               int* info, hipStream_t s) {
-  const PairLds lay = pair_lds_layout<double>(a.wmax);
-  hipLaunchKernelGGL((k_mvdr_fused<THREADS, EPT>), dim3(a.T * a.K), dim3(THREADS), lay.total, s,
-                     a, g, d, Yw, out, wout, starts, info);
+// Matrix-core form, vector form with four waves (held to 128 VGPRs up to 40 bins: four
+// workgroups per CU; a 16-bin build keeps fewer staging registers) and vector form with one
+// wave per pair (up to 40 bins).
+template <int WCAP>
+__global__ __launch_bounds__(256) void k_mvdr_xm(PairArgs a, WindowGeom g, DevDesc d,
+                                                 const float2* __restrict__ Yw,
+                                                 float2* __restrict__ out,
+                                                 float2* __restrict__ wout,
+                                                 int* __restrict__ starts_out,
+                                                 int* __restrict__ info) {
+  mvdr_x_body<WCAP, true, 256>(a, g, d, Yw, out, wout, starts_out, info);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv16(
+    PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
+    float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
+  mvdr_x_body<16, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv40(
+    PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
+    float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
+  mvdr_x_body<40, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+}
+
+__global__ __launch_bounds__(256) void k_mvdr_xv64(
+    PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
+    float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
+  mvdr_x_body<64, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+}
+
+__global__ __launch_bounds__(64) void k_mvdr_xw40(
+    PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
+    float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
+  mvdr_x_body<40, false, 64>(a, g, d, Yw, out, wout, starts_out, info);
+}
+
+hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                            const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                            hipStream_t s) {
+  if (a.wmax > 64) return hipErrorInvalidValue;
+  const XLds lay = x_lds_layout<true, 256>(a.wmax);
+  const dim3 grid(a.T * a.K), blk(256);
+  if (a.wmax <= 40)
+    hipLaunchKernelGGL(k_mvdr_xm<40>, grid, blk, lay.total, s, a, g, d, Yw, out, wout, starts, info);
+  else
+    hipLaunchKernelGGL(k_mvdr_xm<64>, grid, blk, lay.total, s, a, g, d, Yw, out, wout, starts, info);
   return hipGetLastError();
 }
 
-bool mvdr_wave_supported(int wmax) { return wmax <= kWaveWMax; }
-
-hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
-                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
-                             int threads, hipStream_t s) {
-  const int nE = a.wmax * (a.wmax + 1) / 2;
-  if (threads == 64 && a.wmax <= kWaveWMax) {
-    // one wave64 per pair; entries per lane = ceil(nE / 64)
-    const int ept = (nE + 63) / 64;
-    if (ept <= 1) return fused_launch<64, 1>(a, g, d, Yw, out, wout, starts, info, s);
-    if (ept <= 2) return fused_launch<64, 2>(a, g, d, Yw, out, wout, starts, info, s);
-    if (ept <= 3) return fused_launch<64, 3>(a, g, d, Yw, out, wout, starts, info, s);
-    if (ept <= 5) return fused_launch<64, 5>(a, g, d, Yw, out, wout, starts, info, s);
-    if (ept <= 9) return fused_launch<64, 9>(a, g, d, Yw, out, wout, starts, info, s);
-    return fused_launch<64, 13>(a, g, d, Yw, out, wout, starts, info, s);
+hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
+                              int threads, hipStream_t s) {
+  if (a.wmax > 64 || (threads == 64 && a.wmax > 40)) return hipErrorInvalidValue;
+  const dim3 grid(a.T * a.K);
+  if (threads == 64) {
+    const XLds lay = x_lds_layout<false, 64>(a.wmax);
+    hipLaunchKernelGGL(k_mvdr_xw40, grid, dim3(64), lay.total, s, a, g, d, Yw, out, wout, starts,
+                       info);
+    return hipGetLastError();
   }
-  return fused_launch<256, 9>(a, g, d, Yw, out, wout, starts, info, s);
+  const XLds lay = x_lds_layout<false, 256>(a.wmax);
+  if (a.wmax <= 16)
+    hipLaunchKernelGGL(k_mvdr_xv16, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
+                       info);
+  else if (a.wmax <= 40)
+    hipLaunchKernelGGL(k_mvdr_xv40, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
+                       info);
+  else
+    hipLaunchKernelGGL(k_mvdr_xv64, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
+                       info);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
@@ -486,11 +1073,12 @@ hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* 
 }
 
 hipError_t set_pair_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_fused<256, 9>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_xm<64>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)x_lds_layout<true, 256>(64).total);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_mvdr_fused<64, 13>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+  return hipFuncSetAttribute((const void*)k_mvdr_xv64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)x_lds_layout<false, 256>(64).total);
 }
 
 }  // namespace wbm
@@ -582,8 +1170,8 @@ __global__ __launch_bounds__(kMixThreads) void k_mvdr_mixed(PairArgs a, WindowGe
   float* R32 = reinterpret_cast<float*>(smem + lay.r);   // FP32 view used by the FP32 Cholesky
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-  const int p = blockIdx.x;
-  const int k = p / a.T, t = p - k * a.T;
+  int t, k;
+  pair_of_block(a, d, t, k);
   const int W = d.win[t], woff = d.woff[t];
   const int64_t pair = (int64_t)t * a.K + k;
   double u;

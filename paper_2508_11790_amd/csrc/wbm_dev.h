@@ -150,9 +150,29 @@ struct Fft {
     j = b & ((1 << LOGQ) - 1);
   }
 
+  // Radix-8 passes after the first, and the twiddles a thread applies in them: pass q
+  // (stride 2^LOGNS, LOGNS = LOGR0 + 3 q) multiplies input r of its butterfly by
+  // w_n^(r * kq * 2^(LOGN - LOGNS - 3)), kq = the butterfly's position within its stride.
+  // They depend only on the thread, so a workgroup loads them once into registers.
+  static constexpr int NP = (LOGN - LOGR0) / 3;
+  static constexpr int NPA = NP > 0 ? NP : 1;
+
+  __device__ __forceinline__ static void load_twiddles(float2 (&tr)[NPA][7],
+                                                       const float2* __restrict__ tw) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const int logns = LOGR0 + 3 * q;
+      int row, j;
+      bf<3>(0, row, j);
+      const int step = (j & ((1 << logns) - 1)) << (LOGN - logns - 3);
+#pragma unroll
+      for (int r = 1; r < 8; ++r) tr[q][r - 1] = tw[r * step];
+    }
+  }
+
   template <int R, int LOGR, int LOGNS>
   __device__ __forceinline__ static void compute_write(float2 (&v)[8], float2* lds,
-                                                       const float2* __restrict__ tw) {
+                                                       const float2 (&tr)[NPA][7]) {
 #pragma unroll
     for (int p = 0; p < 8 / R; ++p) {
       int row, j;
@@ -160,9 +180,10 @@ struct Fft {
       float2* b = v + p * R;
       const int k = j & ((1 << LOGNS) - 1);
       if constexpr (LOGNS > 0) {
-        const int step = k << (LOGN - LOGNS - LOGR);
+        // only radix-8 passes follow the first (LOGNS == 0) pass: one butterfly per thread
+        constexpr int q = (LOGNS - LOGR0) / 3;
 #pragma unroll
-        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tw[r * step]);
+        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tr[q][r - 1]);
       }
       dftR<R>(b);
       const int base = ((j >> LOGNS) << (LOGNS + LOGR)) | k;
@@ -181,13 +202,13 @@ struct Fft {
 
   template <int LOGNS>
   __device__ __forceinline__ static void rest(float2 (&v)[8], float2* lds,
-                                              const float2* __restrict__ tw) {
+                                              const float2 (&tr)[NPA][7]) {
     if constexpr (LOGNS < LOGN) {
       __syncthreads();
       read8(v, lds);
       __syncthreads();
-      compute_write<8, 3, LOGNS>(v, lds, tw);
-      rest<LOGNS + 3>(v, lds, tw);
+      compute_write<8, 3, LOGNS>(v, lds, tr);
+      rest<LOGNS + 3>(v, lds, tr);
     }
   }
 
@@ -198,12 +219,13 @@ struct Fft {
     pos = j + (r << (LOGN - LOGR0));
   }
 
-  // v holds the first-pass inputs (slot p*R0 + r <-> first_input(p, r)); on return the
-  // transform of every row is in LDS in natural order (addr(row, i)), visible to all threads.
+  // v holds the first-pass inputs (slot p*R0 + r <-> first_input(p, r)), tr the thread's
+  // twiddles (load_twiddles); on return the transform of every row is in LDS in natural order
+  // (addr(row, i)), visible to all threads.
   __device__ __forceinline__ static void run(float2 (&v)[8], float2* lds,
-                                             const float2* __restrict__ tw) {
-    compute_write<R0, LOGR0, 0>(v, lds, tw);
-    rest<LOGR0>(v, lds, tw);
+                                             const float2 (&tr)[NPA][7]) {
+    compute_write<R0, LOGR0, 0>(v, lds, tr);
+    rest<LOGR0>(v, lds, tr);
     __syncthreads();
   }
 };

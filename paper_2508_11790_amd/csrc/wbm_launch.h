@@ -14,6 +14,7 @@ struct DevDesc {
   const int* win;         // [T]
   const int* woff;        // [T] first window row of target t (prefix sum of win)
   const int* rowtab;      // [sumW] window row r -> (t << 8) | i
+  const int* torder;      // [T] targets by window width, widest first (pair kernels' order)
 };
 
 // FFT tile sizes the kernels are built for (log2 complex per workgroup tile).
@@ -49,7 +50,9 @@ struct PairArgs {
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
 // solve -> apply, reading the window rows written by the beamspace kernel.
-// threads = 64 (one wave per pair, windows up to 40 bins) or 256 (four waves per pair).
+// threads = kPairMfma (four waves, FP64 matrix-core covariance), 64 (one wave per pair on the
+// vector units, windows up to 40 bins) or 256 (four waves per pair on the vector units).
+constexpr int kPairMfma = 1;
 hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s);

@@ -154,6 +154,49 @@ def test_batch_config_full_size_sampled_subbands(torch, wb):
     plan.close()
 
 
+def _pin(plan, pair):
+    chan, beam, _ = plan.tuning
+    plan.set_tuning(chan, beam, pair)
+    assert plan.tuning[2] == pair
+
+
+@pytest.mark.parametrize("pair", ["mfma", "wave", "block"])
+@pytest.mark.parametrize("name", ["small", "gpu"])
+def test_pair_kernels_match_oracle(torch, wb, name, pair):
+    cfg = scenes.config_by_name(name)
+    log(f"pair kernel {pair} on the {name} config, all pairs")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    _pin(plan, pair)
+    res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form="fused")
+    torch.cuda.synchronize()
+    st = compare_beamform(sc, ref, res)
+    log(f"  {st}")
+    assert st["max_weight_err"] < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("pair", ["mfma", "block"])
+def test_pair_kernels_batch_config_sampled_subbands(torch, wb, pair):
+    cfg = scenes.BATCH
+    log(f"pair kernel {pair}, batch config (W in {{5,9,17,33}}, 64 targets), sampled subbands")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    plan = _plan(wb, cfg, sc)
+    _pin(plan, pair)
+    xd = torch.from_numpy(x32).cuda()
+    res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form="fused")
+    torch.cuda.synchronize()
+    ks = [0, 3, 130, 255]
+    ref = _oracle(sc, x32, subbands=ks)
+    st = compare_beamform(sc, ref, res, subbands=ks)
+    log(f"  {st}")
+    del xd
+    plan.close()
+
+
 def test_graph_replays_match_eager(torch, wb):
     cfg = scenes.GPU
     sc = scenes.make_scene(cfg)
@@ -199,7 +242,12 @@ def test_edge_shapes(torch, wb, case):
     x32 = _x32(sc)
     ref = _oracle(sc, x32)
     plan = _plan(wb, cfg, sc)
-    for form in ("plain", "fused"):
+    runs = [("plain", None), ("fused", "mfma"), ("fused", "block")]
+    if max(W) <= 40:
+        runs.append(("fused", "wave"))
+    for form, pair in runs:
+        if pair:
+            _pin(plan, pair)
         res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
         torch.cuda.synchronize()
         compare_beamform(sc, ref, res, plain=(form == "plain"))
@@ -235,10 +283,13 @@ def test_rejects_bad_targets(torch, wb):
     plan.close()
 
 
-@pytest.mark.parametrize("form", ["plain", "fused"])
+@pytest.mark.parametrize("form", ["plain", "fused-mfma", "fused-block", "fused-wave"])
 def test_zero_loading_singular_reports_info(torch, wb, form):
     # silent input and no loading: the window covariance is 0, the first pivot fails (info = 1)
     plan = wb.Plan(16, 32, 4, 3, 2, 1, 9)
+    if form.startswith("fused"):
+        form, pair = form.split("-")
+        _pin(plan, pair)
     x = torch.zeros((16, 5 * 4), dtype=torch.complex64, device="cuda")
     res = plan.beamform(x, [0.2], [9], 0.0, form=form)
     torch.cuda.synchronize()
