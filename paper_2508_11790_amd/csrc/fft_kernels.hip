@@ -18,6 +18,22 @@ __host__ __device__ constexpr int fft_threads(int logn, int logtile) {
   return (1 << fft_tile(logn, logtile)) / 8;
 }
 
+// LDS row padding (complex slots) of a multi-row tile: fewest modelled bank-conflict cycles
+// over every pass and the kernel's output gather (channelizer: lanes walk tile rows;
+// beamspace: lanes walk snapshots, then window bins), for 32- and 64-bank LDS models.
+__host__ __device__ constexpr int chan_pad(int logtile, int logn) {
+  return logn <= 3 ? 1 : logn == 4 ? 2 : logn == 5 ? 3 : logn == 6 ? 13
+       : logtile == 11 ? (logn == 7 ? 2 : logn == 8 ? 2 : logn == 9 ? 4 : logn == 10 ? 8 : 0)
+       : logtile == 12 ? (logn == 7 ? 1 : logn == 8 ? 1 : logn == 9 ? 2 : logn == 10 ? 4 : logn == 11 ? 8 : 0)
+       : (logn <= 9 ? 1 : logn == 10 ? 2 : logn == 11 ? 4 : logn == 12 ? 8 : 0);
+}
+__host__ __device__ constexpr int beam_pad(int logtile, int logn) {
+  return logn <= 3 ? 1 : logn == 4 ? 2 : logn == 5 ? 3 : logn == 6 ? 13
+       : logtile == 11 ? (logn == 7 ? 1 : logn == 8 ? 14 : logn == 9 ? 12 : logn == 10 ? 5 : 0)
+       : logtile == 12 ? (logn == 7 ? 1 : logn == 8 ? 1 : logn == 9 ? 14 : logn == 10 ? 8 : logn == 11 ? 5 : 0)
+       : (logn <= 9 ? 1 : logn == 10 ? 14 : logn == 11 ? 8 : logn == 12 ? 5 : 0);
+}
+
 // x [N][S] (S = B*K) -> X [K][B][N].  Workgroup = (TE = tile/K elements, blocks b =
 // blockIdx.y, blockIdx.y + gridDim.y, ...).  Rows e >= N are zero-filled and not written.
 // Optional pre-twiddle hb[tau] (half-bin centres).  Output scaled by K^-1/2 (unitary DFT).
@@ -26,7 +42,7 @@ template <int LOGK, int LOGT>
 __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
     const float2* __restrict__ x, float2* __restrict__ X, int N, int B, int64_t S,
     const float2* __restrict__ twK, const float2* __restrict__ hb, float scale) {
-  using F = Fft<LOGK, fft_tile(LOGK, LOGT)>;
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK)>;
   constexpr int K = F::n, TE = F::rows;
   constexpr int LOGTE = fft_tile(LOGK, LOGT) - LOGK;
   __shared__ float2 lds[F::lds_complex];
@@ -94,7 +110,7 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
     const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int N, int B,
     int K, const float2* __restrict__ twM, float scale, const int* __restrict__ rowtab, int sumW,
     WindowGeom g, float* __restrict__ prof, int L) {
-  using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   constexpr int M = F::n, TB = F::rows;
   constexpr int LOGTB = fft_tile(LOGM, LOGT) - LOGM;
   __shared__ float2 lds[F::lds_complex];
@@ -212,7 +228,7 @@ static int resident_blocks(KERN kernel, int threads, size_t dyn_shm, int* cache)
 template <int LOGK, int LOGT>
 static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const float2* twK,
                               const float2* hb, hipStream_t s) {
-  using F = Fft<LOGK, fft_tile(LOGK, LOGT)>;
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK)>;
   static int resident = 0;
   const int gx = (N + F::rows - 1) / F::rows;
   const int cap = resident_blocks(k_channelize<LOGK, LOGT>, F::threads, 0, &resident);
@@ -228,7 +244,7 @@ template <int LOGM, int LOGT>
 static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
                               const float2* twM, const int* rowtab, int sumW,
                               const WindowGeom& g, float* prof, int L, int G, hipStream_t s) {
-  using F = Fft<LOGM, fft_tile(LOGM, LOGT)>;
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   const int nbt = (B + F::rows - 1) / F::rows;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
   size_t shm = 0;
@@ -312,9 +328,9 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
   return hipErrorInvalidValue;
 }
 
-// Static LDS is at most 8192 * 9/8 + 8 complex = 72 KiB; the beamspace kernel adds 8 + 256
-// bytes per target (window starts, beam bins, profile sums), requested at launch when the
-// total passes 64 KiB.
+// Static LDS is at most 128 rows x (64 + 13) complex = 77 KiB (64-point rows in an 8192 tile);
+// the beamspace kernel adds 8 + 256 bytes per target (window starts, beam bins, profile sums)
+// and 4 per window row, requested at launch when the total passes 64 KiB.
 hipError_t set_fft_attributes() { return hipSuccess; }
 
 }  // namespace wbm

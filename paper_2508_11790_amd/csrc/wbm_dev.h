@@ -125,21 +125,25 @@ __device__ __forceinline__ void dftR(float2* v) {
 // leading radix-2 or radix-4 pass).  Pass p of radix R over sub-length Ns: butterfly j of
 // a row takes v[r] = x[j + r n/R], multiplies v[r] by exp(-2 pi i r (j mod Ns) / (Ns R)),
 // applies the R-point DFT and stores v[r] at (j div Ns) Ns R + (j mod Ns) + r Ns.  Values
-// live in registers inside a pass and in LDS between passes; the LDS row stride and one pad
-// slot every eight values keep the strided accesses off a single bank.
-template <int LOGN, int LOGTILE>
+// live in registers inside a pass and in LDS between passes.  LDS position i of a row holds
+// element i ^ ((i >> 3) & 31) (bits 0-4 XORed with bits 3-7: the stride-8 butterfly writes,
+// the contiguous reads and the stride-64 blocks all land on distinct banks), and rows are PAD
+// slots apart beyond n, chosen per shape for the kernel's output gather.
+template <int LOGN, int LOGTILE, int PAD>
 struct Fft {
   static constexpr int n = 1 << LOGN;
   static constexpr int tile = 1 << LOGTILE;
   static constexpr int rows = tile / n;
   static constexpr int threads = tile / 8;
-  static constexpr int rs = n + n / 8 + 1;                  // LDS row stride (complex)
+  static constexpr int rs = rows > 1 ? n + PAD : n;         // LDS row stride (complex)
   static constexpr int lds_complex = rows * rs;
   static constexpr int R0 = (LOGN % 3 == 1) ? 2 : ((LOGN % 3 == 2) ? 4 : 8);
   static constexpr int LOGR0 = (R0 == 2) ? 1 : (R0 == 4 ? 2 : 3);
   static_assert(LOGTILE >= LOGN && LOGTILE >= 3, "tile must hold a row and 8 values/thread");
 
-  __device__ __forceinline__ static int addr(int row, int i) { return row * rs + i + (i >> 3); }
+  __device__ __forceinline__ static int addr(int row, int i) {
+    return row * rs + (i ^ ((i >> 3) & 31));
+  }
 
   // row and in-row butterfly index of this thread's p-th butterfly of a radix-R pass
   template <int LOGR>
