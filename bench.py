@@ -28,6 +28,33 @@ if ROOT not in sys.path:
 
 METRIC = "(target,subband) MVDR beams/s at ≤0.1 dB SINR loss vs FP64; chosen vs plain"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILES = {"gpu": os.path.join(ROOT, "profiles", "traffic_gpu_N256_M512_K128.json")}
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2508_11790_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE record of this workload,
+    or None when there is none or the kernel sources changed since it was taken."""
+    path = TRAFFIC_FILES.get(workload)
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes"]
 
 
 def log(msg):
@@ -206,7 +233,8 @@ def main():
     kern = max(bytes_per, key=lambda n: st[n])
     achieved = bytes_per[kern] / (st[kern] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=counter_traffic(cfg.name, kern),
                     bytes_per_launch=bytes_per[kern], ms_per_launch=st[kern],
                     stage_ms={k: round(v, 5) for k, v in st.items()},
                     stage_gbs={n: round(bytes_per[n] / (st[n] * 1e-3) / 1e9, 1) for n in bytes_per})
