@@ -47,7 +47,7 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
   constexpr int LOGTE = fft_tile(LOGK, LOGT) - LOGK;
   __shared__ float2 lds[F::lds_complex];
   const int e0 = blockIdx.x * TE;
-  float2 tr[F::NPA][7];
+  float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twK);
   float2 hv[8];
 #pragma unroll
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);      // [sumW] bin of window row r (Yw)
   const int k = blockIdx.y;
   const int nbt = (B + TB - 1) / TB;
-  float2 tr[F::NPA][7];
+  float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twM);
   auto fetch = [&](int j, float2 (&v)[8]) {
     const int b0 = j * TB;

@@ -342,7 +342,7 @@ hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDe
 
 // ------------------------------------------------------------------------------------------
 // Fused pair kernels, second generation.  One workgroup of TH threads per (target, subband)
-// pair, in chunks of CH = TH / 4 training snapshots staged through LDS, the next chunk already
+// pair, in chunks of CH training snapshots staged through LDS, the next chunk already
 // in flight in registers (after the last training chunk, the first test chunk), each thread's
 // chunk elements mapped once per pair:
 //   - vector form (TH = 256: four waves per pair; TH = 64: one wave per pair, more pairs per
@@ -362,9 +362,9 @@ constexpr int kXRSP = 64 + 4;   // float row stride of the matrix-core form's st
 
 // Register budgets for windows up to WCAP bins and TH threads: Gram tiles per wave (matrix
 // cores), staged elements per thread and chunk, covariance entries per thread (matrix cores).
-template <int WCAP, int TH>
+template <int WCAP, int TH, int CHUNK>
 struct XCap {
-  static constexpr int CH = TH / 4;
+  static constexpr int CH = CHUNK;
   static constexpr int kMaxT = WCAP <= 40 ? 4 : 9;
   static constexpr int kPre = (WCAP * CH + TH - 1) / TH;
   static constexpr int kEnt = (WCAP * (WCAP + 1) / 2 + TH - 1) / TH;
@@ -378,9 +378,9 @@ struct XLds {
 // LDS of the pair kernels: one region reused by the staged chunks, the Gram tiles (matrix
 // cores) and the complex R, then the pivots, weights, steering vector and the apply's partial
 // sums.
-template <bool MF, int TH>
+template <bool MF, int TH, int CH>
 __host__ __device__ inline XLds x_lds_layout(int wmax) {
-  constexpr int CH = TH / 4;
+  constexpr int NG = TH / CH > 0 ? TH / CH : 1;   // row groups of the apply
   XLds p;
   p.RS = wmax + 1;
   const size_t r = sizeof(C2<double>) * (size_t)wmax * p.RS;          // complex R (lower)
@@ -401,7 +401,7 @@ __host__ __device__ inline XLds x_lds_layout(int wmax) {
   p.wv = p.diag + sizeof(double) * 64;
   p.av = p.wv + sizeof(C2<double>) * 64;
   p.red = p.av + sizeof(double2) * 64;
-  p.total = p.red + sizeof(double2) * 4 * CH;
+  p.total = p.red + sizeof(double2) * NG * CH;
   return p;
 }
 
@@ -442,9 +442,8 @@ __device__ __forceinline__ void chunk_elem(const PairArgs& a, int W, int e, int&
 // their offsets from the chunk's first element in the window layout (valid when chunks start
 // at multiples of CH: then a chunk never splits a tile block differently).  The mapping is the
 // same for every chunk.
-template <int PRE, int TH>
+template <int PRE, int TH, int CH>
 __device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off) {
-  constexpr int CH = TH / 4;
   const int TB = 1 << a.logTB;
 #pragma unroll
   for (int m = 0; m < PRE; ++m) {
@@ -582,12 +581,12 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
 // (LDS, row stride RS).  A thread owns a BS x BS block of the lower triangle and a slice of S
 // interleaved snapshots (S a power of two; the S slices of a block on consecutive lanes,
 // summed by shuffles in a fixed order).  Requires nblk <= TH.
-template <int BS, int PRE, int TH>
+template <int BS, int PRE, int TH, int CH>
 __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const PairArgs& a,
                                          const GramArgs& ga, const int* map, const int* off,
                                          float2* pre, float2* zf, C2<double>* R, int RS,
                                          double delta) {
-  constexpr int CH = TH / 4, RSF = CH + 1;
+  constexpr int RSF = CH + 1;
   const int W = ga.W;
   const int nb = (W + BS - 1) / BS, nblk = nb * (nb + 1) / 2;
   int S = 1;
@@ -724,15 +723,18 @@ __device__ void ldl_solve(const C2<double>* R, int RS, int W, const double2* av,
   if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
 }
 
-template <int WCAP, bool MF, int TH>
+template <int WCAP, bool MF, int TH, int CHUNK>
 __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom& g,
                                             const DevDesc& d, const float2* __restrict__ Yw,
                                             float2* __restrict__ out, float2* __restrict__ wout,
                                             int* __restrict__ starts_out, int* __restrict__ info) {
-  using Cap = XCap<WCAP, TH>;
+  using Cap = XCap<WCAP, TH, CHUNK>;
   constexpr int CH = Cap::CH, PRE = Cap::kPre, RSF = CH + 1;
+  constexpr int NG = TH / CH;   // row groups of the apply
+  static_assert(TH % CH == 0 && CH <= 256, "chunk: a divisor of the workgroup, at most 256");
+  static_assert(!MF || CH == 64, "the matrix-core Gram steps through 64-snapshot chunks");
   extern __shared__ __align__(16) unsigned char smem[];
-  const XLds lay = x_lds_layout<MF, TH>(a.wmax);
+  const XLds lay = x_lds_layout<MF, TH, CH>(a.wmax);
   float* z = reinterpret_cast<float*>(smem + lay.region);
   float2* zf = reinterpret_cast<float2*>(smem + lay.region);
   double* P = reinterpret_cast<double*>(smem + lay.region);
@@ -765,7 +767,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   const double delta = a.pdelta ? (double)a.pdelta[pair] : a.delta;
 
   int map[PRE], off[PRE];
-  chunk_map<PRE, TH>(a, W, map, off);
+  chunk_map<PRE, TH, CH>(a, W, map, off);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
@@ -777,12 +779,12 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if constexpr (TH >= 256) {
       // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
       if (WCAP <= 44 || W <= 44)
-        gram_vec<2, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+        gram_vec<2, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
       else if constexpr (WCAP > 44)
-        gram_vec<4, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+        gram_vec<4, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
     } else {
       // one wave: 4 x 4 blocks (at most 55 blocks for 40 bins)
-      gram_vec<4, PRE, TH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+      gram_vec<4, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
     }
   } else {
     static_assert(!MF || TH == 256, "the matrix-core form runs four waves");
@@ -845,7 +847,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   const int fail = ldl_lds<TH>(R, lay.RS, W);
   if (!fail) ldl_solve(R, lay.RS, W, av, wv);
   // beam outputs on the test snapshots, CH at a time: thread (row group q = tid / CH, snapshot
-  // l = tid % CH) sums window rows i = q mod 4, then the four partials are added in order
+  // l = tid % CH) sums window rows i = q mod NG, then the NG partials are added in order
   const int rg = tid / CH, ls = tid % CH;
   float2* o = out + pair * a.Lt;
   const int nch = (a.Lt + CH - 1) / CH;
@@ -860,7 +862,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
       fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt, pre);
     double zx = 0.0, zy = 0.0;
     if (!fail) {
-      for (int i = rg; i < W; i += 4) {
+      for (int i = rg; i < W; i += NG) {
         double yr, yi;
         if constexpr (MF) {
           yr = z[i * kXRSP + ls];
@@ -881,7 +883,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if (tid < CH && l < a.Lt) {
       double2 acc = red[tid];
 #pragma unroll
-      for (int q = 1; q < 4; ++q) {
+      for (int q = 1; q < NG; ++q) {
         acc.x += red[q * CH + tid].x;
         acc.y += red[q * CH + tid].y;
       }
@@ -908,38 +910,38 @@ __global__ __launch_bounds__(256) void k_mvdr_xm(PairArgs a, WindowGeom g, DevDe
                                                  float2* __restrict__ wout,
                                                  int* __restrict__ starts_out,
                                                  int* __restrict__ info) {
-  mvdr_x_body<WCAP, true, 256>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<WCAP, true, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv16(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<16, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<16, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv40(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<40, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<40, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 __global__ __launch_bounds__(256) void k_mvdr_xv64(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<64, false, 256>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<64, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 __global__ __launch_bounds__(64) void k_mvdr_xw40(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<40, false, 64>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<40, false, 64, 16>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                             const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                             hipStream_t s) {
   if (a.wmax > 64) return hipErrorInvalidValue;
-  const XLds lay = x_lds_layout<true, 256>(a.wmax);
+  const XLds lay = x_lds_layout<true, 256, 64>(a.wmax);
   const dim3 grid(a.T * a.K), blk(256);
   if (a.wmax <= 40)
     hipLaunchKernelGGL(k_mvdr_xm<40>, grid, blk, lay.total, s, a, g, d, Yw, out, wout, starts, info);
@@ -954,16 +956,19 @@ hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevD
   if (a.wmax > 64 || (threads == 64 && a.wmax > 40)) return hipErrorInvalidValue;
   const dim3 grid(a.T * a.K);
   if (threads == 64) {
-    const XLds lay = x_lds_layout<false, 64>(a.wmax);
+    const XLds lay = x_lds_layout<false, 64, 16>(a.wmax);
     hipLaunchKernelGGL(k_mvdr_xw40, grid, dim3(64), lay.total, s, a, g, d, Yw, out, wout, starts,
                        info);
     return hipGetLastError();
   }
-  const XLds lay = x_lds_layout<false, 256>(a.wmax);
-  if (a.wmax <= 16)
-    hipLaunchKernelGGL(k_mvdr_xv16, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
+  if (a.wmax <= 16) {
+    const XLds l16 = x_lds_layout<false, 256, 64>(a.wmax);
+    hipLaunchKernelGGL(k_mvdr_xv16, grid, dim3(256), l16.total, s, a, g, d, Yw, out, wout, starts,
                        info);
-  else if (a.wmax <= 40)
+    return hipGetLastError();
+  }
+  const XLds lay = x_lds_layout<false, 256, 64>(a.wmax);
+  if (a.wmax <= 40)
     hipLaunchKernelGGL(k_mvdr_xv40, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
                        info);
   else
@@ -1075,10 +1080,10 @@ hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* 
 hipError_t set_pair_attributes() {
   hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_xm<64>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)x_lds_layout<true, 256>(64).total);
+                                     (int)x_lds_layout<true, 256, 64>(64).total);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_mvdr_xv64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)x_lds_layout<false, 256>(64).total);
+                             (int)x_lds_layout<false, 256, 64>(64).total);
 }
 
 }  // namespace wbm

@@ -156,12 +156,17 @@ struct Fft {
 
   // Radix-8 passes after the first, and the twiddles a thread applies in them: pass q
   // (stride 2^LOGNS, LOGNS = LOGR0 + 3 q) multiplies input r of its butterfly by
-  // w_n^(r * kq * 2^(LOGN - LOGNS - 3)), kq = the butterfly's position within its stride.
-  // They depend only on the thread, so a workgroup loads them once into registers.
+  // w^r, w = w_n^(kq * 2^(LOGN - LOGNS - 3)), kq = the butterfly's position within its stride.
+  // They depend only on the thread, so a workgroup loads them once into registers: all seven
+  // per pass up to two passes; from three passes on only w, w^2 and w^4 (table values), the
+  // others formed by at most two complex products (w^3 = w^2 w, w^5 = w^4 w, w^6 = w^4 w^2,
+  // w^7 = w^4 w^3) so that the large transforms stay within their register budget.
   static constexpr int NP = (LOGN - LOGR0) / 3;
   static constexpr int NPA = NP > 0 ? NP : 1;
+  static constexpr bool kCompact = NP >= 3;
+  static constexpr int NTW = kCompact ? 3 : 7;
 
-  __device__ __forceinline__ static void load_twiddles(float2 (&tr)[NPA][7],
+  __device__ __forceinline__ static void load_twiddles(float2 (&tr)[NPA][NTW],
                                                        const float2* __restrict__ tw) {
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -169,14 +174,20 @@ struct Fft {
       int row, j;
       bf<3>(0, row, j);
       const int step = (j & ((1 << logns) - 1)) << (LOGN - logns - 3);
+      if constexpr (kCompact) {
+        tr[q][0] = tw[step];
+        tr[q][1] = tw[2 * step];
+        tr[q][2] = tw[4 * step];
+      } else {
 #pragma unroll
-      for (int r = 1; r < 8; ++r) tr[q][r - 1] = tw[r * step];
+        for (int r = 1; r < 8; ++r) tr[q][r - 1] = tw[r * step];
+      }
     }
   }
 
   template <int R, int LOGR, int LOGNS>
   __device__ __forceinline__ static void compute_write(float2 (&v)[8], float2* lds,
-                                                       const float2 (&tr)[NPA][7]) {
+                                                       const float2 (&tr)[NPA][NTW]) {
 #pragma unroll
     for (int p = 0; p < 8 / R; ++p) {
       int row, j;
@@ -186,8 +197,23 @@ struct Fft {
       if constexpr (LOGNS > 0) {
         // only radix-8 passes follow the first (LOGNS == 0) pass: one butterfly per thread
         constexpr int q = (LOGNS - LOGR0) / 3;
+        if constexpr (kCompact) {
+          float2 w1 = tr[q][0], w2 = tr[q][1], w4 = tr[q][2];
+          // empty register constraint: keeps the derived twiddles inside the tile loop (the
+          // compiler would otherwise hoist them out and hold all seven per pass again)
+          asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y), "+v"(w4.x), "+v"(w4.y));
+          const float2 w3 = cmul(w2, w1);
+          b[1] = cmul(b[1], w1);
+          b[2] = cmul(b[2], w2);
+          b[3] = cmul(b[3], w3);
+          b[4] = cmul(b[4], w4);
+          b[5] = cmul(b[5], cmul(w4, w1));
+          b[6] = cmul(b[6], cmul(w4, w2));
+          b[7] = cmul(b[7], cmul(w4, w3));
+        } else {
 #pragma unroll
-        for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tr[q][r - 1]);
+          for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tr[q][r - 1]);
+        }
       }
       dftR<R>(b);
       const int base = ((j >> LOGNS) << (LOGNS + LOGR)) | k;
@@ -206,7 +232,7 @@ struct Fft {
 
   template <int LOGNS>
   __device__ __forceinline__ static void rest(float2 (&v)[8], float2* lds,
-                                              const float2 (&tr)[NPA][7]) {
+                                              const float2 (&tr)[NPA][NTW]) {
     if constexpr (LOGNS < LOGN) {
       __syncthreads();
       read8(v, lds);
@@ -227,7 +253,7 @@ struct Fft {
   // twiddles (load_twiddles); on return the transform of every row is in LDS in natural order
   // (addr(row, i)), visible to all threads.
   __device__ __forceinline__ static void run(float2 (&v)[8], float2* lds,
-                                             const float2 (&tr)[NPA][7]) {
+                                             const float2 (&tr)[NPA][NTW]) {
     compute_write<R0, LOGR0, 0>(v, lds, tr);
     rest<LOGR0>(v, lds, tr);
     __syncthreads();
