@@ -103,6 +103,7 @@ struct wbm_plan {
   float2* prof_out = nullptr;
   float2* prof_w = nullptr;
   int* prof_info = nullptr;
+  int* route = nullptr;      // [T_max][K] mixed forms: windows routed to the FP64 kernel
   // loading / window predictor buffers (first use)
   float* pprof = nullptr;    // [K][G][T_max][64] power-profile partials
   float* feat = nullptr;     // [T_max][K][64]
@@ -511,7 +512,7 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   void* bufs[] = {p->twK, p->twM, p->hb, p->desc_dev, p->X, p->Yw, p->Y, p->R32,
                   p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
                   p->prof_out, p->prof_w, p->prof_info, p->pprof, p->feat, p->nnout,
-                  p->pw, p->pdelta, p->jam_dev};
+                  p->pw, p->pdelta, p->jam_dev, p->route};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -683,8 +684,12 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
   } else if (form == WBM_FORM_MIXED || form == WBM_FORM_MIXED_BF16) {
     WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
     WBM_HIP(enqueue_beamspace_windows(p, T, sumW, st), "beamspace launch");
+    if (!p->route) {
+      wbm_status rs = dev_alloc(p, &p->route, (size_t)c.max_targets * c.k_sub, "route flags");
+      if (rs) return rs;
+    }
     WBM_HIP(wbm::launch_mvdr_mixed(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, o, w,
-                                   starts, info, form == WBM_FORM_MIXED, st),
+                                   starts, info, p->route, form == WBM_FORM_MIXED, st),
             "mixed MVDR launch");
   } else {
     GraphKey key;

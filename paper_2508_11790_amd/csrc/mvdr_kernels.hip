@@ -666,20 +666,20 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
 // In-LDS LDL^H factorisation R = L D L^H (L unit lower) by TH threads on a G x G grid
 // (G = 16 or 8), one barrier per column: column j keeps l_ij d_j below the diagonal, d_j on
 // it.  Returns 0, or j + 1 when pivot d_j is not positive and finite (uniform).
-template <int TH>
-__device__ int ldl_lds(C2<double>* R, int RS, int W) {
+template <int TH, typename T = double>
+__device__ int ldl_lds(C2<T>* R, int RS, int W) {
   constexpr int G = TH >= 256 ? 16 : 8;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   for (int j = 0; j < W; ++j) {
-    const double d = R[j * RS + j].x;
-    if (!(d > 0.0) || !(d < INFINITY)) return j + 1;
-    const double inv = 1.0 / d;
+    const T d = R[j * RS + j].x;
+    if (!(d > (T)0) || !(d < (T)INFINITY)) return j + 1;
+    const T inv = (T)1 / d;
     for (int i = j + 1 + ty; i < W; i += G) {
-      const C2<double> gi = R[i * RS + j];
-      const double lx = gi.x * inv, ly = gi.y * inv;   // l_ij
+      const C2<T> gi = R[i * RS + j];
+      const T lx = gi.x * inv, ly = gi.y * inv;         // l_ij
       for (int c = j + 1 + tx; c <= i; c += G) {
-        const C2<double> gc = R[c * RS + j];            // l_cj d_j
-        C2<double> r = R[i * RS + c];
+        const C2<T> gc = R[c * RS + j];                 // l_cj d_j
+        C2<T> r = R[i * RS + c];
         r.x = fma(-lx, gc.x, fma(-ly, gc.y, r.x));      // - l_ij conj(l_cj) d_j
         r.y = fma(-ly, gc.x, fma(lx, gc.y, r.y));
         R[i * RS + c] = r;
@@ -723,6 +723,91 @@ __device__ void ldl_solve(const C2<double>* R, int RS, int W, const double2* av,
   if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
 }
 
+struct PairSetup {
+  int t, k, W, woff, s;
+  int64_t pair;
+  double u, delta;
+};
+
+// The pair of this workgroup, its window (start, width, first row in the window layout; with a
+// per-pair width, the centred sub-window of the gathered one: for widths of equal parity the
+// start moves by half the difference) and its loading.
+__device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowGeom& g,
+                                                const DevDesc& d) {
+  PairSetup ps;
+  pair_of_block(a, d, ps.t, ps.k);
+  ps.W = d.win[ps.t];
+  ps.woff = d.woff[ps.t];
+  ps.pair = (int64_t)ps.t * a.K + ps.k;
+  window_of(g, ps.t, ps.k, &ps.u, &ps.s);
+  if (a.pw) {
+    const int Wp = a.pw[ps.pair];
+    if (Wp >= 1 && Wp <= ps.W && ((ps.W - Wp) & 1) == 0) {
+      const int off = (ps.W - Wp) >> 1;
+      ps.woff += off;
+      ps.s += off;
+      ps.W = Wp;
+    }
+  }
+  ps.delta = a.pdelta ? (double)a.pdelta[ps.pair] : a.delta;
+  return ps;
+}
+
+// Beam outputs on the test snapshots, CH at a time staged like the training chunks (pre holds
+// the first test chunk on entry): thread (row group q = tid / CH, snapshot l = tid % CH) sums
+// window rows i = q mod NG in FP64, then the NG partials are added in order.  Zero outputs
+// when fail.
+template <int PRE, int TH, int CH, bool PLANES>
+__device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, const PairArgs& a,
+                                             int k, int woff, int W, const int* map,
+                                             const int* off, bool aligned, float2* pre, float* z,
+                                             float2* zf, const C2<double>* wv, double2* red,
+                                             int fail, float2* __restrict__ o) {
+  constexpr int NG = TH / CH, RSF = CH + 1;
+  const int tid = threadIdx.x;
+  const int rg = tid / CH, ls = tid % CH;
+  const int nch = (a.Lt + CH - 1) / CH;
+  for (int c = 0; c < nch; ++c) {
+    __syncthreads();   // R / the previous chunk no longer read
+    if constexpr (PLANES)
+      store_planes<PRE>(W, map, pre, z);
+    else
+      store_rows<PRE, RSF>(map, pre, zf);
+    __syncthreads();
+    if (c + 1 < nch)
+      fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt, pre);
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = rg; i < W; i += NG) {
+        double yr, yi;
+        if constexpr (PLANES) {
+          yr = z[i * kXRSP + ls];
+          yi = z[(W + i) * kXRSP + ls];
+        } else {
+          const float2 y = zf[i * RSF + ls];
+          yr = y.x;
+          yi = y.y;
+        }
+        const C2<double> w = wv[i];
+        zx = fma(w.x, yr, fma(w.y, yi, zx));     // conj(w) y
+        zy = fma(w.x, yi, fma(-w.y, yr, zy));
+      }
+    }
+    red[rg * CH + ls] = make_double2(zx, zy);
+    __syncthreads();
+    const int l = c * CH + tid;
+    if (tid < CH && l < a.Lt) {
+      double2 acc = red[tid];
+#pragma unroll
+      for (int q = 1; q < NG; ++q) {
+        acc.x += red[q * CH + tid].x;
+        acc.y += red[q * CH + tid].y;
+      }
+      o[l] = make_float2((float)acc.x, (float)acc.y);
+    }
+  }
+}
+
 template <int WCAP, bool MF, int TH, int CHUNK>
 __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom& g,
                                             const DevDesc& d, const float2* __restrict__ Yw,
@@ -746,33 +831,19 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   // scalar instructions
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-
-  int t, k;
-  pair_of_block(a, d, t, k);
-  int W = d.win[t], woff = d.woff[t];
-  const int64_t pair = (int64_t)t * a.K + k;
-  double u;
-  int s;
-  window_of(g, t, k, &u, &s);
-  if (a.pw) {
-    // centred sub-window: for widths of equal parity the start moves by the half difference
-    const int Wp = a.pw[pair];
-    if (Wp >= 1 && Wp <= W && ((W - Wp) & 1) == 0) {
-      const int off = (W - Wp) >> 1;
-      woff += off;
-      s += off;
-      W = Wp;
-    }
-  }
-  const double delta = a.pdelta ? (double)a.pdelta[pair] : a.delta;
+  const PairSetup ps = pair_setup(a, g, d);
+  const int k = ps.k, W = ps.W, woff = ps.woff;
+  const int64_t pair = ps.pair;
+  const double delta = ps.delta;
+  if (a.route && !a.route[pair]) return;   // solved by the mixed-precision launch
 
   int map[PRE], off[PRE];
   chunk_map<PRE, TH, CH>(a, W, map, off);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
-  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, u, s, i);
-  if (starts_out && tid == 0) starts_out[pair] = s;
+  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  if (starts_out && tid == 0) starts_out[pair] = ps.s;
 
   if constexpr (!MF) {
     GramArgs ga{W, woff, k, 0, 0, 0, 0, lane, aligned};
@@ -846,50 +917,8 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
 
   const int fail = ldl_lds<TH>(R, lay.RS, W);
   if (!fail) ldl_solve(R, lay.RS, W, av, wv);
-  // beam outputs on the test snapshots, CH at a time: thread (row group q = tid / CH, snapshot
-  // l = tid % CH) sums window rows i = q mod NG, then the NG partials are added in order
-  const int rg = tid / CH, ls = tid % CH;
-  float2* o = out + pair * a.Lt;
-  const int nch = (a.Lt + CH - 1) / CH;
-  for (int c = 0; c < nch; ++c) {
-    __syncthreads();   // R / the previous chunk no longer read
-    if constexpr (MF)
-      store_planes<PRE>(W, map, pre, z);
-    else
-      store_rows<PRE, RSF>(map, pre, zf);
-    __syncthreads();
-    if (c + 1 < nch)
-      fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt, pre);
-    double zx = 0.0, zy = 0.0;
-    if (!fail) {
-      for (int i = rg; i < W; i += NG) {
-        double yr, yi;
-        if constexpr (MF) {
-          yr = z[i * kXRSP + ls];
-          yi = z[(W + i) * kXRSP + ls];
-        } else {
-          const float2 y = zf[i * RSF + ls];
-          yr = y.x;
-          yi = y.y;
-        }
-        const C2<double> w = wv[i];
-        zx = fma(w.x, yr, fma(w.y, yi, zx));     // conj(w) y
-        zy = fma(w.x, yi, fma(-w.y, yr, zy));
-      }
-    }
-    red[rg * CH + ls] = make_double2(zx, zy);
-    __syncthreads();
-    const int l = c * CH + tid;
-    if (tid < CH && l < a.Lt) {
-      double2 acc = red[tid];
-#pragma unroll
-      for (int q = 1; q < NG; ++q) {
-        acc.x += red[q * CH + tid].x;
-        acc.y += red[q * CH + tid].y;
-      }
-      o[l] = make_float2((float)acc.x, (float)acc.y);
-    }
-  }
+  apply_chunks<PRE, TH, CH, MF>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red, fail,
+                                out + pair * a.Lt);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
       float2 v = make_float2(0.f, 0.f);
@@ -897,7 +926,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
       wout[pair * a.wmax + i] = v;
     }
   }
-  if (info && tid == 0) info[pair] = fail;
+  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0);
 }
 
 // Matrix-core form, vector form with four waves (held to 128 VGPRs up to 40 bins: four
@@ -1094,20 +1123,18 @@ hipError_t set_pair_attributes() {
 // Im R = G21 - G12.  G runs on MFMA (v_mfma_f32_32x32x16_bf16, FP32 accumulation) over 32 x 32
 // tiles of the lower triangle, either with the BF16-rounded snapshots (one product per tile and
 // step) or with each FP32 snapshot split into BF16 hi + lo parts (hi*hi + hi*lo + lo*hi, three
-// products).  The Cholesky and both triangular solves run in FP32; the residual of one
-// iterative-refinement step and the normalisation a^H R^-1 a run in FP64.  A window whose
-// Cholesky pivots span more than kRouteKappa (condition-number estimate) is routed to the exact
-// path instead: FP64 accumulation of the FP32 snapshots and FP64 Cholesky; its info entry then
-// carries bit 30.
+// products).  The LDL^H factorisation and both triangular solves run in FP32; the residual of
+// the iterative-refinement step and the normalisation a^H R^-1 a run in FP64.  A window whose
+// pivots span more than kRouteKappa (condition-number estimate) is routed to the exact path
+// instead: a second launch runs the exact vector pair kernel on the flagged windows only (FP64
+// accumulation of the FP32 snapshots, FP64 LDL^H); their info entry carries bit 30.  Staging,
+// prefetch, pair order and the apply are those of the fused pair kernels above.
 namespace wbm {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-constexpr int kMixThreads = 256;
-constexpr int kMixCH = 64;                 // snapshots per LDS chunk (4 MFMA k-steps)
-constexpr int kMixRS = kMixCH + 8;         // bf16 row stride (144 B: off the bank period)
-constexpr int kMaxTiles = 10;              // lower-triangle 32x32 tiles of 2W <= 128
+constexpr int kMixRS = 64 + 8;             // bf16 row stride of a staged plane (144 B)
 constexpr double kRouteKappa = 1.0e4;
 constexpr int kInfoRouted = 1 << 30;
 
@@ -1123,279 +1150,324 @@ __device__ __forceinline__ float from_bf16(__bf16 b) {
 }
 
 struct MixLds {
-  size_t zhi, zlo, g, r, diag, wv, av, total;
-  int RS;
+  size_t region, r32, wv, av, red, total;
+  int RS, pad;
 };
 
-__host__ __device__ inline MixLds mix_lds_layout(int wmax) {
+// region: staged BF16 planes, then the tile-packed FP32 Gram; r32: the FP32 complex R and its
+// LDL^H factor; the apply stages its chunks in region.
+__host__ __device__ inline MixLds mix_lds_layout(int wmax, bool split) {
   MixLds p;
-  const int rows = 2 * wmax;
-  const int pad = (rows + 31) / 32 * 32;
-  size_t o = 0;
-  p.zhi = o;
-  o += sizeof(__bf16) * (size_t)pad * kMixRS;
-  p.zlo = o;
-  o += sizeof(__bf16) * (size_t)pad * kMixRS;
-  o = (o + 15) & ~(size_t)15;
-  // G (FP32, pad x pad) aliases the staging area after the last chunk
-  const size_t gbytes = sizeof(float) * (size_t)pad * pad;
-  const size_t ybytes = sizeof(float2) * (size_t)wmax * kCHS;  // FP64-route / apply staging
-  p.g = 0;
-  if (gbytes > o) o = (gbytes + 15) & ~(size_t)15;
-  if (ybytes > o) o = (ybytes + 15) & ~(size_t)15;
   p.RS = wmax + 1;
-  p.r = o;                                               // complex R, FP64 (routing needs it)
-  o += sizeof(C2<double>) * (size_t)wmax * p.RS;
-  p.diag = o;
-  o += sizeof(double) * 64;
-  p.wv = o;
-  o += sizeof(C2<double>) * 64;
-  p.av = o;
-  o += sizeof(double2) * 64;
-  p.total = o;
+  p.pad = (2 * wmax + 31) / 32 * 32;
+  const int nt = p.pad / 32;
+  const size_t planes = sizeof(__bf16) * (size_t)p.pad * kMixRS * (split ? 2 : 1);
+  const size_t gram = sizeof(float) * 1024 * (size_t)(nt * (nt + 1) / 2);
+  size_t a = planes > gram ? planes : gram;
+  a = (a + 15) & ~(size_t)15;
+  const size_t r32 = sizeof(C2<float>) * (size_t)wmax * p.RS;
+  size_t big = a + r32;
+  const size_t zf = sizeof(float2) * (size_t)((wmax + 3) / 4 * 4) * 65;
+  if (zf > big) big = zf;
+  big = (big + 15) & ~(size_t)15;
+  p.region = 0;
+  p.r32 = a;
+  p.wv = big;
+  p.av = p.wv + sizeof(C2<double>) * 64;
+  p.red = p.av + sizeof(double2) * 64;
+  p.total = p.red + sizeof(double2) * 4 * 64;
   return p;
 }
 
-template <bool SPLIT>
-__global__ __launch_bounds__(kMixThreads) void k_mvdr_mixed(PairArgs a, WindowGeom g, DevDesc d,
-                                                            const float2* __restrict__ Yw,
-                                                            float2* __restrict__ out,
-                                                            float2* __restrict__ wout,
-                                                            int* __restrict__ starts_out,
-                                                            int* __restrict__ info) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const MixLds lay = mix_lds_layout(a.wmax);
-  __bf16* zhi = reinterpret_cast<__bf16*>(smem + lay.zhi);
-  __bf16* zlo = reinterpret_cast<__bf16*>(smem + lay.zlo);
-  float* G = reinterpret_cast<float*>(smem + lay.g);
-  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r);
-  double* diag = reinterpret_cast<double*>(smem + lay.diag);
-  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv);
-  double2* av = reinterpret_cast<double2*>(smem + lay.av);
-  float* R32 = reinterpret_cast<float*>(smem + lay.r);   // FP32 view used by the FP32 Cholesky
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  int t, k;
-  pair_of_block(a, d, t, k);
-  const int W = d.win[t], woff = d.woff[t];
-  const int64_t pair = (int64_t)t * a.K + k;
-  double u;
-  int s;
-  window_of(g, t, k, &u, &s);
-  if (tid < W) av[tid] = window_steering(g, u, s, tid);
-  if (starts_out && tid == 0) starts_out[pair] = s;
-
-  const int rows = 2 * W;
-  const int nt = (rows + 31) / 32;
-  const int ntiles = nt * (nt + 1) / 2;
-  f32x16_t acc[3];
+// Registers -> BF16 planes: hi (and lo = BF16(y - hi) when split) of the real parts in rows i,
+// of the imaginary parts in rows W + i.
+template <int PRE, bool SPLIT>
+__device__ __forceinline__ void store_bf16(int W, int pad, const int* map, const float2* pre,
+                                           __bf16* zh) {
+  __bf16* zl = zh + pad * kMixRS;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) acc[q] = f32x16_t{};
-  // this wave's tiles: q-th tile = wave + 4 q
-  for (int c0 = 0; c0 < a.L; c0 += kMixCH) {
-    __syncthreads();
-    // complex snapshots in the source order (as stage_rows), real parts to rows i, imaginary
-    // parts to rows W + i; padding rows stay zero
-    for (int idx = tid; idx < (nt * 32 - rows) * kMixCH; idx += kMixThreads) {
-      const int r = rows + idx / kMixCH, bb = idx % kMixCH;
-      zhi[r * kMixRS + bb] = to_bf16(0.f);
-      if (SPLIT) zlo[r * kMixRS + bb] = to_bf16(0.f);
-    }
-    const bool runs = a.logTB >= 6;
-    const int per = W << a.logTB, tbm = (1 << a.logTB) - 1;
-    for (int idx = tid; idx < W * kMixCH; idx += kMixThreads) {
-      int i, bb;
-      if (runs) {
-        i = idx / kMixCH;
-        bb = idx - i * kMixCH;
-      } else {
-        const int q = idx / per, r = idx - q * per;
-        i = r >> a.logTB;
-        bb = (q << a.logTB) + (r & tbm);
-      }
-      const int b = c0 + bb;
-      const float2 y = (b < a.L) ? load_y<true>(Yw, a, k, woff, s, i, b) : make_float2(0.f, 0.f);
-      const __bf16 hr = to_bf16(y.x), hi = to_bf16(y.y);
-      zhi[i * kMixRS + bb] = hr;
-      zhi[(W + i) * kMixRS + bb] = hi;
+  for (int m = 0; m < PRE; ++m) {
+    if (map[m] >= 0) {
+      const int o = (map[m] >> 8) * kMixRS + (map[m] & 255);
+      const __bf16 hr = to_bf16(pre[m].x), hi = to_bf16(pre[m].y);
+      zh[o] = hr;
+      zh[o + W * kMixRS] = hi;
       if (SPLIT) {
-        zlo[i * kMixRS + bb] = to_bf16(y.x - from_bf16(hr));
-        zlo[(W + i) * kMixRS + bb] = to_bf16(y.y - from_bf16(hi));
+        zl[o] = to_bf16(pre[m].x - from_bf16(hr));
+        zl[o + W * kMixRS] = to_bf16(pre[m].y - from_bf16(hi));
       }
     }
+  }
+}
+
+// BF16 Gram of the training snapshots into the tile-packed FP32 P[tile][32][32]: NT tiles per
+// wave (tile tg + q TG; past ntiles a stand-in tile whose sum is dropped), the four 16-snapshot
+// steps of a chunk split over KS = 4 / TG slices, summed in slice order.
+template <int NT, int PRE, bool SPLIT>
+__device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const PairArgs& a,
+                                          const GramArgs& ga, int pad, const int* map,
+                                          const int* off, float2* pre, __bf16* zh, float* P) {
+  constexpr int CH = 64;
+  const int KS = 4 / ga.TG;
+  const __bf16* zl = zh + pad * kMixRS;
+  int ra[NT], rb[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    int tile = ga.tg + q * ga.TG, ti, tj;
+    if (tile >= ga.ntiles) tile = 0;
+    tri_index(tile, ti, tj);
+    ra[q] = (ti * 32 + (ga.lane & 31)) * kMixRS + (ga.lane >> 5) * 8;
+    rb[q] = (tj * 32 + (ga.lane & 31)) * kMixRS + (ga.lane >> 5) * 8;
+  }
+  f32x16_t acc[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q) acc[q] = f32x16_t{};
+  for (int c0 = 0; c0 < a.L; c0 += CH) {
+    __syncthreads();   // previous chunk consumed
+    store_bf16<PRE, SPLIT>(ga.W, pad, map, pre, zh);
     __syncthreads();
+    if (c0 + CH < a.L)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+    else if (a.Lt > 0)
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+    for (int st = ga.kq; st < CH / 16; st += KS) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int tile = wave + 4 * q;
-      if (tile < ntiles) {
-        int ti, tj;
-        tri_index(tile, ti, tj);
-        const int ra = ti * 32 + (lane & 31), rb = tj * 32 + (lane & 31);
-        const int kofs = (lane >> 5) * 8;
+      for (int q = 0; q < NT; ++q) {
+        const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(zh + ra[q] + st * 16);
+        const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(zh + rb[q] + st * 16);
+        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[q], 0, 0, 0);
+        if (SPLIT) {
+          const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(zl + ra[q] + st * 16);
+          const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(zl + rb[q] + st * 16);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[q], 0, 0, 0);
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[q], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // C layout of the 32 x 32 MFMA: column lane % 32, row 8 (r / 4) + 4 (lane / 32) + r % 4
+  for (int sl = 0; sl < KS; ++sl) {
+    __syncthreads();
+    if (ga.kq == sl) {
 #pragma unroll
-        for (int ks = 0; ks < kMixCH; ks += 16) {
-          const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(zhi + ra * kMixRS + ks + kofs);
-          const bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(zhi + rb * kMixRS + ks + kofs);
-          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc[q], 0, 0, 0);
-          if (SPLIT) {
-            const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(zlo + ra * kMixRS + ks + kofs);
-            const bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(zlo + rb * kMixRS + ks + kofs);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc[q], 0, 0, 0);
-            acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc[q], 0, 0, 0);
+      for (int q = 0; q < NT; ++q) {
+        const int tile = ga.tg + q * ga.TG;
+        if (tile < ga.ntiles) {
+          float* dst = P + (size_t)tile * 1024 + (ga.lane & 31);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r >> 2) + 4 * (ga.lane >> 5) + (r & 3);
+            dst[row * 32] = (sl == 0 ? 0.f : dst[row * 32]) + acc[q][r];
           }
         }
       }
     }
   }
-  __syncthreads();   // staging no longer read; G aliases it
-  const int pad = nt * 32;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int tile = wave + 4 * q;
-    if (tile < ntiles) {
-      int ti, tj;
-      tri_index(tile, ti, tj);
-      const int col = tj * 32 + (lane & 31);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        G[row * pad + col] = acc[q][r];
-      }
-    }
+}
+
+// Entry (r, c) of the tile-packed Gram, r >= c tile-wise.
+__device__ __forceinline__ float gram32(const float* P, int r, int c) {
+  const int ti = r >> 5, tj = c >> 5;
+  return P[(size_t)(ti * (ti + 1) / 2 + tj) * 1024 + (r & 31) * 32 + (c & 31)];
+}
+
+template <int WCAP, bool SPLIT>
+__device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowGeom& g,
+                                                const DevDesc& d, const float2* __restrict__ Yw,
+                                                float2* __restrict__ out,
+                                                float2* __restrict__ wout,
+                                                int* __restrict__ starts_out,
+                                                int* __restrict__ info, int* __restrict__ flags) {
+  constexpr int TH = 256, CH = 64;
+  using Cap = XCap<WCAP, TH, CH>;
+  constexpr int PRE = Cap::kPre;
+  constexpr int kMaxT = WCAP <= 48 ? 2 : 3;   // 32 x 32 tiles per wave
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MixLds lay = mix_lds_layout(a.wmax, SPLIT);
+  __bf16* zh = reinterpret_cast<__bf16*>(smem + lay.region);
+  float* P = reinterpret_cast<float*>(smem + lay.region);
+  float2* zf = reinterpret_cast<float2*>(smem + lay.region);
+  C2<float>* R32 = reinterpret_cast<C2<float>*>(smem + lay.r32);
+  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv);
+  double2* av = reinterpret_cast<double2*>(smem + lay.av);
+  double2* red = reinterpret_cast<double2*>(smem + lay.red);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const PairSetup ps = pair_setup(a, g, d);
+  const int k = ps.k, W = ps.W, woff = ps.woff;
+  const int64_t pair = ps.pair;
+  const double delta = ps.delta;
+  const int RS = lay.RS, pad = lay.pad;
+
+  int map[PRE], off[PRE];
+  chunk_map<PRE, TH, CH>(a, W, map, off);
+  const bool aligned = (a.L % CH) == 0;
+  float2 pre[PRE];
+  fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
+  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  if (starts_out && tid == 0) starts_out[pair] = ps.s;
+
+  const int rows = 2 * W;
+  const int nt = (rows + 31) >> 5;
+  const int ntiles = nt * (nt + 1) / 2;
+  const int TG = mfma_tile_groups(ntiles, kMaxT);
+  const int NT = (ntiles + TG - 1) / TG;
+  // plane rows 2W .. 32 nt - 1 stay zero for the whole loop
+  for (int e = tid; e < (nt * 32 - rows) * kMixRS; e += TH) {
+    zh[rows * kMixRS + e] = to_bf16(0.f);
+    if (SPLIT) zh[(pad + rows) * kMixRS + e] = to_bf16(0.f);
   }
+  GramArgs ga{W, woff, k, ntiles, TG, wave % TG, wave / TG, lane, aligned};
+  if (NT == 1) gram_bf16<1, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
+  else if (NT == 2) gram_bf16<2, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
+  else if constexpr (kMaxT >= 3) gram_bf16<3, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
   __syncthreads();
-  // complex R (lower) from the real Gram, scaled and loaded; FP32 copy for the FP32 Cholesky
-  const int RS = lay.RS;
+  // FP32 complex R (lower) from the Gram, scaled and loaded
   const float invL = 1.0f / (float)a.L;
-  for (int e = tid; e < W * W; e += kMixThreads) {
+  for (int e = tid; e < W * W; e += TH) {
     const int i = e / W, j = e - i * W;
     if (j <= i) {
-      const float g11 = G[i * pad + j], g22 = G[(W + i) * pad + (W + j)];
-      const float g21 = G[(W + i) * pad + j], g12t = G[(W + j) * pad + i];   // G12[i][j] = G[W+j][i]
-      float re = (g11 + g22) * invL, im = (g21 - g12t) * invL;
+      float re = (gram32(P, i, j) + gram32(P, W + i, W + j)) * invL;
+      float im = (gram32(P, W + i, j) - gram32(P, W + j, i)) * invL;
       if (i == j) {
-        re += (float)a.delta;
+        re += (float)delta;
         im = 0.f;
       }
-      R32[2 * (i * RS + j)] = re;       // FP32 complex in the first half of R's storage
-      R32[2 * (i * RS + j) + 1] = im;
+      R32[i * RS + j] = c2<float>(re, im);
     }
   }
   __syncthreads();
-  C2<float>* Rf = reinterpret_cast<C2<float>*>(R32);
-  float* diagf = reinterpret_cast<float*>(diag);
-  int fail = chol_lds<float, kMixThreads>(Rf, RS, diagf, W);
-  // condition estimate from the pivots: (max / min)^2
+  int fail = ldl_lds<TH, float>(R32, RS, W);
+  // condition estimate from the pivots: max d / min d (d = squared Cholesky pivots)
   bool route = fail != 0;
   if (!fail) {
     float dmax = 0.f, dmin = 3.0e38f;
     for (int j = 0; j < W; ++j) {
-      dmax = fmaxf(dmax, diagf[j]);
-      dmin = fminf(dmin, diagf[j]);
+      dmax = fmaxf(dmax, R32[j * RS + j].x);
+      dmin = fminf(dmin, R32[j * RS + j].x);
     }
-    route = (double)dmax * dmax > kRouteKappa * (double)dmin * dmin;
+    route = (double)dmax > kRouteKappa * (double)dmin;
   }
   __syncthreads();
   if (!route) {
-    // FP32 solves of R x = a, one FP64-residual refinement, FP64 normalisation (wave 0)
+    // wave 0: two refinement steps x += R^-1 (a - R x), the residual in FP64 with R the
+    // MFMA-formed matrix read back from the Gram, the correction from the FP32 factor; then
+    // q = a^H x in FP64 and w = x / q
     if (tid < 64) {
-      C2<double> x = c2<double>(0, 0);
-      C2<double> b = c2<double>(0, 0);
+      const float invd = (lane < W) ? 1.0f / R32[lane * RS + lane].x : 0.f;
+      C2<double> x = c2<double>(0.0, 0.0);
+      C2<double> b = c2<double>(0.0, 0.0);
       if (lane < W) b = c2<double>(av[lane].x, av[lane].y);
+      const double iL = 1.0 / (double)a.L;
       for (int it = 0; it < 2; ++it) {
-        // rhs = b - R x in FP64 with R the MFMA-formed matrix, read back from the Gram G
-        // (lower tiles): R_ij = (G[i][j] + G[W+i][W+j] + i (G[W+i][j] - G[W+j][i])) / L for
-        // i >= j, R_ij = conj(R_ji) above the diagonal, + delta on it.
-        C2<float> v = c2<float>(0.f, 0.f);
-        {
-          double rx = 0.0, ry = 0.0;
-          for (int j = 0; j < W; ++j) {
-            const double xj_x = __shfl(x.x, j), xj_y = __shfl(x.y, j);
-            if (lane < W) {
-              const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
-              double re = ((double)G[hi * pad + lo] + (double)G[(W + hi) * pad + (W + lo)]) / a.L;
-              double im = ((double)G[(W + hi) * pad + lo] - (double)G[(W + lo) * pad + hi]) / a.L;
-              if (lane < j) im = -im;
-              if (lane == j) {
-                re += a.delta;
-                im = 0.0;
-              }
-              rx += re * xj_x - im * xj_y;
-              ry += re * xj_y + im * xj_x;
-            }
-          }
-          if (lane < W) v = c2<float>((float)(b.x - rx), (float)(b.y - ry));
-        }
-        // dx = R^-1 rhs in FP32: forward then backward substitution with the factor
+        double rx = 0.0, ry = 0.0;
         for (int j = 0; j < W; ++j) {
-          const float dinv = 1.0f / diagf[j];
-          const float vx = __shfl(v.x, j) * dinv, vy = __shfl(v.y, j) * dinv;
-          if (lane == j) {
-            v = c2<float>(vx, vy);
-          } else if (lane > j && lane < W) {
-            const C2<float> gg = Rf[lane * RS + j];
-            v.x -= gg.x * vx - gg.y * vy;
-            v.y -= gg.x * vy + gg.y * vx;
+          const double xjx = __shfl(x.x, j), xjy = __shfl(x.y, j);
+          if (lane < W) {
+            const int hi = lane >= j ? lane : j, lo = lane >= j ? j : lane;
+            double re = ((double)gram32(P, hi, lo) + (double)gram32(P, W + hi, W + lo)) * iL;
+            double im = ((double)gram32(P, W + hi, lo) - (double)gram32(P, W + lo, hi)) * iL;
+            if (lane < j) im = -im;
+            if (lane == j) {
+              re += delta;
+              im = 0.0;
+            }
+            rx += re * xjx - im * xjy;
+            ry += re * xjy + im * xjx;
           }
         }
+        C2<float> v = c2<float>(0.f, 0.f);
+        if (lane < W) v = c2<float>((float)(b.x - rx), (float)(b.y - ry));
+        // L y = v, y /= d, L^H z = y (FP32, unit L with l_ij = R32_ij / d_j)
+        for (int j = 0; j < W; ++j) {
+          const float ivj = __shfl(invd, j);
+          const float yx = __shfl(v.x, j) * ivj, yy = __shfl(v.y, j) * ivj;
+          if (lane > j && lane < W) {
+            const C2<float> gg = R32[lane * RS + j];
+            v.x -= gg.x * yx - gg.y * yy;
+            v.y -= gg.x * yy + gg.y * yx;
+          }
+        }
+        v.x *= invd;
+        v.y *= invd;
         for (int j = W - 1; j >= 0; --j) {
-          const float dinv = 1.0f / diagf[j];
-          const float xx = __shfl(v.x, j) * dinv, xy = __shfl(v.y, j) * dinv;
-          if (lane == j) {
-            v = c2<float>(xx, xy);
-          } else if (lane < j) {
-            const C2<float> gg = Rf[j * RS + lane];
-            v.x -= gg.x * xx + gg.y * xy;
-            v.y -= gg.x * xy - gg.y * xx;
+          const float zx = __shfl(v.x, j), zy = __shfl(v.y, j);
+          if (lane < j) {
+            const C2<float> gg = R32[j * RS + lane];
+            v.x -= (gg.x * zx + gg.y * zy) * invd;
+            v.y -= (gg.x * zy - gg.y * zx) * invd;
           }
         }
         x.x += (double)v.x;
         x.y += (double)v.y;
       }
-      // q = a^H x in FP64 (real for Hermitian positive definite R)
       double qq = (lane < W) ? b.x * x.x + b.y * x.y : 0.0;
-      for (int off = 32; off > 0; off >>= 1) qq += __shfl_xor(qq, off);
+      for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
       if (lane < W) wv[lane] = c2<double>(x.x / qq, x.y / qq);
     }
   } else {
-    // exact route: FP64 accumulation of the FP32 snapshots and FP64 Cholesky
-    float2* ys = reinterpret_cast<float2*>(smem);
-    pair_covariance<double, true, kMixThreads, 9>(Yw, a, k, W, woff, s, ys, R, RS, a.delta);
-    fail = chol_lds<double, kMixThreads>(R, RS, diag, W);
-    if (!fail) solve_lds<double>(R, RS, diag, W, av, wv);
+    // the exact FP64 path solves this window in the second launch
+    if (tid == 0) {
+      flags[pair] = 1;
+      if (info) info[pair] = kInfoRouted;
+    }
+    return;
   }
-  apply_staged<kMixThreads>(Yw, a, k, woff, s, W, fail, wv, reinterpret_cast<float2*>(smem),
-                            out + pair * a.Lt);
+  if (tid == 0) flags[pair] = 0;
+  apply_chunks<PRE, TH, CH, false>(Yw, a, k, woff, W, map, off, aligned, pre, nullptr, zf, wv,
+                                   red, fail, out + pair * a.Lt);
   if (wout) {
-    for (int i = tid; i < a.wmax; i += kMixThreads) {
+    for (int i = tid; i < a.wmax; i += TH) {
       float2 v = make_float2(0.f, 0.f);
       if (!fail && i < W) v = make_float2((float)wv[i].x, (float)wv[i].y);
       wout[pair * a.wmax + i] = v;
     }
   }
-  if (info && tid == 0) info[pair] = fail | (route ? kInfoRouted : 0);
+  if (info && tid == 0) info[pair] = fail;
+}
+
+template <int WCAP, bool SPLIT>
+__global__ __launch_bounds__(256) void k_mvdr_mx(PairArgs a, WindowGeom g, DevDesc d,
+                                                 const float2* __restrict__ Yw,
+                                                 float2* __restrict__ out,
+                                                 float2* __restrict__ wout,
+                                                 int* __restrict__ starts_out,
+                                                 int* __restrict__ info, int* __restrict__ flags) {
+  mvdr_mixed_body<WCAP, SPLIT>(a, g, d, Yw, out, wout, starts_out, info, flags);
+}
+
+template <int WCAP, bool SPLIT>
+static hipError_t mixed_launch(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                               const float2* Yw, float2* out, float2* wout, int* starts,
+                               int* info, int* flags, hipStream_t s) {
+  const MixLds lay = mix_lds_layout(a.wmax, SPLIT);
+  if (lay.total > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mx<WCAP, SPLIT>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)lay.total);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_mvdr_mx<WCAP, SPLIT>), dim3(a.T * a.K), dim3(256), lay.total, s, a, g, d,
+                     Yw, out, wout, starts, info, flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
-                             bool split, hipStream_t s) {
-  if (a.wmax > 64) return hipErrorInvalidValue;
-  MixLds lay = mix_lds_layout(a.wmax);
-  const unsigned grid = (unsigned)(a.T * a.K);
-  if (split) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mixed<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mvdr_mixed<true>, dim3(grid), dim3(kMixThreads), lay.total, s, a, g, d, Yw,
-                       out, wout, starts, info);
-  } else {
-    hipError_t e = hipFuncSetAttribute((const void*)k_mvdr_mixed<false>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lay.total);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mvdr_mixed<false>, dim3(grid), dim3(kMixThreads), lay.total, s, a, g, d,
-                       Yw, out, wout, starts, info);
-  }
-  return hipGetLastError();
+                             int* flags, bool split, hipStream_t s) {
+  if (a.wmax > 64 || !flags) return hipErrorInvalidValue;
+  hipError_t e;
+  if (a.wmax <= 40)
+    e = split ? mixed_launch<40, true>(a, g, d, Yw, out, wout, starts, info, flags, s)
+              : mixed_launch<40, false>(a, g, d, Yw, out, wout, starts, info, flags, s);
+  else
+    e = split ? mixed_launch<64, true>(a, g, d, Yw, out, wout, starts, info, flags, s)
+              : mixed_launch<64, false>(a, g, d, Yw, out, wout, starts, info, flags, s);
+  if (e != hipSuccess) return e;
+  // second launch: the routed windows on the exact FP64 vector kernel
+  PairArgs r = a;
+  r.route = flags;
+  return launch_mvdr_vector(r, g, d, Yw, out, wout, starts, info, 256, s);
 }
 
 }  // namespace wbm

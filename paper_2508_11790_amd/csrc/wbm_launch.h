@@ -47,6 +47,9 @@ struct PairArgs {
   // and per-pair loading [T][K]; nullptr = the target's window / delta
   const int* pw = nullptr;
   const float* pdelta = nullptr;
+  // optional [T][K] flags: when set, the fused pair kernels solve only the flagged pairs (the
+  // mixed forms' windows routed to FP64) and mark their info with bit 30
+  const int* route = nullptr;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
 // solve -> apply, reading the window rows written by the beamspace kernel.
@@ -60,9 +63,10 @@ bool mvdr_wave_supported(int wmax);
 // Mixed-precision pair kernel: MFMA BF16 covariance (split = BF16 hi/lo, three products;
 // else one BF16 product) with FP32 accumulation, FP32 Cholesky and solves, FP64 refinement
 // residual and normalisation; ill-conditioned windows routed to FP64 (info bit 30).
+// flags: [T][K] int scratch written by the first launch (1 = routed), read by the second.
 hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
-                             bool split, hipStream_t s);
+                             int* flags, bool split, hipStream_t s);
 // Plain per-stage FP32 form reading the full beamspace Y [K][M][B]: gather + covariance,
 // Cholesky + solve, apply -- three launches with R and w in HBM.
 hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* Y,
