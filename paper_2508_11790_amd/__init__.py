@@ -85,21 +85,24 @@ class Plan:
 
     _PAIR_KERNELS = {"mfma": _lib.PAIR_MFMA, "wave": _lib.PAIR_WAVE, "block": _lib.PAIR_BLOCK}
 
-    def set_tuning(self, chan_logtile: int, beam_logtile: int, pair_kernel: str = "mfma"):
-        """Pin the fused form's FFT tiles (log2 complex per workgroup: 11..13) and pair kernel
-        ("mfma", "wave" or "block"); skips the first call's timing search."""
+    def set_tuning(self, chan_logtile: int, beam_logtile: int, pair_kernel: str = "block",
+                   overlap: int = 1):
+        """Pin the fused form's FFT tiles (log2 complex per workgroup: 11..13), pair kernel
+        ("mfma", "wave" or "block") and subband chunks overlapping the spatial DFT with the pair
+        kernel (1, 2, 4, 8); skips the first call's timing search."""
         if pair_kernel not in self._PAIR_KERNELS:
             raise ValueError(f"pair_kernel must be one of {sorted(self._PAIR_KERNELS)}")
         _lib.check(_lib.load().wbm_plan_set_tuning(self._h, int(chan_logtile), int(beam_logtile),
-                                                   self._PAIR_KERNELS[pair_kernel]))
+                                                   self._PAIR_KERNELS[pair_kernel], int(overlap)))
 
     @property
     def tuning(self):
-        """(chan_logtile, beam_logtile, pair_kernel name) currently in use."""
-        c, b, p = C.c_int32(), C.c_int32(), C.c_int32()
-        _lib.check(_lib.load().wbm_plan_get_tuning(self._h, C.byref(c), C.byref(b), C.byref(p)))
+        """(chan_logtile, beam_logtile, pair_kernel name, overlap chunks) currently in use."""
+        c, b, p, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.load().wbm_plan_get_tuning(self._h, C.byref(c), C.byref(b), C.byref(p),
+                                                   C.byref(o)))
         name = {v: k for k, v in self._PAIR_KERNELS.items()}[p.value]
-        return int(c.value), int(b.value), name
+        return int(c.value), int(b.value), name, int(o.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -57,8 +57,8 @@ def load() -> C.CDLL:
     lib.wbm_plan_destroy.argtypes = [P]
     lib.wbm_plan_workspace_bytes.argtypes = [P]
     lib.wbm_plan_workspace_bytes.restype = I64
-    lib.wbm_plan_set_tuning.argtypes = [P, I32, I32, I32]
-    lib.wbm_plan_get_tuning.argtypes = [P, P, P, P]
+    lib.wbm_plan_set_tuning.argtypes = [P, I32, I32, I32, I32]
+    lib.wbm_plan_get_tuning.argtypes = [P, P, P, P, P]
     lib.wbm_beamform.argtypes = [P, P, P, P, I32, D, I32, P, P, P, P, P]
     lib.wbm_channelize.argtypes = [P, P, P, P]
     lib.wbm_beamspace.argtypes = [P, P, P, P]

@@ -45,6 +45,8 @@ int ilog2i(int v) {
   return l;
 }
 
+constexpr int kMaxOverlap = 8;
+
 struct GraphKey {
   const void* x = nullptr;
   void* out = nullptr;
@@ -69,7 +71,11 @@ struct wbm_plan {
   int logTB = 0, TB = 0, nbt = 0;     // beamspace tile (snapshots per workgroup) of the fused form
   int chan_logtile = 12, beam_logtile = 12;
   int pair_threads = WBM_PAIR_MFMA;   // fused MVDR pair kernel: WBM_PAIR_*
+  int overlap = 1;                    // subband chunks overlapping beamspace and pair kernels
   bool tuned = false;
+  // second stream of the overlapped fused sequence and its fork / join events
+  hipStream_t side_stream = nullptr;
+  hipEvent_t chunk_evt[kMaxOverlap + 1] = {};
   int device = 0;
   // tables
   float2* twK = nullptr;
@@ -275,16 +281,60 @@ hipError_t enqueue_beamspace_windows(wbm_plan* p, int T, int sumW, hipStream_t s
                                p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st);
 }
 
+bool overlap_supported(const wbm_plan* p, int chunks) {
+  return chunks == 1 || (chunks >= 2 && chunks <= kMaxOverlap && (chunks & (chunks - 1)) == 0 &&
+                         p->cfg.k_sub % (8 * chunks) == 0);
+}
+
+hipError_t ensure_side_stream(wbm_plan* p) {
+  if (p->side_stream) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
+  for (int i = 0; i <= kMaxOverlap && e == hipSuccess; ++i)
+    e = hipEventCreateWithFlags(&p->chunk_evt[i], hipEventDisableTiming);
+  return e;
+}
+
 // Channelize -> windowed beamspace -> fused MVDR on stream st (the beamspace and pair
-// kernels place the windows themselves).
+// kernels place the windows themselves).  With C > 1 overlap chunks the subbands are split in
+// C ranges: the pair kernel of range c runs on the plan's second stream while the beamspace
+// kernel of range c + 1 streams on st (the first is HBM-bound, the second latency- or
+// FP64-bound), joined back into st at the end; under graph capture this becomes a fork / join.
 hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
-                         float2* out, float2* wout, int* starts, int* info, hipStream_t st) {
+                         float2* out, float2* wout, int* starts, int* info, hipStream_t st,
+                         int chunks) {
   hipError_t e = enqueue_channelize(p, x, st);
   if (e != hipSuccess) return e;
-  e = enqueue_beamspace_windows(p, T, sumW, st);
-  if (e != hipSuccess) return e;
-  return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, out,
-                                wout, starts, info, p->pair_threads, st);
+  const wbm_config& c = p->cfg;
+  if (chunks <= 1 || !overlap_supported(p, chunks)) {
+    e = enqueue_beamspace_windows(p, T, sumW, st);
+    if (e != hipSuccess) return e;
+    return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, out,
+                                  wout, starts, info, p->pair_threads, st);
+  }
+  if ((e = ensure_side_stream(p)) != hipSuccess) return e;
+  const int kc = c.k_sub / chunks;
+  for (int ch = 0; ch < chunks && e == hipSuccess; ++ch) {
+    e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
+                              p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st, nullptr, 0, 0,
+                              ch * kc, kc);
+    if (e == hipSuccess) e = hipEventRecord(p->chunk_evt[ch], st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(p->side_stream, p->chunk_evt[ch], 0);
+    if (e == hipSuccess) {
+      wbm::PairArgs a = pair_args(p, T, sumW, loading);
+      a.k0 = ch * kc;
+      a.kc = kc;
+      e = wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, out, wout, starts, info,
+                                 p->pair_threads, p->side_stream);
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->chunk_evt[chunks], p->side_stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, p->chunk_evt[chunks], 0);
+  return e;
+}
+
+hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
+                         float2* out, float2* wout, int* starts, int* info, hipStream_t st) {
+  return enqueue_fused(p, x, T, sumW, loading, out, wout, starts, info, st, p->overlap);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -303,7 +353,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p2";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p3";
   return os.str();
 }
 
@@ -314,9 +364,10 @@ std::string cache_path() {
   return std::string(home ? home : "/tmp") + "/.cache/wbmvdr/autotune.json";
 }
 
-// The cache file is a flat JSON object {"key": [chan_logtile, beam_logtile, pair_kernel], ...}
+// The cache file is a flat JSON object
+// {"key": [chan_logtile, beam_logtile, pair_kernel, overlap_chunks], ...}
 // (pair_kernel: 1 = FP64 matrix-core kernel, 64 / 256 = vector kernel with that many threads).
-bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr) {
+bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr, int* ovl) {
   std::ifstream f(cache_path());
   if (!f) return false;
   std::stringstream ss;
@@ -325,17 +376,19 @@ bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr) {
   const std::string pat = "\"" + key + "\": [";
   const size_t pos = txt.find(pat);
   if (pos == std::string::npos) return false;
-  int a = 0, b = 0, c = 0;
-  if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d", &a, &b, &c) != 3) return false;
+  int a = 0, b = 0, c = 0, o = 0;
+  if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d, %d", &a, &b, &c, &o) != 4)
+    return false;
   if (!wbm::fft_logtile_supported(a) || !wbm::fft_logtile_supported(b)) return false;
   if (c != WBM_PAIR_MFMA && c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK) return false;
   *chan = a;
   *beam = b;
   *thr = c;
+  *ovl = o;
   return true;
 }
 
-void cache_store(const std::string& key, int chan, int beam, int thr) {
+void cache_store(const std::string& key, int chan, int beam, int thr, int ovl) {
   const std::string path = cache_path();
   std::string txt;
   {
@@ -352,7 +405,7 @@ void cache_store(const std::string& key, int chan, int beam, int thr) {
   while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
   std::ostringstream os;
   os << "{" << body << (body.empty() ? "" : ",") << "\n  \"" << key << "\": [" << chan << ", "
-     << beam << ", " << thr << "]\n}\n";
+     << beam << ", " << thr << ", " << ovl << "]\n}\n";
   const size_t slash = path.rfind('/');
   if (slash != std::string::npos) {
     std::string dir = path.substr(0, slash);
@@ -394,11 +447,12 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   const char* env = std::getenv("WBM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
   const std::string key = tune_key(p);
-  int chan = 12, beam = 12, thr = WBM_PAIR_MFMA;
-  if (cache_lookup(key, &chan, &beam, &thr)) {
+  int chan = 12, beam = 12, thr = WBM_PAIR_MFMA, ovl = 1;
+  if (cache_lookup(key, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl)) {
     p->chan_logtile = chan;
     set_beam_tile(p, beam);
     p->pair_threads = thr;
+    p->overlap = ovl;
     return hipSuccess;
   }
   float best_c = 1e30f, best_b = 1e30f;
@@ -440,7 +494,23 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
     }
   }
   p->pair_threads = thr;
-  cache_store(key, chan, beam, thr);
+  // subband chunks overlapping the beamspace and pair kernels: the whole fused sequence
+  float best_o = 1e30f;
+  for (int ch = 1; ch <= kMaxOverlap; ch <<= 1) {
+    if (!overlap_supported(p, ch)) continue;
+    float ms;
+    e = time_best([&]() {
+      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr, p->prof_info,
+                           st, ch);
+    }, st, &ms);
+    if (e != hipSuccess) return e;
+    if (ms < best_o) {
+      best_o = ms;
+      ovl = ch;
+    }
+  }
+  p->overlap = ovl;
+  cache_store(key, chan, beam, thr, ovl);
   return hipSuccess;
 }
 
@@ -475,7 +545,8 @@ const char* wbm_status_str(wbm_status s) {
 
 int64_t wbm_plan_workspace_bytes(const wbm_plan* p) { return p ? p->ws_bytes : 0; }
 
-wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t pair) {
+wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t pair,
+                               int32_t overlap) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
   if (!wbm::fft_logtile_supported(chan) || !wbm::fft_logtile_supported(beam))
     return fail(WBM_ERR_ARG, "FFT tile log2 must be 11, 12 or 13");
@@ -483,19 +554,26 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
     return fail(WBM_ERR_ARG, "pair_kernel must be WBM_PAIR_MFMA, WBM_PAIR_WAVE or WBM_PAIR_BLOCK");
   if (pair == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max))
     return fail(WBM_ERR_UNSUPPORTED, "the one-wave pair kernel needs w_max <= 40");
+  if (overlap != 1 && overlap != 2 && overlap != 4 && overlap != 8)
+    return fail(WBM_ERR_ARG, "overlap_chunks must be 1, 2, 4 or 8");
+  if (!overlap_supported(p, overlap))
+    return fail(WBM_ERR_UNSUPPORTED, "overlap_chunks needs K to be a multiple of 8 * chunks");
   p->chan_logtile = chan;
   set_beam_tile(p, beam);
   p->pair_threads = pair;
+  p->overlap = overlap;
   p->tuned = true;
   p->gkey.valid = false;
   return WBM_OK;
 }
 
-wbm_status wbm_plan_get_tuning(const wbm_plan* p, int32_t* chan, int32_t* beam, int32_t* pair) {
+wbm_status wbm_plan_get_tuning(const wbm_plan* p, int32_t* chan, int32_t* beam, int32_t* pair,
+                               int32_t* overlap) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
   if (chan) *chan = p->chan_logtile;
   if (beam) *beam = p->beam_logtile;
   if (pair) *pair = p->pair_threads;
+  if (overlap) *overlap = p->overlap;
   return WBM_OK;
 }
 
@@ -505,6 +583,9 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   (void)hipDeviceSynchronize();
   if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  for (hipEvent_t ev : p->chunk_evt)
+    if (ev) (void)hipEventDestroy(ev);
   if (p->desc_evt) (void)hipEventDestroy(p->desc_evt);
   if (p->desc_host) (void)hipHostFree(p->desc_host);
   if (p->jam_evt) (void)hipEventDestroy(p->jam_evt);

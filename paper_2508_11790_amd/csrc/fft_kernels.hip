@@ -109,7 +109,7 @@ template <int LOGM, int LOGT>
 __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
     const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int N, int B,
     int K, const float2* __restrict__ twM, float scale, const int* __restrict__ rowtab, int sumW,
-    WindowGeom g, float* __restrict__ prof, int L) {
+    WindowGeom g, float* __restrict__ prof, int L, int k0) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   constexpr int M = F::n, TB = F::rows;
   constexpr int LOGTB = fft_tile(LOGM, LOGT) - LOGM;
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   int* s_center = s_dyn + g.T;                             // [T] beam bins (profile centre)
   float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);  // [T][64] profile sums (prof)
   int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);      // [sumW] bin of window row r (Yw)
-  const int k = blockIdx.y;
+  const int k = k0 + blockIdx.y;
   const int nbt = (B + TB - 1) / TB;
   float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twM);
@@ -243,7 +243,8 @@ static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const fl
 template <int LOGM, int LOGT>
 static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
                               const float2* twM, const int* rowtab, int sumW,
-                              const WindowGeom& g, float* prof, int L, int G, hipStream_t s) {
+                              const WindowGeom& g, float* prof, int L, int G, int k0, int kc,
+                              hipStream_t s) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   const int nbt = (B + F::rows - 1) / F::rows;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
@@ -261,12 +262,12 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
   if (!prof) {
     static int resident = 0;
     const int cap = resident_blocks(k_beamspace<LOGM, LOGT>, F::threads, shm, &resident);
-    gx = (cap + K - 1) / K;
+    gx = (cap + kc - 1) / kc;
     if (gx > nbt) gx = nbt;
     if (gx < 1) gx = 1;
   }
-  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), dim3(gx, K), dim3(F::threads), shm, s, X, Y, Yw, N,
-                     B, K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L);
+  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), dim3(gx, kc), dim3(F::threads), shm, s, X, Y, Yw, N,
+                     B, K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L, k0);
   return hipGetLastError();
 }
 
@@ -308,11 +309,14 @@ int beamspace_tiles(int M, int B, int logtile) {
 
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
                             const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
-                            int logtile, hipStream_t s, float* prof, int L, int G) {
+                            int logtile, hipStream_t s, float* prof, int L, int G, int k0,
+                            int kc) {
   const int lm = ilog2(M);
-#define C(LG, T)                                                                     \
-  case LG:                                                                           \
-    return beam_launch<LG, T>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, prof, L, G, s);
+  if (kc < 0) kc = K - k0;
+  if (k0 < 0 || kc < 1 || k0 + kc > K) return hipErrorInvalidValue;
+#define C(LG, T)                                                                          \
+  case LG:                                                                                \
+    return beam_launch<LG, T>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, prof, L, G, k0, kc, s);
   switch (logtile) {
     case 11:
       switch (lm) { WBM_LOG_CASES(C, 11) }

@@ -70,20 +70,22 @@ __device__ __forceinline__ void tri_index(int e, int& i, int& j) {
   j = e - ii * (ii + 1) / 2;
 }
 
-// Workgroup -> (target, subband) of the pair kernels.  Workgroups go round-robin to the eight
-// XCDs (workgroup id mod 8), so with K a multiple of 8 XCD x takes subbands k = x mod 8, all
-// targets of a subband back to back (they read the same window tile blocks through one L2),
-// widest windows first (d.torder); otherwise targets widest first, subbands fastest.  Either
-// way the costly pairs are dispatched first.
+// Workgroup -> (target, subband) of the pair kernels over subbands k0 .. k0 + kc - 1.
+// Workgroups go round-robin to the eight XCDs (workgroup id mod 8), so with kc a multiple of 8
+// XCD x takes subbands k0 + x, k0 + 8 + x, ..., all targets of a subband back to back (they
+// read the same window tile blocks through one L2), widest windows first (d.torder);
+// otherwise targets widest first, subbands fastest.  Either way the costly pairs are
+// dispatched first.
 __device__ __forceinline__ void pair_of_block(const PairArgs& a, const DevDesc& d, int& t, int& k) {
   const int p = blockIdx.x;
-  if ((a.K & 7) == 0) {
+  const int kc = a.kc > 0 ? a.kc : a.K;
+  if ((kc & 7) == 0) {
     const int slot = p >> 3;
     t = d.torder[slot % a.T];
-    k = ((slot / a.T) << 3) + (p & 7);
+    k = a.k0 + ((slot / a.T) << 3) + (p & 7);
   } else {
-    t = d.torder[p / a.K];
-    k = p % a.K;
+    t = d.torder[p / kc];
+    k = a.k0 + p % kc;
   }
 }
 
@@ -971,7 +973,7 @@ hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDes
                             hipStream_t s) {
   if (a.wmax > 64) return hipErrorInvalidValue;
   const XLds lay = x_lds_layout<true, 256, 64>(a.wmax);
-  const dim3 grid(a.T * a.K), blk(256);
+  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K)), blk(256);
   if (a.wmax <= 40)
     hipLaunchKernelGGL(k_mvdr_xm<40>, grid, blk, lay.total, s, a, g, d, Yw, out, wout, starts, info);
   else
@@ -983,7 +985,7 @@ hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevD
                               const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                               int threads, hipStream_t s) {
   if (a.wmax > 64 || (threads == 64 && a.wmax > 40)) return hipErrorInvalidValue;
-  const dim3 grid(a.T * a.K);
+  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K));
   if (threads == 64) {
     const XLds lay = x_lds_layout<false, 64, 16>(a.wmax);
     hipLaunchKernelGGL(k_mvdr_xw40, grid, dim3(64), lay.total, s, a, g, d, Yw, out, wout, starts,
@@ -1095,7 +1097,7 @@ hipError_t launch_mvdr_plain(const PairArgs& a, const DevDesc& d, const float2* 
                              const int* starts, const double2* abar, float2* R32, float2* w32,
                              float2* out, float2* wout, int* info, hipStream_t s) {
   const PairLds lay = pair_lds_layout<float>(a.wmax);
-  const dim3 grid(a.T * a.K), blk(kPlainThreads);
+  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K)), blk(kPlainThreads);
   hipLaunchKernelGGL(k_plain_cov, grid, blk, lay.total, s, a, d, Y, starts, R32);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1447,8 +1449,9 @@ static hipError_t mixed_launch(const PairArgs& a, const WindowGeom& g, const Dev
                                              (int)lay.total);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_mvdr_mx<WCAP, SPLIT>), dim3(a.T * a.K), dim3(256), lay.total, s, a, g, d,
-                     Yw, out, wout, starts, info, flags);
+  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K));
+  hipLaunchKernelGGL((k_mvdr_mx<WCAP, SPLIT>), grid, dim3(256), lay.total, s, a, g, d, Yw, out,
+                     wout, starts, info, flags);
   return hipGetLastError();
 }
 

@@ -29,10 +29,11 @@ hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, co
 // kernel places the windows of subband k itself from g).  With prof, G workgroups per
 // subband each loop over snapshot tiles and write training power-profile partials
 // prof [K][G][T][64] (64 bins centred on each target's beam bin, snapshots b < L).
+// Subbands k0 .. k0 + kc - 1 only (kc < 0: through K - 1).
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
                             const float2* twM, const int* rowtab, int sumW, const WindowGeom& g,
                             int logtile, hipStream_t s, float* prof = nullptr, int L = 0,
-                            int G = 0);
+                            int G = 0, int k0 = 0, int kc = -1);
 // Snapshot tiles of the beamspace kernel for M, B at a tile size.
 int beamspace_tiles(int M, int B, int logtile);
 
@@ -50,6 +51,8 @@ struct PairArgs {
   // optional [T][K] flags: when set, the fused pair kernels solve only the flagged pairs (the
   // mixed forms' windows routed to FP64) and mark their info with bit 30
   const int* route = nullptr;
+  // subbands k0 .. k0 + kc - 1 only (kc = 0: all K); the grid is T * kc workgroups
+  int k0 = 0, kc = 0;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
 // solve -> apply, reading the window rows written by the beamspace kernel.

@@ -154,10 +154,10 @@ def test_batch_config_full_size_sampled_subbands(torch, wb):
     plan.close()
 
 
-def _pin(plan, pair):
-    chan, beam, _ = plan.tuning
-    plan.set_tuning(chan, beam, pair)
-    assert plan.tuning[2] == pair
+def _pin(plan, pair, overlap=1):
+    chan, beam, _, _ = plan.tuning
+    plan.set_tuning(chan, beam, pair, overlap)
+    assert plan.tuning[2] == pair and plan.tuning[3] == overlap
 
 
 @pytest.mark.parametrize("pair", ["mfma", "wave", "block"])
@@ -175,6 +175,35 @@ def test_pair_kernels_match_oracle(torch, wb, name, pair):
     st = compare_beamform(sc, ref, res)
     log(f"  {st}")
     assert st["max_weight_err"] < 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("form", ["fused", "graph"])
+@pytest.mark.parametrize("overlap", [2, 4])
+def test_overlapped_subband_chunks_match_oracle(torch, wb, overlap, form):
+    # spatial DFT and pair kernel overlapped over subband chunks on two streams (graph: fork/join)
+    cfg = scenes.GPU
+    log(f"overlap {overlap} chunks, form {form}, gpu config all pairs")
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    _pin(plan, "block", overlap)
+    x = torch.from_numpy(x32).cuda()
+    res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+    torch.cuda.synchronize()
+    st = compare_beamform(sc, ref, res)
+    log(f"  {st}")
+    assert st["max_weight_err"] < 1e-5
+    # same results as the unchunked sequence, every replay
+    _pin(plan, "block", 1)
+    one = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    _pin(plan, "block", overlap)
+    for rep in range(3):
+        again = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        assert torch.equal(again["out"], one["out"]), rep
+        assert torch.equal(again["weights"], one["weights"]), rep
     plan.close()
 
 
@@ -333,6 +362,45 @@ def test_full_dimensional_mvdr_matches_oracle(torch, wb, name, subbands):
 
 
 # ----------------------------------------------------------------------------- mixed precision
+
+@pytest.mark.parametrize("form", ["mixed", "mixed_bf16"])
+def test_mixed_forms_route_ill_conditioned_windows_to_fp64(torch, wb, form):
+    """A 60 dB jammer inside a target's window drives its covariance past the routing threshold
+    (condition estimate 1e4): those windows must be flagged (info bit 30) and solved by the exact
+    FP64 kernel (bit-identical to the fused form on the same vector kernel); the others stay on
+    the mixed path within its bound."""
+    cfg = scenes.SceneConfig(name="route", N=32, M=64, K=16, L=64, Lt=32, T=4, W=9,
+                             W_choices=(9,), n_jammers=2,
+                             target_az_deg=(0.0, -25.0, 20.0, 45.0), target_snr_db=(0.0,) * 4,
+                             jammer_az_deg=(1.5, -55.0), jammer_inr_db=(60.0, 30.0), seed=21)
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    _pin(plan, "block")
+    x = torch.from_numpy(x32).cuda()
+    exact = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+    torch.cuda.synchronize()
+    info = res["info"].cpu().numpy()
+    routed = (info & wb.INFO_ROUTED) != 0
+    log(f"  {form}: routed {int(routed.sum())}/{routed.size}")
+    assert routed.sum() > 0 and not routed.all()
+    assert np.all((info & ~wb.INFO_ROUTED) == 0)
+    w_m = res["weights"].cpu().numpy()
+    w_e = exact["weights"].cpu().numpy()
+    o_m = res["out"].cpu().numpy()
+    o_e = exact["out"].cpu().numpy()
+    assert np.array_equal(w_m[routed], w_e[routed])
+    assert np.array_equal(o_m[routed], o_e[routed])
+    res = dict(res)
+    res["info"] = torch.zeros_like(res["info"])
+    unit = 2.0 ** -16 if form == "mixed" else 2.0 ** -8
+    st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit,
+                          check_sinr=(form == "mixed"))
+    log(f"  {st}")
+    plan.close()
+
 
 @pytest.mark.parametrize("name", ["small", "gpu"])
 def test_mixed_precision_forms(torch, wb, name):
