@@ -107,20 +107,23 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
 #define WBM_PAIR_MFMA 1    /* four waves, covariance on the FP64 matrix cores */
 #define WBM_PAIR_WAVE 64   /* one wave per pair on the vector units, w_max <= 40 */
 #define WBM_PAIR_BLOCK 256 /* four waves per pair on the vector units */
+#define WBM_PAIR_RESIDENT 2 /* four waves, the pair's window data held whole in LDS;
+                               w_max * (L + Lt) <= 5120 */
 
 /* Launch configuration of the fused form.  Without a call to wbm_plan_set_tuning the first
  * fused / graph call times the candidates on the caller's data (FFT tiles of 2^11..2^13
- * complex per workgroup for the channelizer and the spatial DFT, the three pair kernels, the
+ * complex per workgroup for the channelizer and the spatial DFT, the four pair kernels, the
  * number of subband chunks over which the spatial DFT and the pair kernel overlap on two
  * streams) and keeps the fastest, cached on disk per device and shape.  Setting pins the
  * choice and skips that search; every choice computes the same quantities (Eq. 4-20),
  * differing only in rounding order.
  *   chan_logtile, beam_logtile  11, 12 or 13.
- *   pair_kernel                 WBM_PAIR_MFMA, WBM_PAIR_WAVE (needs w_max <= 40) or
- *                               WBM_PAIR_BLOCK.
+ *   pair_kernel                 WBM_PAIR_MFMA, WBM_PAIR_WAVE (needs w_max <= 40),
+ *                               WBM_PAIR_BLOCK or WBM_PAIR_RESIDENT (needs
+ *                               w_max * (L + Lt) <= 5120).
  *   overlap_chunks              1 (no overlap), 2, 4 or 8; K must be a multiple of 8 x chunks.
  * Errors: WBM_ERR_ARG for a NULL plan or a value outside those sets, WBM_ERR_UNSUPPORTED for
- * WBM_PAIR_WAVE with w_max > 40 or a chunk count K does not allow.  A pinned choice drops a
+ * WBM_PAIR_WAVE or WBM_PAIR_RESIDENT beyond their limits or a chunk count K does not allow.  A pinned choice drops a
  * captured graph (recaptured on the next graph call).  wbm_plan_get_tuning writes the current
  * choice (NULL pointers skipped). */
 wbm_status wbm_plan_set_tuning(wbm_plan* plan, int32_t chan_logtile, int32_t beam_logtile,

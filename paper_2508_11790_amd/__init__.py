@@ -83,12 +83,13 @@ class Plan:
     def workspace_bytes(self) -> int:
         return int(_lib.load().wbm_plan_workspace_bytes(self._h))
 
-    _PAIR_KERNELS = {"mfma": _lib.PAIR_MFMA, "wave": _lib.PAIR_WAVE, "block": _lib.PAIR_BLOCK}
+    _PAIR_KERNELS = {"mfma": _lib.PAIR_MFMA, "wave": _lib.PAIR_WAVE, "block": _lib.PAIR_BLOCK,
+                     "resident": _lib.PAIR_RESIDENT}
 
     def set_tuning(self, chan_logtile: int, beam_logtile: int, pair_kernel: str = "block",
                    overlap: int = 1):
         """Pin the fused form's FFT tiles (log2 complex per workgroup: 11..13), pair kernel
-        ("mfma", "wave" or "block") and subband chunks overlapping the spatial DFT with the pair
+        ("mfma", "wave", "block" or "resident") and subband chunks overlapping the spatial DFT with the pair
         kernel (1, 2, 4, 8); skips the first call's timing search."""
         if pair_kernel not in self._PAIR_KERNELS:
             raise ValueError(f"pair_kernel must be one of {sorted(self._PAIR_KERNELS)}")

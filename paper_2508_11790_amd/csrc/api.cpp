@@ -353,7 +353,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p3";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p4";
   return os.str();
 }
 
@@ -366,7 +366,8 @@ std::string cache_path() {
 
 // The cache file is a flat JSON object
 // {"key": [chan_logtile, beam_logtile, pair_kernel, overlap_chunks], ...}
-// (pair_kernel: 1 = FP64 matrix-core kernel, 64 / 256 = vector kernel with that many threads).
+// (pair_kernel: 1 = FP64 matrix-core kernel, 2 = LDS-resident kernel, 64 / 256 = vector kernel
+// with that many threads).
 bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr, int* ovl) {
   std::ifstream f(cache_path());
   if (!f) return false;
@@ -380,7 +381,9 @@ bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr, int* o
   if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d, %d", &a, &b, &c, &o) != 4)
     return false;
   if (!wbm::fft_logtile_supported(a) || !wbm::fft_logtile_supported(b)) return false;
-  if (c != WBM_PAIR_MFMA && c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK) return false;
+  if (c != WBM_PAIR_MFMA && c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK &&
+      c != WBM_PAIR_RESIDENT)
+    return false;
   *chan = a;
   *beam = b;
   *thr = c;
@@ -448,7 +451,8 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
   const std::string key = tune_key(p);
   int chan = 12, beam = 12, thr = WBM_PAIR_MFMA, ovl = 1;
-  if (cache_lookup(key, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl)) {
+  if (cache_lookup(key, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl) &&
+      (thr != WBM_PAIR_RESIDENT || wbm::mvdr_resident_supported(p->cfg.w_max, p->B))) {
     p->chan_logtile = chan;
     set_beam_tile(p, beam);
     p->pair_threads = thr;
@@ -480,8 +484,9 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   if (e != hipSuccess) return e;
   float best_p = 1e30f;
   const wbm::PairArgs pa = pair_args(p, T, sumW, loading);
-  for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE}) {
+  for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
     if (thr_c == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
+    if (thr_c == WBM_PAIR_RESIDENT && !wbm::mvdr_resident_supported(p->cfg.w_max, p->B)) continue;
     float ms;
     e = time_best([&]() {
       return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
@@ -514,7 +519,8 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   return hipSuccess;
 }
 
-static_assert(WBM_PAIR_MFMA == wbm::kPairMfma, "pair kernel ids");
+static_assert(WBM_PAIR_MFMA == wbm::kPairMfma && WBM_PAIR_RESIDENT == wbm::kPairResident,
+              "pair kernel ids");
 
 wbm_status check_plan(const wbm_plan* p) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
@@ -550,10 +556,16 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
   if (!wbm::fft_logtile_supported(chan) || !wbm::fft_logtile_supported(beam))
     return fail(WBM_ERR_ARG, "FFT tile log2 must be 11, 12 or 13");
-  if (pair != WBM_PAIR_MFMA && pair != WBM_PAIR_WAVE && pair != WBM_PAIR_BLOCK)
-    return fail(WBM_ERR_ARG, "pair_kernel must be WBM_PAIR_MFMA, WBM_PAIR_WAVE or WBM_PAIR_BLOCK");
+  if (pair != WBM_PAIR_MFMA && pair != WBM_PAIR_WAVE && pair != WBM_PAIR_BLOCK &&
+      pair != WBM_PAIR_RESIDENT)
+    return fail(WBM_ERR_ARG,
+                "pair_kernel must be WBM_PAIR_MFMA, WBM_PAIR_WAVE, WBM_PAIR_BLOCK or "
+                "WBM_PAIR_RESIDENT");
   if (pair == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max))
     return fail(WBM_ERR_UNSUPPORTED, "the one-wave pair kernel needs w_max <= 40");
+  if (pair == WBM_PAIR_RESIDENT && !wbm::mvdr_resident_supported(p->cfg.w_max, p->B))
+    return fail(WBM_ERR_UNSUPPORTED,
+                "the resident pair kernel needs w_max * (L + Lt) <= 5120");
   if (overlap != 1 && overlap != 2 && overlap != 4 && overlap != 8)
     return fail(WBM_ERR_ARG, "overlap_chunks must be 1, 2, 4 or 8");
   if (!overlap_supported(p, overlap))

@@ -332,11 +332,16 @@ hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDes
 hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                               const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                               int threads, hipStream_t s);
+hipError_t launch_mvdr_resident(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                                const float2* Yw, float2* out, float2* wout, int* starts,
+                                int* info, hipStream_t s);
 
 hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s) {
   if (threads == kPairMfma) return launch_mvdr_mfma(a, g, d, Yw, out, wout, starts, info, s);
+  if (threads == kPairResident)
+    return launch_mvdr_resident(a, g, d, Yw, out, wout, starts, info, s);
   if (threads == 256 || (threads == 64 && a.wmax <= kWaveWMax))
     return launch_mvdr_vector(a, g, d, Yw, out, wout, starts, info, threads, s);
   return hipErrorInvalidValue;
@@ -725,6 +730,82 @@ __device__ void ldl_solve(const C2<double>* R, int RS, int W, const double2* av,
   if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
 }
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Wave 0, W <= WCAP: the same LDL^H factorisation and solves as ldl_lds + ldl_solve with the
+// matrix in registers, no barriers.  Lane i holds row i of the full Hermitian matrix (the part
+// above the diagonal as the conjugate of the lower part, updated alongside it); column j's
+// entries l_cj d_j reach every lane as scalars (readlane of lane c).  The forward substitution
+// y = L^-1 a runs with the elimination (column j is final at step j); the backward one,
+// x = L^-H D^-1 y, reads conj(l_ci) d_i from lane i's own upper part.  Writes w = x / q
+// (q = a^H R^-1 a = sum |y_i|^2 / d_i) into wv[0..W); returns 0 or j + 1 for a pivot that is
+// not positive and finite (uniform over the wave).  Caller syncs afterwards.
+template <int WCAP>
+__device__ __forceinline__ int ldl_reg_solve(const C2<double>* R, int RS, int W, const double2* av,
+                                             C2<double>* wv) {
+  const int lane = threadIdx.x & 63;
+  C2<double> r[WCAP];
+#pragma unroll
+  for (int c = 0; c < WCAP; ++c) {
+    r[c] = c2<double>(0.0, 0.0);
+    if (lane < W && c < W) {
+      const bool lo = c <= lane;   // lower part: R[lane][c]; upper: conj(R[c][lane])
+      const C2<double> u = R[lo ? lane * RS + c : c * RS + lane];
+      r[c] = c2<double>(u.x, lo ? u.y : -u.y);
+    }
+  }
+  C2<double> y = c2<double>(0.0, 0.0);
+  if (lane < W) y = c2<double>(av[lane].x, av[lane].y);
+  double invd = 0.0;   // 1 / d_lane
+  // every loop runs to the compile-time bound (guards, no breaks): r[] stays in registers
+#pragma unroll
+  for (int j = 0; j < WCAP; ++j) {
+    if (j < W) {
+      const double dj = readlane_f64(r[j].x, j);
+      if (!(dj > 0.0) || !(dj < (double)INFINITY)) return j + 1;
+      const double inv = 1.0 / dj;
+      if (lane == j) invd = inv;
+      const double lx = r[j].x * inv, ly = r[j].y * inv;   // l_ij on lanes i > j
+      const double yx = readlane_f64(y.x, j) * inv, yy = readlane_f64(y.y, j) * inv;
+      if (lane > j) {
+        y.x -= r[j].x * yx - r[j].y * yy;
+        y.y -= r[j].x * yy + r[j].y * yx;
+      }
+#pragma unroll
+      for (int c = j + 1; c < WCAP; ++c) {
+        if (c < W) {
+          const double gx = readlane_f64(r[j].x, c), gy = readlane_f64(r[j].y, c);   // l_cj d_j
+          if (lane > j) {
+            r[c].x = fma(-lx, gx, fma(-ly, gy, r[c].x));   // - l_ij conj(l_cj) d_j
+            r[c].y = fma(-ly, gx, fma(lx, gy, r[c].y));
+          }
+        }
+      }
+    }
+  }
+  double q = (y.x * y.x + y.y * y.y) * invd;
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  C2<double> x = c2<double>(y.x * invd, y.y * invd);
+#pragma unroll
+  for (int c = WCAP - 1; c >= 0; --c) {
+    if (c < W) {
+      const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);   // x_c, final
+      if (lane < c) {
+        const C2<double> h = r[c];                                          // conj(l_ci) d_i
+        x.x -= (h.x * xx - h.y * xy) * invd;
+        x.y -= (h.x * xy + h.y * xx) * invd;
+      }
+    }
+  }
+  const double qinv = 1.0 / q;
+  if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
+  return 0;
+}
+
 struct PairSetup {
   int t, k, W, woff, s;
   int64_t pair;
@@ -917,8 +998,19 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     __syncthreads();
   }
 
-  const int fail = ldl_lds<TH>(R, lay.RS, W);
-  if (!fail) ldl_solve(R, lay.RS, W, av, wv);
+  int fail;
+  if constexpr (WCAP <= 16) {
+    __shared__ int s_fail;
+    if (tid < 64) {
+      const int f = ldl_reg_solve<WCAP>(R, lay.RS, W, av, wv);
+      if (tid == 0) s_fail = f;
+    }
+    __syncthreads();
+    fail = s_fail;
+  } else {
+    fail = ldl_lds<TH>(R, lay.RS, W);
+    if (!fail) ldl_solve(R, lay.RS, W, av, wv);
+  }
   apply_chunks<PRE, TH, CH, MF>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red, fail,
                                 out + pair * a.Lt);
   if (wout) {
@@ -1005,6 +1097,207 @@ hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevD
   else
     hipLaunchKernelGGL(k_mvdr_xv64, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
                        info);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Resident pair kernel (small problems: w_max (L + Lt) <= kResElems): every window row of the
+// pair, training and test snapshots, is loaded at once (all loads in flight together, one
+// latency) into LDS; the covariance, LDL^H, solves and beam outputs then run from LDS with no
+// further global reads.  Same arithmetic as the vector kernel: FP32 x FP32 products exact in
+// FP64, FP64 sums, FP64 factorisation and solves.
+constexpr int kResPre = 18;                    // staged elements per thread (256 threads)
+constexpr int kResElems = kResPre * 256;
+constexpr int kResRegW = 16;                   // widest window factorised in registers
+
+struct ResLds {
+  size_t y, r, wv, av, total;
+  int RS, YS;
+};
+
+// window rows [wmax][B + 1] (float2), R [wmax][wmax + 1], w and steering [wmax] (FP64)
+__host__ __device__ inline ResLds res_lds_layout(int wmax, int B) {
+  ResLds p;
+  p.RS = wmax + 1;
+  p.YS = B + 1;
+  p.y = 0;
+  p.r = (sizeof(float2) * (size_t)wmax * p.YS + 15) & ~(size_t)15;
+  p.wv = p.r + sizeof(C2<double>) * (size_t)wmax * p.RS;
+  p.av = p.wv + sizeof(C2<double>) * (size_t)wmax;
+  p.total = p.av + sizeof(double2) * (size_t)wmax;
+  return p;
+}
+
+// LDS of at most 40 KiB: four workgroups per compute unit
+bool mvdr_resident_supported(int wmax, int B) {
+  return wmax * B <= kResElems && res_lds_layout(wmax, B).total <= 40 * 1024;
+}
+
+__global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevDesc d,
+                                                  const float2* __restrict__ Yw,
+                                                  float2* __restrict__ out,
+                                                  float2* __restrict__ wout,
+                                                  int* __restrict__ starts_out,
+                                                  int* __restrict__ info) {
+  constexpr int TH = 256, BS = 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ResLds lay = res_lds_layout(a.wmax, a.B);
+  float2* ys = reinterpret_cast<float2*>(smem + lay.y);
+  C2<double>* R = reinterpret_cast<C2<double>*>(smem + lay.r);
+  C2<double>* wv = reinterpret_cast<C2<double>*>(smem + lay.wv);
+  double2* av = reinterpret_cast<double2*>(smem + lay.av);
+  const int tid = threadIdx.x;
+  const PairSetup ps = pair_setup(a, g, d);
+  const int k = ps.k, W = ps.W, woff = ps.woff;
+  const int64_t pair = ps.pair;
+  if (a.route && !a.route[pair]) return;
+  const int YS = lay.YS, RS = lay.RS;
+
+  // every element (row i, snapshot b) of the pair's window rows, b fastest: runs of TB
+  // consecutive snapshots are contiguous in the tiled layout.  i = e / B through a float
+  // reciprocal: e + 1/2 lies at least 1/2 from a multiple of B and e < 2^13, far beyond the
+  // reciprocal's rounding.
+  const int TB = 1 << a.logTB;
+  const float2* base = Yw + (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
+  const int n = W * a.B;
+  const float invB = 1.0f / (float)a.B;
+  float2 v[kResPre];
+#pragma unroll
+  for (int m = 0; m < kResPre; ++m) {
+    const int e = tid + m * TH;
+    v[m] = make_float2(0.f, 0.f);
+    if (e < n) {
+      const int i = (int)(((float)e + 0.5f) * invB), b = e - i * a.B;
+      v[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
+    }
+  }
+  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  if (starts_out && tid == 0) starts_out[pair] = ps.s;
+#pragma unroll
+  for (int m = 0; m < kResPre; ++m) {
+    const int e = tid + m * TH;
+    if (e < n) {
+      const int i = (int)(((float)e + 0.5f) * invB), b = e - i * a.B;
+      ys[i * YS + b] = v[m];
+    }
+  }
+  __syncthreads();
+
+  // covariance over the L training snapshots: BS x BS blocks, S interleaved snapshot slices
+  {
+    const int nb = (W + BS - 1) / BS, nblk = nb * (nb + 1) / 2;
+    int S = 1;
+    while (2 * S * nblk <= TH && S < 64) S *= 2;
+    const int blk = tid / S, sg = tid & (S - 1);
+    const bool act = blk < nblk;
+    int bi = 0, bj = 0;
+    if (act) tri_index(blk, bi, bj);
+    // rows past W (odd W) read row W - 1: their sums are dropped below
+    int ri[BS], rc[BS];
+#pragma unroll
+    for (int u = 0; u < BS; ++u) {
+      ri[u] = min(bi * BS + u, W - 1) * YS;
+      rc[u] = min(bj * BS + u, W - 1) * YS;
+    }
+    double ax[BS][BS], ay[BS][BS];
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+      for (int w = 0; w < BS; ++w) ax[u][w] = ay[u][w] = 0.0;
+    if (act) {
+      for (int b = sg; b < a.L; b += S) {
+        double rx[BS], ry[BS], cx[BS], cy[BS];
+#pragma unroll
+        for (int u = 0; u < BS; ++u) {
+          const float2 yr = ys[ri[u] + b], yc = ys[rc[u] + b];
+          rx[u] = yr.x;
+          ry[u] = yr.y;
+          cx[u] = yc.x;
+          cy[u] = yc.y;
+        }
+#pragma unroll
+        for (int u = 0; u < BS; ++u)
+#pragma unroll
+          for (int w = 0; w < BS; ++w) {
+            ax[u][w] = fma(rx[u], cx[w], ax[u][w]);
+            ax[u][w] = fma(ry[u], cy[w], ax[u][w]);
+            ay[u][w] = fma(ry[u], cx[w], ay[u][w]);
+            ay[u][w] = fma(-rx[u], cy[w], ay[u][w]);
+          }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BS; ++u)
+#pragma unroll
+      for (int w = 0; w < BS; ++w)
+        for (int off = S >> 1; off > 0; off >>= 1) {
+          ax[u][w] += __shfl_xor(ax[u][w], off);
+          ay[u][w] += __shfl_xor(ay[u][w], off);
+        }
+    const double invL = 1.0 / (double)a.L;
+    if (act && sg == 0) {
+#pragma unroll
+      for (int u = 0; u < BS; ++u)
+#pragma unroll
+        for (int w = 0; w < BS; ++w) {
+          const int i = bi * BS + u, j = bj * BS + w;
+          if (i < W && j <= i) {
+            C2<double> r = c2<double>(ax[u][w] * invL, ay[u][w] * invL);
+            if (i == j) {
+              r.x += ps.delta;
+              r.y = 0.0;
+            }
+            R[i * RS + j] = r;
+          }
+        }
+    }
+  }
+  __syncthreads();
+  __shared__ int s_fail;
+  int fail;
+  if (a.wmax <= kResRegW) {
+    if (tid < 64) {
+      const int f = ldl_reg_solve<kResRegW>(R, RS, W, av, wv);
+      if (tid == 0) s_fail = f;
+    }
+    __syncthreads();
+    fail = s_fail;
+  } else {
+    fail = ldl_lds<TH, double>(R, RS, W);
+    if (!fail) ldl_solve(R, RS, W, av, wv);
+    __syncthreads();
+  }
+  // beam outputs: one test snapshot per thread, FP64 sums over the window rows
+  float2* o = out + pair * a.Lt;
+  for (int l = tid; l < a.Lt; l += TH) {
+    double zx = 0.0, zy = 0.0;
+    if (!fail) {
+      for (int i = 0; i < W; ++i) {
+        const float2 y = ys[i * YS + a.L + l];
+        const C2<double> w = wv[i];
+        zx = fma(w.x, (double)y.x, fma(w.y, (double)y.y, zx));    // conj(w) y
+        zy = fma(w.x, (double)y.y, fma(-w.y, (double)y.x, zy));
+      }
+    }
+    o[l] = make_float2((float)zx, (float)zy);
+  }
+  if (wout) {
+    for (int i = tid; i < a.wmax; i += TH) {
+      float2 vv = make_float2(0.f, 0.f);
+      if (!fail && i < W) vv = make_float2((float)wv[i].x, (float)wv[i].y);
+      wout[pair * a.wmax + i] = vv;
+    }
+  }
+  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0);
+}
+
+hipError_t launch_mvdr_resident(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                                const float2* Yw, float2* out, float2* wout, int* starts,
+                                int* info, hipStream_t s) {
+  if (!mvdr_resident_supported(a.wmax, a.B)) return hipErrorInvalidValue;
+  const ResLds lay = res_lds_layout(a.wmax, a.B);
+  hipLaunchKernelGGL(k_mvdr_res, dim3(a.T * (a.kc > 0 ? a.kc : a.K)), dim3(256), lay.total, s, a,
+                     g, d, Yw, out, wout, starts, info);
   return hipGetLastError();
 }
 

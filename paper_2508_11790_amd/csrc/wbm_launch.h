@@ -54,11 +54,16 @@ struct PairArgs {
   // subbands k0 .. k0 + kc - 1 only (kc = 0: all K); the grid is T * kc workgroups
   int k0 = 0, kc = 0;
 };
-// Fused per-pair window/steering -> covariance (FP64 accumulation) -> Cholesky (FP64) ->
-// solve -> apply, reading the window rows written by the beamspace kernel.
-// threads = kPairMfma (four waves, FP64 matrix-core covariance), 64 (one wave per pair on the
-// vector units, windows up to 40 bins) or 256 (four waves per pair on the vector units).
+// Fused per-pair window/steering -> covariance (FP64 accumulation) -> LDL^H (FP64) -> solve
+// -> apply, reading the window rows written by the beamspace kernel.
+// threads = kPairMfma (four waves, FP64 matrix-core covariance), kPairResident (below), 64 (one
+// wave per pair on the vector units, windows up to 40 bins) or 256 (four waves per pair on the
+// vector units).
 constexpr int kPairMfma = 1;
+// kPairResident: four waves, the pair's whole window data resident in LDS (small problems,
+// mvdr_resident_supported)
+constexpr int kPairResident = 2;
+bool mvdr_resident_supported(int wmax, int B);
 hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s);

@@ -160,7 +160,7 @@ def _pin(plan, pair, overlap=1):
     assert plan.tuning[2] == pair and plan.tuning[3] == overlap
 
 
-@pytest.mark.parametrize("pair", ["mfma", "wave", "block"])
+@pytest.mark.parametrize("pair", ["mfma", "wave", "block", "resident"])
 @pytest.mark.parametrize("name", ["small", "gpu"])
 def test_pair_kernels_match_oracle(torch, wb, name, pair):
     cfg = scenes.config_by_name(name)
@@ -271,7 +271,7 @@ def test_edge_shapes(torch, wb, case):
     x32 = _x32(sc)
     ref = _oracle(sc, x32)
     plan = _plan(wb, cfg, sc)
-    runs = [("plain", None), ("fused", "mfma"), ("fused", "block")]
+    runs = [("plain", None), ("fused", "mfma"), ("fused", "block"), ("fused", "resident")]
     if max(W) <= 40:
         runs.append(("fused", "wave"))
     for form, pair in runs:
@@ -312,7 +312,8 @@ def test_rejects_bad_targets(torch, wb):
     plan.close()
 
 
-@pytest.mark.parametrize("form", ["plain", "fused-mfma", "fused-block", "fused-wave"])
+@pytest.mark.parametrize("form", ["plain", "fused-mfma", "fused-block", "fused-wave",
+                                  "fused-resident"])
 def test_zero_loading_singular_reports_info(torch, wb, form):
     # silent input and no loading: the window covariance is 0, the first pivot fails (info = 1)
     plan = wb.Plan(16, 32, 4, 3, 2, 1, 9)
@@ -325,6 +326,17 @@ def test_zero_loading_singular_reports_info(torch, wb, form):
     assert np.all(res["info"].cpu().numpy() == 1)
     assert np.all(res["out"].cpu().numpy() == 0)
     assert np.all(res["weights"].cpu().numpy() == 0)
+    plan.close()
+
+
+def test_pair_kernel_limits_rejected(torch, wb):
+    # the one-wave kernel needs w_max <= 40; the resident kernel w_max (L + Lt) <= 5120
+    plan = wb.Plan(64, 128, 8, 512, 512, 2, 41)
+    chan, beam, _, _ = plan.tuning
+    for pair in ("wave", "resident"):
+        with pytest.raises(wb.WbmError):
+            plan.set_tuning(chan, beam, pair)
+    plan.set_tuning(chan, beam, "block")
     plan.close()
 
 
