@@ -108,7 +108,7 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
 #define WBM_PAIR_WAVE 64   /* one wave per pair on the vector units, w_max <= 40 */
 #define WBM_PAIR_BLOCK 256 /* four waves per pair on the vector units */
 #define WBM_PAIR_RESIDENT 2 /* four waves, the pair's window data held whole in LDS;
-                               w_max * (L + Lt) <= 5120 */
+                               w_max * L <= 2304 and w_max * Lt <= 2304 */
 
 /* Launch configuration of the fused form.  Without a call to wbm_plan_set_tuning the first
  * fused / graph call times the candidates on the caller's data (FFT tiles of 2^11..2^13
@@ -120,7 +120,7 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
  *   chan_logtile, beam_logtile  11, 12 or 13.
  *   pair_kernel                 WBM_PAIR_MFMA, WBM_PAIR_WAVE (needs w_max <= 40),
  *                               WBM_PAIR_BLOCK or WBM_PAIR_RESIDENT (needs
- *                               w_max * (L + Lt) <= 5120).
+ *                               w_max * L and w_max * Lt <= 2304).
  *   overlap_chunks              1 (no overlap), 2, 4 or 8; K must be a multiple of 8 x chunks.
  * Errors: WBM_ERR_ARG for a NULL plan or a value outside those sets, WBM_ERR_UNSUPPORTED for
  * WBM_PAIR_WAVE or WBM_PAIR_RESIDENT beyond their limits or a chunk count K does not allow.  A pinned choice drops a

@@ -262,6 +262,10 @@ wbm::WindowGeom geom(const wbm_plan* p, int T) {
   return g;
 }
 
+bool resident_ok(const wbm_plan* p) {
+  return wbm::mvdr_resident_supported(p->cfg.w_max, p->cfg.l_train, p->cfg.l_test);
+}
+
 void set_beam_tile(wbm_plan* p, int logtile) {
   p->beam_logtile = logtile;
   p->logTB = wbm::beamspace_tile_log(p->cfg.m_fft, logtile);
@@ -452,7 +456,7 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   const std::string key = tune_key(p);
   int chan = 12, beam = 12, thr = WBM_PAIR_MFMA, ovl = 1;
   if (cache_lookup(key, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl) &&
-      (thr != WBM_PAIR_RESIDENT || wbm::mvdr_resident_supported(p->cfg.w_max, p->B))) {
+      (thr != WBM_PAIR_RESIDENT || resident_ok(p))) {
     p->chan_logtile = chan;
     set_beam_tile(p, beam);
     p->pair_threads = thr;
@@ -486,7 +490,7 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   const wbm::PairArgs pa = pair_args(p, T, sumW, loading);
   for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
     if (thr_c == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
-    if (thr_c == WBM_PAIR_RESIDENT && !wbm::mvdr_resident_supported(p->cfg.w_max, p->B)) continue;
+    if (thr_c == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
     float ms;
     e = time_best([&]() {
       return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
@@ -563,9 +567,9 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
                 "WBM_PAIR_RESIDENT");
   if (pair == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max))
     return fail(WBM_ERR_UNSUPPORTED, "the one-wave pair kernel needs w_max <= 40");
-  if (pair == WBM_PAIR_RESIDENT && !wbm::mvdr_resident_supported(p->cfg.w_max, p->B))
+  if (pair == WBM_PAIR_RESIDENT && !resident_ok(p))
     return fail(WBM_ERR_UNSUPPORTED,
-                "the resident pair kernel needs w_max * (L + Lt) <= 5120");
+                "the resident pair kernel needs w_max * L <= 2304 and w_max * Lt <= 2304");
   if (overlap != 1 && overlap != 2 && overlap != 4 && overlap != 8)
     return fail(WBM_ERR_ARG, "overlap_chunks must be 1, 2, 4 or 8");
   if (!overlap_supported(p, overlap))

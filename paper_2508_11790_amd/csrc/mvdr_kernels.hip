@@ -741,9 +741,11 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
 // above the diagonal as the conjugate of the lower part, updated alongside it); column j's
 // entries l_cj d_j reach every lane as scalars (readlane of lane c).  The forward substitution
 // y = L^-1 a runs with the elimination (column j is final at step j); the backward one,
-// x = L^-H D^-1 y, reads conj(l_ci) d_i from lane i's own upper part.  Writes w = x / q
-// (q = a^H R^-1 a = sum |y_i|^2 / d_i) into wv[0..W); returns 0 or j + 1 for a pivot that is
-// not positive and finite (uniform over the wave).  Caller syncs afterwards.
+// x = L^-H D^-1 y, reads conj(l_ci) d_i from lane i's own upper part.  The matrix is padded to
+// WCAP with an identity block and zero steering, so every loop runs its compile-time count
+// without branches; the padding adds and subtracts exact zeros to rows 0..W-1.  Writes
+// w = x / q (q = a^H R^-1 a = sum |y_i|^2 / d_i) into wv[0..W); returns 0 or j + 1 for a pivot
+// that is not positive and finite (uniform over the wave).  Caller syncs afterwards.
 template <int WCAP>
 __device__ __forceinline__ int ldl_reg_solve(const C2<double>* R, int RS, int W, const double2* av,
                                              C2<double>* wv) {
@@ -751,7 +753,7 @@ __device__ __forceinline__ int ldl_reg_solve(const C2<double>* R, int RS, int W,
   C2<double> r[WCAP];
 #pragma unroll
   for (int c = 0; c < WCAP; ++c) {
-    r[c] = c2<double>(0.0, 0.0);
+    r[c] = c2<double>(c == lane ? 1.0 : 0.0, 0.0);
     if (lane < W && c < W) {
       const bool lo = c <= lane;   // lower part: R[lane][c]; upper: conj(R[c][lane])
       const C2<double> u = R[lo ? lane * RS + c : c * RS + lane];
@@ -761,49 +763,114 @@ __device__ __forceinline__ int ldl_reg_solve(const C2<double>* R, int RS, int W,
   C2<double> y = c2<double>(0.0, 0.0);
   if (lane < W) y = c2<double>(av[lane].x, av[lane].y);
   double invd = 0.0;   // 1 / d_lane
-  // every loop runs to the compile-time bound (guards, no breaks): r[] stays in registers
 #pragma unroll
   for (int j = 0; j < WCAP; ++j) {
-    if (j < W) {
-      const double dj = readlane_f64(r[j].x, j);
-      if (!(dj > 0.0) || !(dj < (double)INFINITY)) return j + 1;
-      const double inv = 1.0 / dj;
-      if (lane == j) invd = inv;
-      const double lx = r[j].x * inv, ly = r[j].y * inv;   // l_ij on lanes i > j
-      const double yx = readlane_f64(y.x, j) * inv, yy = readlane_f64(y.y, j) * inv;
-      if (lane > j) {
-        y.x -= r[j].x * yx - r[j].y * yy;
-        y.y -= r[j].x * yy + r[j].y * yx;
-      }
+    const double dj = readlane_f64(r[j].x, j);
+    if (!(dj > 0.0) || !(dj < (double)INFINITY)) return j + 1;
+    const double inv = 1.0 / dj;
+    if (lane == j) invd = inv;
+    // l_ij on lanes i > j; zero on lanes i <= j, whose rows the updates below then leave as
+    // they are (they subtract exact zeros)
+    const bool below = lane > j;
+    const double gjx = below ? r[j].x : 0.0, gjy = below ? r[j].y : 0.0;
+    const double lx = gjx * inv, ly = gjy * inv;
+    const double yx = readlane_f64(y.x, j) * inv, yy = readlane_f64(y.y, j) * inv;
+    y.x -= gjx * yx - gjy * yy;
+    y.y -= gjx * yy + gjy * yx;
 #pragma unroll
-      for (int c = j + 1; c < WCAP; ++c) {
-        if (c < W) {
-          const double gx = readlane_f64(r[j].x, c), gy = readlane_f64(r[j].y, c);   // l_cj d_j
-          if (lane > j) {
-            r[c].x = fma(-lx, gx, fma(-ly, gy, r[c].x));   // - l_ij conj(l_cj) d_j
-            r[c].y = fma(-ly, gx, fma(lx, gy, r[c].y));
-          }
-        }
-      }
+    for (int c = j + 1; c < WCAP; ++c) {
+      const double gx = readlane_f64(r[j].x, c), gy = readlane_f64(r[j].y, c);   // l_cj d_j
+      r[c].x = fma(-lx, gx, fma(-ly, gy, r[c].x));   // - l_ij conj(l_cj) d_j
+      r[c].y = fma(-ly, gx, fma(lx, gy, r[c].y));
     }
   }
-  double q = (y.x * y.x + y.y * y.y) * invd;
+  double q = (lane < W) ? (y.x * y.x + y.y * y.y) * invd : 0.0;
   for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
   C2<double> x = c2<double>(y.x * invd, y.y * invd);
 #pragma unroll
   for (int c = WCAP - 1; c >= 0; --c) {
-    if (c < W) {
-      const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);   // x_c, final
-      if (lane < c) {
-        const C2<double> h = r[c];                                          // conj(l_ci) d_i
-        x.x -= (h.x * xx - h.y * xy) * invd;
-        x.y -= (h.x * xy + h.y * xx) * invd;
-      }
+    const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);   // x_c, final
+    if (lane < c) {
+      const C2<double> h = r[c];                                          // conj(l_ci) d_i
+      x.x -= (h.x * xx - h.y * xy) * invd;
+      x.y -= (h.x * xy + h.y * xx) * invd;
     }
   }
   const double qinv = 1.0 / q;
   if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
   return 0;
+}
+
+// As ldl_reg_solve, with column j (and y_j) handed to the lanes through LDS broadcast reads
+// instead of readlanes: one write and independent reads per step.
+template <int WCAP>
+__device__ __forceinline__ int ldl_bcast_solve(const C2<double>* R, int RS, int W,
+                                               const double2* av, C2<double>* wv) {
+  __shared__ C2<double> col[WCAP + 1];
+  const int lane = threadIdx.x & 63;
+  C2<double> r[WCAP];
+#pragma unroll
+  for (int c = 0; c < WCAP; ++c) {
+    r[c] = c2<double>(c == lane ? 1.0 : 0.0, 0.0);
+    if (lane < W && c < W) {
+      const bool lo = c <= lane;
+      const C2<double> u = R[lo ? lane * RS + c : c * RS + lane];
+      r[c] = c2<double>(u.x, lo ? u.y : -u.y);
+    }
+  }
+  C2<double> y = c2<double>(0.0, 0.0);
+  if (lane < W) y = c2<double>(av[lane].x, av[lane].y);
+  double invd = 0.0;
+#pragma unroll
+  for (int j = 0; j < WCAP; ++j) {
+    if (lane >= j && lane < WCAP) col[lane] = r[j];
+    if (lane == j) col[WCAP] = y;
+    const double dj = col[j].x;
+    C2<double> g[WCAP];
+#pragma unroll
+    for (int c = j + 1; c < WCAP; ++c) g[c] = col[c];
+    const C2<double> yj = col[WCAP];
+    if (!(dj > 0.0) || !(dj < (double)INFINITY)) return j + 1;
+    const double inv = 1.0 / dj;
+    if (lane == j) invd = inv;
+    const double lx = r[j].x * inv, ly = r[j].y * inv;
+    const double yx = yj.x * inv, yy = yj.y * inv;
+    if (lane > j) {
+      y.x -= r[j].x * yx - r[j].y * yy;
+      y.y -= r[j].x * yy + r[j].y * yx;
+    }
+#pragma unroll
+    for (int c = j + 1; c < WCAP; ++c) {
+      if (lane > j) {
+        r[c].x = fma(-lx, g[c].x, fma(-ly, g[c].y, r[c].x));
+        r[c].y = fma(-ly, g[c].x, fma(lx, g[c].y, r[c].y));
+      }
+    }
+  }
+  double q = (lane < W) ? (y.x * y.x + y.y * y.y) * invd : 0.0;
+  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  C2<double> x = c2<double>(y.x * invd, y.y * invd);
+#pragma unroll
+  for (int c = WCAP - 1; c >= 0; --c) {
+    const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);
+    if (lane < c) {
+      const C2<double> h = r[c];
+      x.x -= (h.x * xx - h.y * xy) * invd;
+      x.y -= (h.x * xy + h.y * xx) * invd;
+    }
+  }
+  const double qinv = 1.0 / q;
+  if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
+  return 0;
+}
+
+// ldl_reg_solve at the smallest of 4, 8, 12, 16 rows that holds W (W <= 16; uniform branch).
+__device__ __forceinline__ int ldl_reg_solve_w(const C2<double>* R, int RS, int W,
+                                               const double2* av, C2<double>* wv) {
+  if (W <= 4) return ldl_reg_solve<4>(R, RS, W, av, wv);
+  if (W <= 8) return ldl_reg_solve<8>(R, RS, W, av, wv);
+  if (W <= 12) return ldl_reg_solve<12>(R, RS, W, av, wv);
+  return ldl_reg_solve<16>(R, RS, W, av, wv);
 }
 
 struct PairSetup {
@@ -1002,7 +1069,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   if constexpr (WCAP <= 16) {
     __shared__ int s_fail;
     if (tid < 64) {
-      const int f = ldl_reg_solve<WCAP>(R, lay.RS, W, av, wv);
+      const int f = ldl_reg_solve_w(R, lay.RS, W, av, wv);
       if (tid == 0) s_fail = f;
     }
     __syncthreads();
@@ -1101,13 +1168,16 @@ hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevD
 }
 
 // ------------------------------------------------------------------------------------------
-// Resident pair kernel (small problems: w_max (L + Lt) <= kResElems): every window row of the
-// pair, training and test snapshots, is loaded at once (all loads in flight together, one
-// latency) into LDS; the covariance, LDL^H, solves and beam outputs then run from LDS with no
-// further global reads.  Same arithmetic as the vector kernel: FP32 x FP32 products exact in
-// FP64, FP64 sums, FP64 factorisation and solves.
-constexpr int kResPre = 18;                    // staged elements per thread (256 threads)
-constexpr int kResElems = kResPre * 256;
+// Resident pair kernel: every window row of the pair sits in LDS once loaded; the covariance,
+// LDL^H, solves and beam outputs run from LDS with no further global reads.  Same arithmetic as
+// the vector kernel: FP32 x FP32 products exact in FP64, FP64 sums, FP64 factorisation and
+// solves.
+// Resident pair kernel (small problems: w_max L <= kResPart and w_max Lt <= kResPart): the
+// training rows are loaded and staged first; the test rows' loads are issued with them and stay
+// in flight in registers through the covariance and the factorisation, staged only for the
+// beam outputs.
+constexpr int kResPre = 9;                     // elements per thread of each part (256 threads)
+constexpr int kResPart = kResPre * 256;
 constexpr int kResRegW = 16;                   // widest window factorised in registers
 
 struct ResLds {
@@ -1129,8 +1199,9 @@ __host__ __device__ inline ResLds res_lds_layout(int wmax, int B) {
 }
 
 // LDS of at most 40 KiB: four workgroups per compute unit
-bool mvdr_resident_supported(int wmax, int B) {
-  return wmax * B <= kResElems && res_lds_layout(wmax, B).total <= 40 * 1024;
+bool mvdr_resident_supported(int wmax, int L, int Lt) {
+  return wmax * L <= kResPart && wmax * Lt <= kResPart &&
+         res_lds_layout(wmax, L + Lt).total <= 40 * 1024;
 }
 
 __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevDesc d,
@@ -1153,32 +1224,38 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
   if (a.route && !a.route[pair]) return;
   const int YS = lay.YS, RS = lay.RS;
 
-  // every element (row i, snapshot b) of the pair's window rows, b fastest: runs of TB
-  // consecutive snapshots are contiguous in the tiled layout.  i = e / B through a float
-  // reciprocal: e + 1/2 lies at least 1/2 from a multiple of B and e < 2^13, far beyond the
-  // reciprocal's rounding.
+  // every element (row i, snapshot b) of the training part [W][L], then of the test part
+  // [W][Lt], b fastest: runs of TB consecutive snapshots are contiguous in the tiled layout.
+  // i = e / len through a float reciprocal: e + 1/2 lies at least 1/2 from a multiple of len
+  // and e < 2^12, far beyond the reciprocal's rounding.
   const int TB = 1 << a.logTB;
   const float2* base = Yw + (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
-  const int n = W * a.B;
-  const float invB = 1.0f / (float)a.B;
-  float2 v[kResPre];
+  const int ntr = W * a.L, nte = W * a.Lt;
+  const float invL = 1.0f / (float)a.L, invLt = 1.0f / (float)max(a.Lt, 1);
+  if (starts_out && tid == 0) starts_out[pair] = ps.s;
+  // loads without branches (an index past the part reads its last element, dropped later), so
+  // that each use waits only for its own load and the test loads stay in flight
+  float2 vtr[kResPre], vte[kResPre];
 #pragma unroll
   for (int m = 0; m < kResPre; ++m) {
-    const int e = tid + m * TH;
-    v[m] = make_float2(0.f, 0.f);
-    if (e < n) {
-      const int i = (int)(((float)e + 0.5f) * invB), b = e - i * a.B;
-      v[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
-    }
+    const int e = min(tid + m * TH, ntr - 1);
+    const int i = (int)(((float)e + 0.5f) * invL), b = e - i * a.L;
+    vtr[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
+  }
+#pragma unroll
+  for (int m = 0; m < kResPre; ++m) {
+    const int e = max(min(tid + m * TH, nte - 1), 0);
+    const int i = (int)(((float)e + 0.5f) * invLt), b = a.L + e - i * a.Lt;
+    const int bb = nte > 0 ? b : 0;
+    vte[m] = base[((int64_t)(bb >> a.logTB) * a.sumW + i) * TB + (bb & (TB - 1))];
   }
   for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
-  if (starts_out && tid == 0) starts_out[pair] = ps.s;
 #pragma unroll
   for (int m = 0; m < kResPre; ++m) {
     const int e = tid + m * TH;
-    if (e < n) {
-      const int i = (int)(((float)e + 0.5f) * invB), b = e - i * a.B;
-      ys[i * YS + b] = v[m];
+    if (e < ntr) {
+      const int i = (int)(((float)e + 0.5f) * invL), b = e - i * a.L;
+      ys[i * YS + b] = vtr[m];
     }
   }
   __syncthreads();
@@ -1205,6 +1282,7 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
 #pragma unroll
       for (int w = 0; w < BS; ++w) ax[u][w] = ay[u][w] = 0.0;
     if (act) {
+#pragma unroll 4
       for (int b = sg; b < a.L; b += S) {
         double rx[BS], ry[BS], cx[BS], cy[BS];
 #pragma unroll
@@ -1257,7 +1335,7 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
   int fail;
   if (a.wmax <= kResRegW) {
     if (tid < 64) {
-      const int f = ldl_reg_solve<kResRegW>(R, RS, W, av, wv);
+      const int f = ldl_reg_solve_w(R, RS, W, av, wv);
       if (tid == 0) s_fail = f;
     }
     __syncthreads();
@@ -1267,6 +1345,16 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
     if (!fail) ldl_solve(R, RS, W, av, wv);
     __syncthreads();
   }
+  // test rows (loads in flight until now) into LDS
+#pragma unroll
+  for (int m = 0; m < kResPre; ++m) {
+    const int e = tid + m * TH;
+    if (e < nte) {
+      const int i = (int)(((float)e + 0.5f) * invLt), b = a.L + e - i * a.Lt;
+      ys[i * YS + b] = vte[m];
+    }
+  }
+  __syncthreads();
   // beam outputs: one test snapshot per thread, FP64 sums over the window rows
   float2* o = out + pair * a.Lt;
   for (int l = tid; l < a.Lt; l += TH) {
@@ -1294,7 +1382,7 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
 hipError_t launch_mvdr_resident(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                                 const float2* Yw, float2* out, float2* wout, int* starts,
                                 int* info, hipStream_t s) {
-  if (!mvdr_resident_supported(a.wmax, a.B)) return hipErrorInvalidValue;
+  if (!mvdr_resident_supported(a.wmax, a.L, a.Lt)) return hipErrorInvalidValue;
   const ResLds lay = res_lds_layout(a.wmax, a.B);
   hipLaunchKernelGGL(k_mvdr_res, dim3(a.T * (a.kc > 0 ? a.kc : a.K)), dim3(256), lay.total, s, a,
                      g, d, Yw, out, wout, starts, info);

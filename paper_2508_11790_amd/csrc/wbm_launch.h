@@ -63,13 +63,13 @@ constexpr int kPairMfma = 1;
 // kPairResident: four waves, the pair's whole window data resident in LDS (small problems,
 // mvdr_resident_supported)
 constexpr int kPairResident = 2;
-bool mvdr_resident_supported(int wmax, int B);
+bool mvdr_resident_supported(int wmax, int L, int Lt);
 hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s);
 bool mvdr_wave_supported(int wmax);
 // Mixed-precision pair kernel: MFMA BF16 covariance (split = BF16 hi/lo, three products;
-// else one BF16 product) with FP32 accumulation, FP32 Cholesky and solves, FP64 refinement
+// else one BF16 product) with FP32 accumulation, FP32 LDL^H and solves, FP64 refinement
 // residual and normalisation; ill-conditioned windows routed to FP64 (info bit 30).
 // flags: [T][K] int scratch written by the first launch (1 = routed), read by the second.
 hipError_t launch_mvdr_mixed(const PairArgs& a, const WindowGeom& g, const DevDesc& d,

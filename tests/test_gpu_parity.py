@@ -330,7 +330,7 @@ def test_zero_loading_singular_reports_info(torch, wb, form):
 
 
 def test_pair_kernel_limits_rejected(torch, wb):
-    # the one-wave kernel needs w_max <= 40; the resident kernel w_max (L + Lt) <= 5120
+    # the one-wave kernel needs w_max <= 40; the resident kernel w_max L, w_max Lt <= 2304
     plan = wb.Plan(64, 128, 8, 512, 512, 2, 41)
     chan, beam, _, _ = plan.tuning
     for pair in ("wave", "resident"):
