@@ -329,6 +329,36 @@ def test_zero_loading_singular_reports_info(torch, wb, form):
     plan.close()
 
 
+def test_target_changes_between_calls(torch, wb):
+    # an unchanged target list is not uploaded again; a changed one must be
+    cfg = scenes.SMALL
+    sc = scenes.make_scene(cfg)
+    x = torch.from_numpy(_x32(sc)).cuda()
+
+    def new_plan():
+        return wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, 3, 5, beta=cfg.beta,
+                       d_over_lambda=cfg.dl, half_bin=cfg.half_bin)
+
+    plan = new_plan()
+    az_a, win_a = [0.1, -0.3, 0.5], [5, 3, 5]
+    az_b, win_b = [0.2, 0.4], [3, 5]
+    a1 = plan.beamform(x, az_a, win_a, cfg.delta, form="fused")
+    a2 = plan.beamform(x, az_a, win_a, cfg.delta, form="fused")
+    b1 = plan.beamform(x, az_b, win_b, cfg.delta, form="fused")
+    a3 = plan.beamform(x, az_a, win_a, cfg.delta, form="graph")
+    torch.cuda.synchronize()
+    fresh = new_plan()
+    fresh.set_tuning(*plan.tuning)
+    b2 = fresh.beamform(x, az_b, win_b, cfg.delta, form="fused")
+    torch.cuda.synchronize()
+    for key in ("out", "weights", "starts"):
+        assert torch.equal(a1[key], a2[key]), key
+        assert torch.equal(a1[key], a3[key]), key
+        assert torch.equal(b1[key], b2[key]), key
+    plan.close()
+    fresh.close()
+
+
 def test_pair_kernel_limits_rejected(torch, wb):
     # the one-wave kernel needs w_max <= 40; the resident kernel w_max L, w_max Lt <= 2304
     plan = wb.Plan(64, 128, 8, 512, 512, 2, 41)
