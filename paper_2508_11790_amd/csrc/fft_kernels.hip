@@ -105,7 +105,9 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
 // fetching the next tile's inputs into registers while the current one is transformed.
 // With windows or profiles the first threads place the targets of subband k (same FP64
 // evaluation as the steering kernel) into LDS.
-template <int LOGM, int LOGT>
+// ZH: N <= M / 2, so the upper half of every zero-padded row is zero; those inputs are neither
+// loaded nor added.
+template <int LOGM, int LOGT, bool ZH>
 __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
     const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int N, int B,
     int K, const float2* __restrict__ twM, float scale, const int* __restrict__ rowtab, int sumW,
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
         int row, e;
         F::first_input(p, r, row, e);
         float2 val = make_float2(0.f, 0.f);
-        if (e < N && b0 + row < B) val = X[((int64_t)k * B + b0 + row) * N + e];
+        if (!(ZH && 2 * r >= F::R0) && e < N && b0 + row < B)
+          val = X[((int64_t)k * B + b0 + row) * N + e];
         v[p * F::R0 + r] = val;
       }
     }
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = nv[q];
     if (j + (int)gridDim.x < nbt) fetch(j + gridDim.x, nv);
-    F::run(v, lds, tr);
+    F::template run<ZH>(v, lds, tr);
     if (Y) {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -240,11 +243,11 @@ static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const fl
   return hipGetLastError();
 }
 
-template <int LOGM, int LOGT>
-static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
-                              const float2* twM, const int* rowtab, int sumW,
-                              const WindowGeom& g, float* prof, int L, int G, int k0, int kc,
-                              hipStream_t s) {
+template <int LOGM, int LOGT, bool ZH>
+static hipError_t beam_launch_zh(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
+                                 const float2* twM, const int* rowtab, int sumW,
+                                 const WindowGeom& g, float* prof, int L, int G, int k0, int kc,
+                                 hipStream_t s) {
   using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   const int nbt = (B + F::rows - 1) / F::rows;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
@@ -254,21 +257,33 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
   if (Yw) shm += sizeof(int) * (size_t)sumW;
   if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
     // beyond the default 64 KiB per workgroup: ask for exactly the dynamic part
-    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LOGM, LOGT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LOGM, LOGT, ZH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
   int gx = G;
   if (!prof) {
     static int resident = 0;
-    const int cap = resident_blocks(k_beamspace<LOGM, LOGT>, F::threads, shm, &resident);
+    const int cap = resident_blocks(k_beamspace<LOGM, LOGT, ZH>, F::threads, shm, &resident);
     gx = (cap + kc - 1) / kc;
     if (gx > nbt) gx = nbt;
     if (gx < 1) gx = 1;
   }
-  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT>), dim3(gx, kc), dim3(F::threads), shm, s, X, Y, Yw, N,
-                     B, K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L, k0);
+  hipLaunchKernelGGL((k_beamspace<LOGM, LOGT, ZH>), dim3(gx, kc), dim3(F::threads), shm, s, X, Y,
+                     Yw, N, B, K, twM, 1.0f / sqrtf((float)F::n), rowtab, sumW, g, prof, L, k0);
   return hipGetLastError();
+}
+
+template <int LOGM, int LOGT>
+static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
+                              const float2* twM, const int* rowtab, int sumW,
+                              const WindowGeom& g, float* prof, int L, int G, int k0, int kc,
+                              hipStream_t s) {
+  if (2 * N <= (1 << LOGM))
+    return beam_launch_zh<LOGM, LOGT, true>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, prof, L, G,
+                                            k0, kc, s);
+  return beam_launch_zh<LOGM, LOGT, false>(X, Y, Yw, N, B, K, twM, rowtab, sumW, g, prof, L, G,
+                                           k0, kc, s);
 }
 
 #define WBM_LOG_CASES(M, T) \

@@ -120,6 +120,42 @@ __device__ __forceinline__ void dftR(float2* v) {
   else dft8(v);
 }
 
+// The same DFTs when the upper half of the inputs is zero (v[R/2 .. R-1] = 0, not read): the
+// additions of those zeros are left out, which changes no value.
+__device__ __forceinline__ void dft4_zh(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 x0 = a0, x1 = a1, t3 = cmul_mj(x1);
+  a0 = cadd(x0, x1);
+  a2 = csub(x0, x1);
+  a1 = cadd(x0, t3);
+  a3 = csub(x0, t3);
+}
+
+__device__ __forceinline__ void dft8_zh(float2* v) {
+  float2 e0 = v[0], e1 = v[2], e2, e3;
+  float2 o0 = v[1], o1 = v[3], o2, o3;
+  dft4_zh(e0, e1, e2, e3);
+  dft4_zh(o0, o1, o2, o3);
+  const float r = 0.70710678118654752440f;
+  float2 w1 = make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);     // (1 - i)/sqrt2
+  float2 w2 = cmul_mj(o2);                                            // -i
+  float2 w3 = make_float2((o3.y - o3.x) * r, -(o3.x + o3.y) * r);     // (-1 - i)/sqrt2
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, w1); v[5] = csub(e1, w1);
+  v[2] = cadd(e2, w2); v[6] = csub(e2, w2);
+  v[3] = cadd(e3, w3); v[7] = csub(e3, w3);
+}
+
+template <int R>
+__device__ __forceinline__ void dftR_zh(float2* v) {
+  if constexpr (R == 2) {
+    v[1] = v[0];
+  } else if constexpr (R == 4) {
+    dft4_zh(v[0], v[1], v[2], v[3]);
+  } else {
+    dft8_zh(v);
+  }
+}
+
 // Batched forward DFT of `rows` rows of n = 2^LOGN points held across a workgroup of
 // tile/8 threads, eight complex values per thread (Stockham autosort, radix 8 with one
 // leading radix-2 or radix-4 pass).  Pass p of radix R over sub-length Ns: butterfly j of
@@ -185,7 +221,7 @@ struct Fft {
     }
   }
 
-  template <int R, int LOGR, int LOGNS>
+  template <int R, int LOGR, int LOGNS, bool ZH = false>
   __device__ __forceinline__ static void compute_write(float2 (&v)[8], float2* lds,
                                                        const float2 (&tr)[NPA][NTW]) {
 #pragma unroll
@@ -215,7 +251,10 @@ struct Fft {
           for (int r = 1; r < R; ++r) b[r] = cmul(b[r], tr[q][r - 1]);
         }
       }
-      dftR<R>(b);
+      if constexpr (ZH && LOGNS == 0)
+        dftR_zh<R>(b);
+      else
+        dftR<R>(b);
       const int base = ((j >> LOGNS) << (LOGNS + LOGR)) | k;
 #pragma unroll
       for (int r = 0; r < R; ++r) lds[addr(row, base + (r << LOGNS))] = b[r];
@@ -251,10 +290,12 @@ struct Fft {
 
   // v holds the first-pass inputs (slot p*R0 + r <-> first_input(p, r)), tr the thread's
   // twiddles (load_twiddles); on return the transform of every row is in LDS in natural order
-  // (addr(row, i)), visible to all threads.
+  // (addr(row, i)), visible to all threads.  ZH: the inputs at positions >= n/2 are zero (the
+  // slots r >= R0/2 are not read).
+  template <bool ZH = false>
   __device__ __forceinline__ static void run(float2 (&v)[8], float2* lds,
                                              const float2 (&tr)[NPA][NTW]) {
-    compute_write<R0, LOGR0, 0>(v, lds, tr);
+    compute_write<R0, LOGR0, 0, ZH>(v, lds, tr);
     rest<LOGR0>(v, lds, tr);
     __syncthreads();
   }
