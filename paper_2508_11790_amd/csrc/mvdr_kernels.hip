@@ -1242,13 +1242,6 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
     const int i = (int)(((float)e + 0.5f) * invL), b = e - i * a.L;
     vtr[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
   }
-#pragma unroll
-  for (int m = 0; m < kResPre; ++m) {
-    const int e = max(min(tid + m * TH, nte - 1), 0);
-    const int i = (int)(((float)e + 0.5f) * invLt), b = a.L + e - i * a.Lt;
-    const int bb = nte > 0 ? b : 0;
-    vte[m] = base[((int64_t)(bb >> a.logTB) * a.sumW + i) * TB + (bb & (TB - 1))];
-  }
   for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
 #pragma unroll
   for (int m = 0; m < kResPre; ++m) {
@@ -1331,6 +1324,15 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
     }
   }
   __syncthreads();
+  // test rows: issued once every workgroup's training rows are in (they compete with none of
+  // them), in flight through the factorisation
+#pragma unroll
+  for (int m = 0; m < kResPre; ++m) {
+    const int e = max(min(tid + m * TH, nte - 1), 0);
+    const int i = (int)(((float)e + 0.5f) * invLt), b = a.L + e - i * a.Lt;
+    const int bb = nte > 0 ? b : 0;
+    vte[m] = base[((int64_t)(bb >> a.logTB) * a.sumW + i) * TB + (bb & (TB - 1))];
+  }
   __shared__ int s_fail;
   int fail;
   if (a.wmax <= kResRegW) {
