@@ -180,10 +180,10 @@ wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                          void* stream);
 
 /* Per-stage timing of the fused sequence (same arguments as wbm_beamform with
- * form = WBM_FORM_FUSED, outputs go to plan-internal scratch): runs it `reps` times on
- * `stream` with HIP events around every kernel and writes the average milliseconds of
- * steer, channelize, windowed beamspace and fused MVDR to stage_ms (host [4]).  Blocks
- * until the stream has drained. */
+ * form = WBM_FORM_FUSED, outputs go to plan-internal scratch): launches each kernel of it
+ * (steer, channelize, windowed beamspace, fused MVDR, in that order) once untimed and then
+ * `reps` times back to back on `stream` between two HIP events, and writes the average
+ * milliseconds per launch to stage_ms (host [4]).  Blocks until the stream has drained. */
 wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                            const int32_t* win, int32_t T, double loading, int32_t reps,
                            double* stage_ms, void* stream);

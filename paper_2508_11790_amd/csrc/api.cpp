@@ -858,32 +858,34 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   if ((s = ensure_prof(p))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
   if (!p->tuned) WBM_HIP(autotune(p, xx, T, sumW, loading, st), "autotune");
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
-  double acc[4] = {0, 0, 0, 0};
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
+  // each stage launched `reps` times back to back between two events (every launch rewrites
+  // the same output from the same input), after one untimed launch; stages in pipeline order
   hipError_t e = hipSuccess;
-  for (int r = -1; r < reps && e == hipSuccess; ++r) {   // r = -1: untimed warm-up
-    e = hipEventRecord(ev[0], st);
-    if (e == hipSuccess) e = wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess) e = enqueue_channelize(p, xx, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[2], st);
-    if (e == hipSuccess) e = enqueue_beamspace_windows(p, T, sumW, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[3], st);
-    if (e == hipSuccess)
-      e = wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw,
-                                 p->prof_out, p->prof_w, nullptr, p->prof_info, p->pair_threads, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[4], st);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
-    for (int i = 0; i < 4 && e == hipSuccess && r >= 0; ++i) {
-      float ms = 0.f;
-      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-      acc[i] += ms;
+  auto stage = [&](int i) -> hipError_t {
+    switch (i) {
+      case 0: return wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st);
+      case 1: return enqueue_channelize(p, xx, st);
+      case 2: return enqueue_beamspace_windows(p, T, sumW, st);
+      default:
+        return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw,
+                                      p->prof_out, p->prof_w, nullptr, p->prof_info,
+                                      p->pair_threads, st);
     }
+  };
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+    e = stage(i);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = stage(i);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    stage_ms[i] = ms / reps;
   }
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ev[i]);
   if (e != hipSuccess) return hip_fail(e, "stage timing");
-  for (int i = 0; i < 4; ++i) stage_ms[i] = acc[i] / reps;
   return WBM_OK;
 }
 
