@@ -255,7 +255,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: ULA N={cfg.N}, M={cfg.M}, K={cfg.K}, W={wmax}, "
                                f"L={cfg.L}, Lt={cfg.Lt}, T={T}, {cfg.n_jammers} jammers",
-                   "form": "fused + HIP graph", "pairs_per_step": beams},
+                   "form": "fused + HIP graph", "pairs_per_step": beams,
+                   "tuning": dict(zip(("chan_logtile", "beam_logtile", "pair_kernel",
+                                       "overlap_chunks"), plan.tuning))},
         "plain": {"value": beams / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                   "form": "per-stage FP32 kernels, full beamspace in HBM, no graph"},
         "mixed": {f: {k2: v for k2, v in r.items() if k2 != "weights"} for f, r in mixed.items()},

@@ -27,7 +27,7 @@
  * - Work is enqueued on the given HIP stream (NULL = default stream) and the call
  *   returns without waiting; synchronise the stream before reading outputs.
  * - Numerical failure of one (target, subband) solve does not fail the call: its
- *   info entry is set to j > 0 (the Cholesky pivot j-1 was not positive/finite),
+ *   info entry is set to j > 0 (factorisation pivot j-1 was not positive/finite),
  *   and its outputs are zero.
  * - A plan is not thread safe; independent plans may be used concurrently.
  *
@@ -65,15 +65,15 @@ typedef enum {
 #define WBM_FORM_PLAIN 0    /* per-stage kernels, FP32 arithmetic, one launch per stage, full
                                beamspace written to HBM and gathered per pair */
 #define WBM_FORM_FUSED 1    /* beamspace FFT writes only the windows; one fused per-pair
-                               covariance -> Cholesky -> solve -> apply launch; FP64
-                               accumulation of the covariance and FP64 Cholesky */
+                               covariance -> LDL^H -> solves -> apply launch; FP64
+                               accumulation of the covariance and FP64 LDL^H */
 #define WBM_FORM_GRAPH 2    /* WBM_FORM_FUSED with the launch sequence replayed from a
                                HIP graph (captured on first use for a given argument set) */
 #define WBM_FORM_MIXED 3    /* fused sequence with the window covariance on MFMA: each FP32
                                snapshot split into BF16 hi + lo (three BF16 products, FP32
-                               accumulation), FP32 Cholesky and solves, one FP64-residual
+                               accumulation), FP32 LDL^H and solves, one FP64-residual
                                refinement step and FP64 normalisation a^H R^-1 a; windows whose
-                               Cholesky pivots span a condition estimate above 1e4 take the
+                               LDL^H pivots span a condition estimate above 1e4 take the
                                FP64 path instead and report info bit 30 (info & (1 << 30)) */
 #define WBM_FORM_MIXED_BF16 4  /* as WBM_FORM_MIXED with one BF16 product per step (snapshots
                                rounded to BF16) */
@@ -144,7 +144,7 @@ wbm_status wbm_plan_get_tuning(const wbm_plan* plan, int32_t* chan_logtile,
  *           (bins (s + i) mod M, i < W_t), zero padded to w_max.
  *   starts  device [T][K] int32 or NULL: first window bin s of every pair (may be
  *           negative; the bins are taken mod M).
- *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's Cholesky failed at
+ *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's factorisation failed at
  *           pivot j-1 (mixed forms: plus WBM_INFO_ROUTED when the FP64 path was taken).
  *   stream  hipStream_t or NULL. */
 wbm_status wbm_beamform(wbm_plan* plan, const wbm_c32* x, const double* az_rad,

@@ -10,7 +10,7 @@
 // waves or one wave per pair on the vector units, four waves on the FP64 matrix cores.
 // Plain form: the same steps as three FP32 launches with R and c in HBM, gathering the window
 // rows from the full beamspace.
-// Mixed form (end of file): BF16 matrix-core covariance, FP32 Cholesky, FP64 refinement.
+// Mixed form (end of file): BF16 matrix-core covariance, FP32 LDL^H, FP64 refinement.
 #include <math.h>
 
 #include "wbm_dev.h"
@@ -792,69 +792,6 @@ __device__ __forceinline__ int ldl_reg_solve(const C2<double>* R, int RS, int W,
     const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);   // x_c, final
     if (lane < c) {
       const C2<double> h = r[c];                                          // conj(l_ci) d_i
-      x.x -= (h.x * xx - h.y * xy) * invd;
-      x.y -= (h.x * xy + h.y * xx) * invd;
-    }
-  }
-  const double qinv = 1.0 / q;
-  if (lane < W) wv[lane] = c2<double>(x.x * qinv, x.y * qinv);
-  return 0;
-}
-
-// As ldl_reg_solve, with column j (and y_j) handed to the lanes through LDS broadcast reads
-// instead of readlanes: one write and independent reads per step.
-template <int WCAP>
-__device__ __forceinline__ int ldl_bcast_solve(const C2<double>* R, int RS, int W,
-                                               const double2* av, C2<double>* wv) {
-  __shared__ C2<double> col[WCAP + 1];
-  const int lane = threadIdx.x & 63;
-  C2<double> r[WCAP];
-#pragma unroll
-  for (int c = 0; c < WCAP; ++c) {
-    r[c] = c2<double>(c == lane ? 1.0 : 0.0, 0.0);
-    if (lane < W && c < W) {
-      const bool lo = c <= lane;
-      const C2<double> u = R[lo ? lane * RS + c : c * RS + lane];
-      r[c] = c2<double>(u.x, lo ? u.y : -u.y);
-    }
-  }
-  C2<double> y = c2<double>(0.0, 0.0);
-  if (lane < W) y = c2<double>(av[lane].x, av[lane].y);
-  double invd = 0.0;
-#pragma unroll
-  for (int j = 0; j < WCAP; ++j) {
-    if (lane >= j && lane < WCAP) col[lane] = r[j];
-    if (lane == j) col[WCAP] = y;
-    const double dj = col[j].x;
-    C2<double> g[WCAP];
-#pragma unroll
-    for (int c = j + 1; c < WCAP; ++c) g[c] = col[c];
-    const C2<double> yj = col[WCAP];
-    if (!(dj > 0.0) || !(dj < (double)INFINITY)) return j + 1;
-    const double inv = 1.0 / dj;
-    if (lane == j) invd = inv;
-    const double lx = r[j].x * inv, ly = r[j].y * inv;
-    const double yx = yj.x * inv, yy = yj.y * inv;
-    if (lane > j) {
-      y.x -= r[j].x * yx - r[j].y * yy;
-      y.y -= r[j].x * yy + r[j].y * yx;
-    }
-#pragma unroll
-    for (int c = j + 1; c < WCAP; ++c) {
-      if (lane > j) {
-        r[c].x = fma(-lx, g[c].x, fma(-ly, g[c].y, r[c].x));
-        r[c].y = fma(-ly, g[c].x, fma(lx, g[c].y, r[c].y));
-      }
-    }
-  }
-  double q = (lane < W) ? (y.x * y.x + y.y * y.y) * invd : 0.0;
-  for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off);
-  C2<double> x = c2<double>(y.x * invd, y.y * invd);
-#pragma unroll
-  for (int c = WCAP - 1; c >= 0; --c) {
-    const double xx = readlane_f64(x.x, c), xy = readlane_f64(x.y, c);
-    if (lane < c) {
-      const C2<double> h = r[c];
       x.x -= (h.x * xx - h.y * xy) * invd;
       x.y -= (h.x * xy + h.y * xx) * invd;
     }
@@ -1723,7 +1660,8 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
   }
   __syncthreads();
   int fail = ldl_lds<TH, float>(R32, RS, W);
-  // condition estimate from the pivots: max d / min d (d = squared Cholesky pivots)
+  // condition estimate from the pivots: max d / min d (d = LDL^H pivots, the squared
+  // Cholesky ones)
   bool route = fail != 0;
   if (!fail) {
     float dmax = 0.f, dmin = 3.0e38f;
