@@ -33,7 +33,7 @@ __all__ = [
     "beamspace", "beamspace_rows", "spatial_frequency", "beam_position",
     "window_start", "window_bins", "steering", "beamspace_steering",
     "sample_covariance", "mvdr_weights", "beam_output", "lift_correlator",
-    "beam_pattern", "windowed_mvdr", "full_mvdr", "interference_covariance",
+    "beam_pattern", "synthesize", "lifted_outputs", "windowed_mvdr", "full_mvdr", "interference_covariance",
     "sinr", "sinr_loss_db", "rel_weight_error",
 ]
 
@@ -208,6 +208,38 @@ def beam_pattern(c: np.ndarray, omegas: Sequence[float]) -> np.ndarray:
         a = steering(N, om)
         out[i] = abs(np.vdot(c, a)) / (np.linalg.norm(c) * np.linalg.norm(a))
     return out
+
+
+def synthesize(Z: np.ndarray, K: int, half_bin: bool = False) -> np.ndarray:
+    """Subband synthesis (Sec. II / Sec. IV-B: the per-subband beamformer outputs are combined by
+    an inverse FFT into the wideband signal): the inverse of :func:`channelize` per block.
+
+    Z[..., K, B] (subband axis, then block axis) -> z[..., B*K],
+    z[b*K + tau] = K^-1/2 conj(h[tau]) sum_k Z[k, b] exp(+j 2 pi tau k / K), with h the
+    channelizer's pre-twiddle (1, or exp(-j pi tau / K) for the half-bin centres).
+    """
+    Z = np.asarray(Z, dtype=np.complex128)
+    assert Z.shape[-2] == K
+    blocks = np.fft.ifft(np.moveaxis(Z, -2, -1), axis=-1, norm="ortho")     # [..., B, K]
+    if half_bin:
+        blocks = blocks * np.exp(1j * np.pi * np.arange(K) / K)
+    return blocks.reshape(*blocks.shape[:-2], -1)
+
+
+def lifted_outputs(x: np.ndarray, c_hat: np.ndarray, *, K: int, L: int, Lt: int,
+                   half_bin: bool = False) -> np.ndarray:
+    """Beam outputs from lifted correlators applied in element space (Eq. 21 and the remark
+    after it): z[t, k, l] = c^_tk^H X_k[:, L + l] for the test snapshots, no beamspace step.
+
+    x[N, S]; c_hat[T, K, N] -> z[T, K, Lt].
+    """
+    X = channelize(x, K, half_bin)                         # [N, B, K]
+    T = c_hat.shape[0]
+    z = np.empty((T, K, Lt), dtype=np.complex128)
+    for t in range(T):
+        for k in range(K):
+            z[t, k] = beam_output(c_hat[t, k], X[:, L:L + Lt, k])
+    return z
 
 
 # --------------------------------------------------------------------------- pipelines
