@@ -170,6 +170,30 @@ def main():
     ms_chosen = timed_steps(torch, step("graph"), args.steps, args.warmup)
     assert int(info.abs().sum()) == 0
     w_chosen = wts.cpu().numpy().astype(np.complex128)
+
+    # beside the path: lifted correlators applied in element space (Eq. 21), subband synthesis
+    log("timing lifted correlators in element space and subband synthesis")
+    fres = plan.beamform(x, az, win, delta, form="fused")
+    ms_lift = timed_steps(torch, lambda: plan.lift(fres["weights"], fres["starts"]),
+                          args.steps, args.warmup)
+    c_hat = plan.lift(fres["weights"], fres["starts"])
+    out_l = torch.empty_like(out)
+    ms_applied = timed_steps(torch, lambda: plan.apply_lifted(x, c_hat, out=out_l), args.steps,
+                             args.warmup)
+    lift_diff = float((out_l - fres["out"]).abs().max() / fres["out"].abs().max())
+    zbuf = torch.empty((T, cfg.Lt * K), dtype=torch.complex64, device=x.device)
+    ms_synth = timed_steps(torch, lambda: plan.synthesize(fres["out"], z=zbuf), args.steps,
+                           args.warmup)
+    synth_bytes = 2.0 * T * K * cfg.Lt * 8
+    lifted_res = {
+        "value": T * K / (ms_applied * 1e-3), "ms_per_step": ms_applied,
+        "form": "channelize + c^H X on the test snapshots (no spatial DFT, no window gather)",
+        "lift_ms": ms_lift, "max_rel_diff_vs_fused_outputs": lift_diff,
+    }
+    synth_res = {"ms_per_call": ms_synth, "gbs": synth_bytes / (ms_synth * 1e-3) / 1e9,
+                 "bytes": synth_bytes}
+    del fres, c_hat, out_l, zbuf
+
     log("timing plain per-stage FP32 form")
     ms_plain = timed_steps(torch, step("plain"), args.steps, args.warmup)
     w_plain = wts.cpu().numpy().astype(np.complex128)
@@ -261,6 +285,8 @@ def main():
         "plain": {"value": beams / (ms_plain * 1e-3), "ms_per_step": ms_plain,
                   "form": "per-stage FP32 kernels, full beamspace in HBM, no graph"},
         "mixed": {f: {k2: v for k2, v in r.items() if k2 != "weights"} for f, r in mixed.items()},
+        "lifted": lifted_res,
+        "synthesis": synth_res,
         "learned": learned_res,
         "full_dim": (None if ms_full is None else
                      {"value": beams / (ms_full * 1e-3), "ms_per_step": ms_full,

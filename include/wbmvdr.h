@@ -161,6 +161,36 @@ wbm_status wbm_channelize(wbm_plan* plan, const wbm_c32* x, wbm_c32* X, void* st
  * Y[k][m][b] = M^-1/2 sum_{e<N} X[k][b][e] exp(-j 2 pi m e / M). */
 wbm_status wbm_beamspace(wbm_plan* plan, const wbm_c32* X, wbm_c32* Y, void* stream);
 
+/* Lifted correlators (Eq. 21): c^_tk = D^H S_tk^T c~_tk, every pair's windowed weights mapped
+ * back to the N elements, c^[n] = M^-1/2 sum_i c~_i exp(+j 2 pi n m_i / M), m_i = (s + i) mod M.
+ *   weights device [T][K][w_max] wbm_c32: window-bin order from the pair's start, zero past its
+ *           width (as wbm_beamform / wbm_beamform_pairs write them).
+ *   starts  device [T][K] int32: each pair's first window bin (may be negative).
+ *   c_hat   device [T][K][N] wbm_c32, written.
+ * Errors: WBM_ERR_ARG for NULL pointers or T outside [1, max_targets]. */
+wbm_status wbm_lift(wbm_plan* plan, const wbm_c32* weights, const int32_t* starts, int32_t T,
+                    wbm_c32* c_hat, void* stream);
+
+/* Beam outputs from lifted correlators applied in element space (the remark after Eq. 21: no
+ * spatial transform and no window gather): channelizes x into the plan's workspace and writes
+ * out[t][k][l] = c^_tk^H X_k[:, L + l] for the Lt test snapshots.
+ *   x      device [N][S] wbm_c32 as for wbm_beamform.
+ *   c_hat  device [T][K][N] wbm_c32 (e.g. from wbm_lift).
+ *   out    device [T][K][Lt] wbm_c32, written.
+ * Errors: WBM_ERR_ARG for NULL pointers or T outside [1, max_targets]. */
+wbm_status wbm_apply_lifted(wbm_plan* plan, const wbm_c32* x, const wbm_c32* c_hat, int32_t T,
+                            wbm_c32* out, void* stream);
+
+/* Subband synthesis (the inverse FFT across subbands that recovers the wideband beam output,
+ * Sec. II and IV-B): the inverse of the channelizer per test block,
+ *   z[t][b K + tau] = K^-1/2 conj(h[tau]) sum_k out[t][k][b] exp(+j 2 pi tau k / K),
+ * h as for wbm_channelize, b < Lt.
+ *   out device [T][K][Lt] wbm_c32 (beam outputs, e.g. from wbm_beamform).
+ *   z   device [T][Lt*K] wbm_c32, written.
+ * Errors: WBM_ERR_ARG for NULL pointers or T outside [1, max_targets]. */
+wbm_status wbm_synthesize(wbm_plan* plan, const wbm_c32* out, int32_t T, wbm_c32* z,
+                          void* stream);
+
 /* Stage: window placement and windowed steering (Eq. 18-19; a~ = S D a below Eq. 20).
  *   starts device [T][K] int32: s = floor(u - (W_t-1)/2 + 1/2), u = M (d/lambda) sin(az) f_k/f_c
  *          evaluated in IEEE double as ((M * dl) * sin(az)) * ratio, ratio = 1 + (beta*(ks+h))/K,

@@ -182,6 +182,46 @@ class Plan:
         _lib.check(_lib.load().wbm_beamspace(self._h, _ptr(X), _ptr(Y), _stream(stream)))
         return Y
 
+    def lift(self, weights, starts, c_hat=None, stream=None):
+        """Lifted correlators (Eq. 21) of every pair: weights [T, K, w_max] complex64 and
+        starts [T, K] int32 (as beamform returns them) -> c_hat [T, K, N] complex64."""
+        torch = _torch()
+        T = int(weights.shape[0])
+        _check_tensor(weights, "weights", (T, self.K, self.w_max), torch.complex64, self.device)
+        _check_tensor(starts, "starts", (T, self.K), torch.int32, self.device)
+        if c_hat is None:
+            c_hat = torch.empty((T, self.K, self.N), dtype=torch.complex64, device=self.device)
+        _check_tensor(c_hat, "c_hat", (T, self.K, self.N), torch.complex64, self.device)
+        _lib.check(_lib.load().wbm_lift(self._h, _ptr(weights), _ptr(starts), T, _ptr(c_hat),
+                                        _stream(stream)))
+        return c_hat
+
+    def apply_lifted(self, x, c_hat, out=None, stream=None):
+        """Beam outputs of lifted correlators applied in element space to the test snapshots:
+        x [N, S] and c_hat [T, K, N] -> out [T, K, Lt] complex64 (channelizes x itself)."""
+        torch = _torch()
+        self._x(x)
+        T = int(c_hat.shape[0])
+        _check_tensor(c_hat, "c_hat", (T, self.K, self.N), torch.complex64, self.device)
+        if out is None:
+            out = torch.empty((T, self.K, self.Lt), dtype=torch.complex64, device=self.device)
+        _check_tensor(out, "out", (T, self.K, self.Lt), torch.complex64, self.device)
+        _lib.check(_lib.load().wbm_apply_lifted(self._h, _ptr(x), _ptr(c_hat), T, _ptr(out),
+                                                _stream(stream)))
+        return out
+
+    def synthesize(self, out, z=None, stream=None):
+        """Subband synthesis (inverse channelizer per test block): out [T, K, Lt] -> z [T, Lt*K]
+        complex64, the wideband beam output of every target."""
+        torch = _torch()
+        T = int(out.shape[0])
+        _check_tensor(out, "out", (T, self.K, self.Lt), torch.complex64, self.device)
+        if z is None:
+            z = torch.empty((T, self.Lt * self.K), dtype=torch.complex64, device=self.device)
+        _check_tensor(z, "z", (T, self.Lt * self.K), torch.complex64, self.device)
+        _lib.check(_lib.load().wbm_synthesize(self._h, _ptr(out), T, _ptr(z), _stream(stream)))
+        return z
+
     def steer(self, az_rad, win, stream=None):
         """Window starts [T, K] int32 and windowed steering vectors [T, K, w_max] complex128."""
         torch = _torch()

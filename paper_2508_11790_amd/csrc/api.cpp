@@ -745,6 +745,50 @@ wbm_status wbm_channelize(wbm_plan* p, const wbm_c32* x, wbm_c32* X, void* strea
   return WBM_OK;
 }
 
+wbm_status wbm_lift(wbm_plan* p, const wbm_c32* weights, const int32_t* starts, int32_t T,
+                    wbm_c32* c_hat, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!weights || !starts || !c_hat) return fail(WBM_ERR_ARG, "weights / starts / c_hat is NULL");
+  const wbm_config& c = p->cfg;
+  if (T < 1 || T > c.max_targets) return fail(WBM_ERR_ARG, "T outside [1, max_targets]");
+  WBM_HIP(wbm::launch_lift(reinterpret_cast<const float2*>(weights), starts, T * c.k_sub,
+                           c.w_max, c.n_elem, c.m_fft, p->twM, reinterpret_cast<float2*>(c_hat),
+                           static_cast<hipStream_t>(stream)),
+          "lift launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_apply_lifted(wbm_plan* p, const wbm_c32* x, const wbm_c32* c_hat, int32_t T,
+                            wbm_c32* out, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!x || !c_hat || !out) return fail(WBM_ERR_ARG, "x / c_hat / out is NULL");
+  const wbm_config& c = p->cfg;
+  if (T < 1 || T > c.max_targets) return fail(WBM_ERR_ARG, "T outside [1, max_targets]");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  WBM_HIP(enqueue_channelize(p, reinterpret_cast<const float2*>(x), st), "channelize launch");
+  WBM_HIP(wbm::launch_lift_apply(p->X, reinterpret_cast<const float2*>(c_hat),
+                                 reinterpret_cast<float2*>(out), c.n_elem, c.k_sub, p->B,
+                                 c.l_train, c.l_test, T, st),
+          "lifted apply launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_synthesize(wbm_plan* p, const wbm_c32* out, int32_t T, wbm_c32* z, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!out || !z) return fail(WBM_ERR_ARG, "out / z is NULL");
+  const wbm_config& c = p->cfg;
+  if (T < 1 || T > c.max_targets) return fail(WBM_ERR_ARG, "T outside [1, max_targets]");
+  WBM_HIP(wbm::launch_synth(reinterpret_cast<const float2*>(out), reinterpret_cast<float2*>(z),
+                            c.k_sub, c.l_test, T, p->twK,
+                            (c.flags & WBM_HALF_BIN) ? p->hb : nullptr,
+                            static_cast<hipStream_t>(stream)),
+          "synthesis launch");
+  return WBM_OK;
+}
+
 wbm_status wbm_beamspace(wbm_plan* p, const wbm_c32* X, wbm_c32* Y, void* stream) {
   wbm_status s = check_plan(p);
   if (s) return s;

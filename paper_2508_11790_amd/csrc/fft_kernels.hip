@@ -205,6 +205,60 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   }
 }
 
+// Subband synthesis, the inverse of the channelizer per block: Z [T][K][Lt] (beam outputs of
+// every subband on the test blocks) -> z [T][Lt*K], z[t][b K + tau] = K^-1/2 conj(h[tau])
+// sum_k Z[t][k][b] exp(+j 2 pi tau k / K), computed as the conjugate of the forward transform
+// of conj(Z).  Workgroup = (tiles of TB = tile/K blocks, target t): the block-contiguous
+// inputs are staged through LDS (reads run along the blocks), the output rows are written
+// time-contiguous.
+template <int LOGK>
+__global__ __launch_bounds__(fft_threads(LOGK, 11)) void k_synth(
+    const float2* __restrict__ Z, float2* __restrict__ z, int Lt, const float2* __restrict__ twK,
+    const float2* __restrict__ hb, float scale) {
+  using F = Fft<LOGK, fft_tile(LOGK, 11), chan_pad(fft_tile(LOGK, 11), LOGK)>;
+  constexpr int K = F::n, TB = F::rows;
+  constexpr int LOGTB = fft_tile(LOGK, 11) - LOGK;
+  __shared__ float2 lds[F::lds_complex];
+  float2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twK);
+  const float2* Zt = Z + (int64_t)blockIdx.y * K * Lt;
+  float2* zt = z + (int64_t)blockIdx.y * Lt * K;
+  for (int b0 = blockIdx.x * TB; b0 < Lt; b0 += gridDim.x * TB) {
+    for (int idx = threadIdx.x; idx < K * TB; idx += F::threads) {
+      const int k = idx >> LOGTB, r = idx & (TB - 1);
+      float2 val = make_float2(0.f, 0.f);
+      if (b0 + r < Lt) {
+        const float2 u = Zt[(int64_t)k * Lt + b0 + r];
+        val = make_float2(u.x, -u.y);
+      }
+      lds[F::addr(r, k)] = val;
+    }
+    __syncthreads();
+    float2 v[8];
+#pragma unroll
+    for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        int row, pos;
+        F::first_input(p, r, row, pos);
+        v[p * F::R0 + r] = lds[F::addr(row, pos)];
+      }
+    }
+    __syncthreads();
+    F::run(v, lds, tr);
+    for (int idx = threadIdx.x; idx < TB * K; idx += F::threads) {
+      const int row = idx >> LOGK, i = idx & (K - 1);
+      if (b0 + row < Lt) {
+        const float2 u = lds[F::addr(row, i)];
+        float2 y = make_float2(u.x * scale, -u.y * scale);
+        if (hb) y = cmul(y, make_float2(hb[i].x, -hb[i].y));
+        zt[(int64_t)(b0 + row) * K + i] = y;
+      }
+    }
+    __syncthreads();   // the next tile's staging overwrites lds
+  }
+}
+
 static int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -311,6 +365,24 @@ hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, co
       switch (lk) { WBM_LOG_CASES(C, 13) }
       break;
   }
+#undef C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_synth(const float2* Z, float2* z, int K, int Lt, int T, const float2* twK,
+                        const float2* hb, hipStream_t s) {
+  if (Lt < 1 || T < 1) return hipSuccess;
+  const int lk = ilog2(K);
+  if ((1 << lk) != K) return hipErrorInvalidValue;
+#define C(L, unused)                                                                          \
+  case L: {                                                                                   \
+    constexpr int TB = (1 << fft_tile(L, 11)) >> L;                                           \
+    const int gx = (Lt + TB - 1) / TB;                                                        \
+    hipLaunchKernelGGL((k_synth<L>), dim3(gx, T), dim3(fft_threads(L, 11)), 0, s, Z, z, Lt,   \
+                       twK, hb, 1.0f / sqrtf((float)K));                                      \
+    return hipGetLastError();                                                                 \
+  }
+  switch (lk) { WBM_LOG_CASES(C, 0) }
 #undef C
   return hipErrorInvalidValue;
 }

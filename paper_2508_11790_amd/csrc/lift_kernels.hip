@@ -1,0 +1,99 @@
+// Lifted correlators (Eq. 21) and their use in element space: c^ = D^H S^T c~ maps a pair's
+// windowed beamspace weights back to the N array elements; applying c^ to the channelized
+// element snapshots gives the same beam outputs without the spatial transform or the window
+// gather (the remark after Eq. 21).
+#include "wbm_dev.h"
+#include "wbm_launch.h"
+
+namespace wbm {
+
+// c_hat[pair][n] = M^-1/2 sum_{i < wmax} w[pair][i] exp(+j 2 pi n m_i / M), m_i = (s + i) mod M
+// (s = the pair's window start; weights past the pair's width are zero).  The phase index
+// (n m_i) mod M is exact in integers and reads the M-entry table tw[q] = exp(-j 2 pi q / M);
+// products summed in FP64.  Grid: (ceil(N / 256), pairs).
+__global__ __launch_bounds__(256) void k_lift(const float2* __restrict__ w,
+                                              const int* __restrict__ starts, int wmax, int N,
+                                              int M, const float2* __restrict__ tw,
+                                              float2* __restrict__ c_hat) {
+  const int64_t pair = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int s = starts[pair];
+  const float2* wp = w + pair * wmax;
+  double ax = 0.0, ay = 0.0;
+  for (int i = 0; i < wmax; ++i) {
+    const int m = (s + i) & (M - 1);   // M is a power of two; two's complement wraps s < 0
+    const float2 e = tw[(int)(((int64_t)n * m) & (M - 1))];   // exp(-j 2 pi n m / M)
+    const float2 c = wp[i];
+    ax += (double)c.x * e.x + (double)c.y * e.y;   // c conj(e)
+    ay += (double)c.y * e.x - (double)c.x * e.y;
+  }
+  const double r = 1.0 / sqrt((double)M);
+  c_hat[pair * N + n] = make_float2((float)(ax * r), (float)(ay * r));
+}
+
+// out[t][k][l] = sum_n conj(c_hat[t][k][n]) X[k][L + l][n]: per subband a (T x N) by (N x Lt)
+// product, HBM-bound at these shapes (one pass over the test snapshots per 8 targets).
+// Workgroup = (64 test snapshots, 8 targets, subband k); N in chunks of 64 staged in LDS
+// (snapshot rows padded by one), each thread sums two targets for one snapshot in FP32.
+constexpr int kLaTL = 64, kLaTT = 8, kLaNC = 64;
+
+__global__ __launch_bounds__(256) void k_lift_apply(const float2* __restrict__ X,
+                                                    const float2* __restrict__ c_hat,
+                                                    float2* __restrict__ out, int N, int K,
+                                                    int B, int L, int Lt, int T) {
+  __shared__ float2 xs[kLaTL][kLaNC + 1];
+  __shared__ float2 cs[kLaTT][kLaNC];
+  const int tid = threadIdx.x, li = tid & (kLaTL - 1), tg = tid / kLaTL;   // tg in 0..3
+  const int l0 = blockIdx.x * kLaTL, t0 = blockIdx.y * kLaTT, k = blockIdx.z;
+  float ax0 = 0.f, ay0 = 0.f, ax1 = 0.f, ay1 = 0.f;
+  for (int n0 = 0; n0 < N; n0 += kLaNC) {
+    for (int e = tid; e < kLaTL * kLaNC; e += 256) {
+      const int r = e / kLaNC, c = e % kLaNC, l = l0 + r;
+      float2 v = make_float2(0.f, 0.f);
+      if (l < Lt && n0 + c < N) v = X[((int64_t)k * B + L + l) * N + n0 + c];
+      xs[r][c] = v;
+    }
+    for (int e = tid; e < kLaTT * kLaNC; e += 256) {
+      const int tt = e / kLaNC, c = e % kLaNC, t = t0 + tt;
+      float2 v = make_float2(0.f, 0.f);
+      if (t < T && n0 + c < N) v = c_hat[((int64_t)t * K + k) * N + n0 + c];
+      cs[tt][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < kLaNC; ++c) {
+      const float2 x = xs[li][c], c0 = cs[tg][c], c1 = cs[tg + 4][c];
+      ax0 = fmaf(c0.x, x.x, fmaf(c0.y, x.y, ax0));   // conj(c) x
+      ay0 = fmaf(c0.x, x.y, fmaf(-c0.y, x.x, ay0));
+      ax1 = fmaf(c1.x, x.x, fmaf(c1.y, x.y, ax1));
+      ay1 = fmaf(c1.x, x.y, fmaf(-c1.y, x.x, ay1));
+    }
+    __syncthreads();
+  }
+  const int l = l0 + li;
+  if (l < Lt) {
+    if (t0 + tg < T) out[((int64_t)(t0 + tg) * K + k) * Lt + l] = make_float2(ax0, ay0);
+    if (t0 + tg + 4 < T) out[((int64_t)(t0 + tg + 4) * K + k) * Lt + l] = make_float2(ax1, ay1);
+  }
+}
+
+hipError_t launch_lift(const float2* w, const int* starts, int pairs, int wmax, int N, int M,
+                       const float2* twM, float2* c_hat, hipStream_t s) {
+  if (pairs < 1) return hipSuccess;
+  if (pairs > 65535 || (M & (M - 1)) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lift, dim3((N + 255) / 256, pairs), dim3(256), 0, s, w, starts, wmax, N, M,
+                     twM, c_hat);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, int N, int K,
+                             int B, int L, int Lt, int T, hipStream_t s) {
+  if (Lt < 1 || T < 1) return hipSuccess;
+  if (K > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lift_apply, dim3((Lt + kLaTL - 1) / kLaTL, (T + kLaTT - 1) / kLaTT, K),
+                     dim3(256), 0, s, X, c_hat, out, N, K, B, L, Lt, T);
+  return hipGetLastError();
+}
+
+}  // namespace wbm

@@ -90,6 +90,17 @@ struct FullArgs {
 hipError_t launch_full_mvdr(const FullArgs& a, const DevDesc& d, const float2* X, double2* R,
                             double2* wtmp, float2* out, float2* wout, int* info, hipStream_t s);
 
+// Subband synthesis (inverse channelizer per block): Z [T][K][Lt] -> z [T][Lt*K].
+hipError_t launch_synth(const float2* Z, float2* z, int K, int Lt, int T, const float2* twK,
+                        const float2* hb, hipStream_t s);
+// Lifted correlators c^ [pairs][N] from window weights [pairs][wmax] and starts [pairs]
+// (Eq. 21); twM = the M-entry table exp(-j 2 pi q / M).
+hipError_t launch_lift(const float2* w, const int* starts, int pairs, int wmax, int N, int M,
+                       const float2* twM, float2* c_hat, hipStream_t s);
+// Beam outputs out [T][K][Lt] = c^^H X_k[:, L + l] from X [K][B][N] and c^ [T][K][N].
+hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, int N, int K,
+                             int B, int L, int Lt, int T, hipStream_t s);
+
 hipError_t set_fft_attributes();
 hipError_t set_pair_attributes();
 hipError_t set_full_attributes();
