@@ -181,6 +181,10 @@ def main():
     ms_applied = timed_steps(torch, lambda: plan.apply_lifted(x, c_hat, out=out_l), args.steps,
                              args.warmup)
     lift_diff = float((out_l - fres["out"]).abs().max() / fres["out"].abs().max())
+    omega = torch.linspace(-math.pi, math.pi, 512, dtype=torch.float64, device=x.device)
+    pat = torch.empty((T, K, 512), dtype=torch.float32, device=x.device)
+    ms_pattern = timed_steps(torch, lambda: plan.beam_pattern(c_hat, omega, pattern=pat),
+                             max(2, args.steps // 10), 1)
     zbuf = torch.empty((T, cfg.Lt * K), dtype=torch.complex64, device=x.device)
     ms_synth = timed_steps(torch, lambda: plan.synthesize(fres["out"], z=zbuf), args.steps,
                            args.warmup)
@@ -189,10 +193,12 @@ def main():
         "value": T * K / (ms_applied * 1e-3), "ms_per_step": ms_applied,
         "form": "channelize + c^H X on the test snapshots (no spatial DFT, no window gather)",
         "lift_ms": ms_lift, "max_rel_diff_vs_fused_outputs": lift_diff,
+        "beam_pattern_ms": ms_pattern, "beam_pattern": "Eq. 22, every pair's lifted "
+                                                       "correlator at 512 angles",
     }
     synth_res = {"ms_per_call": ms_synth, "gbs": synth_bytes / (ms_synth * 1e-3) / 1e9,
                  "bytes": synth_bytes}
-    del fres, c_hat, out_l, zbuf
+    del fres, c_hat, out_l, zbuf, pat, omega
 
     log("timing plain per-stage FP32 form")
     ms_plain = timed_steps(torch, step("plain"), args.steps, args.warmup)

@@ -181,6 +181,16 @@ wbm_status wbm_lift(wbm_plan* plan, const wbm_c32* weights, const int32_t* start
 wbm_status wbm_apply_lifted(wbm_plan* plan, const wbm_c32* x, const wbm_c32* c_hat, int32_t T,
                             wbm_c32* out, void* stream);
 
+/* Beam pattern diagnostic (Eq. 22): for every correlator and angle, the cosine similarity
+ * |<c, a(Omega)>| / (||c|| ||a(Omega)||) with the element steering a(Omega)_e = exp(j Omega e).
+ *   c       device [pairs][N] wbm_c32 (element-space correlators, e.g. from wbm_lift, or
+ *           full-dimensional weights), N = the plan's element count, at most 4096.
+ *   omega   device [Q] double: electrical angles Omega (radians per element).
+ *   pattern device [pairs][Q] float, written.
+ * Errors: WBM_ERR_ARG for NULL pointers or pairs / Q < 1; WBM_ERR_UNSUPPORTED for N > 4096. */
+wbm_status wbm_beam_pattern(wbm_plan* plan, const wbm_c32* c, int32_t pairs, const double* omega,
+                            int32_t Q, float* pattern, void* stream);
+
 /* Subband synthesis (the inverse FFT across subbands that recovers the wideband beam output,
  * Sec. II and IV-B): the inverse of the channelizer per test block,
  *   z[t][b K + tau] = K^-1/2 conj(h[tau]) sum_k out[t][k][b] exp(+j 2 pi tau k / K),

@@ -222,6 +222,21 @@ class Plan:
         _lib.check(_lib.load().wbm_synthesize(self._h, _ptr(out), T, _ptr(z), _stream(stream)))
         return z
 
+    def beam_pattern(self, c, omega, pattern=None, stream=None):
+        """Beam patterns (Eq. 22): c [..., N] complex64 correlators, omega [Q] float64 angles
+        (device) -> pattern [..., Q] float32 cosine similarities with the element steering."""
+        torch = _torch()
+        if c.dtype != torch.complex64 or c.shape[-1] != self.N or not c.is_contiguous():
+            raise ValueError(f"c must be contiguous complex64 [..., {self.N}]")
+        _check_tensor(omega, "omega", (int(omega.numel()),), torch.float64, self.device)
+        pairs, Q = int(c.numel() // self.N), int(omega.numel())
+        if pattern is None:
+            pattern = torch.empty((*c.shape[:-1], Q), dtype=torch.float32, device=self.device)
+        _check_tensor(pattern, "pattern", (*c.shape[:-1], Q), torch.float32, self.device)
+        _lib.check(_lib.load().wbm_beam_pattern(self._h, _ptr(c), pairs, _ptr(omega), Q,
+                                                _ptr(pattern), _stream(stream)))
+        return pattern
+
     def steer(self, az_rad, win, stream=None):
         """Window starts [T, K] int32 and windowed steering vectors [T, K, w_max] complex128."""
         torch = _torch()

@@ -38,6 +38,7 @@ EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes",
            "wbm_profiles", "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr",
            "wbm_mlp_create", "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
            "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
+           "wbm_beam_pattern",
            "wbm_status_str", "wbm_last_error", "wbm_version")
 MLP_PARAMS = 25090
 PROFILE_BINS = 64
@@ -79,6 +80,7 @@ def load() -> C.CDLL:
     lib.wbm_lift.argtypes = [P, P, P, I32, P, P]
     lib.wbm_apply_lifted.argtypes = [P, P, P, I32, P, P]
     lib.wbm_synthesize.argtypes = [P, P, I32, P, P]
+    lib.wbm_beam_pattern.argtypes = [P, P, I32, P, I32, P, P]
     lib.wbm_status_str.argtypes = [I32]
     lib.wbm_status_str.restype = C.c_char_p
     lib.wbm_last_error.argtypes = []
@@ -88,7 +90,8 @@ def load() -> C.CDLL:
                  "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times", "wbm_profiles",
                  "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr", "wbm_mlp_create",
                  "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
-                 "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize"):
+                 "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
+                 "wbm_beam_pattern"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

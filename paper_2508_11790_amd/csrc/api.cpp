@@ -775,6 +775,19 @@ wbm_status wbm_apply_lifted(wbm_plan* p, const wbm_c32* x, const wbm_c32* c_hat,
   return WBM_OK;
 }
 
+wbm_status wbm_beam_pattern(wbm_plan* p, const wbm_c32* c, int32_t pairs, const double* omega,
+                            int32_t Q, float* pattern, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!c || !omega || !pattern) return fail(WBM_ERR_ARG, "c / omega / pattern is NULL");
+  if (pairs < 1 || Q < 1) return fail(WBM_ERR_ARG, "need pairs >= 1 and Q >= 1");
+  if (p->cfg.n_elem > 4096) return fail(WBM_ERR_UNSUPPORTED, "beam patterns need N <= 4096");
+  WBM_HIP(wbm::launch_beam_pattern(reinterpret_cast<const float2*>(c), pairs, p->cfg.n_elem, omega,
+                                   Q, pattern, static_cast<hipStream_t>(stream)),
+          "beam pattern launch");
+  return WBM_OK;
+}
+
 wbm_status wbm_synthesize(wbm_plan* p, const wbm_c32* out, int32_t T, wbm_c32* z, void* stream) {
   wbm_status s = check_plan(p);
   if (s) return s;

@@ -78,6 +78,57 @@ __global__ __launch_bounds__(256) void k_lift_apply(const float2* __restrict__ X
   }
 }
 
+// Beam pattern of a correlator (Eq. 22): cosine similarity |<c, a(Omega)>| / (||c|| ||a||),
+// a(Omega)_e = exp(j Omega e), ||a|| = sqrt(N).  Workgroup = one correlator (staged in LDS
+// with its FP64 norm); each thread sweeps angles q = tid, tid + 256, ...: the sum
+// sum_e conj(c_e) exp(j Omega e) in FP64, the phase advanced by one FP64 complex product per
+// element from exp(j Omega).  Grid: (pairs).
+constexpr int kBpMaxN = 4096;
+
+__global__ __launch_bounds__(256) void k_beam_pattern(const float2* __restrict__ c, int N,
+                                                      const double* __restrict__ omega, int Q,
+                                                      float* __restrict__ pattern) {
+  __shared__ float2 cs[kBpMaxN];
+  __shared__ double red[256];
+  const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
+  double nn = 0.0;
+  for (int e = tid; e < N; e += 256) {
+    const float2 v = c[p * N + e];
+    cs[e] = v;
+    nn += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  red[tid] = nn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  const double scale = 1.0 / (sqrt(red[0]) * sqrt((double)N));
+  for (int q = tid; q < Q; q += 256) {
+    double sx, cx;
+    sincos(omega[q], &sx, &cx);
+    double zr = 1.0, zi = 0.0, ar = 0.0, ai = 0.0;
+    for (int e = 0; e < N; ++e) {
+      const float2 v = cs[e];
+      ar += (double)v.x * zr + (double)v.y * zi;   // conj(c_e) z
+      ai += (double)v.x * zi - (double)v.y * zr;
+      const double t = zr * cx - zi * sx;
+      zi = zr * sx + zi * cx;
+      zr = t;
+    }
+    pattern[p * Q + q] = (float)(sqrt(ar * ar + ai * ai) * scale);
+  }
+}
+
+hipError_t launch_beam_pattern(const float2* c, int pairs, int N, const double* omega, int Q,
+                               float* pattern, hipStream_t s) {
+  if (pairs < 1 || Q < 1) return hipSuccess;
+  if (N < 1 || N > kBpMaxN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_beam_pattern, dim3(pairs), dim3(256), 0, s, c, N, omega, Q, pattern);
+  return hipGetLastError();
+}
+
 hipError_t launch_lift(const float2* w, const int* starts, int pairs, int wmax, int N, int M,
                        const float2* twM, float2* c_hat, hipStream_t s) {
   if (pairs < 1) return hipSuccess;

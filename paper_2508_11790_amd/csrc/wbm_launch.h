@@ -101,6 +101,11 @@ hipError_t launch_lift(const float2* w, const int* starts, int pairs, int wmax, 
 hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, int N, int K,
                              int B, int L, int Lt, int T, hipStream_t s);
 
+// Beam patterns (Eq. 22) of correlators c [pairs][N] (N <= 4096) at angles omega [Q]
+// (device FP64) -> pattern [pairs][Q].
+hipError_t launch_beam_pattern(const float2* c, int pairs, int N, const double* omega, int Q,
+                               float* pattern, hipStream_t s);
+
 hipError_t set_fft_attributes();
 hipError_t set_pair_attributes();
 hipError_t set_full_attributes();

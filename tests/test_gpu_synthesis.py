@@ -148,3 +148,24 @@ def test_synthesis_and_lift_reject_bad_arguments(torch, wb):
     with pytest.raises(ValueError):
         plan.synthesize(torch.zeros((2, 16, 7), dtype=torch.complex64, device="cuda"))   # shape
     plan.close()
+
+
+@pytest.mark.parametrize("N", [24, 256])
+def test_beam_pattern_matches_oracle(torch, wb, N):
+    # FP64 sums and phase recurrence on the GPU; the FP32 result is within 1e-6 of the oracle
+    plan = wb.Plan(N, 1 << (2 * N - 1).bit_length(), 4, 4, 4, 2, 5)
+    c = _crand((2, 3, N), 26)
+    omegas = np.concatenate([np.linspace(-math.pi, math.pi, 181), [0.0, 0.7, 3 * math.pi]])
+    pat = plan.beam_pattern(torch.from_numpy(c).cuda(), torch.from_numpy(omegas).cuda())
+    torch.cuda.synchronize()
+    pg = pat.cpu().numpy()
+    for i in range(2):
+        for j in range(3):
+            ref = oracle.beam_pattern(c[i, j].astype(np.complex128), omegas)
+            assert np.max(np.abs(pg[i, j] - ref)) < 1e-6
+    # a matched filter is a normalised Dirichlet kernel with its peak of 1 at its own angle
+    a = np.exp(1j * 0.7 * np.arange(N)).astype(np.complex64)
+    pk = plan.beam_pattern(torch.from_numpy(a).cuda(), torch.tensor([0.7], dtype=torch.float64,
+                                                                   device="cuda"))
+    assert abs(float(pk.cpu()[0]) - 1.0) < 1e-6
+    plan.close()
