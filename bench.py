@@ -43,9 +43,28 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def counter_traffic(workload: str, kernel: str):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE record of this workload,
-    or None when there is none or the kernel sources changed since it was taken."""
+def dispatch_name(kernel: str, cfg, tuning, wmax: int) -> str:
+    """Kernel name (as the profiler lists it) that the plan's tuning launches for a stage."""
+    lk, lm = int(math.log2(cfg.K)), int(math.log2(cfg.M))
+    if kernel == "channelize":
+        return f"k_channelize<{lk}, {max(tuning[0], lk)}>"
+    if kernel == "beamspace":
+        zh = "true" if 2 * cfg.N <= cfg.M else "false"
+        return f"k_beamspace<{lm}, {max(tuning[1], lm)}, {zh}>"
+    pair = tuning[2]
+    if pair == "resident":
+        return "k_mvdr_res"
+    if pair == "wave":
+        return "k_mvdr_xw40"
+    if pair == "mfma":
+        return f"k_mvdr_xm<{40 if wmax <= 40 else 64}>"
+    return "k_mvdr_xv16" if wmax <= 16 else "k_mvdr_xv40" if wmax <= 40 else "k_mvdr_xv64"
+
+
+def counter_traffic(workload: str, name: str):
+    """HBM bytes per launch of the named kernel from the committed FETCH_SIZE / WRITE_SIZE
+    record of this workload, or None when there is none, the kernel is not in it or the
+    kernel sources changed since it was taken."""
     path = TRAFFIC_FILES.get(workload)
     if not path or not os.path.exists(path):
         return None
@@ -53,7 +72,7 @@ def counter_traffic(workload: str, kernel: str):
         rec = json.load(f)
     if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("dispatches", {}).get(name)
     return None if k is None else k["hbm_bytes"]
 
 
@@ -264,7 +283,8 @@ def main():
     achieved = bytes_per[kern] / (st[kern] * 1e-3) / 1e9
     roofline = dict(bound="hbm", kernel=kern, achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=counter_traffic(cfg.name, kern),
+                    traffic=counter_traffic(cfg.name, dispatch_name(kern, cfg, plan.tuning, wmax)),
+                    dispatch=dispatch_name(kern, cfg, plan.tuning, wmax),
                     bytes_per_launch=bytes_per[kern], ms_per_launch=st[kern],
                     stage_ms={k: round(v, 5) for k, v in st.items()},
                     stage_gbs={n: round(bytes_per[n] / (st[n] * 1e-3) / 1e9, 1) for n in bytes_per})
