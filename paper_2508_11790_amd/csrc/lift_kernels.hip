@@ -78,6 +78,63 @@ __global__ __launch_bounds__(256) void k_lift_apply(const float2* __restrict__ X
   }
 }
 
+// The same product on the FP32 matrix cores, for many targets (T > 8): per complex element n,
+// with A = [Re c, Im c] (targets x 2) and B = [Re x; Im x] or [Im x; -Re x] (2 x snapshots),
+// Re out += A B1 and Im out += A B2 are two v_mfma_f32_32x32x2f32 steps (conj(c) x =
+// (cr xr + ci xi) + j (cr xi - ci xr)).  Workgroup = 32 targets x 128 test snapshots of one
+// subband, four waves of 32 snapshots each; N in chunks of 32 staged in LDS (rows padded by
+// one).  Lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator register r of
+// lane l is target 8 (r / 4) + 4 (l / 32) + r % 4, snapshot l % 32.
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+constexpr int kLmTT = 32, kLmTL = 128, kLmNC = 32;
+
+__global__ __launch_bounds__(256) void k_lift_apply_mfma(const float2* __restrict__ X,
+                                                         const float2* __restrict__ c_hat,
+                                                         float2* __restrict__ out, int N, int K,
+                                                         int B, int L, int Lt, int T) {
+  __shared__ float2 xs[kLmTL][kLmNC + 1];
+  __shared__ float2 cs[kLmTT][kLmNC + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l0 = blockIdx.x * kLmTL, t0 = blockIdx.y * kLmTT, k = blockIdx.z;
+  const bool hi = lane >= 32;
+  const int lr = lane & 31;
+  f32x16_t accr = {}, acci = {};
+  for (int n0 = 0; n0 < N; n0 += kLmNC) {
+    for (int e = tid; e < kLmTL * kLmNC; e += 256) {
+      const int r = e / kLmNC, c = e % kLmNC, l = l0 + r;
+      float2 v = make_float2(0.f, 0.f);
+      if (l < Lt && n0 + c < N) v = X[((int64_t)k * B + L + l) * N + n0 + c];
+      xs[r][c] = v;
+    }
+    for (int e = tid; e < kLmTT * kLmNC; e += 256) {
+      const int r = e / kLmNC, c = e % kLmNC, t = t0 + r;
+      float2 v = make_float2(0.f, 0.f);
+      if (t < T && n0 + c < N) v = c_hat[((int64_t)t * K + k) * N + n0 + c];
+      cs[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int c = 0; c < kLmNC; ++c) {
+      const float2 cv = cs[lr][c], xv = xs[wave * 32 + lr][c];
+      const float a = hi ? cv.y : cv.x;
+      const float b1 = hi ? xv.y : xv.x;
+      const float b2 = hi ? -xv.x : xv.y;
+      accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, accr, 0, 0, 0);
+      acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b2, acci, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int l = l0 + wave * 32 + lr;
+  if (l < Lt) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int t = t0 + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+      if (t < T) out[((int64_t)t * K + k) * Lt + l] = make_float2(accr[r], acci[r]);
+    }
+  }
+}
+
 // Beam pattern of a correlator (Eq. 22): cosine similarity |<c, a(Omega)>| / (||c|| ||a||),
 // a(Omega)_e = exp(j Omega e), ||a|| = sqrt(N).  Workgroup = one correlator (staged in LDS
 // with its FP64 norm); each thread sweeps angles q = tid, tid + 256, ...: the sum
@@ -142,8 +199,14 @@ hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, 
                              int B, int L, int Lt, int T, hipStream_t s) {
   if (Lt < 1 || T < 1) return hipSuccess;
   if (K > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_lift_apply, dim3((Lt + kLaTL - 1) / kLaTL, (T + kLaTT - 1) / kLaTT, K),
-                     dim3(256), 0, s, X, c_hat, out, N, K, B, L, Lt, T);
+  if (T > kLaTT) {
+    hipLaunchKernelGGL(k_lift_apply_mfma,
+                       dim3((Lt + kLmTL - 1) / kLmTL, (T + kLmTT - 1) / kLmTT, K), dim3(256), 0,
+                       s, X, c_hat, out, N, K, B, L, Lt, T);
+  } else {
+    hipLaunchKernelGGL(k_lift_apply, dim3((Lt + kLaTL - 1) / kLaTL, (T + kLaTT - 1) / kLaTT, K),
+                       dim3(256), 0, s, X, c_hat, out, N, K, B, L, Lt, T);
+  }
   return hipGetLastError();
 }
 

@@ -90,8 +90,13 @@ def test_lift_matches_oracle(torch, wb, sh):
     plan.close()
 
 
+APPLY_SHAPES = SHAPES[:3] + [
+    dict(N=100, M=128, K=16, L=8, Lt=150, T=40),   # T > 8: matrix-core product, ragged tiles
+]
+
+
 @pytest.mark.parametrize("half_bin", [False, True])
-@pytest.mark.parametrize("sh", SHAPES[:3], ids=lambda d: f"N{d['N']}K{d['K']}Lt{d['Lt']}")
+@pytest.mark.parametrize("sh", APPLY_SHAPES, ids=lambda d: f"N{d['N']}K{d['K']}Lt{d['Lt']}T{d['T']}")
 def test_apply_lifted_matches_oracle(torch, wb, sh, half_bin):
     N, K, L, Lt, T = sh["N"], sh["K"], sh["L"], sh["Lt"], sh["T"]
     log(f"element-space apply {sh} half_bin={half_bin}")
