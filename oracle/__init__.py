@@ -21,3 +21,4 @@ words "parity unpinned" in their docstring.
 from .bmvdr import *  # noqa: F401,F403
 from . import mlp  # noqa: F401
 from . import learned  # noqa: F401
+from . import radar  # noqa: F401
