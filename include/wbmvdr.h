@@ -191,6 +191,25 @@ wbm_status wbm_apply_lifted(wbm_plan* plan, const wbm_c32* x, const wbm_c32* c_h
 wbm_status wbm_beam_pattern(wbm_plan* plan, const wbm_c32* c, int32_t pairs, const double* omega,
                             int32_t Q, float* pattern, void* stream);
 
+/* Range-Doppler map and 1-D CFAR of beamformed pulse trains (the processing after synthesis,
+ * Sec. II and IV; readings of the unstated parameters in the design notes):
+ *   z       device [T][z_stride] wbm_c32: per target, P pulses of R samples (z[p R + n]),
+ *           e.g. the output of wbm_synthesize; z_stride >= P R.
+ *   chirp   device [Lp] wbm_c32: the transmitted pulse, 1 <= Lp <= R.
+ *   power   device [T][R][P] float: |RD|^2, RD[d][v] = P^-1/2 sum_p r[p][d] exp(-j 2 pi p v / P)
+ *           with r[p][d] = sum_{m < Lp, d + m < R} conj(chirp[m]) z[p R + d + m].
+ *   det     device [T][R][P] uint8: 1 where power > 10^(threshold_db / 10) times the mean power
+ *           of the cells guard < |d' - d| <= guard + train (inside [0, R)) of the same
+ *           velocity bin, else 0.
+ *   work    device scratch of T P R + 2 F + P wbm_c32, F = the smallest power of two
+ *           >= R + Lp - 1 (at most 8192).
+ * Errors: WBM_ERR_ARG for NULL pointers or out-of-range sizes (P must be a power of two in
+ * [2, 8192]); WBM_ERR_UNSUPPORTED when F would exceed 8192. */
+wbm_status wbm_range_doppler(wbm_plan* plan, const wbm_c32* z, int32_t T, int64_t z_stride,
+                             const wbm_c32* chirp, int32_t Lp, int32_t R, int32_t P,
+                             int32_t guard, int32_t train, double threshold_db, wbm_c32* work,
+                             float* power, uint8_t* det, void* stream);
+
 /* Subband synthesis (the inverse FFT across subbands that recovers the wideband beam output,
  * Sec. II and IV-B): the inverse of the channelizer per test block,
  *   z[t][b K + tau] = K^-1/2 conj(h[tau]) sum_k out[t][k][b] exp(+j 2 pi tau k / K),

@@ -237,6 +237,28 @@ class Plan:
                                                 _ptr(pattern), _stream(stream)))
         return pattern
 
+    def range_doppler(self, z, chirp, R: int, P: int, guard: int = 2, train: int = 8,
+                      threshold_db: float = 10.0, stream=None):
+        """Range-Doppler power maps and 1-D CFAR detections of pulse trains: z [T, >= P R]
+        complex64 (P pulses of R samples), chirp [Lp] complex64 -> (power [T, R, P] float32,
+        det [T, R, P] uint8)."""
+        torch = _torch()
+        if z.dtype != torch.complex64 or z.dim() != 2 or not z.is_contiguous():
+            raise ValueError("z must be a contiguous complex64 [T, S] tensor")
+        _check_tensor(chirp, "chirp", (int(chirp.numel()),), torch.complex64, self.device)
+        T, Lp = int(z.shape[0]), int(chirp.numel())
+        F = 1
+        while F < R + Lp - 1:
+            F *= 2
+        work = torch.empty(T * P * R + 2 * F + P, dtype=torch.complex64, device=self.device)
+        power = torch.empty((T, R, P), dtype=torch.float32, device=self.device)
+        det = torch.empty((T, R, P), dtype=torch.uint8, device=self.device)
+        _lib.check(_lib.load().wbm_range_doppler(
+            self._h, _ptr(z), T, int(z.shape[1]), _ptr(chirp), Lp, int(R), int(P), int(guard),
+            int(train), float(threshold_db), _ptr(work), _ptr(power), _ptr(det),
+            _stream(stream)))
+        return power, det
+
     def steer(self, az_rad, win, stream=None):
         """Window starts [T, K] int32 and windowed steering vectors [T, K, w_max] complex128."""
         torch = _torch()

@@ -788,6 +788,30 @@ wbm_status wbm_beam_pattern(wbm_plan* p, const wbm_c32* c, int32_t pairs, const 
   return WBM_OK;
 }
 
+wbm_status wbm_range_doppler(wbm_plan* p, const wbm_c32* z, int32_t T, int64_t z_stride,
+                             const wbm_c32* chirp, int32_t Lp, int32_t R, int32_t P,
+                             int32_t guard, int32_t train, double threshold_db, wbm_c32* work,
+                             float* power, uint8_t* det, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!z || !chirp || !work || !power || !det) return fail(WBM_ERR_ARG, "NULL pointer argument");
+  if (T < 1 || Lp < 1 || R < Lp) return fail(WBM_ERR_ARG, "need T >= 1 and 1 <= Lp <= R");
+  if (P < 2 || P > 8192 || (P & (P - 1)) != 0)
+    return fail(WBM_ERR_ARG, "P must be a power of two in [2, 8192]");
+  if (z_stride < (int64_t)P * R) return fail(WBM_ERR_ARG, "z_stride must be >= P * R");
+  if (guard < 0 || train < 1) return fail(WBM_ERR_ARG, "need guard >= 0 and train >= 1");
+  if (!std::isfinite(threshold_db)) return fail(WBM_ERR_ARG, "threshold_db must be finite");
+  if (wbm::range_doppler_fft_log(R, Lp) > 13)
+    return fail(WBM_ERR_UNSUPPORTED, "R + Lp - 1 must be at most 8192");
+  const float alpha = (float)std::pow(10.0, threshold_db / 10.0);
+  WBM_HIP(wbm::launch_range_doppler(reinterpret_cast<const float2*>(z), z_stride, T,
+                                    reinterpret_cast<const float2*>(chirp), Lp, R, P, guard,
+                                    train, alpha, reinterpret_cast<float2*>(work), power, det,
+                                    static_cast<hipStream_t>(stream)),
+          "range-Doppler launch");
+  return WBM_OK;
+}
+
 wbm_status wbm_synthesize(wbm_plan* p, const wbm_c32* out, int32_t T, wbm_c32* z, void* stream) {
   wbm_status s = check_plan(p);
   if (s) return s;

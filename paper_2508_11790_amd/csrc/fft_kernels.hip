@@ -259,6 +259,146 @@ __global__ __launch_bounds__(fft_threads(LOGK, 11)) void k_synth(
   }
 }
 
+// Range compression of a pulse train (matched filter within each pulse, linear correlation):
+// z [T][>= P R] -> r [T][P][R], r[p][d] = sum_{m < Lp, d + m < R} conj(c[m]) z[p R + d + m],
+// computed per pulse as the inverse F-point DFT of Z conj(C) (F >= R + Lp - 1, so no product
+// wraps): Z = DFT of the pulse zero-padded to F, C = the chirp's spectrum cf (unscaled DFT of
+// the chirp zero-padded to F).  With cf == nullptr the kernel instead writes the spectrum of
+// the single row z (the chirp) into r.  Workgroup = (tiles of F-point rows, target).
+template <int LOGF>
+__global__ __launch_bounds__(fft_threads(LOGF, 11)) void k_range_compress(
+    const float2* __restrict__ z, int64_t zstride, int R, int P, const float2* __restrict__ cf,
+    int Lp, float2* __restrict__ r, const float2* __restrict__ twF) {
+  using F = Fft<LOGF, fft_tile(LOGF, 11), chan_pad(fft_tile(LOGF, 11), LOGF)>;
+  constexpr int NF = F::n, TB = F::rows;
+  __shared__ float2 lds[F::lds_complex];
+  float2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twF);
+  const float2* zt = z + (int64_t)blockIdx.y * zstride;
+  float2* rt = r + (int64_t)blockIdx.y * P * R;
+  const int len = cf ? R : Lp;   // nonzero samples per row
+  const int rows = cf ? P : 1;
+  for (int p0 = blockIdx.x * TB; p0 < rows; p0 += gridDim.x * TB) {
+    for (int idx = threadIdx.x; idx < TB * NF; idx += F::threads) {
+      const int row = idx >> LOGF, n = idx & (NF - 1);
+      float2 v = make_float2(0.f, 0.f);
+      if (p0 + row < rows && n < len) v = zt[(int64_t)(p0 + row) * R + n];
+      lds[F::addr(row, n)] = v;
+    }
+    __syncthreads();
+    float2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8 / F::R0; ++q)
+#pragma unroll
+      for (int rr = 0; rr < F::R0; ++rr) {
+        int row, pos;
+        F::first_input(q, rr, row, pos);
+        v[q * F::R0 + rr] = lds[F::addr(row, pos)];
+      }
+    __syncthreads();
+    F::run(v, lds, tr);
+    if (!cf) {   // the chirp's spectrum
+      for (int i = threadIdx.x; i < NF; i += F::threads) rt[i] = lds[F::addr(0, i)];
+      return;
+    }
+    // inverse transform of Z conj(C): conj(DFT(conj(Z conj(C)))) / F
+#pragma unroll
+    for (int q = 0; q < 8 / F::R0; ++q)
+#pragma unroll
+      for (int rr = 0; rr < F::R0; ++rr) {
+        int row, pos;
+        F::first_input(q, rr, row, pos);
+        const float2 a = lds[F::addr(row, pos)], c = cf[pos];
+        // conj(a conj(c)) = conj(a) c
+        v[q * F::R0 + rr] = make_float2(a.x * c.x + a.y * c.y, a.x * c.y - a.y * c.x);
+      }
+    __syncthreads();
+    F::run(v, lds, tr);
+    const float inv = 1.0f / (float)NF;
+    for (int idx = threadIdx.x; idx < TB * NF; idx += F::threads) {
+      const int row = idx >> LOGF, d = idx & (NF - 1);
+      if (p0 + row < P && d < R) {
+        const float2 u = lds[F::addr(row, d)];
+        rt[(int64_t)(p0 + row) * R + d] = make_float2(u.x * inv, -u.y * inv);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Doppler processing: r [T][P][R] -> power [T][R][P] = |RD|^2, RD[d][v] = P^-1/2 sum_p
+// r[p][d] exp(-j 2 pi p v / P).  Workgroup = (tiles of TB range bins, target): the pulses of
+// TB consecutive range bins are staged through LDS (reads run along range), one P-point row
+// per range bin, powers written velocity-contiguous.
+template <int LOGP>
+__global__ __launch_bounds__(fft_threads(LOGP, 11)) void k_doppler(
+    const float2* __restrict__ r, int R, float* __restrict__ power,
+    const float2* __restrict__ twP) {
+  using F = Fft<LOGP, fft_tile(LOGP, 11), chan_pad(fft_tile(LOGP, 11), LOGP)>;
+  constexpr int P = F::n, TB = F::rows;
+  constexpr int LOGTB = fft_tile(LOGP, 11) - LOGP;
+  __shared__ float2 lds[F::lds_complex];
+  float2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twP);
+  const float2* rt = r + (int64_t)blockIdx.y * P * R;
+  float* pt = power + (int64_t)blockIdx.y * R * P;
+  for (int d0 = blockIdx.x * TB; d0 < R; d0 += gridDim.x * TB) {
+    for (int idx = threadIdx.x; idx < TB * P; idx += F::threads) {
+      const int p = idx >> LOGTB, j = idx & (TB - 1);
+      float2 v = make_float2(0.f, 0.f);
+      if (d0 + j < R) v = rt[(int64_t)p * R + d0 + j];
+      lds[F::addr(j, p)] = v;
+    }
+    __syncthreads();
+    float2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8 / F::R0; ++q)
+#pragma unroll
+      for (int rr = 0; rr < F::R0; ++rr) {
+        int row, pos;
+        F::first_input(q, rr, row, pos);
+        v[q * F::R0 + rr] = lds[F::addr(row, pos)];
+      }
+    __syncthreads();
+    F::run(v, lds, tr);
+    const float inv = 1.0f / (float)P;
+    for (int idx = threadIdx.x; idx < TB * P; idx += F::threads) {
+      const int j = idx >> LOGP, vb = idx & (P - 1);
+      if (d0 + j < R) {
+        const float2 u = lds[F::addr(j, vb)];
+        pt[(int64_t)(d0 + j) * P + vb] = (u.x * u.x + u.y * u.y) * inv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Cell-averaging CFAR along range for every velocity bin: noise = mean power of the cells
+// guard < |d' - d| <= guard + train inside [0, R); detection when power > alpha noise (FP32).
+// One thread per (d, v), consecutive threads along v.
+__global__ __launch_bounds__(256) void k_cfar(const float* __restrict__ power, int R, int P,
+                                              int guard, int train, float alpha,
+                                              unsigned char* __restrict__ det) {
+  const int64_t t = blockIdx.y;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * P) return;
+  const int d = idx / P, v = idx - d * P;
+  const float* pt = power + t * R * P;
+  float sum = 0.f;
+  int cnt = 0;
+  for (int o = guard + 1; o <= guard + train; ++o) {
+    if (d - o >= 0) {
+      sum += pt[(int64_t)(d - o) * P + v];
+      ++cnt;
+    }
+    if (d + o < R) {
+      sum += pt[(int64_t)(d + o) * P + v];
+      ++cnt;
+    }
+  }
+  det[t * R * P + idx] = (cnt > 0 && pt[idx] > alpha * (sum / (float)cnt)) ? 1 : 0;
+}
+
 static int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -385,6 +525,72 @@ hipError_t launch_synth(const float2* Z, float2* z, int K, int Lt, int T, const 
   switch (lk) { WBM_LOG_CASES(C, 0) }
 #undef C
   return hipErrorInvalidValue;
+}
+
+// tw[q] = exp(-j 2 pi q / n), q < n, evaluated in FP64 (as the plan's own tables)
+__global__ void k_twiddles(float2* __restrict__ tw, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double sn, cs;
+  sincospi(-2.0 * (double)q / (double)n, &sn, &cs);
+  tw[q] = make_float2((float)cs, (float)sn);
+}
+
+int range_doppler_fft_log(int R, int Lp) {
+  int lf = 0;
+  while ((1 << lf) < R + Lp - 1) ++lf;
+  return lf < 1 ? 1 : lf;
+}
+
+// work: [T][P][R] compressed pulses, then the chirp spectrum and the F- and P-point twiddle
+// tables (F = 2^range_doppler_fft_log(R, Lp)): T P R + 2 F + P complex.
+hipError_t launch_range_doppler(const float2* z, int64_t zstride, int T, const float2* chirp,
+                                int Lp, int R, int P, int guard, int train, float alpha,
+                                float2* work, float* power, unsigned char* det, hipStream_t s) {
+  const int lf = range_doppler_fft_log(R, Lp);
+  const int lp = ilog2(P);
+  if ((1 << lp) != P || lf > 13 || lp > 13 || lp < 1) return hipErrorInvalidValue;
+  const int NF = 1 << lf;
+  float2* cf = work + (int64_t)T * P * R;   // chirp spectrum
+  float2* twF = cf + NF;
+  float2* twP = twF + NF;
+  hipLaunchKernelGGL(k_twiddles, dim3((NF + 255) / 256), dim3(256), 0, s, twF, NF);
+  hipLaunchKernelGGL(k_twiddles, dim3((P + 255) / 256), dim3(256), 0, s, twP, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  switch (lf) {
+#define C(L, unused)                                                                           \
+  case L: {                                                                                    \
+    constexpr int TB = (1 << fft_tile(L, 11)) >> L;                                            \
+    hipLaunchKernelGGL((k_range_compress<L>), dim3(1, 1), dim3(fft_threads(L, 11)), 0, s,      \
+                       chirp, (int64_t)0, Lp, 1, (const float2*)nullptr, Lp, cf, twF);         \
+    if ((e = hipGetLastError()) != hipSuccess) return e;                                       \
+    hipLaunchKernelGGL((k_range_compress<L>), dim3((P + TB - 1) / TB, T),                      \
+                       dim3(fft_threads(L, 11)), 0, s, z, zstride, R, P, (const float2*)cf, Lp, \
+                       work, twF);                                                             \
+    if ((e = hipGetLastError()) != hipSuccess) return e;                                       \
+    break;                                                                                     \
+  }
+    WBM_LOG_CASES(C, 0)
+#undef C
+    default: return hipErrorInvalidValue;
+  }
+  switch (lp) {
+#define C(L, unused)                                                                           \
+  case L: {                                                                                    \
+    constexpr int TB = (1 << fft_tile(L, 11)) >> L;                                            \
+    hipLaunchKernelGGL((k_doppler<L>), dim3((R + TB - 1) / TB, T), dim3(fft_threads(L, 11)), 0, \
+                       s, work, R, power, twP);                                                \
+    if ((e = hipGetLastError()) != hipSuccess) return e;                                       \
+    break;                                                                                     \
+  }
+    WBM_LOG_CASES(C, 0)
+#undef C
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_cfar, dim3((R * P + 255) / 256, T), dim3(256), 0, s, power, R, P, guard,
+                     train, alpha, det);
+  return hipGetLastError();
 }
 
 int beamspace_tile_log(int M, int logtile) { return fft_tile(ilog2(M), logtile) - ilog2(M); }

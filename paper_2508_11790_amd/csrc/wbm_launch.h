@@ -106,6 +106,14 @@ hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, 
 hipError_t launch_beam_pattern(const float2* c, int pairs, int N, const double* omega, int Q,
                                float* pattern, hipStream_t s);
 
+// Range-Doppler map and CFAR of pulse trains z [T] (row stride zstride, P pulses of R
+// samples), chirp [Lp] (device): power [T][R][P] = |RD|^2, det [T][R][P] in {0, 1};
+// work = T P R + 2 F + P complex, F = 2^range_doppler_fft_log(R, Lp) (at most 2^13).
+int range_doppler_fft_log(int R, int Lp);
+hipError_t launch_range_doppler(const float2* z, int64_t zstride, int T, const float2* chirp,
+                                int Lp, int R, int P, int guard, int train, float alpha,
+                                float2* work, float* power, unsigned char* det, hipStream_t s);
+
 hipError_t set_fft_attributes();
 hipError_t set_pair_attributes();
 hipError_t set_full_attributes();
