@@ -22,3 +22,4 @@ from .bmvdr import *  # noqa: F401,F403
 from . import mlp  # noqa: F401
 from . import learned  # noqa: F401
 from . import radar  # noqa: F401
+from . import upa  # noqa: F401

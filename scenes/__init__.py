@@ -31,3 +31,4 @@ chunking used to build it.
 from .configs import SceneConfig, CONFIGS, config_by_name, SMALL, GPU, BATCH, PRECISION, LEARNED_EVAL, LEARNED_TRAIN  # noqa: F401
 from .generate import Scene, make_scene, subband_freq_ratio_gen  # noqa: F401
 from .generate_torch import make_scene_torch  # noqa: F401
+from .upa import UpaSceneConfig, UpaScene, make_upa_scene, UPA, UPA_SMALL, UPA_CONFIGS  # noqa: F401
