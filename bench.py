@@ -136,6 +136,64 @@ def sinr_check(scene, ref, weights):
     return worst_loss, worst_err
 
 
+def upa_leg(torch, wb, scenes, steps, warmup):
+    """The paper's planar geometry (Sec. IV): 4 x 32 array, 8 x 64 beam grid, 128 subbands,
+    20 targets with 2x4 / 4x4 / 4x8 windows, fused form timed per step."""
+    cfg = scenes.UPA
+    sc = scenes.make_upa_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    x = torch.from_numpy(x32).cuda()
+    wmax = int(np.max(sc.win_z * sc.win_x))
+    plan = wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, cfg.T, wmax, beta=cfg.beta,
+                   d_over_lambda=cfg.dl)
+    out = torch.empty((cfg.T, cfg.K, cfg.Lt), dtype=torch.complex64, device=x.device)
+    wts = torch.empty((cfg.T, cfg.K, wmax), dtype=torch.complex64, device=x.device)
+    info = torch.empty((cfg.T, cfg.K), dtype=torch.int32, device=x.device)
+    args = (x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x, cfg.delta)
+    res = {}
+
+    def step(form):
+        return lambda: plan.beamform_upa(*args, form=form, out=out, weights=wts, info=info,
+                                         want_starts=False)
+    ms = timed_steps(torch, step("fused"), steps, warmup)
+    assert int(info.abs().sum()) == 0
+    res["fused"] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms}
+    w_fused = wts.cpu().numpy().astype(np.complex128)
+    st = plan.beamform_upa(*args, form="fused")["starts"].cpu().numpy()
+    for form in ("mixed", "mixed_bf16"):
+        ms = timed_steps(torch, step(form), steps, warmup)
+        res[form] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms,
+                     "routed_pairs": int(((info.cpu().numpy() & wb.INFO_ROUTED) != 0).sum())}
+    plan.close()
+    sumW = int(np.sum(sc.win_z * sc.win_x))
+    res.update({"workload": f"UPA {cfg.Nz}x{cfg.Nx}, beams {cfg.Mz}x{cfg.Mx}, K={cfg.K}, "
+                            f"L={cfg.L}, Lt={cfg.Lt}, T={cfg.T}, windows "
+                            f"{sorted({f'{a}x{b}' for a, b in zip(sc.win_z, sc.win_x)})}, "
+                            f"{cfg.n_jammers} jammers",
+                "window_rows_per_subband": sumW,
+                "algorithmic_bytes_per_step": 2.0 * cfg.N * cfg.S * 8 + cfg.N * cfg.S * 8
+                + 2.0 * cfg.K * cfg.B * sumW * 8 + cfg.T * cfg.K * cfg.Lt * 8})
+    return res, (sc, x32, w_fused, st)
+
+
+def upa_validity(scene, x32, weights, starts, subbands=(0, 64, 127)):
+    """Oracle check of the planar leg on a few subbands: starts, relative weight error."""
+    import oracle.upa as oupa
+    cfg = scene.cfg
+    ref = oupa.upa_windowed_mvdr(x32.astype(np.complex128), Nz=cfg.Nz, Mz=cfg.Mz, Mx=cfg.Mx,
+                                 K=cfg.K, L=cfg.L, Lt=cfg.Lt, az=scene.target_az,
+                                 el=scene.target_el, win_z=scene.win_z, win_x=scene.win_x,
+                                 delta=cfg.delta, subbands=list(subbands))
+    err = 0.0
+    for ik, k in enumerate(subbands):
+        for t in range(cfg.T):
+            W = int(scene.win_z[t] * scene.win_x[t])
+            wo, wg = ref["w"][t, ik, :W], weights[t, k, :W]
+            err = max(err, float(np.linalg.norm(wg - wo) / np.linalg.norm(wo)))
+    same = bool(np.array_equal(starts[:, list(subbands)], ref["start"]))
+    return {"subbands": list(subbands), "starts_equal": same, "max_rel_weight_err": err}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +208,7 @@ def main():
                                                         "predictor_params.npz"),
                     help="trained loading/window predictor for the learned form ('' to skip)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision forms")
+    ap.add_argument("--no-upa", action="store_true", help="skip the planar-array leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the path is measured on one GPU's share of the "
@@ -279,6 +338,11 @@ def main():
         ms_full = timed_steps(torch, lambda: plan.full_mvdr(x, az, delta, want_weights=False),
                               nfs, 2)
 
+    upa_res, upa_chk = None, None
+    if not args.no_upa:
+        log("timing the planar-array leg (4 x 32 array, 8 x 64 beams)")
+        upa_res, upa_chk = upa_leg(torch, wb, scenes, args.steps, args.warmup)
+
     if args.copy_calib:
         src = torch.empty(args.copy_calib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -333,6 +397,7 @@ def main():
         "synthesis": synth_res,
         "range_doppler": rd_res,
         "learned": learned_res,
+        "upa": upa_res,
         "full_dim": (None if ms_full is None else
                      {"value": beams / (ms_full * 1e-3), "ms_per_step": ms_full,
                       "form": f"element-space {cfg.N}x{cfg.N} MVDR per subband, FP64"}),
@@ -351,6 +416,8 @@ def main():
             lf, ef = sinr_check(sc, ref, r["weights"])
             val[f + "_max_sinr_loss_db"] = lf
             val[f + "_max_rel_weight_err"] = ef
+        if upa_chk is not None:
+            val["upa"] = upa_validity(*upa_chk)
         val["valid"] = bool(ok)
         result["validity"] = val
     else:

@@ -123,8 +123,9 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
  *                               w_max * L and w_max * Lt <= 2304).
  *   overlap_chunks              1 (no overlap), 2, 4 or 8; K must be a multiple of 8 x chunks.
  * Errors: WBM_ERR_ARG for a NULL plan or a value outside those sets, WBM_ERR_UNSUPPORTED for
- * WBM_PAIR_WAVE or WBM_PAIR_RESIDENT beyond their limits or a chunk count K does not allow.  A pinned choice drops a
- * captured graph (recaptured on the next graph call).  wbm_plan_get_tuning writes the current
+ * WBM_PAIR_WAVE or WBM_PAIR_RESIDENT beyond their limits or a chunk count K does not allow.
+ * A pinned choice drops a captured graph (recaptured on the next graph call) and also fixes
+ * the pair kernel of the planar-array path (wbm_beamform_upa).  wbm_plan_get_tuning writes the current
  * choice (NULL pointers skipped). */
 wbm_status wbm_plan_set_tuning(wbm_plan* plan, int32_t chan_logtile, int32_t beam_logtile,
                                int32_t pair_kernel, int32_t overlap_chunks);
@@ -227,6 +228,49 @@ wbm_status wbm_synthesize(wbm_plan* plan, const wbm_c32* out, int32_t T, wbm_c32
  *   abar   device [T][K][w_max] wbm_c64: a~_i = M^-1/2 sum_{e<N} e^{j Omega e} e^{-j 2 pi m_i e / M}. */
 wbm_status wbm_steer(wbm_plan* plan, const double* az_rad, const int32_t* win, int32_t T,
                      int32_t* starts, wbm_c64* abar, void* stream);
+
+/* Planar array (Sec. II-A, Sec. III-B, Eq. 6 and 14-19).  The plan's n_elem = Nz * Nx and
+ * m_fft = Mz * Mx describe an Nz x Nx array with an Mz x Mx beam grid; each call names
+ *   nz = Nz (dividing n_elem) and mz = Mz (a power of two, Nz <= Mz; Mx = m_fft / mz must
+ *   satisfy Nx <= Mx, 2 <= Mx and next_pow2(Nz) * Mx <= 2048).
+ * Vectorisation: element (iz, ix) is x row ix Nz + iz (a = a_x kron a_z, Eq. 6); beam
+ * (mz, mx) is index mx Mz + mz (D = D_h^T kron D_v, Eq. 16); window cell (iz_w, ix_w) is
+ * index ix_w Wz + iz_w of the Wz x Wx window (Eq. 18).  Per axis the window starts at
+ * s = floor(u - (W-1)/2 + 1/2) with u_z = Mz (d/lambda) sin(el) f_k/f_c and
+ * u_x = Mx (d/lambda) cos(el) sin(az) f_k/f_c (FP64, evaluated as for the linear array from
+ * the direction cosines cos(el) * sin(az) and sin(el)), bins mod Mz and Mx.
+ * Errors: WBM_ERR_SHAPE for a geometry outside those limits or T outside [1, max_targets],
+ * WBM_ERR_ARG for NULL pointers, non-finite angles or windows outside [1, Mz] x [1, Mx] or
+ * above w_max. */
+
+/* Windowed beamspace MVDR on the planar array for every (target, subband) pair: as
+ * wbm_beamform with the 2-D transform and windows.
+ *   az_rad, el_rad  host [T] azimuth and elevation of each target from broadside (radians).
+ *   win_z, win_x    host [T] window rows Wz and columns Wx, Wz * Wx <= w_max.
+ *   form            WBM_FORM_FUSED, WBM_FORM_MIXED or WBM_FORM_MIXED_BF16 (others:
+ *                   WBM_ERR_UNSUPPORTED).  The fused form's pair kernel is timed on the first
+ *                   call of the plan (WBM_AUTOTUNE=0: the matrix-core kernel).
+ *   weights         device [T][K][w_max] or NULL, in window-cell order.
+ *   starts          device [T][K][2] int32 or NULL: (s_z, s_x) of every pair.
+ *   out, info       as for wbm_beamform. */
+wbm_status wbm_beamform_upa(wbm_plan* plan, const wbm_c32* x, int32_t nz, int32_t mz,
+                            const double* az_rad, const double* el_rad, const int32_t* win_z,
+                            const int32_t* win_x, int32_t T, double loading, int32_t form,
+                            wbm_c32* out, wbm_c32* weights, int32_t* starts, int32_t* info,
+                            void* stream);
+
+/* Stage: planar beamspace (Eq. 16-17).  X device [K][B][N] -> Y device [K][Mz Mx][B],
+ * Y[k][mx Mz + mz][b] = (Mz Mx)^-1/2 sum_{ix<Nx, iz<Nz} X[k][b][ix Nz + iz]
+ *                       exp(-j 2 pi (mz iz / Mz + mx ix / Mx)). */
+wbm_status wbm_beamspace_upa(wbm_plan* plan, const wbm_c32* X, int32_t nz, int32_t mz,
+                             wbm_c32* Y, void* stream);
+
+/* Stage: planar window placement and windowed steering.
+ *   starts device [T][K][2] int32 or NULL: (s_z, s_x).
+ *   abar   device [T][K][w_max] wbm_c64: a~ = S D a (a of Eq. 6), zero past Wz * Wx. */
+wbm_status wbm_steer_upa(wbm_plan* plan, int32_t nz, int32_t mz, const double* az_rad,
+                         const double* el_rad, const int32_t* win_z, const int32_t* win_x,
+                         int32_t T, int32_t* starts, wbm_c64* abar, void* stream);
 
 /* Full-dimensional element-space MVDR per subband (Sec. II-B, Eq. 11-13): the
  * comparison method.  R = (1/L) sum_{b<L} X_b X_b^H + loading I_N (N x N, FP64

@@ -26,7 +26,7 @@ from typing import Dict, Optional, Sequence
 
 import numpy as np
 
-from .bmvdr import (beam_output, channelize, mvdr_weights, sample_covariance,
+from .bmvdr import (beam_output, channelize, channelize_bins, mvdr_weights, sample_covariance,
                     subband_freq_ratio, window_start)
 
 __all__ = ["upa_direction_cosines", "upa_spatial_frequencies", "upa_steering",
@@ -99,8 +99,8 @@ def upa_lift_correlator(w: np.ndarray, rows: Sequence[int], Nz: int, Nx: int, Mz
 def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: int, Lt: int,
                       az: Sequence[float], el: Sequence[float], win_z: Sequence[int],
                       win_x: Sequence[int], delta: float, beta: float = 0.2, dl: float = 0.5,
-                      half_bin: bool = False, subbands: Optional[Sequence[int]] = None
-                      ) -> Dict[str, np.ndarray]:
+                      half_bin: bool = False, subbands: Optional[Sequence[int]] = None,
+                      return_windows: bool = False) -> Dict[str, np.ndarray]:
     """Windowed beamspace MVDR on the planar array for every (target, subband) pair.
 
     Per subband: channelize (Sec. III-A) -> 2-D beamspace (Eq. 16-17) -> Wz x Wx window
@@ -108,7 +108,8 @@ def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: in
     with a~ = S D a (a of Eq. 6) -> output on the next Lt snapshots.
 
     Returns ``start`` [T, nk, 2] (s_z, s_x), ``u`` [T, nk, 2], ``rows`` (list of lists),
-    ``w`` and ``a`` [T, nk, Wmax] zero padded, ``z`` [T, nk, Lt].
+    ``w`` and ``a`` [T, nk, Wmax] zero padded, ``z`` [T, nk, Lt], and with ``return_windows``
+    the loaded covariances ``R`` and windowed snapshots ``Yw`` [W, L + Lt] (lists of lists).
     """
     N = x.shape[0]
     Nx = N // Nz
@@ -117,7 +118,8 @@ def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: in
     wx = [int(v) for v in win_x]
     Wmax = max(a * b for a, b in zip(wz, wx))
     ks = list(range(K)) if subbands is None else [int(k) for k in subbands]
-    X = channelize(x, K, half_bin)
+    X = channelize(x, K, half_bin) if subbands is None else channelize_bins(x, K, ks, half_bin)
+    kcol = {k: (k if subbands is None else i) for i, k in enumerate(ks)}
     ratio = subband_freq_ratio(K, beta, half_bin)
     nk = len(ks)
     start = np.zeros((T, nk, 2), dtype=np.int64)
@@ -126,8 +128,10 @@ def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: in
     a_out = np.zeros((T, nk, Wmax), dtype=np.complex128)
     z_out = np.zeros((T, nk, Lt), dtype=np.complex128)
     rows_out = [[None] * nk for _ in range(T)]
+    R_out = [[None] * nk for _ in range(T)]
+    Yw_out = [[None] * nk for _ in range(T)]
     for ik, k in enumerate(ks):
-        Yk = upa_beamspace(X[:, :L + Lt, k], Nz, Mz, Mx)                  # [M, B]
+        Yk = upa_beamspace(X[:, :L + Lt, kcol[k]], Nz, Mz, Mx)            # [M, B]
         for t in range(T):
             uz, ux = upa_beam_position(float(az[t]), float(el[t]), float(ratio[k]), Mz, Mx, dl)
             sz, sx = window_start(uz, wz[t]), window_start(ux, wx[t])
@@ -144,8 +148,13 @@ def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: in
             a_out[t, ik, :W] = a
             z_out[t, ik] = beam_output(w, Yw[:, L:L + Lt])
             rows_out[t][ik] = rows
-    return dict(start=start, u=upos, w=w_out, a=a_out, z=z_out, rows=rows_out,
-                subbands=np.asarray(ks))
+            if return_windows:
+                R_out[t][ik], Yw_out[t][ik] = R, Yw
+    out = dict(start=start, u=upos, w=w_out, a=a_out, z=z_out, rows=rows_out,
+               subbands=np.asarray(ks))
+    if return_windows:
+        out.update(R=R_out, Yw=Yw_out)
+    return out
 
 
 def upa_full_mvdr(x: np.ndarray, *, Nz: int, K: int, L: int, Lt: int, az: Sequence[float],

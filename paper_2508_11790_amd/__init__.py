@@ -270,6 +270,70 @@ class Plan:
                                          _ptr(abar), _stream(stream)))
         return starts, abar
 
+    # ------------------------------------------------------------------ planar array
+    def _upa_targets(self, az_rad, el_rad, win_z, win_x):
+        az = np.ascontiguousarray(np.asarray(az_rad, dtype=np.float64).ravel())
+        el = np.ascontiguousarray(np.asarray(el_rad, dtype=np.float64).ravel())
+        wz = np.ascontiguousarray(np.asarray(win_z, dtype=np.int32).ravel())
+        wx = np.ascontiguousarray(np.asarray(win_x, dtype=np.int32).ravel())
+        T = int(az.size)
+        if not (el.size == wz.size == wx.size == T):
+            raise ValueError("el_rad, win_z and win_x must have one entry per target")
+        return az, el, wz, wx, T
+
+    def beamform_upa(self, x, nz: int, mz: int, az_rad, el_rad, win_z, win_x, loading: float,
+                     form: str = "fused", out=None, weights=None, starts=None, info=None,
+                     want_weights: bool = True, want_starts: bool = True, stream=None):
+        """Windowed beamspace MVDR on an nz x (N / nz) planar array with an mz x (M / mz) beam
+        grid; returns ``out`` [T, K, Lt], ``weights`` [T, K, w_max] (window cells, z fastest),
+        ``starts`` [T, K, 2] int32 (s_z, s_x) and ``info`` [T, K]."""
+        torch = _torch()
+        self._x(x)
+        az, el, wz, wx, T = self._upa_targets(az_rad, el_rad, win_z, win_x)
+        dev = self.device
+        if out is None:
+            out = torch.empty((T, self.K, self.Lt), dtype=torch.complex64, device=dev)
+        if weights is None and want_weights:
+            weights = torch.empty((T, self.K, self.w_max), dtype=torch.complex64, device=dev)
+        if starts is None and want_starts:
+            starts = torch.empty((T, self.K, 2), dtype=torch.int32, device=dev)
+        if info is None:
+            info = torch.empty((T, self.K), dtype=torch.int32, device=dev)
+        _check_tensor(out, "out", (T, self.K, self.Lt), torch.complex64, dev)
+        if weights is not None:
+            _check_tensor(weights, "weights", (T, self.K, self.w_max), torch.complex64, dev)
+        if starts is not None:
+            _check_tensor(starts, "starts", (T, self.K, 2), torch.int32, dev)
+        _check_tensor(info, "info", (T, self.K), torch.int32, dev)
+        _lib.check(_lib.load().wbm_beamform_upa(
+            self._h, _ptr(x), int(nz), int(mz), az.ctypes.data, el.ctypes.data, wz.ctypes.data,
+            wx.ctypes.data, T, float(loading), _FORMS[form], _ptr(out), _ptr(weights),
+            _ptr(starts), _ptr(info), _stream(stream)))
+        return dict(out=out, weights=weights, starts=starts, info=info)
+
+    def beamspace_upa(self, X, nz: int, mz: int, Y=None, stream=None):
+        """Planar beamspace: X [K, B, N] -> Y [K, M, B] complex64, beam (mz, mx) at mx * Mz + mz."""
+        torch = _torch()
+        _check_tensor(X, "X", (self.K, self.B, self.N), torch.complex64, self.device)
+        if Y is None:
+            Y = torch.empty((self.K, self.M, self.B), dtype=torch.complex64, device=self.device)
+        _check_tensor(Y, "Y", (self.K, self.M, self.B), torch.complex64, self.device)
+        _lib.check(_lib.load().wbm_beamspace_upa(self._h, _ptr(X), int(nz), int(mz), _ptr(Y),
+                                                 _stream(stream)))
+        return Y
+
+    def steer_upa(self, nz: int, mz: int, az_rad, el_rad, win_z, win_x, stream=None):
+        """Planar window starts [T, K, 2] int32 (s_z, s_x) and windowed steering [T, K, w_max]
+        complex128."""
+        torch = _torch()
+        az, el, wz, wx, T = self._upa_targets(az_rad, el_rad, win_z, win_x)
+        starts = torch.empty((T, self.K, 2), dtype=torch.int32, device=self.device)
+        abar = torch.empty((T, self.K, self.w_max), dtype=torch.complex128, device=self.device)
+        _lib.check(_lib.load().wbm_steer_upa(self._h, int(nz), int(mz), az.ctypes.data,
+                                             el.ctypes.data, wz.ctypes.data, wx.ctypes.data, T,
+                                             _ptr(starts), _ptr(abar), _stream(stream)))
+        return starts, abar
+
     STAGES = ("steer", "channelize", "beamspace", "mvdr")
 
     def stage_times(self, x, az_rad, win, loading: float, reps: int = 20, stream=None):

@@ -73,6 +73,8 @@ struct wbm_plan {
   int pair_threads = WBM_PAIR_MFMA;   // fused MVDR pair kernel: WBM_PAIR_*
   int overlap = 1;                    // subband chunks overlapping beamspace and pair kernels
   bool tuned = false;
+  int upa_pair = WBM_PAIR_MFMA;       // pair kernel of the planar-array path (timed on first use)
+  bool upa_tuned = false;
   // second stream of the overlapped fused sequence and its fork / join events
   hipStream_t side_stream = nullptr;
   hipEvent_t chunk_evt[kMaxOverlap + 1] = {};
@@ -166,6 +168,69 @@ wbm_status upload_twiddles(float2* dst, int n, double sign_frac) {
   return WBM_OK;
 }
 
+// Byte offsets of the per-call descriptor: FP64 arrays first, then the int arrays.
+struct DescLayout {
+  size_t sin_az, cz, win, woff, rowtab, torder, wz, bytes;
+};
+
+DescLayout desc_layout(int Tm, int wmax) {
+  DescLayout l;
+  l.sin_az = 0;
+  l.cz = l.sin_az + sizeof(double) * Tm;
+  l.win = l.cz + sizeof(double) * Tm;
+  l.woff = l.win + sizeof(int) * Tm;
+  l.rowtab = l.woff + sizeof(int) * Tm;
+  l.torder = l.rowtab + sizeof(int) * (size_t)Tm * wmax;
+  l.wz = l.torder + sizeof(int) * Tm;
+  l.bytes = l.wz + sizeof(int) * Tm;
+  return l;
+}
+
+// Window offsets, window-row table and pair order of the staged descriptor from the widths
+// already in it; returns sumW.
+int desc_rows(wbm_plan* p, int T) {
+  const DescLayout l = desc_layout(p->cfg.max_targets, p->cfg.w_max);
+  unsigned char* buf = p->desc_next.data();
+  const int* wv = reinterpret_cast<const int*>(buf + l.win);
+  int* woff = reinterpret_cast<int*>(buf + l.woff);
+  int* rowtab = reinterpret_cast<int*>(buf + l.rowtab);
+  int* torder = reinterpret_cast<int*>(buf + l.torder);
+  int sumW = 0;
+  for (int t = 0; t < T; ++t) {
+    woff[t] = sumW;
+    for (int i = 0; i < wv[t]; ++i) rowtab[sumW + i] = (t << 8) | i;
+    sumW += wv[t];
+    torder[t] = t;
+  }
+  // pair kernels take the widest windows first (longest-processing-time order): workgroups
+  // are handed out in index order, so the expensive pairs start early and spread evenly
+  std::stable_sort(torder, torder + T, [wv](int x, int y) { return wv[x] > wv[y]; });
+  return sumW;
+}
+
+// Upload the staged descriptor, unless the device copy already holds these bytes (the same
+// targets as the previous call, on the same stream, outside graph capture).
+wbm_status commit_desc(wbm_plan* p, hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  WBM_HIP(hipStreamIsCapturing(st, &cap), "capture query");
+  if (p->desc_evt_recorded && st == p->desc_stream && cap == hipStreamCaptureStatusNone &&
+      p->desc_next == p->desc_last) {
+    // the device copy already holds these bytes (or will, in this stream's order)
+    return WBM_OK;
+  }
+  if (p->desc_evt_recorded) {
+    WBM_HIP(hipEventSynchronize(p->desc_evt), "descriptor staging wait");
+  }
+  std::memcpy(p->desc_host, p->desc_next.data(), p->desc_bytes);
+  WBM_HIP(hipMemcpyAsync(p->desc_dev, p->desc_host, p->desc_bytes, hipMemcpyHostToDevice, st),
+          "descriptor upload");
+  WBM_HIP(hipEventRecord(p->desc_evt, st), "descriptor event");
+  p->desc_evt_recorded = true;
+  p->desc_last.swap(p->desc_next);
+  p->desc_stream = st;
+  return WBM_OK;
+}
+
 // Validate the per-call targets and upload their description; returns sumW.
 wbm_status upload_desc(wbm_plan* p, const double* az_rad, const int32_t* win, int T,
                        hipStream_t st, int* sumW_out) {
@@ -183,46 +248,76 @@ wbm_status upload_desc(wbm_plan* p, const double* az_rad, const int32_t* win, in
                                      " outside [1, w_max=" + std::to_string(c.w_max) + "]");
     }
   }
-  const int Tm = c.max_targets;
+  const DescLayout l = desc_layout(c.max_targets, c.w_max);
   p->desc_next.assign(p->desc_bytes, 0);
   unsigned char* buf = p->desc_next.data();
-  double* sin_az = reinterpret_cast<double*>(buf);
-  int* wv = reinterpret_cast<int*>(buf + sizeof(double) * Tm);
-  int* woff = wv + Tm;
-  int* rowtab = woff + Tm;
-  int* torder = rowtab + (size_t)Tm * c.w_max;
-  int sumW = 0;
+  double* sin_az = reinterpret_cast<double*>(buf + l.sin_az);
+  int* wv = reinterpret_cast<int*>(buf + l.win);
   for (int t = 0; t < T; ++t) {
     sin_az[t] = std::sin(az_rad[t]);
-    const int W = win ? win[t] : c.w_max;
-    wv[t] = W;
-    woff[t] = sumW;
-    for (int i = 0; i < W; ++i) rowtab[sumW + i] = (t << 8) | i;
-    sumW += W;
-    torder[t] = t;
+    wv[t] = win ? win[t] : c.w_max;
   }
-  // pair kernels take the widest windows first (longest-processing-time order): workgroups
-  // are handed out in index order, so the expensive pairs start early and spread evenly
-  std::stable_sort(torder, torder + T, [wv](int x, int y) { return wv[x] > wv[y]; });
-  *sumW_out = sumW;
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  WBM_HIP(hipStreamIsCapturing(st, &cap), "capture query");
-  if (p->desc_evt_recorded && st == p->desc_stream && cap == hipStreamCaptureStatusNone &&
-      p->desc_next == p->desc_last) {
-    // the device copy already holds these bytes (or will, in this stream's order)
-    return WBM_OK;
-  }
-  if (p->desc_evt_recorded) {
-    WBM_HIP(hipEventSynchronize(p->desc_evt), "descriptor staging wait");
-  }
-  std::memcpy(p->desc_host, buf, p->desc_bytes);
-  WBM_HIP(hipMemcpyAsync(p->desc_dev, p->desc_host, p->desc_bytes, hipMemcpyHostToDevice, st),
-          "descriptor upload");
-  WBM_HIP(hipEventRecord(p->desc_evt, st), "descriptor event");
-  p->desc_evt_recorded = true;
-  p->desc_last.swap(p->desc_next);
-  p->desc_stream = st;
+  *sumW_out = desc_rows(p, T);
+  return commit_desc(p, st);
+}
+
+// Planar array: validate the geometry (nz rows, mz-point vertical DFT) and the targets, and
+// upload their description (direction cosines, Wz * Wx windows); returns sumW.
+wbm_status check_upa_shape(const wbm_plan* p, int nz, int mz) {
+  const wbm_config& c = p->cfg;
+  if (nz < 1 || c.n_elem % nz != 0)
+    return fail(WBM_ERR_SHAPE, "nz=" + std::to_string(nz) + " must divide n_elem=" +
+                                   std::to_string(c.n_elem));
+  if (!is_pow2(mz) || mz < nz || c.m_fft % mz != 0)
+    return fail(WBM_ERR_SHAPE, "mz=" + std::to_string(mz) +
+                                   " must be a power of two with nz <= mz, dividing m_fft");
+  const int nx = c.n_elem / nz, mx = c.m_fft / mz;
+  int pz = 1;
+  while (pz < nz) pz <<= 1;
+  if (mx < 2 || mx < nx || (int64_t)pz * mx > 2048)
+    return fail(WBM_ERR_SHAPE, "need 2 <= m_fft/mz, n_elem/nz <= m_fft/mz and next_pow2(nz) * "
+                               "(m_fft/mz) <= 2048 (got nx=" + std::to_string(nx) + ", mx=" +
+                               std::to_string(mx) + ")");
   return WBM_OK;
+}
+
+wbm_status upload_desc_upa(wbm_plan* p, int nz, int mz, const double* az_rad,
+                           const double* el_rad, const int32_t* win_z, const int32_t* win_x,
+                           int T, hipStream_t st, int* sumW_out) {
+  const wbm_config& c = p->cfg;
+  wbm_status s = check_upa_shape(p, nz, mz);
+  if (s) return s;
+  const int mx = c.m_fft / mz;
+  if (!az_rad || !el_rad || !win_z || !win_x)
+    return fail(WBM_ERR_ARG, "az_rad / el_rad / win_z / win_x is NULL");
+  if (T < 1 || T > c.max_targets)
+    return fail(WBM_ERR_SHAPE, "T=" + std::to_string(T) + " outside [1, max_targets=" +
+                                   std::to_string(c.max_targets) + "]");
+  for (int t = 0; t < T; ++t) {
+    const std::string ts = "[" + std::to_string(t) + "]";
+    if (!std::isfinite(az_rad[t]) || !std::isfinite(el_rad[t]))
+      return fail(WBM_ERR_ARG, "az_rad / el_rad" + ts + " not finite");
+    if (win_z[t] < 1 || win_z[t] > mz || win_x[t] < 1 || win_x[t] > mx ||
+        win_z[t] * win_x[t] > c.w_max)
+      return fail(WBM_ERR_ARG, "window" + ts + " = " + std::to_string(win_z[t]) + " x " +
+                                   std::to_string(win_x[t]) + " outside [1, mz] x [1, m_fft/mz]"
+                                   " or above w_max=" + std::to_string(c.w_max));
+  }
+  const DescLayout l = desc_layout(c.max_targets, c.w_max);
+  p->desc_next.assign(p->desc_bytes, 0);
+  unsigned char* buf = p->desc_next.data();
+  double* cx = reinterpret_cast<double*>(buf + l.sin_az);
+  double* cz = reinterpret_cast<double*>(buf + l.cz);
+  int* wv = reinterpret_cast<int*>(buf + l.win);
+  int* wz = reinterpret_cast<int*>(buf + l.wz);
+  for (int t = 0; t < T; ++t) {
+    cx[t] = std::cos(el_rad[t]) * std::sin(az_rad[t]);
+    cz[t] = std::sin(el_rad[t]);
+    wv[t] = win_z[t] * win_x[t];
+    wz[t] = win_z[t];
+  }
+  *sumW_out = desc_rows(p, T);
+  return commit_desc(p, st);
 }
 
 wbm_status ensure_plain(wbm_plan* p) {
@@ -275,6 +370,25 @@ wbm::WindowGeom geom(const wbm_plan* p, int T) {
   g.dl = p->cfg.d_over_lambda;
   g.sin_az = p->dd.sin_az;
   g.win = p->dd.win;
+  return g;
+}
+
+// Geometry of a planar-array call (nz, mz validated by upload_desc_upa or check_upa_shape).
+wbm::UpaGeom upa_geom(const wbm_plan* p, int T, int nz, int mz) {
+  wbm::UpaGeom g;
+  g.T = T;
+  g.K = p->cfg.k_sub;
+  g.Nz = nz;
+  g.Nx = p->cfg.n_elem / nz;
+  g.Mz = mz;
+  g.Mx = p->cfg.m_fft / mz;
+  g.half_bin = (p->cfg.flags & WBM_HALF_BIN) ? 1 : 0;
+  g.beta = p->cfg.beta;
+  g.dl = p->cfg.d_over_lambda;
+  g.cx = p->dd.sin_az;
+  g.cz = p->dd.cz;
+  g.win = p->dd.win;
+  g.wz = p->dd.wz;
   return g;
 }
 
@@ -595,6 +709,8 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
   p->pair_threads = pair;
   p->overlap = overlap;
   p->tuned = true;
+  p->upa_pair = pair;
+  p->upa_tuned = true;
   p->gkey.valid = false;
   return WBM_OK;
 }
@@ -681,7 +797,8 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   if ((s = upload_twiddles(p->hb, c.k_sub, 0.5))) return bail(s);
 
   const int Tm = c.max_targets;
-  p->desc_bytes = sizeof(double) * Tm + sizeof(int) * (size_t)Tm * (3 + c.w_max);
+  const DescLayout dl = desc_layout(Tm, c.w_max);
+  p->desc_bytes = dl.bytes;
   if ((s = dev_alloc(p, &p->desc_dev, p->desc_bytes, "descriptor"))) return bail(s);
   if (hipHostMalloc((void**)&p->desc_host, p->desc_bytes, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -690,11 +807,13 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   std::memset(p->desc_host, 0, p->desc_bytes);
   if (hipEventCreateWithFlags(&p->desc_evt, hipEventDisableTiming) != hipSuccess)
     return bail(fail(WBM_ERR_HIP, "hipEventCreate failed"));
-  p->dd.sin_az = reinterpret_cast<const double*>(p->desc_dev);
-  p->dd.win = reinterpret_cast<const int*>(p->desc_dev + sizeof(double) * Tm);
-  p->dd.woff = p->dd.win + Tm;
-  p->dd.rowtab = p->dd.woff + Tm;
-  p->dd.torder = p->dd.rowtab + (size_t)Tm * c.w_max;
+  p->dd.sin_az = reinterpret_cast<const double*>(p->desc_dev + dl.sin_az);
+  p->dd.cz = reinterpret_cast<const double*>(p->desc_dev + dl.cz);
+  p->dd.win = reinterpret_cast<const int*>(p->desc_dev + dl.win);
+  p->dd.woff = reinterpret_cast<const int*>(p->desc_dev + dl.woff);
+  p->dd.rowtab = reinterpret_cast<const int*>(p->desc_dev + dl.rowtab);
+  p->dd.torder = reinterpret_cast<const int*>(p->desc_dev + dl.torder);
+  p->dd.wz = reinterpret_cast<const int*>(p->desc_dev + dl.wz);
 
   const size_t NS = (size_t)c.n_elem * p->S;
   if ((s = dev_alloc(p, &p->X, NS, "channelized X"))) return bail(s);
@@ -920,6 +1039,128 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
       p->gkey = key;
     }
     WBM_HIP(hipGraphLaunch(p->gexec, st), "graph launch");
+  }
+  return WBM_OK;
+}
+
+wbm_status wbm_steer_upa(wbm_plan* p, int32_t nz, int32_t mz, const double* az_rad,
+                         const double* el_rad, const int32_t* win_z, const int32_t* win_x,
+                         int32_t T, int32_t* starts, wbm_c64* abar, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!abar) return fail(WBM_ERR_ARG, "abar is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc_upa(p, nz, mz, az_rad, el_rad, win_z, win_x, T, st, &sumW))) return s;
+  WBM_HIP(wbm::launch_steer_upa(upa_geom(p, T, nz, mz), p->cfg.w_max, starts,
+                                reinterpret_cast<double2*>(abar), st),
+          "planar steer launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beamspace_upa(wbm_plan* p, const wbm_c32* X, int32_t nz, int32_t mz, wbm_c32* Y,
+                             void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!X || !Y) return fail(WBM_ERR_ARG, "X / Y is NULL");
+  if ((s = check_upa_shape(p, nz, mz))) return s;
+  WBM_HIP(wbm::launch_beamspace_upa(reinterpret_cast<const float2*>(X),
+                                    reinterpret_cast<float2*>(Y), nullptr, p->B, p->twM, nullptr,
+                                    0, upa_geom(p, 0, nz, mz), p->logTB, p->nbt,
+                                    static_cast<hipStream_t>(stream)),
+          "planar beamspace launch");
+  return WBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Channelize -> planar beamspace windows for the uploaded targets (steering already in abar).
+hipError_t enqueue_upa_windows(wbm_plan* p, const float2* x, int T, int sumW,
+                               const wbm::UpaGeom& g, hipStream_t st) {
+  hipError_t e = enqueue_channelize(p, x, st);
+  if (e != hipSuccess) return e;
+  return wbm::launch_beamspace_upa(p->X, nullptr, p->Yw, p->B, p->twM, p->dd.rowtab, sumW, g,
+                                   p->logTB, p->nbt, st);
+}
+
+// First planar-array call of a plan: the pair kernel of the fused form is timed on these
+// windows (best of three after a warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0
+// keeps the matrix-core kernel.
+hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::UpaGeom& g,
+                    double loading, hipStream_t st) {
+  p->upa_tuned = true;
+  const char* env = std::getenv("WBM_AUTOTUNE");
+  if (env && std::strcmp(env, "0") == 0) return hipSuccess;
+  hipError_t e = enqueue_upa_windows(p, x, T, sumW, g, st);
+  if (e != hipSuccess) return e;
+  wbm::PairArgs pa = pair_args(p, T, sumW, loading);
+  pa.abar = p->abar;
+  float best = 1e30f;
+  for (int thr : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
+    if (thr == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
+    if (thr == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
+    float ms;
+    e = time_best([&]() {
+      return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
+                                    p->prof_info, thr, st);
+    }, st, &ms);
+    if (e != hipSuccess) return e;
+    if (ms < best) {
+      best = ms;
+      p->upa_pair = thr;
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t mz,
+                            const double* az_rad, const double* el_rad, const int32_t* win_z,
+                            const int32_t* win_x, int32_t T, double loading, int32_t form,
+                            wbm_c32* out, wbm_c32* weights, int32_t* starts, int32_t* info,
+                            void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  const wbm_config& c = p->cfg;
+  if (!x) return fail(WBM_ERR_ARG, "x is NULL");
+  if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
+  if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
+  if (form != WBM_FORM_FUSED && form != WBM_FORM_MIXED && form != WBM_FORM_MIXED_BF16)
+    return fail(WBM_ERR_UNSUPPORTED, "the planar array runs the fused and mixed forms");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int sumW = 0;
+  if ((s = upload_desc_upa(p, nz, mz, az_rad, el_rad, win_z, win_x, T, st, &sumW))) return s;
+  if (sizeof(float2) * (size_t)mz + sizeof(int) * (2 * (size_t)T + sumW) > 96 * 1024)
+    return fail(WBM_ERR_SHAPE, "too many window rows for the planar beamspace kernel");
+  const wbm::UpaGeom g = upa_geom(p, T, nz, mz);
+  const float2* xx = reinterpret_cast<const float2*>(x);
+  float2* o = reinterpret_cast<float2*>(out);
+  float2* w = reinterpret_cast<float2*>(weights);
+  WBM_HIP(wbm::launch_steer_upa(g, c.w_max, starts, p->abar, st), "planar steer launch");
+  if (form == WBM_FORM_FUSED && !p->upa_tuned) {
+    if ((s = ensure_prof(p))) return s;
+    WBM_HIP(tune_upa(p, xx, T, sumW, g, loading, st), "planar pair kernel tuning");
+  }
+  WBM_HIP(enqueue_upa_windows(p, xx, T, sumW, g, st), "planar beamspace launch");
+  wbm::PairArgs pa = pair_args(p, T, sumW, loading);
+  pa.abar = p->abar;
+  if (form == WBM_FORM_FUSED) {
+    WBM_HIP(wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, o, w, nullptr, info, p->upa_pair,
+                                   st),
+            "fused MVDR launch");
+  } else {
+    if (!p->route) {
+      wbm_status rs = dev_alloc(p, &p->route, (size_t)c.max_targets * c.k_sub, "route flags");
+      if (rs) return rs;
+    }
+    WBM_HIP(wbm::launch_mvdr_mixed(pa, geom(p, T), p->dd, p->Yw, o, w, nullptr, info, p->route,
+                                   form == WBM_FORM_MIXED, st),
+            "mixed MVDR launch");
   }
   return WBM_OK;
 }

@@ -480,6 +480,140 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
                                            k0, kc, s);
 }
 
+// Planar-array beamspace (Eq. 16-17): X [K][B][N], N = Nz Nx (element ix Nz + iz) ->
+//   full  : Y [K][Mz Mx][B], beam mx Mz + mz                              (stage output), and/or
+//   window: Yw [K][nbt][sumW][TB] in the layout of the linear-array kernel (TB = 2^logTB
+//           snapshots per tile block), row r = cell i of target t's Wz x Wx window.
+// The Kronecker transform factors into a zero-padded Mx-point FFT along x of every (snapshot,
+// iz) row, tiles of 2^11 values through LDS as in the linear-array kernel (rows of one
+// snapshot are Pz = 2^logPz >= Nz apart, the rows iz >= Nz zero), followed by the Nz-term
+// DFT along z of the bins the kernel writes.  Workgroup = (first tile, subband k), looping
+// over tiles of TB2 = 2^11 / (Pz Mx) snapshots.  ZH: 2 Nx <= Mx.
+constexpr int kUpaLogTile = 11;
+
+template <int LOGMX, bool ZH>
+__global__ __launch_bounds__(fft_threads(LOGMX, kUpaLogTile)) void k_beamspace_upa(
+    const float2* __restrict__ X, float2* __restrict__ Y, float2* __restrict__ Yw, int logPz,
+    int logMz, int B, const float2* __restrict__ twM, float scale,
+    const int* __restrict__ rowtab, int sumW, UpaGeom g, int logTB, int nbt) {
+  using F = Fft<LOGMX, fft_tile(LOGMX, kUpaLogTile), beam_pad(fft_tile(LOGMX, kUpaLogTile), LOGMX)>;
+  constexpr int Mx = F::n;
+  const int Nz = g.Nz, Nx = g.Nx, N = Nz * Nx;
+  const int Mz = 1 << logMz;
+  const int logTB2 = fft_tile(LOGMX, kUpaLogTile) - LOGMX - logPz;
+  const int TB2 = 1 << logTB2;
+  const int nbt2 = (B + TB2 - 1) >> logTB2;
+  const int TB = 1 << logTB;
+  const int lw = logTB < logTB2 ? logTB : logTB2;
+  __shared__ float2 lds[F::lds_complex];
+  extern __shared__ int s_dyn[];
+  float2* s_twz = reinterpret_cast<float2*>(s_dyn);        // [Mz] exp(-j 2 pi q / Mz)
+  int* s_sz = reinterpret_cast<int*>(s_twz + Mz);          // [T] window starts along z
+  int* s_sx = s_sz + g.T;                                  // [T] along x
+  int* s_bin = s_sx + g.T;                                 // [sumW] beam of window row r
+  const int k = blockIdx.y;
+  float2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twM, Mz);                           // Mx-point table = twM[q Mz]
+  auto fetch = [&](int j, float2 (&v)[8]) {
+    const int b0 = j * TB2;
+#pragma unroll
+    for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        int row, ix;
+        F::first_input(p, r, row, ix);
+        const int iz = row & ((1 << logPz) - 1), bb = row >> logPz;
+        float2 val = make_float2(0.f, 0.f);
+        if (!(ZH && 2 * r >= F::R0) && ix < Nx && iz < Nz && b0 + bb < B)
+          val = X[((int64_t)k * B + b0 + bb) * N + ix * Nz + iz];
+        v[p * F::R0 + r] = val;
+      }
+    }
+  };
+  float2 nv[8];
+  if ((int)blockIdx.x < nbt2) fetch(blockIdx.x, nv);
+  for (int q = threadIdx.x; q < Mz; q += F::threads) s_twz[q] = twM[q << LOGMX];
+  if (Yw) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) {
+      double uz, ux;
+      upa_window_of(g, t, k, &uz, &s_sz[t], &ux, &s_sx[t]);
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < sumW; r += F::threads) {
+      const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+      const int Wz = g.wz[t], ixw = i / Wz, izw = i - ixw * Wz;
+      s_bin[r] = (((s_sx[t] + ixw) & (Mx - 1)) << logMz) | ((s_sz[t] + izw) & (Mz - 1));
+    }
+  }
+  __syncthreads();
+  // beam m of tile snapshot bb: the z-DFT of the x-transformed rows
+  auto beam = [&](int m, int bb) {
+    const int mx = m >> logMz, mz = m & (Mz - 1);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int iz = 0; iz < Nz; ++iz) {
+      const float2 v = lds[F::addr((bb << logPz) + iz, mx)];
+      const float2 w = s_twz[(mz * iz) & (Mz - 1)];
+      acc.x += v.x * w.x - v.y * w.y;
+      acc.y += v.x * w.y + v.y * w.x;
+    }
+    return cscale(acc, scale);
+  };
+  for (int j = blockIdx.x; j < nbt2; j += gridDim.x) {
+    const int b0 = j * TB2;
+    float2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = nv[q];
+    if (j + (int)gridDim.x < nbt2) fetch(j + gridDim.x, nv);
+    F::template run<ZH>(v, lds, tr);
+    if (Y) {
+      const int M = Mz << LOGMX;
+      for (int idx = threadIdx.x; idx < (M << logTB2); idx += F::threads) {
+        const int m = idx >> logTB2, bb = idx & (TB2 - 1);
+        if (b0 + bb < B) Y[((int64_t)k * M + m) * B + b0 + bb] = beam(m, bb);
+      }
+    }
+    if (Yw) {
+      // snapshot-fastest runs of min(TB, TB2) within each window row; snapshots past B (zero
+      // inputs) fill the padding of the last tile block
+      for (int idx = threadIdx.x; idx < (sumW << logTB2); idx += F::threads) {
+        const int blo = idx & ((1 << lw) - 1), rest = idx >> lw;
+        const int r = rest % sumW, bq = rest / sumW;
+        const int bb = (bq << lw) | blo, b = b0 + bb;
+        if (b < nbt * TB)
+          Yw[(((int64_t)k * nbt + (b >> logTB)) * sumW + r) * TB + (b & (TB - 1))] =
+              beam(s_bin[r], bb);
+      }
+    }
+    __syncthreads();   // the next tile's first pass overwrites lds
+  }
+}
+
+template <int LOGMX, bool ZH>
+static hipError_t beam_upa_launch(const float2* X, float2* Y, float2* Yw, int logPz, int logMz,
+                                  int B, int K, const float2* twM, const int* rowtab, int sumW,
+                                  const UpaGeom& g, int logTB, int nbt, hipStream_t s) {
+  using F = Fft<LOGMX, fft_tile(LOGMX, kUpaLogTile), beam_pad(fft_tile(LOGMX, kUpaLogTile), LOGMX)>;
+  const int logTB2 = fft_tile(LOGMX, kUpaLogTile) - LOGMX - logPz;
+  if (logTB2 < 0) return hipErrorInvalidValue;
+  const int nbt2 = (B + (1 << logTB2) - 1) >> logTB2;
+  const size_t shm = sizeof(float2) * ((size_t)1 << logMz) +
+                     sizeof(int) * (2 * (size_t)g.T + (size_t)sumW);
+  if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_upa<LOGMX, ZH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  static int resident = 0;
+  const int cap = resident_blocks(k_beamspace_upa<LOGMX, ZH>, F::threads, shm, &resident);
+  int gx = (cap + K - 1) / K;
+  if (gx > nbt2) gx = nbt2;
+  if (gx < 1) gx = 1;
+  hipLaunchKernelGGL((k_beamspace_upa<LOGMX, ZH>), dim3(gx, K), dim3(F::threads), shm, s, X, Y,
+                     Yw, logPz, logMz, B, twM, 1.0f / sqrtf((float)((size_t)F::n << logMz)),
+                     rowtab, sumW, g, logTB, nbt);
+  return hipGetLastError();
+}
+
 #define WBM_LOG_CASES(M, T) \
   M(1, T) M(2, T) M(3, T) M(4, T) M(5, T) M(6, T) M(7, T) M(8, T) M(9, T) M(10, T) M(11, T) \
   M(12, T) M(13, T)
@@ -621,6 +755,25 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
       switch (lm) { WBM_LOG_CASES(C, 13) }
       break;
   }
+#undef C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_beamspace_upa(const float2* X, float2* Y, float2* Yw, int B, const float2* twM,
+                                const int* rowtab, int sumW, const UpaGeom& g, int logTB, int nbt,
+                                hipStream_t s) {
+  const int lmx = ilog2(g.Mx), lmz = ilog2(g.Mz), lpz = ilog2(g.Nz);
+  if ((1 << lmx) != g.Mx || (1 << lmz) != g.Mz || g.Nx > g.Mx || g.Nz > g.Mz || lmx < 1 ||
+      lmx + lpz > kUpaLogTile)
+    return hipErrorInvalidValue;
+  const bool zh = 2 * g.Nx <= g.Mx;
+#define C(LG, unused)                                                                           \
+  case LG:                                                                                      \
+    return zh ? beam_upa_launch<LG, true>(X, Y, Yw, lpz, lmz, B, g.K, twM, rowtab, sumW, g,     \
+                                          logTB, nbt, s)                                        \
+              : beam_upa_launch<LG, false>(X, Y, Yw, lpz, lmz, B, g.K, twM, rowtab, sumW, g,    \
+                                           logTB, nbt, s);
+  switch (lmx) { C(1, 0) C(2, 0) C(3, 0) C(4, 0) C(5, 0) C(6, 0) C(7, 0) C(8, 0) C(9, 0) C(10, 0) C(11, 0) }
 #undef C
   return hipErrorInvalidValue;
 }

@@ -60,6 +60,41 @@ hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* aba
   return hipGetLastError();
 }
 
+// Planar array: one thread per (t, k, i < wmax): window starts (s_z, s_x) of the pair and its
+// windowed steering a~ = S D a, cell i = ix_w Wz + iz_w the product of the two axes' Dirichlet
+// sums (D a of Eq. 6 factors over the Kronecker product).
+__global__ void k_steer_upa(UpaGeom g, int wmax, int* __restrict__ starts,
+                            double2* __restrict__ abar) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)g.T * g.K * wmax;
+  if (idx >= total) return;
+  const int i = (int)(idx % wmax);
+  const int64_t pk = idx / wmax;
+  const int k = (int)(pk % g.K), t = (int)(pk / g.K);
+  double uz, ux;
+  int sz, sx;
+  upa_window_of(g, t, k, &uz, &sz, &ux, &sx);
+  if (starts && i == 0) {
+    starts[2 * pk] = sz;
+    starts[2 * pk + 1] = sx;
+  }
+  double2 a = make_double2(0.0, 0.0);
+  if (i < g.win[t]) {
+    const int Wz = g.wz[t], ixw = i / Wz, izw = i - ixw * Wz;
+    a = dmul(axis_steering(g.Nx, g.Mx, ux, sx + ixw), axis_steering(g.Nz, g.Mz, uz, sz + izw));
+  }
+  abar[idx] = a;
+}
+
+hipError_t launch_steer_upa(const UpaGeom& g, int wmax, int* starts, double2* abar,
+                            hipStream_t s) {
+  const int64_t total = (int64_t)g.T * g.K * wmax;
+  const int bs = 256;
+  hipLaunchKernelGGL(k_steer_upa, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, g,
+                     wmax, starts, abar);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
 // Row e of the packed lower triangle -> (i, j), j <= i.
 __device__ __forceinline__ void tri_index(int e, int& i, int& j) {
@@ -929,7 +964,8 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
-  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  for (int i = tid; i < W; i += TH)
+    av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
 
   if constexpr (!MF) {
@@ -1179,7 +1215,8 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
     const int i = (int)(((float)e + 0.5f) * invL), b = e - i * a.L;
     vtr[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
   }
-  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  for (int i = tid; i < W; i += TH)
+    av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
 #pragma unroll
   for (int m = 0; m < kResPre; ++m) {
     const int e = tid + m * TH;
@@ -1626,7 +1663,8 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
-  for (int i = tid; i < W; i += TH) av[i] = window_steering(g, ps.u, ps.s, i);
+  for (int i = tid; i < W; i += TH)
+    av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
 
   const int rows = 2 * W;

@@ -77,6 +77,41 @@ __device__ __forceinline__ double2 window_steering(const WindowGeom& g, double u
 }
 
 // ---------------------------------------------------------------------------------------------
+// Planar array (Sec. II-A, Sec. III-B): Nz x Nx elements, element (iz, ix) at vector index
+// ix Nz + iz; an Mz x Mx beam grid, beam (mz, mx) at index mx Mz + mz; a Wz x Wx window, cell
+// (iz_w, ix_w) at index ix_w Wz + iz_w.  Each axis places its window as the linear array
+// does, from the direction cosines cx = cos(el) sin(az) and cz = sin(el).
+struct UpaGeom {
+  int T, K, Nz, Nx, Mz, Mx, half_bin;
+  double beta, dl;
+  const double* cx;   // [T]
+  const double* cz;   // [T]
+  const int* win;     // [T] Wz * Wx
+  const int* wz;      // [T]
+};
+
+__device__ __forceinline__ void upa_window_of(const UpaGeom& g, int t, int k, double* uz,
+                                              int* sz, double* ux, int* sx) {
+  const int ks = (k < g.K / 2) ? k : k - g.K;
+  const double ksh = (double)ks + (g.half_bin ? 0.5 : 0.0);
+  const int Wz = g.wz[t], Wx = g.win[t] / Wz;
+  window_geom((double)g.Mz, g.dl, g.cz[t], g.beta, ksh, (double)g.K, Wz, uz, sz);
+  window_geom((double)g.Mx, g.dl, g.cx[t], g.beta, ksh, (double)g.K, Wx, ux, sx);
+}
+
+// One axis of the windowed steering: M^-1/2 sum_{e<N} e^{j psi e}, psi = 2 pi (u - m) / M
+// (Dirichlet closed form; |u - m| < M for every window bin, so the only pole is u = m).
+__device__ __forceinline__ double2 axis_steering(int N, int M, double u, int m) {
+  const double xx = (u - (double)m) / (double)M;
+  const double num = sinpi((double)N * xx), den = sinpi(xx);
+  double mag = (den == 0.0) ? (double)N : num / den;
+  mag /= sqrt((double)M);
+  double sp, cp;
+  sincospi((double)(N - 1) * xx, &sp, &cp);
+  return make_double2(mag * cp, mag * sp);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Small DFTs in registers, forward sign: X[k] = sum_r v[r] exp(-2 pi i r k / R).
 
 __device__ __forceinline__ void dft2(float2* v) {
@@ -202,8 +237,11 @@ struct Fft {
   static constexpr bool kCompact = NP >= 3;
   static constexpr int NTW = kCompact ? 3 : 7;
 
+  // tw[q * stride] = exp(-2 pi i q / n): an n-point table, or every stride-th entry of a
+  // larger one.
   __device__ __forceinline__ static void load_twiddles(float2 (&tr)[NPA][NTW],
-                                                       const float2* __restrict__ tw) {
+                                                       const float2* __restrict__ tw,
+                                                       int stride = 1) {
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
       const int logns = LOGR0 + 3 * q;
@@ -211,12 +249,12 @@ struct Fft {
       bf<3>(0, row, j);
       const int step = (j & ((1 << logns) - 1)) << (LOGN - logns - 3);
       if constexpr (kCompact) {
-        tr[q][0] = tw[step];
-        tr[q][1] = tw[2 * step];
-        tr[q][2] = tw[4 * step];
+        tr[q][0] = tw[step * stride];
+        tr[q][1] = tw[2 * step * stride];
+        tr[q][2] = tw[4 * step * stride];
       } else {
 #pragma unroll
-        for (int r = 1; r < 8; ++r) tr[q][r - 1] = tw[r * step];
+        for (int r = 1; r < 8; ++r) tr[q][r - 1] = tw[r * step * stride];
       }
     }
   }

@@ -15,6 +15,8 @@ struct DevDesc {
   const int* woff;        // [T] first window row of target t (prefix sum of win)
   const int* rowtab;      // [sumW] window row r -> (t << 8) | i
   const int* torder;      // [T] targets by window width, widest first (pair kernels' order)
+  const double* cz;       // [T] planar array: sin(el) (sin_az then holds cos(el) sin(az))
+  const int* wz;          // [T] planar array: window rows along z (win = Wz * Wx)
 };
 
 // FFT tile sizes the kernels are built for (log2 complex per workgroup tile).
@@ -40,6 +42,17 @@ int beamspace_tiles(int M, int B, int logtile);
 // Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
 hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar, hipStream_t s);
 
+// Planar array: window starts [T][K][2] (s_z, s_x; optional) and windowed steering abar
+// [T][K][wmax] (FP64).
+hipError_t launch_steer_upa(const UpaGeom& g, int wmax, int* starts, double2* abar,
+                            hipStream_t s);
+// Planar-array beamspace X [K][B][Nz Nx] -> Y [K][Mz Mx][B] (if Y) and the Wz x Wx windows Yw
+// [K][nbt][sumW][2^logTB] (if Yw) for every subband.  Needs Mx, Mz powers of two,
+// Nx <= Mx, Nz <= Mz, 2 <= Mx and next_pow2(Nz) Mx <= 2048.
+hipError_t launch_beamspace_upa(const float2* X, float2* Y, float2* Yw, int B, const float2* twM,
+                                const int* rowtab, int sumW, const UpaGeom& g, int logTB, int nbt,
+                                hipStream_t s);
+
 struct PairArgs {
   int T, K, M, L, Lt, B, wmax;
   int logTB, nbt, sumW;          // windowed layout (fused form)
@@ -53,6 +66,9 @@ struct PairArgs {
   const int* route = nullptr;
   // subbands k0 .. k0 + kc - 1 only (kc = 0: all K); the grid is T * kc workgroups
   int k0 = 0, kc = 0;
+  // optional windowed steering [T][K][wmax] (the planar array's); nullptr = the pair kernels
+  // evaluate the linear array's from the window geometry
+  const double2* abar = nullptr;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> LDL^H (FP64) -> solve
 // -> apply, reading the window rows written by the beamspace kernel.

@@ -1,0 +1,314 @@
+"""GPU parity of the planar-array path (Sec. II-A, Sec. III-B: 2-D zero-padded beamspace,
+Wz x Wx windows, windowed MVDR) against the FP64 planar oracle on the same seeded complex64
+inputs, through the C ABI.
+
+Bounds (u = 2^-24, FP32 unit roundoff):
+* beamspace: a unitary transform computed as an Mx-point FP32 FFT and an Nz-term FP32 DFT is
+  off by at most about (log2 Mx + Nz) u ||X[k, b]||_2 per output; allowed
+  4 (log2 Mx + Nz + 1) u ||X[k, b]||_2.
+* steering: FP64 closed forms against the oracle's FP64 transform of a: 1e-12 absolute.
+* window starts: integer decisions, identical.
+* weights, SINR loss: the linear array's bounds (tests/gpu_helpers.weight_tol: FP32 rounding of
+  the snapshots and of the FFTs, FP64 covariance and factorisation; the mixed forms' BF16
+  product precision), SINR loss <= 0.1 dB.
+* outputs against the GPU's own weights on the oracle's snapshots: the FFT rounding above in
+  every window beam, relative to the element-space snapshot norm, summed with |w|, plus
+  1e-6 ||w|| ||y|| for the apply.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from gpu_helpers import EPS32, log, snapshot_dynamic_range, weight_tol
+from oracle import upa
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    _t.cuda.set_device(0)
+    return _t
+
+
+@pytest.fixture(scope="module")
+def wb():
+    import paper_2508_11790_amd as _wb
+    return _wb
+
+
+def _plan(wb, cfg, sc):
+    return wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, cfg.T,
+                   int(np.max(sc.win_z * sc.win_x)), beta=cfg.beta, d_over_lambda=cfg.dl,
+                   half_bin=cfg.half_bin)
+
+
+def _oracle(sc, x32, subbands=None):
+    cfg = sc.cfg
+    return upa.upa_windowed_mvdr(x32.astype(np.complex128), Nz=cfg.Nz, Mz=cfg.Mz, Mx=cfg.Mx,
+                                 K=cfg.K, L=cfg.L, Lt=cfg.Lt, az=sc.target_az, el=sc.target_el,
+                                 win_z=sc.win_z, win_x=sc.win_x, delta=cfg.delta, beta=cfg.beta,
+                                 dl=cfg.dl, half_bin=cfg.half_bin, subbands=subbands,
+                                 return_windows=True)
+
+
+def _windowed_interference(sc, k, rows):
+    cfg = sc.cfg
+    ratio = oracle.subband_freq_ratio(cfg.K, cfg.beta, cfg.half_bin)[k]
+    Rin = cfg.noise_var * np.eye(cfg.N, dtype=np.complex128)
+    for az, el, inr in zip(sc.jammer_az, sc.jammer_el, sc.jammer_inr):
+        omz, omx = upa.upa_spatial_frequencies(az, el, ratio, cfg.dl)
+        a = upa.upa_steering(cfg.Nz, cfg.Nx, omz, omx)
+        Rin += inr * np.outer(a, a.conj())
+    Dw = upa.upa_dft_matrix(cfg.Nz, cfg.Nx, cfg.Mz, cfg.Mx)[np.asarray(rows)]
+    return Dw @ Rin @ Dw.conj().T
+
+
+def _compare(sc, ref, res, subbands=None, plain=False, unit=EPS32, check_sinr=True, x32=None):
+    cfg = sc.cfg
+    T, K = cfg.T, cfg.K
+    ks = list(range(K)) if subbands is None else list(subbands)
+    # largest element-space test snapshot norm per subband: the FP32 FFTs' rounding in every
+    # beam is relative to it, not to the window's own snapshot norm
+    Xt = oracle.channelize_bins(x32.astype(np.complex128), K, ks, cfg.half_bin)
+    xnorm = np.max(np.linalg.norm(Xt[:, cfg.L:cfg.L + cfg.Lt, :], axis=0), axis=0) \
+        if cfg.Lt else np.zeros(len(ks))
+    fft_u = 4 * (math.log2(cfg.Mx) + cfg.Nz + 1) * EPS32
+    starts = res["starts"].cpu().numpy()
+    w_g = res["weights"].cpu().numpy().astype(np.complex128)
+    z_g = res["out"].cpu().numpy().astype(np.complex128)
+    info = res["info"].cpu().numpy()
+    assert np.all(info[:, ks] == 0), "factorisation failures reported"
+    assert np.array_equal(starts[:, ks], ref["start"]), "window starts differ"
+    dr = snapshot_dynamic_range(sc)
+    worst = dict(w=0.0, ratio=0.0, z=0.0, loss=0.0)
+    for ik, k in enumerate(ks):
+        for t in range(T):
+            W = int(sc.win_z[t] * sc.win_x[t])
+            wo, wg = ref["w"][t, ik, :W], w_g[t, k, :W]
+            assert np.all(w_g[t, k, W:] == 0), "weights not zero padded"
+            kappa = float(np.linalg.cond(ref["R"][t][ik]))
+            err = oracle.rel_weight_error(wg, wo)
+            tol = weight_tol(kappa, plain, dr, unit)
+            assert err <= tol, f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
+            worst["w"] = max(worst["w"], err)
+            worst["ratio"] = max(worst["ratio"], err / tol)
+            Yt = ref["Yw"][t][ik][:, cfg.L:cfg.L + cfg.Lt]
+            if cfg.Lt:
+                # apply step: GPU output vs the GPU's own weights on the oracle's test snapshots;
+                # bound: the snapshots' FFT rounding, fft_u ||x_b|| per beam, summed with |w|,
+                # plus 1e-6 ||w|| max ||y|| for the apply's own arithmetic
+                zc = wg.conj() @ Yt
+                bound = fft_u * np.sum(np.abs(wg)) * xnorm[ik] + \
+                    1e-6 * np.linalg.norm(wg) * np.max(np.linalg.norm(Yt, axis=0))
+                dz = float(np.max(np.abs(z_g[t, k] - zc)) / bound)
+                assert dz <= 1.0, f"pair t={t} k={k}: output error {dz:.3e} of its bound"
+                worst["z"] = max(worst["z"], dz)
+            if check_sinr and sc.jammer_az.size:
+                Rin = _windowed_interference(sc, k, ref["rows"][t][ik])
+                loss = abs(oracle.sinr_loss_db(wg, wo, ref["a"][t, ik, :W], Rin))
+                assert loss <= 0.1, f"pair t={t} k={k}: SINR loss {loss:.3e} dB"
+                worst["loss"] = max(worst["loss"], loss)
+    return worst
+
+
+def _run(torch, wb, cfg, pair=None, form="fused", subbands=None, plain_bound=False, unit=EPS32,
+         check_sinr=True):
+    sc = scenes.make_upa_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    log(f"upa {cfg.name} Nz{cfg.Nz} Nx{cfg.Nx} Mz{cfg.Mz} Mx{cfg.Mx} K{cfg.K} L{cfg.L} "
+        f"Lt{cfg.Lt} T{cfg.T} pair={pair} form={form}")
+    plan = _plan(wb, cfg, sc)
+    if pair is not None:
+        chan, beam, _, _ = plan.tuning
+        plan.set_tuning(chan, beam, pair, 1)
+    x = torch.from_numpy(x32).cuda()
+    res = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
+                            cfg.delta, form=form)
+    torch.cuda.synchronize()
+    ref = _oracle(sc, x32, subbands)
+    if form != "fused":
+        info = res["info"].cpu().numpy()
+        assert np.all((info & ~wb.INFO_ROUTED) == 0), "factorisation failures"
+        res = dict(res)
+        res["info"] = torch.zeros_like(res["info"])
+    st = _compare(sc, ref, res, subbands, plain_bound, unit, check_sinr, x32)
+    log(f"  {st}")
+    plan.close()
+    return st
+
+
+# ----------------------------------------------------------------------------- stages
+
+BEAM_SHAPES = [
+    dict(Nz=4, Nx=32, Mz=8, Mx=64, K=8, L=29, Lt=8),     # paper grid, ragged snapshot tiles
+    dict(Nz=2, Nx=8, Mz=4, Mx=16, K=4, L=6, Lt=3),
+    dict(Nz=3, Nx=5, Mz=4, Mx=8, K=2, L=4, Lt=1),        # Nz not a power of two, Nx > Mx / 2
+    dict(Nz=1, Nx=16, Mz=1, Mx=32, K=2, L=5, Lt=5),      # one row
+    dict(Nz=8, Nx=1, Mz=16, Mx=2, K=2, L=7, Lt=2),       # one column
+    dict(Nz=4, Nx=4, Mz=4, Mx=4, K=4, L=3, Lt=2),        # no zero padding
+    dict(Nz=2, Nx=300, Mz=2, Mx=1024, K=2, L=3, Lt=2),   # widest x-FFT of a two-row array
+]
+
+
+@pytest.mark.parametrize("sh", BEAM_SHAPES, ids=lambda d: f"{d['Nz']}x{d['Nx']}_{d['Mz']}x{d['Mx']}")
+def test_planar_beamspace_matches_oracle(torch, wb, sh):
+    log(f"upa beamspace {sh}")
+    N, M = sh["Nz"] * sh["Nx"], sh["Mz"] * sh["Mx"]
+    plan = wb.Plan(N, M, sh["K"], sh["L"], sh["Lt"], 1, 1)
+    B = sh["L"] + sh["Lt"]
+    r = np.random.default_rng(3)
+    X = (r.standard_normal((sh["K"], B, N)) + 1j * r.standard_normal((sh["K"], B, N))).astype(np.complex64)
+    Y = plan.beamspace_upa(torch.from_numpy(X).cuda(), sh["Nz"], sh["Mz"])
+    torch.cuda.synchronize()
+    Yg = Y.cpu().numpy().astype(np.complex128)
+    bound = 4 * (math.log2(sh["Mx"]) + sh["Nz"] + 1) * EPS32
+    for k in range(sh["K"]):
+        ref = upa.upa_beamspace(X[k].T.astype(np.complex128), sh["Nz"], sh["Mz"], sh["Mx"])  # [M, B]
+        err = np.abs(Yg[k] - ref) / np.linalg.norm(X[k].astype(np.complex128), axis=1)[None, :]
+        assert float(err.max()) <= bound, (k, float(err.max()), bound)
+    plan.close()
+
+
+@pytest.mark.parametrize("half_bin", [False, True])
+def test_planar_steering_matches_oracle(torch, wb, half_bin):
+    Nz, Nx, Mz, Mx, K = 4, 32, 8, 64, 16
+    plan = wb.Plan(Nz * Nx, Mz * Mx, K, 4, 4, 6, 64, half_bin=half_bin)
+    rng = np.random.default_rng(8)
+    az = np.deg2rad(rng.uniform(-70, 70, size=6))
+    el = np.deg2rad(np.array([-60.0, -20.0, 0.0, 15.0, 45.0, 70.0]))
+    wz = np.array([1, 2, 4, 8, 3, 8], dtype=np.int32)
+    wx = np.array([1, 4, 8, 8, 5, 2], dtype=np.int32)
+    starts, abar = plan.steer_upa(Nz, Mz, az, el, wz, wx)
+    torch.cuda.synchronize()
+    st, ab = starts.cpu().numpy(), abar.cpu().numpy()
+    ratio = oracle.subband_freq_ratio(K, 0.2, half_bin)
+    for t in range(6):
+        for k in range(K):
+            uz, ux = upa.upa_beam_position(az[t], el[t], ratio[k], Mz, Mx)
+            sz, sx = oracle.window_start(uz, int(wz[t])), oracle.window_start(ux, int(wx[t]))
+            assert (st[t, k, 0], st[t, k, 1]) == (sz, sx)
+            rows = upa.upa_window_rows(sz, sx, int(wz[t]), int(wx[t]), Mz, Mx)
+            omz, omx = upa.upa_spatial_frequencies(az[t], el[t], ratio[k])
+            a = upa.upa_beamspace(upa.upa_steering(Nz, Nx, omz, omx)[:, None], Nz, Mz, Mx)[rows, 0]
+            W = int(wz[t] * wx[t])
+            assert np.max(np.abs(ab[t, k, :W] - a)) < 1e-12
+            assert np.all(ab[t, k, W:] == 0)
+    plan.close()
+
+
+# ----------------------------------------------------------------------------- beamformer
+
+SMALL = scenes.UPA_SMALL
+PAPER_K16 = scenes.UPA.replace(name="upa_k16", K=16, seed=16)
+RAGGED = scenes.UpaSceneConfig(name="upa_ragged", Nz=3, Nx=5, Mz=4, Mx=8, K=4, L=37, Lt=11, T=4,
+                               windows=((3, 2), (1, 1), (4, 8), (2, 5)), n_jammers=1,
+                               target_dir_deg=((-62.0, 55.0), (0.0, 0.0), (48.0, -58.0),
+                                               (71.0, 8.0)),
+                               jammer_dir_deg=((20.0, -20.0),), seed=23)
+
+
+@pytest.mark.parametrize("pair", ["mfma", "wave", "block", "resident"])
+def test_planar_pair_kernels_match_oracle(torch, wb, pair):
+    _run(torch, wb, SMALL, pair=pair)
+
+
+@pytest.mark.parametrize("pair", [None, "mfma", "block"])
+def test_planar_paper_grid_matches_oracle(torch, wb, pair):
+    # 4 x 32 array, 8 x 64 beams, windows 2x4 / 4x4 / 4x8, 20 targets, 16 subbands
+    _run(torch, wb, PAPER_K16, pair=pair)
+
+
+@pytest.mark.parametrize("pair", ["mfma", "block", "wave", "resident"])
+def test_planar_ragged_and_wrapping_windows(torch, wb, pair):
+    # Nz = 3, windows wrapping both axes, a full-grid 4 x 8 window, a 1 x 1 window, L = 37
+    _run(torch, wb, RAGGED, pair=pair)
+
+
+def test_planar_full_workload_sampled_subbands(torch, wb):
+    # the benchmark's configuration (128 subbands, 20 targets) with its timed pair kernel,
+    # checked on the subbands at both ends and the middle
+    _run(torch, wb, scenes.UPA, subbands=[0, 1, 63, 64, 126, 127])
+
+
+@pytest.mark.parametrize("form", ["mixed", "mixed_bf16"])
+def test_planar_mixed_forms(torch, wb, form):
+    unit = 2.0 ** -16 if form == "mixed" else 2.0 ** -8
+    _run(torch, wb, PAPER_K16, form=form, plain_bound=True, unit=unit,
+         check_sinr=(form == "mixed"))
+
+
+def test_one_row_planar_equals_linear_path(torch, wb):
+    # Nz = Mz = 1 at elevation 0 is the linear array: both GPU paths against each other
+    cfg = scenes.UPA_SMALL.replace(Nz=1, Nx=16, Mz=1, Mx=32, windows=((1, 5), (1, 3)),
+                                   target_dir_deg=((14.0, 0.0), (-31.0, 0.0)),
+                                   jammer_dir_deg=((40.0, 0.0),))
+    sc = scenes.make_upa_scene(cfg)
+    x = torch.from_numpy(sc.x.astype(np.complex64)).cuda()
+    plan = _plan(wb, cfg, sc)
+    plan.set_tuning(12, 12, "block", 1)
+    r2 = plan.beamform_upa(x, 1, 1, sc.target_az, sc.target_el, sc.win_z, sc.win_x, cfg.delta)
+    r1 = plan.beamform(x, sc.target_az, sc.win_x, cfg.delta, form="fused")
+    torch.cuda.synchronize()
+    assert np.array_equal(r2["starts"].cpu().numpy()[:, :, 1], r1["starts"].cpu().numpy())
+    w1, w2 = r1["weights"].cpu().numpy(), r2["weights"].cpu().numpy()
+    assert np.max(np.abs(w1 - w2)) <= 1e-5 * np.max(np.abs(w1))
+    plan.close()
+
+
+def test_linear_and_planar_calls_interleave(torch, wb):
+    # the per-call descriptor changes between the two geometries on one plan and stream
+    cfg = PAPER_K16
+    sc = scenes.make_upa_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    x = torch.from_numpy(x32).cuda()
+    plan = _plan(wb, cfg, sc)
+    plan.set_tuning(12, 12, "block", 1)
+    win = np.full(cfg.T, 9, dtype=np.int32)
+    kw = dict(form="fused")
+    a = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
+                          cfg.delta, **kw)
+    a = {k: v.clone() for k, v in a.items()}
+    lin = plan.beamform(x, sc.target_az, win, cfg.delta, **kw)
+    lin = {k: v.clone() for k, v in lin.items()}
+    b = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
+                          cfg.delta, **kw)
+    torch.cuda.synchronize()
+    for key in ("out", "weights", "starts"):
+        assert torch.equal(a[key], b[key]), key
+    lref = plan.beamform(x, sc.target_az, win, cfg.delta, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(lin["weights"], lref["weights"])
+    plan.close()
+
+
+def test_planar_bad_arguments(torch, wb):
+    plan = wb.Plan(128, 512, 8, 16, 8, 4, 32)
+    x = torch.zeros((128, 24 * 8), dtype=torch.complex64, device="cuda")
+    az, el = [0.1, 0.2], [0.0, 0.3]
+    good = dict(win_z=[2, 4], win_x=[4, 8])
+
+    def call(nz=4, mz=8, form="fused", **kw):
+        args = dict(good)
+        args.update(kw)
+        return plan.beamform_upa(x, nz, mz, az, el, args["win_z"], args["win_x"], 10.0, form=form)
+
+    for bad in (dict(nz=3), dict(mz=6), dict(mz=2), dict(nz=2, mz=256), dict(nz=1, mz=1),
+                dict(win_z=[9, 1]), dict(win_x=[4, 65]), dict(win_z=[4, 8], win_x=[8, 8]),
+                dict(win_z=[0, 1])):
+        with pytest.raises(wb.WbmError):
+            call(**bad)
+    for form in ("plain", "graph"):
+        with pytest.raises(wb.WbmError) as e:
+            call(form=form)
+        assert e.value.status == 5
+    with pytest.raises(wb.WbmError):
+        plan.beamform_upa(x, 4, 8, [float("nan"), 0.0], el, [2, 2], [4, 4], 10.0)
+    call()   # the good call still works after the rejected ones
+    torch.cuda.synchronize()
+    plan.close()
