@@ -1085,15 +1085,32 @@ hipError_t enqueue_upa_windows(wbm_plan* p, const float2* x, int T, int sumW,
                                    p->logTB, p->nbt, st);
 }
 
-// First planar-array call of a plan: the pair kernel of the fused form is timed on these
-// windows (best of three after a warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0
-// keeps the matrix-core kernel.
+// First planar-array call of a plan: the channelizer tile (unless already tuned or pinned)
+// and the pair kernel of the fused form are timed on this call's data and windows (best of
+// three after a warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0 keeps the
+// defaults (tile 2^12, matrix-core kernel).
 hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::UpaGeom& g,
                     double loading, hipStream_t st) {
   p->upa_tuned = true;
   const char* env = std::getenv("WBM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
-  hipError_t e = enqueue_upa_windows(p, x, T, sumW, g, st);
+  hipError_t e = hipSuccess;
+  if (!p->tuned) {
+    float best_c = 1e30f;
+    int chan = p->chan_logtile;
+    for (int lt = 11; lt <= 13; ++lt) {
+      float ms;
+      p->chan_logtile = lt;
+      e = time_best([&]() { return enqueue_channelize(p, x, st); }, st, &ms);
+      if (e != hipSuccess) return e;
+      if (ms < best_c) {
+        best_c = ms;
+        chan = lt;
+      }
+    }
+    p->chan_logtile = chan;
+  }
+  e = enqueue_upa_windows(p, x, T, sumW, g, st);
   if (e != hipSuccess) return e;
   wbm::PairArgs pa = pair_args(p, T, sumW, loading);
   pa.abar = p->abar;

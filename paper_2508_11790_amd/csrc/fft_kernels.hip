@@ -573,15 +573,17 @@ __global__ __launch_bounds__(fft_threads(LOGMX, kUpaLogTile)) void k_beamspace_u
       }
     }
     if (Yw) {
-      // snapshot-fastest runs of min(TB, TB2) within each window row; snapshots past B (zero
-      // inputs) fill the padding of the last tile block
-      for (int idx = threadIdx.x; idx < (sumW << logTB2); idx += F::threads) {
-        const int blo = idx & ((1 << lw) - 1), rest = idx >> lw;
-        const int r = rest % sumW, bq = rest / sumW;
-        const int bb = (bq << lw) | blo, b = b0 + bb;
-        if (b < nbt * TB)
-          Yw[(((int64_t)k * nbt + (b >> logTB)) * sumW + r) * TB + (b & (TB - 1))] =
-              beam(s_bin[r], bb);
+      // per run of 2^lw = min(TB, TB2) snapshots: the [sumW][2^lw] block it fills, written
+      // contiguously (window row, then snapshot); snapshots past B (zero inputs) fill the
+      // padding of the last tile block
+      for (int bq = 0; bq < (TB2 >> lw); ++bq) {
+        const int b1 = b0 + (bq << lw);
+        if (b1 >= nbt * TB) break;
+        float2* dst = Yw + ((int64_t)k * nbt + (b1 >> logTB)) * sumW * TB + (b1 & (TB - 1));
+        for (int idx = threadIdx.x; idx < (sumW << lw); idx += F::threads) {
+          const int r = idx >> lw, blo = idx & ((1 << lw) - 1);
+          dst[r * TB + blo] = beam(s_bin[r], (bq << lw) | blo);
+        }
       }
     }
     __syncthreads();   // the next tile's first pass overwrites lds
