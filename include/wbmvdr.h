@@ -248,8 +248,10 @@ wbm_status wbm_steer(wbm_plan* plan, const double* az_rad, const int32_t* win, i
  *   az_rad, el_rad  host [T] azimuth and elevation of each target from broadside (radians).
  *   win_z, win_x    host [T] window rows Wz and columns Wx, Wz * Wx <= w_max.
  *   form            WBM_FORM_FUSED, WBM_FORM_MIXED or WBM_FORM_MIXED_BF16 (others:
- *                   WBM_ERR_UNSUPPORTED).  The fused form's pair kernel is timed on the first
- *                   call of the plan (WBM_AUTOTUNE=0: the matrix-core kernel).
+ *                   WBM_ERR_UNSUPPORTED).  The first fused call of a plan times the pair
+ *                   kernels on its windows, and the channelizer tiles if the plan is neither
+ *                   tuned nor pinned (WBM_AUTOTUNE=0: tile 2^12, the matrix-core kernel);
+ *                   wbm_plan_set_tuning pins both.
  *   weights         device [T][K][w_max] or NULL, in window-cell order.
  *   starts          device [T][K][2] int32 or NULL: (s_z, s_x) of every pair.
  *   out, info       as for wbm_beamform. */
