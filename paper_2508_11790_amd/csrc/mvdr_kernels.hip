@@ -510,19 +510,28 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const
   const int TB = 1 << a.logTB;
   const float2* base = Yw + (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
   if (aligned) {
-    const float2* cb = base + (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1));
+    // the chunk base is uniform; each element adds a 32-bit byte offset, kept opaque (empty
+    // register constraint) so that the compiler does not hoist PRE 64-bit addresses out of
+    // the chunk loops, where they would be spilled to scratch
+    const char* cb = reinterpret_cast<const char*>(
+        base + (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1)));
     const int rem = lim - c0;
 #pragma unroll
     for (int m = 0; m < PRE; ++m) {
       pre[m] = make_float2(0.f, 0.f);
-      if (map[m] >= 0 && (map[m] & 255) < rem) pre[m] = cb[off[m]];
+      uint32_t o = (uint32_t)off[m] << 3;
+      asm volatile("" : "+v"(o));
+      if (map[m] >= 0 && (map[m] & 255) < rem)
+        pre[m] = *reinterpret_cast<const float2*>(cb + o);
     }
   } else {
 #pragma unroll
     for (int m = 0; m < PRE; ++m) {
       pre[m] = make_float2(0.f, 0.f);
-      const int i = map[m] >> 8, b = c0 + (map[m] & 255);
-      if (map[m] >= 0 && b < lim)
+      int mm = map[m];
+      asm volatile("" : "+v"(mm));   // as above: no hoisted per-element addresses
+      const int i = mm >> 8, b = c0 + (mm & 255);
+      if (mm >= 0 && b < lim)
         pre[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
     }
   }
