@@ -85,7 +85,8 @@ typedef struct {
   int32_t k_sub;            /* K: power of two, 2 <= K <= 8192 */
   int32_t l_train;          /* L >= 1 training snapshots per subband */
   int32_t l_test;           /* Lt >= 0 test snapshots per subband */
-  int32_t max_targets;      /* T_max >= 1: capacity for targets per call */
+  int32_t max_targets;      /* T_max >= 1: capacity for targets per call;
+                               T_max * w_max * max(64, 8192 / M) * 8 < 2^32 */
   int32_t w_max;            /* 1 <= w_max <= 64, <= M: largest window width */
   int32_t flags;            /* WBM_HALF_BIN or 0 */
   double beta;              /* fractional bandwidth f_s / f_c, 0 <= beta < 2 */

@@ -768,6 +768,14 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   if (c.flags & ~WBM_HALF_BIN) return fail(WBM_ERR_ARG, "unknown flags");
   const int64_t B = (int64_t)c.l_train + c.l_test;
   if (B > 65535) return fail(WBM_ERR_ARG, "l_train + l_test must be <= 65535");
+  // the pair kernels address one chunk of a subband's window tiles with 32-bit byte offsets:
+  // at most max_targets * w_max rows of the largest snapshot tile block (or 64 snapshots)
+  {
+    const int64_t tb = std::max<int64_t>(64, (int64_t)1 << wbm::beamspace_tile_log(c.m_fft, 13));
+    if ((int64_t)c.max_targets * c.w_max * tb * 8 >= ((int64_t)1 << 32))
+      return fail(WBM_ERR_ARG, "max_targets * w_max too large for this m_fft (window tiles "
+                               "beyond 32-bit offsets)");
+  }
 
   int ndev = 0;
   hipError_t he = hipGetDeviceCount(&ndev);

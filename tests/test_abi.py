@@ -56,7 +56,8 @@ def _cfg(**kw):
 @pytest.mark.parametrize("bad", [dict(m_fft=24), dict(m_fft=8), dict(k_sub=12), dict(w_max=65),
                                  dict(w_max=0), dict(l_train=0), dict(n_elem=0), dict(flags=8),
                                  dict(beta=-0.1), dict(d_over_lambda=0.0), dict(max_targets=0),
-                                 dict(m_fft=16384, n_elem=16)])
+                                 dict(m_fft=16384, n_elem=16),
+                                 dict(max_targets=1 << 20, w_max=32)])
 def test_plan_create_rejects_bad_config(lib, bad):
     h = C.c_void_p()
     cfg = _cfg(**bad)

@@ -218,6 +218,11 @@ def test_planar_pair_kernels_match_oracle(torch, wb, pair):
     _run(torch, wb, SMALL, pair=pair)
 
 
+def test_planar_half_bin_subbands(torch, wb):
+    # subband centres of Eq. 1 (half-bin pre-twiddle) on the planar path
+    _run(torch, wb, SMALL.replace(name="upa_small_half_bin", half_bin=True, seed=31))
+
+
 @pytest.mark.parametrize("pair", [None, "mfma", "block"])
 def test_planar_paper_grid_matches_oracle(torch, wb, pair):
     # 4 x 32 array, 8 x 64 beams, windows 2x4 / 4x4 / 4x8, 20 targets, 16 subbands
