@@ -487,7 +487,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p4";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p5";
   return os.str();
 }
 
@@ -613,18 +613,18 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   }
   p->chan_logtile = chan;
   set_beam_tile(p, beam);
-  // threads per pair of the fused MVDR kernel, on the windows the chosen tile wrote
-  hipError_t e = enqueue_beamspace_windows(p, T, sumW, st);
-  if (e != hipSuccess) return e;
+  // pair kernel: each candidate timed in the whole fused sequence (channelize, windows, pair
+  // kernel), where it reads windows the spatial DFT has just written
+  hipError_t e = hipSuccess;
   float best_p = 1e30f;
-  const wbm::PairArgs pa = pair_args(p, T, sumW, loading);
   for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
     if (thr_c == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
     if (thr_c == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
     float ms;
+    p->pair_threads = thr_c;
     e = time_best([&]() {
-      return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
-                                    p->prof_info, thr_c, st);
+      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
+                           p->prof_info, st, 1);
     }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_p) {
@@ -1094,9 +1094,10 @@ hipError_t enqueue_upa_windows(wbm_plan* p, const float2* x, int T, int sumW,
 }
 
 // First planar-array call of a plan: the channelizer tile (unless already tuned or pinned)
-// and the pair kernel of the fused form are timed on this call's data and windows (best of
-// three after a warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0 keeps the
-// defaults (tile 2^12, matrix-core kernel).
+// and the pair kernel of the fused form are timed on this call's data (each pair-kernel
+// candidate with the channelizer and planar spatial DFT before it; best of three after a
+// warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0 keeps the defaults (tile 2^12,
+// matrix-core kernel).
 hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::UpaGeom& g,
                     double loading, hipStream_t st) {
   p->upa_tuned = true;
@@ -1118,8 +1119,6 @@ hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::Up
     }
     p->chan_logtile = chan;
   }
-  e = enqueue_upa_windows(p, x, T, sumW, g, st);
-  if (e != hipSuccess) return e;
   wbm::PairArgs pa = pair_args(p, T, sumW, loading);
   pa.abar = p->abar;
   float best = 1e30f;
@@ -1128,6 +1127,8 @@ hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::Up
     if (thr == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
     float ms;
     e = time_best([&]() {
+      hipError_t le = enqueue_upa_windows(p, x, T, sumW, g, st);
+      if (le != hipSuccess) return le;
       return wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, p->prof_out, p->prof_w, nullptr,
                                     p->prof_info, thr, st);
     }, st, &ms);

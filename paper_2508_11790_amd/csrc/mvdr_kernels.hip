@@ -105,23 +105,16 @@ __device__ __forceinline__ void tri_index(int e, int& i, int& j) {
   j = e - ii * (ii + 1) / 2;
 }
 
-// Workgroup -> (target, subband) of the pair kernels over subbands k0 .. k0 + kc - 1.
-// Workgroups go round-robin to the eight XCDs (workgroup id mod 8), so with kc a multiple of 8
-// XCD x takes subbands k0 + x, k0 + 8 + x, ..., all targets of a subband back to back (they
-// read the same window tile blocks through one L2), widest windows first (d.torder);
-// otherwise targets widest first, subbands fastest.  Either way the costly pairs are
-// dispatched first.
+// Workgroup -> (target, subband) of the pair kernels over subbands k0 .. k0 + kc - 1: targets
+// widest window first (d.torder), subbands fastest, so that workgroups, handed out in index
+// order, start every costly pair before any cheaper one (longest-processing-time order over
+// the whole grid; grouping the targets of a subband per XCD instead left the widest pairs of
+// late subbands to the tail).
 __device__ __forceinline__ void pair_of_block(const PairArgs& a, const DevDesc& d, int& t, int& k) {
   const int p = blockIdx.x;
   const int kc = a.kc > 0 ? a.kc : a.K;
-  if ((kc & 7) == 0) {
-    const int slot = p >> 3;
-    t = d.torder[slot % a.T];
-    k = a.k0 + ((slot / a.T) << 3) + (p & 7);
-  } else {
-    t = d.torder[p / kc];
-    k = a.k0 + p % kc;
-  }
+  t = d.torder[p / kc];
+  k = a.k0 + p % kc;
 }
 
 // Snapshot b of window row i of pair (t, k).
