@@ -31,7 +31,7 @@ from .bmvdr import (beam_output, channelize, channelize_bins, mvdr_weights, samp
 
 __all__ = ["upa_direction_cosines", "upa_spatial_frequencies", "upa_steering",
            "upa_dft_matrix", "upa_beamspace", "upa_beam_position", "upa_window_rows",
-           "upa_lift_correlator", "upa_windowed_mvdr", "upa_full_mvdr"]
+           "upa_lift_correlator", "upa_beam_pattern", "upa_windowed_mvdr", "upa_full_mvdr"]
 
 
 def upa_direction_cosines(az: float, el: float):
@@ -94,6 +94,18 @@ def upa_lift_correlator(w: np.ndarray, rows: Sequence[int], Nz: int, Nx: int, Mz
     """Antenna-space equivalent correlator c^ = D^H S^T c~  (Eq. 21)."""
     D = upa_dft_matrix(Nz, Nx, Mz, Mx)
     return D[np.asarray(rows)].conj().T @ w
+
+
+def upa_beam_pattern(c: np.ndarray, Nz: int, omegas) -> np.ndarray:
+    """Cosine similarity |<c, a(Omega_z, Omega_x)>| / (||c|| ||a||) over (Omega_z, Omega_x)
+    pairs (Eq. 22 with the planar steering vector of Eq. 6), one value per pair."""
+    N = c.shape[0]
+    Nx = N // Nz
+    out = np.empty(len(omegas))
+    for q, (omz, omx) in enumerate(omegas):
+        a = upa_steering(Nz, Nx, float(omz), float(omx))
+        out[q] = abs(np.vdot(c, a)) / (np.linalg.norm(c) * np.linalg.norm(a))
+    return out
 
 
 def upa_windowed_mvdr(x: np.ndarray, *, Nz: int, Mz: int, Mx: int, K: int, L: int, Lt: int,

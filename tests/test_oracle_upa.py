@@ -197,3 +197,34 @@ def test_jammer_pushed_to_the_noise_floor():
         assert jnr < 2.0
         if jnr_conv > 10.0:
             assert jnr < jnr_conv / 100.0
+
+
+def test_lift_of_separable_window_weights_is_kronecker_of_1d_lifts():
+    # c~ = u kron v over (ix_w, iz_w) lifts to (lift_x u) kron (lift_z v), the 1-D lifts of Eq. 21
+    Nz, Nx, Mz, Mx, Wz, Wx, sz, sx = 4, 16, 8, 32, 3, 5, 6, 29
+    u, v = _rand((Wx,), 8), _rand((Wz,), 9)
+    rows = upa.upa_window_rows(sz, sx, Wz, Wx, Mz, Mx)
+    c = upa.upa_lift_correlator(np.kron(u, v), rows, Nz, Nx, Mz, Mx)
+    cx = oracle.lift_correlator(u, oracle.window_bins(sx, Wx, Mx), Mx, Nx)
+    cz = oracle.lift_correlator(v, oracle.window_bins(sz, Wz, Mz), Mz, Nz)
+    assert np.max(np.abs(c - np.kron(cx, cz))) < 1e-12
+
+
+def test_planar_beam_pattern_of_kronecker_correlator_is_product_of_1d_patterns():
+    # |<cx kron cz, ax kron az>| = |<cx, ax>| |<cz, az>| and the norms multiply
+    Nz, Nx = 4, 12
+    cx, cz = _rand((Nx,), 10), _rand((Nz,), 11)
+    rng = np.random.default_rng(12)
+    om = rng.uniform(-math.pi, math.pi, size=(20, 2))
+    B2 = upa.upa_beam_pattern(np.kron(cx, cz), Nz, om)
+    Bx = oracle.beam_pattern(cx, om[:, 1])
+    Bz = oracle.beam_pattern(cz, om[:, 0])
+    assert np.max(np.abs(B2 - Bx * Bz)) < 1e-12
+
+
+def test_planar_matched_filter_pattern_peaks_at_its_direction():
+    Nz, Nx = 4, 32
+    a0 = upa.upa_steering(Nz, Nx, 0.7, -1.1)
+    B = upa.upa_beam_pattern(a0, Nz, [(0.7, -1.1), (0.7 + 2 * math.pi / Nz, -1.1),
+                                      (0.7, -1.1 + 2 * math.pi / Nx)])
+    assert abs(B[0] - 1.0) < 1e-12 and B[1] < 1e-12 and B[2] < 1e-12   # first nulls
