@@ -275,6 +275,30 @@ wbm_status wbm_steer_upa(wbm_plan* plan, int32_t nz, int32_t mz, const double* a
                          const double* el_rad, const int32_t* win_z, const int32_t* win_x,
                          int32_t T, int32_t* starts, wbm_c64* abar, void* stream);
 
+/* Planar lifted correlators (Eq. 21 with D = D_h^T kron D_v): every pair's window weights
+ * mapped back to the Nz x Nx elements,
+ *   c^[ix Nz + iz] = M^-1/2 sum_i c~_i exp(+j 2 pi (mz_i iz / Mz + mx_i ix / Mx)),
+ * window cell i = ix_w Wz + iz_w at beam (mz_i, mx_i) = ((s_z + iz_w) mod Mz, (s_x + ix_w) mod Mx).
+ *   weights device [T][K][w_max] wbm_c32 (as wbm_beamform_upa writes them, zero past Wz * Wx).
+ *   starts  device [T][K][2] int32 (s_z, s_x), as wbm_beamform_upa writes them.
+ *   win_z   device [T] int32: each target's window rows Wz.
+ *   c_hat   device [T][K][N] wbm_c32, written.  Apply it with wbm_apply_lifted.
+ * Errors: WBM_ERR_ARG for NULL pointers or T outside [1, max_targets], WBM_ERR_SHAPE for a
+ * geometry outside the planar limits. */
+wbm_status wbm_lift_upa(wbm_plan* plan, const wbm_c32* weights, const int32_t* starts,
+                        int32_t nz, int32_t mz, const int32_t* win_z, int32_t T, wbm_c32* c_hat,
+                        void* stream);
+
+/* Planar beam pattern (Eq. 22 with a = a_x(Omega_x) kron a_z(Omega_z), Eq. 6): for every
+ * correlator and direction, |<c, a>| / (||c|| ||a||).
+ *   c       device [pairs][N] wbm_c32 (element (iz, ix) at ix Nz + iz), N <= 4096.
+ *   omega   device [Q][2] double: (Omega_z, Omega_x) per direction.
+ *   pattern device [pairs][Q] float, written.
+ * Errors: WBM_ERR_ARG for NULL pointers or pairs / Q < 1, WBM_ERR_SHAPE when nz does not
+ * divide N, WBM_ERR_UNSUPPORTED for N > 4096. */
+wbm_status wbm_beam_pattern_upa(wbm_plan* plan, const wbm_c32* c, int32_t pairs, int32_t nz,
+                                const double* omega, int32_t Q, float* pattern, void* stream);
+
 /* Full-dimensional element-space MVDR per subband (Sec. II-B, Eq. 11-13): the
  * comparison method.  R = (1/L) sum_{b<L} X_b X_b^H + loading I_N (N x N, FP64
  * accumulation), c_t = R^-1 a_t / (a_t^H R^-1 a_t) with a_t the element steering

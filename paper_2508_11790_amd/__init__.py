@@ -334,6 +334,39 @@ class Plan:
                                              _ptr(starts), _ptr(abar), _stream(stream)))
         return starts, abar
 
+    def lift_upa(self, weights, starts, nz: int, mz: int, win_z, c_hat=None, stream=None):
+        """Planar lifted correlators (Eq. 21): weights [T, K, w_max], starts [T, K, 2] int32 (as
+        beamform_upa returns them), win_z [T] -> c_hat [T, K, N] complex64."""
+        torch = _torch()
+        T = int(weights.shape[0])
+        _check_tensor(weights, "weights", (T, self.K, self.w_max), torch.complex64, self.device)
+        _check_tensor(starts, "starts", (T, self.K, 2), torch.int32, self.device)
+        wz = torch.as_tensor(np.asarray(win_z, dtype=np.int32).ravel()).to(self.device)
+        if wz.numel() != T:
+            raise ValueError("win_z must have one entry per target")
+        if c_hat is None:
+            c_hat = torch.empty((T, self.K, self.N), dtype=torch.complex64, device=self.device)
+        _check_tensor(c_hat, "c_hat", (T, self.K, self.N), torch.complex64, self.device)
+        _lib.check(_lib.load().wbm_lift_upa(self._h, _ptr(weights), _ptr(starts), int(nz),
+                                            int(mz), _ptr(wz), T, _ptr(c_hat), _stream(stream)))
+        return c_hat
+
+    def beam_pattern_upa(self, c, nz: int, omega, pattern=None, stream=None):
+        """Planar beam patterns (Eq. 22): c [..., N] complex64 correlators, omega [Q, 2] float64
+        (Omega_z, Omega_x) on the device -> pattern [..., Q] float32."""
+        torch = _torch()
+        if c.dtype != torch.complex64 or c.shape[-1] != self.N or not c.is_contiguous():
+            raise ValueError(f"c must be contiguous complex64 [..., {self.N}]")
+        Q = int(omega.shape[0]) if omega.dim() == 2 else -1
+        _check_tensor(omega, "omega", (Q, 2), torch.float64, self.device)
+        pairs = int(c.numel() // self.N)
+        if pattern is None:
+            pattern = torch.empty((*c.shape[:-1], Q), dtype=torch.float32, device=self.device)
+        _check_tensor(pattern, "pattern", (*c.shape[:-1], Q), torch.float32, self.device)
+        _lib.check(_lib.load().wbm_beam_pattern_upa(self._h, _ptr(c), pairs, int(nz), _ptr(omega),
+                                                    Q, _ptr(pattern), _stream(stream)))
+        return pattern
+
     STAGES = ("steer", "channelize", "beamspace", "mvdr")
 
     def stage_times(self, x, az_rad, win, loading: float, reps: int = 20, stream=None):

@@ -39,7 +39,7 @@ EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes",
            "wbm_mlp_create", "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
            "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
            "wbm_beam_pattern", "wbm_range_doppler", "wbm_beamform_upa", "wbm_beamspace_upa",
-           "wbm_steer_upa", "wbm_status_str", "wbm_last_error", "wbm_version")
+           "wbm_steer_upa", "wbm_lift_upa", "wbm_beam_pattern_upa", "wbm_status_str", "wbm_last_error", "wbm_version")
 MLP_PARAMS = 25090
 PROFILE_BINS = 64
 
@@ -86,6 +86,8 @@ def load() -> C.CDLL:
     lib.wbm_beamform_upa.argtypes = [P, P, I32, I32, P, P, P, P, I32, D, I32, P, P, P, P, P]
     lib.wbm_beamspace_upa.argtypes = [P, P, I32, I32, P, P]
     lib.wbm_steer_upa.argtypes = [P, I32, I32, P, P, P, P, I32, P, P, P]
+    lib.wbm_lift_upa.argtypes = [P, P, P, I32, I32, P, I32, P, P]
+    lib.wbm_beam_pattern_upa.argtypes = [P, P, I32, I32, P, I32, P, P]
     lib.wbm_status_str.argtypes = [I32]
     lib.wbm_status_str.restype = C.c_char_p
     lib.wbm_last_error.argtypes = []
@@ -97,7 +99,8 @@ def load() -> C.CDLL:
                  "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
                  "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
                  "wbm_beam_pattern", "wbm_range_doppler", "wbm_beamform_upa",
-                 "wbm_beamspace_upa", "wbm_steer_upa"):
+                 "wbm_beamspace_upa", "wbm_steer_upa", "wbm_lift_upa",
+                 "wbm_beam_pattern_upa"):
         getattr(lib, name).restype = I32
     _lib = lib
     return lib

@@ -915,6 +915,40 @@ wbm_status wbm_beam_pattern(wbm_plan* p, const wbm_c32* c, int32_t pairs, const 
   return WBM_OK;
 }
 
+wbm_status wbm_lift_upa(wbm_plan* p, const wbm_c32* weights, const int32_t* starts, int32_t nz,
+                        int32_t mz, const int32_t* win_z, int32_t T, wbm_c32* c_hat,
+                        void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!weights || !starts || !win_z || !c_hat)
+    return fail(WBM_ERR_ARG, "weights / starts / win_z / c_hat is NULL");
+  if ((s = check_upa_shape(p, nz, mz))) return s;
+  const wbm_config& c = p->cfg;
+  if (T < 1 || T > c.max_targets) return fail(WBM_ERR_ARG, "T outside [1, max_targets]");
+  WBM_HIP(wbm::launch_lift_upa(reinterpret_cast<const float2*>(weights), starts, win_z, T,
+                               c.k_sub, c.w_max, nz, c.n_elem / nz, mz, c.m_fft / mz, p->twM,
+                               reinterpret_cast<float2*>(c_hat),
+                               static_cast<hipStream_t>(stream)),
+          "planar lift launch");
+  return WBM_OK;
+}
+
+wbm_status wbm_beam_pattern_upa(wbm_plan* p, const wbm_c32* c, int32_t pairs, int32_t nz,
+                                const double* omega, int32_t Q, float* pattern, void* stream) {
+  wbm_status s = check_plan(p);
+  if (s) return s;
+  if (!c || !omega || !pattern) return fail(WBM_ERR_ARG, "c / omega / pattern is NULL");
+  if (pairs < 1 || Q < 1) return fail(WBM_ERR_ARG, "need pairs >= 1 and Q >= 1");
+  if (nz < 1 || p->cfg.n_elem % nz != 0)
+    return fail(WBM_ERR_SHAPE, "nz must divide n_elem");
+  if (p->cfg.n_elem > 4096) return fail(WBM_ERR_UNSUPPORTED, "beam patterns need N <= 4096");
+  WBM_HIP(wbm::launch_beam_pattern_upa(reinterpret_cast<const float2*>(c), pairs, nz,
+                                       p->cfg.n_elem / nz, omega, Q, pattern,
+                                       static_cast<hipStream_t>(stream)),
+          "planar beam pattern launch");
+  return WBM_OK;
+}
+
 wbm_status wbm_range_doppler(wbm_plan* p, const wbm_c32* z, int32_t T, int64_t z_stride,
                              const wbm_c32* chirp, int32_t Lp, int32_t R, int32_t P,
                              int32_t guard, int32_t train, double threshold_db, wbm_c32* work,

@@ -178,6 +178,109 @@ __global__ __launch_bounds__(256) void k_beam_pattern(const float2* __restrict__
   }
 }
 
+// Planar array (Eq. 21 with D = D_h^T kron D_v): c_hat[pair][ix Nz + iz] =
+// M^-1/2 sum_i w[pair][i] exp(+j 2 pi (mz_i iz / Mz + mx_i ix / Mx)), window cell
+// i = ix_w Wz + iz_w at beam (mz_i, mx_i) = ((s_z + iz_w) mod Mz, (s_x + ix_w) mod Mx), M = Mz Mx.
+// The phase index (mz iz Mx + mx ix Mz) mod M is exact in integers and reads the M-entry table;
+// weights past the pair's window are zero.  Grid: (ceil(N / 256), pairs = T K).
+__global__ __launch_bounds__(256) void k_lift_upa(const float2* __restrict__ w,
+                                                  const int* __restrict__ starts,
+                                                  const int* __restrict__ wz, int K, int wmax,
+                                                  int Nz, int Nx, int Mz, int Mx,
+                                                  const float2* __restrict__ tw,
+                                                  float2* __restrict__ c_hat) {
+  const int64_t pair = blockIdx.y;
+  const int N = Nz * Nx, M = Mz * Mx;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int ix = n / Nz, iz = n - ix * Nz;
+  const int sz = starts[2 * pair], sx = starts[2 * pair + 1];
+  const int Wz = wz[pair / K];
+  const float2* wp = w + pair * wmax;
+  double ax = 0.0, ay = 0.0;
+  for (int i = 0; i < wmax; ++i) {
+    const int ixw = i / Wz, izw = i - ixw * Wz;
+    const int mz = (sz + izw) & (Mz - 1), mx = (sx + ixw) & (Mx - 1);
+    const int q = (int)(((int64_t)mz * iz * Mx + (int64_t)mx * ix * Mz) & (M - 1));
+    const float2 e = tw[q];                      // exp(-j 2 pi q / M)
+    const float2 c = wp[i];
+    ax += (double)c.x * e.x + (double)c.y * e.y;   // c conj(e)
+    ay += (double)c.y * e.x - (double)c.x * e.y;
+  }
+  const double r = 1.0 / sqrt((double)M);
+  c_hat[pair * N + n] = make_float2((float)(ax * r), (float)(ay * r));
+}
+
+// Planar beam patterns (Eq. 22 with a = a_x kron a_z): pattern[p][q] =
+// |sum_{ix, iz} conj(c[ix Nz + iz]) e^{j (Omega_z iz + Omega_x ix)}| / (||c|| sqrt(N)) at
+// omega[q] = (Omega_z, Omega_x), FP64 with the phase recurrences along z inside x.  One
+// workgroup per correlator (staged in LDS), one thread per angle.
+__global__ __launch_bounds__(256) void k_beam_pattern_upa(const float2* __restrict__ c, int Nz,
+                                                          int Nx, const double* __restrict__ omega,
+                                                          int Q, float* __restrict__ pattern) {
+  __shared__ float2 cs[kBpMaxN];
+  __shared__ double red[256];
+  const int N = Nz * Nx;
+  const int64_t p = blockIdx.x;
+  const int tid = threadIdx.x;
+  double nn = 0.0;
+  for (int e = tid; e < N; e += 256) {
+    const float2 v = c[p * N + e];
+    cs[e] = v;
+    nn += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  red[tid] = nn;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  const double scale = 1.0 / (sqrt(red[0]) * sqrt((double)N));
+  for (int q = tid; q < Q; q += 256) {
+    double szs, szc, sxs, sxc;
+    sincos(omega[2 * q], &szs, &szc);
+    sincos(omega[2 * q + 1], &sxs, &sxc);
+    double xr = 1.0, xi = 0.0, ar = 0.0, ai = 0.0;
+    for (int ix = 0; ix < Nx; ++ix) {
+      double zr = 1.0, zi = 0.0, br = 0.0, bi = 0.0;
+      for (int iz = 0; iz < Nz; ++iz) {
+        const float2 v = cs[ix * Nz + iz];
+        br += (double)v.x * zr + (double)v.y * zi;   // conj(c) e^{j Omega_z iz}
+        bi += (double)v.x * zi - (double)v.y * zr;
+        const double t = zr * szc - zi * szs;
+        zi = zr * szs + zi * szc;
+        zr = t;
+      }
+      ar += br * xr - bi * xi;                       // times e^{j Omega_x ix}
+      ai += br * xi + bi * xr;
+      const double t = xr * sxc - xi * sxs;
+      xi = xr * sxs + xi * sxc;
+      xr = t;
+    }
+    pattern[p * Q + q] = (float)(sqrt(ar * ar + ai * ai) * scale);
+  }
+}
+
+hipError_t launch_lift_upa(const float2* w, const int* starts, const int* wz, int T, int K,
+                           int wmax, int Nz, int Nx, int Mz, int Mx, const float2* twM,
+                           float2* c_hat, hipStream_t s) {
+  const int pairs = T * K;
+  if (pairs < 1) return hipSuccess;
+  if (pairs > 65535 || (Mz & (Mz - 1)) != 0 || (Mx & (Mx - 1)) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lift_upa, dim3((Nz * Nx + 255) / 256, pairs), dim3(256), 0, s, w, starts,
+                     wz, K, wmax, Nz, Nx, Mz, Mx, twM, c_hat);
+  return hipGetLastError();
+}
+
+hipError_t launch_beam_pattern_upa(const float2* c, int pairs, int Nz, int Nx,
+                                   const double* omega, int Q, float* pattern, hipStream_t s) {
+  if (pairs < 1 || Q < 1) return hipSuccess;
+  if (Nz < 1 || Nx < 1 || Nz * Nx > kBpMaxN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_beam_pattern_upa, dim3(pairs), dim3(256), 0, s, c, Nz, Nx, omega, Q,
+                     pattern);
+  return hipGetLastError();
+}
+
 hipError_t launch_beam_pattern(const float2* c, int pairs, int N, const double* omega, int Q,
                                float* pattern, hipStream_t s) {
   if (pairs < 1 || Q < 1) return hipSuccess;

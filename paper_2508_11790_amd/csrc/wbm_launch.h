@@ -117,6 +117,16 @@ hipError_t launch_lift(const float2* w, const int* starts, int pairs, int wmax, 
 hipError_t launch_lift_apply(const float2* X, const float2* c_hat, float2* out, int N, int K,
                              int B, int L, int Lt, int T, hipStream_t s);
 
+// Planar lifted correlators c^ [T][K][Nz Nx] from window weights [T][K][wmax], starts
+// [T][K][2] (s_z, s_x) and window rows wz [T] (device); twM = the M-entry table, M = Mz Mx.
+hipError_t launch_lift_upa(const float2* w, const int* starts, const int* wz, int T, int K,
+                           int wmax, int Nz, int Nx, int Mz, int Mx, const float2* twM,
+                           float2* c_hat, hipStream_t s);
+// Planar beam patterns of correlators c [pairs][Nz Nx] (Nz Nx <= 4096) at omega [Q][2]
+// = (Omega_z, Omega_x) (device FP64) -> pattern [pairs][Q].
+hipError_t launch_beam_pattern_upa(const float2* c, int pairs, int Nz, int Nx,
+                                   const double* omega, int Q, float* pattern, hipStream_t s);
+
 // Beam patterns (Eq. 22) of correlators c [pairs][N] (N <= 4096) at angles omega [Q]
 // (device FP64) -> pattern [pairs][Q].
 hipError_t launch_beam_pattern(const float2* c, int pairs, int N, const double* omega, int Q,

@@ -317,3 +317,95 @@ def test_planar_bad_arguments(torch, wb):
     call()   # the good call still works after the rejected ones
     torch.cuda.synchronize()
     plan.close()
+
+
+# ----------------------------------------------------------------------------- lift, pattern
+
+def test_planar_lift_matches_oracle(torch, wb):
+    # bound as for the linear lift: W FP32 weight x table products summed in FP64,
+    # at most 2 u sum|w| / sqrt(M); allowed 4 u sum|w| / sqrt(M)
+    Nz, Nx, Mz, Mx, K, T, wmax = 4, 8, 8, 16, 4, 5, 12
+    plan = wb.Plan(Nz * Nx, Mz * Mx, K, 4, 4, T, wmax)
+    r = np.random.default_rng(41)
+    wz = np.array([1, 2, 3, 4, 8], dtype=np.int32)
+    wx = np.array([12, 6, 4, 3, 1], dtype=np.int32)
+    w = (r.standard_normal((T, K, wmax)) + 1j * r.standard_normal((T, K, wmax))).astype(np.complex64)
+    for t in range(T):
+        w[t, :, wz[t] * wx[t]:] = 0
+    starts = np.stack([r.integers(-Mz, Mz, size=(T, K)), r.integers(-Mx, 2 * Mx, size=(T, K))],
+                      axis=-1).astype(np.int32)               # negative and wrapping starts
+    c = plan.lift_upa(torch.from_numpy(w).cuda(), torch.from_numpy(starts).cuda(), Nz, Mz, wz)
+    torch.cuda.synchronize()
+    cg = c.cpu().numpy().astype(np.complex128)
+    for t in range(T):
+        W = int(wz[t] * wx[t])
+        for k in range(K):
+            rows = upa.upa_window_rows(int(starts[t, k, 0]), int(starts[t, k, 1]), int(wz[t]),
+                                       int(wx[t]), Mz, Mx)
+            ref = upa.upa_lift_correlator(w[t, k, :W].astype(np.complex128), rows, Nz, Nx, Mz, Mx)
+            tol = 4 * EPS32 * np.sum(np.abs(w[t, k])) / math.sqrt(Mz * Mx)
+            assert np.max(np.abs(cg[t, k] - ref)) <= tol, (t, k)
+    plan.close()
+
+
+def test_planar_lifted_path_reproduces_windowed_outputs(torch, wb):
+    # beamform_upa -> lift_upa -> element-space apply gives the beamformer's own outputs
+    # (Eq. 21).  Both paths share the channelized X; per output the difference is bounded by the
+    # windowed path's spatial-DFT rounding (4 (log2 Mx + Nz + 1) u ||X_b|| per beam, summed with
+    # |w|), the lift's (4 u sum|w| / sqrt(M) per element) and the two FP32 dot products
+    # ((N + 2) u sum_n |c_n| |X_nb| and (W + 2) u sum_i |w_i| |y_ib|).
+    cfg = PAPER_K16
+    sc = scenes.make_upa_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    x = torch.from_numpy(x32).cuda()
+    plan = _plan(wb, cfg, sc)
+    res = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
+                            cfg.delta)
+    c = plan.lift_upa(res["weights"], res["starts"], cfg.Nz, cfg.Mz, sc.win_z)
+    z = plan.apply_lifted(x, c)
+    torch.cuda.synchronize()
+    a, b = z.cpu().numpy().astype(np.complex128), res["out"].cpu().numpy().astype(np.complex128)
+    wg = res["weights"].cpu().numpy().astype(np.complex128)
+    cg = c.cpu().numpy().astype(np.complex128)
+    X = oracle.channelize(x32.astype(np.complex128), cfg.K)            # [N, B, K]
+    Xt = X[:, cfg.L:cfg.L + cfg.Lt, :]
+    u = EPS32
+    fft_u = 4 * (math.log2(cfg.Mx) + cfg.Nz + 1) * u
+    worst = 0.0
+    for t in range(cfg.T):
+        W = int(sc.win_z[t] * sc.win_x[t])
+        for k in range(cfg.K):
+            w1 = np.sum(np.abs(wg[t, k, :W]))
+            xn = np.linalg.norm(Xt[:, :, k], axis=0)                    # [Lt]
+            bound = (fft_u * w1 * xn + cfg.N * 4 * u * w1 / math.sqrt(cfg.M) * np.max(np.abs(Xt[:, :, k]), axis=0)
+                     + (cfg.N + 2) * u * (np.abs(cg[t, k]) @ np.abs(Xt[:, :, k]))
+                     + (W + 2) * u * w1 * xn)
+            d = np.abs(a[t, k] - b[t, k])
+            assert np.all(d <= bound), (t, k, float(np.max(d / bound)))
+            worst = max(worst, float(np.max(d / bound)))
+    log(f"  planar lifted vs windowed outputs: worst difference / bound {worst:.3f}")
+    plan.close()
+
+
+def test_planar_beam_pattern_matches_oracle(torch, wb):
+    # FP64 sums with phase recurrences on the GPU; the FP32 result within 1e-6 of the oracle
+    Nz, Nx = 4, 32
+    plan = wb.Plan(Nz * Nx, 8 * 64, 4, 4, 4, 2, 5)
+    r = np.random.default_rng(42)
+    c = (r.standard_normal((2, 3, Nz * Nx)) + 1j * r.standard_normal((2, 3, Nz * Nx))).astype(np.complex64)
+    g = np.linspace(-math.pi, math.pi, 37)
+    om = np.array([(oz, ox) for oz in g[::4] for ox in g] + [(0.0, 0.0), (3 * math.pi, -2.5)])
+    pat = plan.beam_pattern_upa(torch.from_numpy(c).cuda(), Nz, torch.from_numpy(om).cuda())
+    torch.cuda.synchronize()
+    pg = pat.cpu().numpy()
+    for i in range(2):
+        for j in range(3):
+            ref = upa.upa_beam_pattern(c[i, j].astype(np.complex128), Nz, om)
+            assert np.max(np.abs(pg[i, j] - ref)) < 1e-6
+    a = upa.upa_steering(Nz, Nx, 0.4, -1.2).astype(np.complex64)
+    pk = plan.beam_pattern_upa(torch.from_numpy(a).cuda(), Nz,
+                               torch.tensor([[0.4, -1.2]], dtype=torch.float64, device="cuda"))
+    assert abs(float(pk.cpu()[0]) - 1.0) < 1e-6
+    with pytest.raises(wb.WbmError):
+        plan.beam_pattern_upa(torch.from_numpy(a).cuda(), 3, torch.from_numpy(om).cuda())
+    plan.close()
