@@ -159,7 +159,26 @@ def upa_leg(torch, wb, scenes, steps, warmup):
     assert int(info.abs().sum()) == 0
     res["fused"] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms}
     w_fused = wts.cpu().numpy().astype(np.complex128)
-    st = plan.beamform_upa(*args, form="fused")["starts"].cpu().numpy()
+    fres = plan.beamform_upa(*args, form="fused")
+    st = fres["starts"].cpu().numpy()
+    # lifted correlators (Eq. 21) applied in element space, and planar beam patterns (Eq. 22)
+    ms_lift = timed_steps(torch, lambda: plan.lift_upa(fres["weights"], fres["starts"], cfg.Nz,
+                                                       cfg.Mz, sc.win_z), steps, warmup)
+    c_hat = plan.lift_upa(fres["weights"], fres["starts"], cfg.Nz, cfg.Mz, sc.win_z)
+    out_l = torch.empty_like(out)
+    ms_applied = timed_steps(torch, lambda: plan.apply_lifted(x, c_hat, out=out_l), steps, warmup)
+    lift_diff = float((out_l - fres["out"]).abs().max() / fres["out"].abs().max())
+    g = torch.linspace(-math.pi, math.pi, 32, dtype=torch.float64, device=x.device)
+    omega = torch.stack(torch.meshgrid(g, g, indexing="ij"), dim=-1).reshape(-1, 2).contiguous()
+    pat = torch.empty((cfg.T, cfg.K, omega.shape[0]), dtype=torch.float32, device=x.device)
+    ms_pattern = timed_steps(torch, lambda: plan.beam_pattern_upa(c_hat, cfg.Nz, omega,
+                                                                  pattern=pat),
+                             max(2, steps // 10), 1)
+    res["lifted"] = {"value": cfg.T * cfg.K / (ms_applied * 1e-3), "ms_per_step": ms_applied,
+                     "lift_ms": ms_lift, "max_rel_diff_vs_fused_outputs": lift_diff,
+                     "beam_pattern_ms": ms_pattern,
+                     "beam_pattern": "Eq. 22 over a 32 x 32 (Omega_z, Omega_x) grid, every pair"}
+    del c_hat, out_l, pat, omega
     for form in ("mixed", "mixed_bf16"):
         ms = timed_steps(torch, step(form), steps, warmup)
         res[form] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms,
