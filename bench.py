@@ -183,6 +183,9 @@ def upa_leg(torch, wb, scenes, steps, warmup):
         ms = timed_steps(torch, step(form), steps, warmup)
         res[form] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms,
                      "routed_pairs": int(((info.cpu().numpy() & wb.INFO_ROUTED) != 0).sum())}
+    ms = timed_steps(torch, step("plain"), steps, warmup)
+    res["plain"] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms,
+                    "form": "per-stage FP32 kernels, full planar beamspace in HBM"}
     plan.close()
     sumW = int(np.sum(sc.win_z * sc.win_x))
     res.update({"workload": f"UPA {cfg.Nz}x{cfg.Nx}, beams {cfg.Mz}x{cfg.Mx}, K={cfg.K}, "

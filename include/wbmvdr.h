@@ -248,7 +248,9 @@ wbm_status wbm_steer(wbm_plan* plan, const double* az_rad, const int32_t* win, i
  * wbm_beamform with the 2-D transform and windows.
  *   az_rad, el_rad  host [T] azimuth and elevation of each target from broadside (radians).
  *   win_z, win_x    host [T] window rows Wz and columns Wx, Wz * Wx <= w_max.
- *   form            WBM_FORM_FUSED, WBM_FORM_MIXED or WBM_FORM_MIXED_BF16 (others:
+ *   form            WBM_FORM_PLAIN (full planar beamspace in HBM, window cells gathered
+ *                   through a beam table, FP32 covariance / Cholesky / apply), WBM_FORM_FUSED,
+ *                   WBM_FORM_MIXED or WBM_FORM_MIXED_BF16 (WBM_FORM_GRAPH:
  *                   WBM_ERR_UNSUPPORTED).  The first fused call of a plan times the pair
  *                   kernels on its windows, and the channelizer tiles if the plan is neither
  *                   tuned nor pinned (WBM_AUTOTUNE=0: tile 2^12, the matrix-core kernel);

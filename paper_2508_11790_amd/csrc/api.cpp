@@ -116,6 +116,7 @@ struct wbm_plan {
   float2* prof_w = nullptr;
   int* prof_info = nullptr;
   int* route = nullptr;      // [T_max][K] mixed forms: windows routed to the FP64 kernel
+  int* upa_rows = nullptr;   // [T_max][K][w_max] planar plain form: beam of every window cell
   // loading / window predictor buffers (first use)
   float* pprof = nullptr;    // [K][G][T_max][64] power-profile partials
   float* feat = nullptr;     // [T_max][K][64]
@@ -741,7 +742,7 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   void* bufs[] = {p->twK, p->twM, p->hb, p->desc_dev, p->X, p->Yw, p->Y, p->R32,
                   p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
                   p->prof_out, p->prof_w, p->prof_info, p->pprof, p->feat, p->nnout,
-                  p->pw, p->pdelta, p->jam_dev, p->route};
+                  p->pw, p->pdelta, p->jam_dev, p->route, p->upa_rows};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete p;
@@ -1190,8 +1191,9 @@ wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t m
   if (!x) return fail(WBM_ERR_ARG, "x is NULL");
   if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
-  if (form != WBM_FORM_FUSED && form != WBM_FORM_MIXED && form != WBM_FORM_MIXED_BF16)
-    return fail(WBM_ERR_UNSUPPORTED, "the planar array runs the fused and mixed forms");
+  if (form != WBM_FORM_PLAIN && form != WBM_FORM_FUSED && form != WBM_FORM_MIXED &&
+      form != WBM_FORM_MIXED_BF16)
+    return fail(WBM_ERR_UNSUPPORTED, "the planar array runs the plain, fused and mixed forms");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc_upa(p, nz, mz, az_rad, el_rad, win_z, win_x, T, st, &sumW))) return s;
@@ -1201,6 +1203,26 @@ wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t m
   const float2* xx = reinterpret_cast<const float2*>(x);
   float2* o = reinterpret_cast<float2*>(out);
   float2* w = reinterpret_cast<float2*>(weights);
+  if (form == WBM_FORM_PLAIN) {
+    // per-stage FP32 baseline: full planar beamspace in HBM, the window cells gathered from it
+    // through the beam table, covariance / Cholesky / apply as three launches
+    if ((s = ensure_plain(p))) return s;
+    if (!p->upa_rows &&
+        (s = dev_alloc(p, &p->upa_rows, (size_t)c.max_targets * c.k_sub * c.w_max, "beam table")))
+      return s;
+    WBM_HIP(wbm::launch_steer_upa(g, c.w_max, starts, p->abar, st, p->upa_rows),
+            "planar steer launch");
+    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
+    WBM_HIP(wbm::launch_beamspace_upa(p->X, p->Y, nullptr, p->B, p->twM, nullptr, 0, g, p->logTB,
+                                      p->nbt, st),
+            "planar beamspace launch");
+    wbm::PairArgs pp = pair_args(p, T, sumW, loading);
+    pp.rows = p->upa_rows;
+    WBM_HIP(wbm::launch_mvdr_plain(pp, p->dd, p->Y, p->starts, p->abar, p->R32, p->w32, o, w, info,
+                                   st),
+            "plain MVDR launch");
+    return WBM_OK;
+  }
   WBM_HIP(wbm::launch_steer_upa(g, c.w_max, starts, p->abar, st), "planar steer launch");
   if (form == WBM_FORM_FUSED && !p->upa_tuned) {
     if ((s = ensure_prof(p))) return s;

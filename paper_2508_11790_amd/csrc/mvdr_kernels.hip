@@ -62,9 +62,10 @@ hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* aba
 
 // Planar array: one thread per (t, k, i < wmax): window starts (s_z, s_x) of the pair and its
 // windowed steering a~ = S D a, cell i = ix_w Wz + iz_w the product of the two axes' Dirichlet
-// sums (D a of Eq. 6 factors over the Kronecker product).
+// sums (D a of Eq. 6 factors over the Kronecker product); optionally the beam index of every
+// window cell (the plain form's row table).
 __global__ void k_steer_upa(UpaGeom g, int wmax, int* __restrict__ starts,
-                            double2* __restrict__ abar) {
+                            double2* __restrict__ abar, int* __restrict__ rows) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)g.T * g.K * wmax;
   if (idx >= total) return;
@@ -79,19 +80,22 @@ __global__ void k_steer_upa(UpaGeom g, int wmax, int* __restrict__ starts,
     starts[2 * pk + 1] = sx;
   }
   double2 a = make_double2(0.0, 0.0);
+  int m = 0;
   if (i < g.win[t]) {
     const int Wz = g.wz[t], ixw = i / Wz, izw = i - ixw * Wz;
     a = dmul(axis_steering(g.Nx, g.Mx, ux, sx + ixw), axis_steering(g.Nz, g.Mz, uz, sz + izw));
+    m = ((sx + ixw) & (g.Mx - 1)) * g.Mz + ((sz + izw) & (g.Mz - 1));
   }
   abar[idx] = a;
+  if (rows) rows[idx] = m;
 }
 
 hipError_t launch_steer_upa(const UpaGeom& g, int wmax, int* starts, double2* abar,
-                            hipStream_t s) {
+                            hipStream_t s, int* rows) {
   const int64_t total = (int64_t)g.T * g.K * wmax;
   const int bs = 256;
   hipLaunchKernelGGL(k_steer_upa, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, s, g,
-                     wmax, starts, abar);
+                     wmax, starts, abar, rows);
   return hipGetLastError();
 }
 
@@ -117,7 +121,9 @@ __device__ __forceinline__ void pair_of_block(const PairArgs& a, const DevDesc& 
   k = a.k0 + p % kc;
 }
 
-// Snapshot b of window row i of pair (t, k).
+// Snapshot b of window row i of pair (t, k).  From the full beamspace the row is bin
+// (s + i) mod M, or with a row table (a.rows, the planar windows) beam a.rows[s wmax + i],
+// s then being the pair index.
 template <bool WINDOWED>
 __device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const PairArgs& a, int k,
                                          int woff, int s, int i, int b) {
@@ -125,7 +131,8 @@ __device__ __forceinline__ float2 load_y(const float2* __restrict__ src, const P
     const int TB = 1 << a.logTB;
     return src[(((int64_t)k * a.nbt + (b >> a.logTB)) * a.sumW + woff + i) * TB + (b & (TB - 1))];
   } else {
-    return src[((int64_t)k * a.M + ((s + i) & (a.M - 1))) * a.B + b];
+    const int m = a.rows ? a.rows[(int64_t)s * a.wmax + i] : ((s + i) & (a.M - 1));
+    return src[((int64_t)k * a.M + m) * a.B + b];
   }
 }
 
@@ -1382,8 +1389,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_cov(PairArgs a, DevDesc
   const int p = blockIdx.x;
   const int k = p / a.T, t = p - k * a.T;
   const int W = d.win[t];
-  const int s = starts[t * a.K + k];
   const int64_t pair = (int64_t)t * a.K + k;
+  const int s = a.rows ? (int)pair : starts[t * a.K + k];
   pair_covariance<float, false, kPlainThreads, 9>(Y, a, k, W, 0, s, ys, R, lay.RS, a.delta);
   float2* dst = R32 + pair * a.wmax * a.wmax;
   for (int e = threadIdx.x; e < W * W; e += kPlainThreads) {
@@ -1433,8 +1440,8 @@ __global__ __launch_bounds__(kPlainThreads) void k_plain_apply(PairArgs a, DevDe
   const int p = blockIdx.x;
   const int k = p / a.T, t = p - k * a.T;
   const int W = d.win[t];
-  const int s = starts[t * a.K + k];
   const int64_t pair = (int64_t)t * a.K + k;
+  const int s = a.rows ? (int)pair : starts[t * a.K + k];
   if (threadIdx.x < a.wmax) {
     wv[threadIdx.x] = w32[pair * a.wmax + threadIdx.x];
     if (wout) wout[pair * a.wmax + threadIdx.x] = w32[pair * a.wmax + threadIdx.x];

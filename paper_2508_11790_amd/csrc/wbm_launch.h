@@ -42,10 +42,10 @@ int beamspace_tiles(int M, int B, int logtile);
 // Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
 hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar, hipStream_t s);
 
-// Planar array: window starts [T][K][2] (s_z, s_x; optional) and windowed steering abar
-// [T][K][wmax] (FP64).
+// Planar array: window starts [T][K][2] (s_z, s_x; optional), windowed steering abar
+// [T][K][wmax] (FP64) and, if rows, the beam index mx Mz + mz of every window cell [T][K][wmax].
 hipError_t launch_steer_upa(const UpaGeom& g, int wmax, int* starts, double2* abar,
-                            hipStream_t s);
+                            hipStream_t s, int* rows = nullptr);
 // Planar-array beamspace X [K][B][Nz Nx] -> Y [K][Mz Mx][B] (if Y) and the Wz x Wx windows Yw
 // [K][nbt][sumW][2^logTB] (if Yw) for every subband.  Needs Mx, Mz powers of two,
 // Nx <= Mx, Nz <= Mz, 2 <= Mx and next_pow2(Nz) Mx <= 2048.
@@ -69,6 +69,9 @@ struct PairArgs {
   // optional windowed steering [T][K][wmax] (the planar array's); nullptr = the pair kernels
   // evaluate the linear array's from the window geometry
   const double2* abar = nullptr;
+  // plain form on the planar array: beam index of every window cell [T][K][wmax] in the full
+  // beamspace (nullptr = bins (s + i) mod M)
+  const int* rows = nullptr;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> LDL^H (FP64) -> solve
 // -> apply, reading the window rows written by the beamspace kernel.
