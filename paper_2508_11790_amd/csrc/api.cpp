@@ -473,11 +473,11 @@ hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double l
 }
 
 // ---------------------------------------------------------------------------------------------
-// FFT tile autotuner: times every supported tile size of the channelizer and the windowed
-// beamspace kernel on the plan's own shape (HIP events, best of 3 after one warm-up launch)
-// and keeps the fastest.  Results are cached in a JSON file keyed by device and shape
-// ($WBM_AUTOTUNE_CACHE, default ~/.cache/wbmvdr/autotune.json); WBM_AUTOTUNE=0 disables
-// tuning (tile 2^12).
+// Autotuner: times every supported tile size of the channelizer and the windowed beamspace
+// kernel, every pair kernel and the overlap chunk counts on the plan's own shape (HIP events,
+// time_best) and keeps the fastest.  Results are cached in a JSON file keyed by device and
+// shape ($WBM_AUTOTUNE_CACHE, default ~/.cache/wbmvdr/autotune.json); WBM_AUTOTUNE=0
+// disables tuning (tile 2^12).
 
 std::string tune_key(const wbm_plan* p) {
   hipDeviceProp_t prop;
@@ -488,7 +488,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p5";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p6";
   return os.str();
 }
 
@@ -554,8 +554,11 @@ void cache_store(const std::string& key, int chan, int beam, int thr, int ovl) {
   if (out) out << os.str();
 }
 
+// Time a candidate: one warm-up launch, then the best of four samples of three back-to-back
+// launches (per launch), so that candidates a few percent apart are ordered reliably.
 template <class F>
 hipError_t time_best(F launch, hipStream_t st, float* best_ms) {
+  constexpr int kSamples = 4, kPerSample = 3;
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
@@ -565,14 +568,15 @@ hipError_t time_best(F launch, hipStream_t st, float* best_ms) {
     return e;
   }
   *best_ms = 1e30f;
-  for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+  e = launch();
+  for (int r = 0; r < kSamples && e == hipSuccess; ++r) {
     e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch();
+    for (int q = 0; q < kPerSample && e == hipSuccess; ++q) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e == hipSuccess && r > 0 && ms < *best_ms) *best_ms = ms;
+    if (e == hipSuccess && ms / kPerSample < *best_ms) *best_ms = ms / kPerSample;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1130,9 +1134,8 @@ hipError_t enqueue_upa_windows(wbm_plan* p, const float2* x, int T, int sumW,
 
 // First planar-array call of a plan: the channelizer tile (unless already tuned or pinned)
 // and the pair kernel of the fused form are timed on this call's data (each pair-kernel
-// candidate with the channelizer and planar spatial DFT before it; best of three after a
-// warm-up, like the linear array's autotuner); WBM_AUTOTUNE=0 keeps the defaults (tile 2^12,
-// matrix-core kernel).
+// candidate with the channelizer and planar spatial DFT before it; time_best, as the linear
+// array's autotuner); WBM_AUTOTUNE=0 keeps the defaults (tile 2^12, matrix-core kernel).
 hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::UpaGeom& g,
                     double loading, hipStream_t st) {
   p->upa_tuned = true;
