@@ -78,3 +78,20 @@ def test_null_arguments_are_rejected(lib):
     assert lib.wbm_plan_workspace_bytes(None) == 0
     assert lib.wbm_plan_set_tuning(None, 12, 12, 1, 1) == 1
     assert lib.wbm_plan_get_tuning(None, None, None, None, None) == 1
+
+
+def test_header_is_plain_c(tmp_path):
+    # the boundary is usable from C: the header compiles as C99 with warnings as errors
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use.c"
+    src.write_text('#include "wbmvdr.h"\nint main(void) { wbm_config c = {0}; (void)c; '
+                   'return (int)WBM_OK; }\n')
+    inc = os.path.join(ROOT, "include")
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc,
+                        "-c", str(src), "-o", str(tmp_path / "use.o")], capture_output=True,
+                       text=True)
+    assert r.returncode == 0, r.stderr
