@@ -546,15 +546,18 @@ __global__ __launch_bounds__(fft_threads(LOGMX, kUpaLogTile)) void k_beamspace_u
     }
   }
   __syncthreads();
-  // beam m of tile snapshot bb: the z-DFT of the x-transformed rows
+  // beam m of tile snapshot bb: the z-DFT of the x-transformed rows, the twiddles
+  // exp(-j 2 pi mz iz / Mz) as powers of the one for iz = 1 (one table read per beam)
   auto beam = [&](int m, int bb) {
     const int mx = m >> logMz, mz = m & (Mz - 1);
-    float2 acc = make_float2(0.f, 0.f);
-    for (int iz = 0; iz < Nz; ++iz) {
+    const float2 w1 = s_twz[mz];
+    float2 acc = lds[F::addr(bb << logPz, mx)];
+    float2 w = w1;
+    for (int iz = 1; iz < Nz; ++iz) {
       const float2 v = lds[F::addr((bb << logPz) + iz, mx)];
-      const float2 w = s_twz[(mz * iz) & (Mz - 1)];
       acc.x += v.x * w.x - v.y * w.y;
       acc.y += v.x * w.y + v.y * w.x;
+      w = cmul(w, w1);
     }
     return cscale(acc, scale);
   };
