@@ -488,7 +488,7 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p7";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p6";
   return os.str();
 }
 
@@ -583,29 +583,6 @@ hipError_t time_best(F launch, hipStream_t st, float* best_ms) {
   return e;
 }
 
-// The fused sequence with chunks subband chunks, captured into a graph and timed by replays
-// (time_best): how the graph form runs it.
-hipError_t time_fused_graph(wbm_plan* p, const float2* x, int T, int sumW, double loading,
-                            hipStream_t st, int chunks, float* ms) {
-  hipGraph_t g = nullptr;
-  hipGraphExec_t ge = nullptr;
-  hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  const hipError_t le = enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
-                                      p->prof_info, p->cap_stream, chunks);
-  const hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
-  if (le != hipSuccess || ce != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return le != hipSuccess ? le : ce;
-  }
-  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return e;
-  e = time_best([&]() { return hipGraphLaunch(ge, st); }, st, ms);
-  const hipError_t de = hipGraphExecDestroy(ge);
-  return e != hipSuccess ? e : de;
-}
-
 hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loading,
                     hipStream_t st) {
   p->tuned = true;
@@ -642,7 +619,7 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   p->chan_logtile = chan;
   set_beam_tile(p, beam);
   // pair kernel: each candidate timed in the whole fused sequence (channelize, windows, pair
-  // kernel) replayed from a graph, where it reads windows the spatial DFT has just written
+  // kernel), where it reads windows the spatial DFT has just written
   hipError_t e = hipSuccess;
   float best_p = 1e30f;
   for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
@@ -650,7 +627,10 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
     if (thr_c == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
     float ms;
     p->pair_threads = thr_c;
-    e = time_fused_graph(p, x, T, sumW, loading, st, 1, &ms);
+    e = time_best([&]() {
+      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
+                           p->prof_info, st, 1);
+    }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_p) {
       best_p = ms;
@@ -663,7 +643,10 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
   for (int ch = 1; ch <= kMaxOverlap; ch <<= 1) {
     if (!overlap_supported(p, ch)) continue;
     float ms;
-    e = time_fused_graph(p, x, T, sumW, loading, st, ch, &ms);
+    e = time_best([&]() {
+      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr, p->prof_info,
+                           st, ch);
+    }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_o) {
       best_o = ms;
