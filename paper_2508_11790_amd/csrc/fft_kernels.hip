@@ -125,18 +125,42 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   const int nbt = (B + TB - 1) / TB;
   float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twM);
+  // This thread's first-pass inputs sit at the same place in every tile: element e of the
+  // tile's snapshot row `row`, byte offset 8 (row N + e) from the tile's first snapshot.  A
+  // tile of TB whole snapshots with every e < N (N = M/2 under ZH, else N = M) is read
+  // without predicates from a uniform base.
+  uint32_t foff[8];
+  int frow[8];
+  bool fok[8];
+#pragma unroll
+  for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      int row, e;
+      F::first_input(p, r, row, e);
+      const int q = p * F::R0 + r;
+      frow[q] = row;
+      fok[q] = e < N;
+      foff[q] = (uint32_t)(row * N + e) * 8u;
+    }
+  }
+  const bool dense = N >= (ZH ? M / 2 : M);
   auto fetch = [&](int j, float2 (&v)[8]) {
     const int b0 = j * TB;
+    const char* base = reinterpret_cast<const char*>(X + ((int64_t)k * B + b0) * N);
+    if (dense && b0 + TB <= B) {
 #pragma unroll
-    for (int p = 0; p < 8 / F::R0; ++p) {
+      for (int q = 0; q < 8; ++q)
+        v[q] = (ZH && 2 * (q % F::R0) >= F::R0)
+                   ? make_float2(0.f, 0.f)
+                   : *reinterpret_cast<const float2*>(base + foff[q]);
+    } else {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) {
-        int row, e;
-        F::first_input(p, r, row, e);
+      for (int q = 0; q < 8; ++q) {
         float2 val = make_float2(0.f, 0.f);
-        if (!(ZH && 2 * r >= F::R0) && e < N && b0 + row < B)
-          val = X[((int64_t)k * B + b0 + row) * N + e];
-        v[p * F::R0 + r] = val;
+        if (!(ZH && 2 * (q % F::R0) >= F::R0) && fok[q] && b0 + frow[q] < B)
+          val = *reinterpret_cast<const float2*>(base + foff[q]);
+        v[q] = val;
       }
     }
   };
