@@ -538,19 +538,42 @@ __global__ __launch_bounds__(fft_threads(LOGMX, kUpaLogTile)) void k_beamspace_u
   const int k = blockIdx.y;
   float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twM, Mz);                           // Mx-point table = twM[q Mz]
+  // This thread's first-pass inputs sit at the same place in every tile: element (iz, ix) of
+  // the tile's snapshot bb, byte offset 8 (bb N + ix Nz + iz) from the tile's first snapshot.
+  // A tile of TB2 whole snapshots with every slot inside the array (Nz = Pz, Nx = Mx/2 under ZH,
+  // else Nx = Mx) is read without predicates from a uniform base.
+  uint32_t foff[8];
+  int fbb[8];
+  bool fok[8];
+#pragma unroll
+  for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      int row, ix;
+      F::first_input(p, r, row, ix);
+      const int iz = row & ((1 << logPz) - 1), bb = row >> logPz, q = p * F::R0 + r;
+      fbb[q] = bb;
+      fok[q] = ix < Nx && iz < Nz;
+      foff[q] = (uint32_t)(bb * N + ix * Nz + iz) * 8u;
+    }
+  }
+  const bool dense = Nz == (1 << logPz) && Nx >= (ZH ? Mx / 2 : Mx);
   auto fetch = [&](int j, float2 (&v)[8]) {
     const int b0 = j * TB2;
+    const char* base = reinterpret_cast<const char*>(X + ((int64_t)k * B + b0) * N);
+    if (dense && b0 + TB2 <= B) {
 #pragma unroll
-    for (int p = 0; p < 8 / F::R0; ++p) {
+      for (int q = 0; q < 8; ++q)
+        v[q] = (ZH && 2 * (q % F::R0) >= F::R0)
+                   ? make_float2(0.f, 0.f)
+                   : *reinterpret_cast<const float2*>(base + foff[q]);
+    } else {
 #pragma unroll
-      for (int r = 0; r < F::R0; ++r) {
-        int row, ix;
-        F::first_input(p, r, row, ix);
-        const int iz = row & ((1 << logPz) - 1), bb = row >> logPz;
+      for (int q = 0; q < 8; ++q) {
         float2 val = make_float2(0.f, 0.f);
-        if (!(ZH && 2 * r >= F::R0) && ix < Nx && iz < Nz && b0 + bb < B)
-          val = X[((int64_t)k * B + b0 + bb) * N + ix * Nz + iz];
-        v[p * F::R0 + r] = val;
+        if (!(ZH && 2 * (q % F::R0) >= F::R0) && fok[q] && b0 + fbb[q] < B)
+          val = *reinterpret_cast<const float2*>(base + foff[q]);
+        v[q] = val;
       }
     }
   };
