@@ -47,7 +47,10 @@ def _oracle(scene, x32, subbands=None, windows=True):
 
 @pytest.mark.parametrize("half_bin", [False, True])
 @pytest.mark.parametrize("shape", [(16, 32, 16, 64, 64), (20, 32, 8, 37, 11), (256, 512, 128, 256, 256),
-                                   (4, 4, 2, 3, 1)])
+                                   (4, 4, 2, 3, 1),
+                                   # N = M/2 with 301 snapshots: whole tiles and a ragged last one
+                                   # at every tile size
+                                   (16, 32, 4, 200, 101)])
 def test_channelizer_and_beamspace_stages(torch, wb, shape, half_bin):
     N, M, K, L, Lt = shape
     log(f"stage case N={N} M={M} K={K} L={L} Lt={Lt} half_bin={half_bin}")
@@ -256,6 +259,7 @@ def test_graph_replays_match_eager(torch, wb):
     dict(N=5, M=8, K=2, L=9, Lt=3, W=(8, 3)),                   # tiny, full window
     dict(N=33, M=64, K=4, L=70, Lt=0, W=(5, 6)),                # no test snapshots
     dict(N=16, M=16, K=16, L=40, Lt=40, W=(16,)),               # M = N (unitary D)
+    dict(N=16, M=32, K=4, L=200, Lt=101, W=(5, 3)),             # N = M/2: whole and ragged tiles
 ])
 def test_edge_shapes(torch, wb, case):
     W = case["W"]
