@@ -66,7 +66,11 @@ typedef enum {
                                beamspace written to HBM and gathered per pair */
 #define WBM_FORM_FUSED 1    /* beamspace FFT writes only the windows; one fused per-pair
                                covariance -> LDL^H -> solves -> apply launch; FP64
-                               accumulation of the covariance and FP64 LDL^H */
+                               accumulation of the covariance and FP64 LDL^H.  Both transforms
+                               run in FP64 and store X and the windows in extended precision
+                               (an FP32 value plus its BF16-rounded remainder, relative error
+                               about 2^-33), so that FP32 rounding of the transforms does not
+                               move the weights of scenes with strong interferers */
 #define WBM_FORM_GRAPH 2    /* WBM_FORM_FUSED with the launch sequence replayed from a
                                HIP graph (captured on first use for a given argument set) */
 #define WBM_FORM_MIXED 3    /* fused sequence with the window covariance on MFMA: each FP32
@@ -77,6 +81,13 @@ typedef enum {
                                FP64 path instead and report info bit 30 (info & (1 << 30)) */
 #define WBM_FORM_MIXED_BF16 4  /* as WBM_FORM_MIXED with one BF16 product per step (snapshots
                                rounded to BF16) */
+#define WBM_FORM_FUSED_F32 5   /* WBM_FORM_FUSED with FP32 transforms and FP32 X and windows
+                               (fewer bytes; the transforms' rounding then moves the weights
+                               by about 0.1 eps32 times the input's dynamic range over the
+                               noise floor: fine at moderate interference, not at 50-60 dB
+                               jammers on thousands of elements).  The mixed forms also use
+                               these FP32 transforms. */
+#define WBM_FORM_GRAPH_F32 6   /* WBM_FORM_FUSED_F32 replayed from a HIP graph */
 #define WBM_INFO_ROUTED (1 << 30)
 
 typedef struct {
@@ -111,26 +122,35 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
 #define WBM_PAIR_RESIDENT 2 /* four waves, the pair's window data held whole in LDS;
                                w_max * L <= 2304 and w_max * Lt <= 2304 */
 
-/* Launch configuration of the fused form.  Without a call to wbm_plan_set_tuning the first
- * fused / graph call times the candidates on the caller's data (FFT tiles of 2^11..2^13
- * complex per workgroup for the channelizer and the spatial DFT, the four pair kernels, the
- * number of subband chunks over which the spatial DFT and the pair kernel overlap on two
- * streams) and keeps the fastest, cached on disk per device and shape.  Setting pins the
- * choice and skips that search; every choice computes the same quantities (Eq. 4-20),
- * differing only in rounding order.
- *   chan_logtile, beam_logtile  11, 12 or 13.
+/* Precision of the fused sequence a launch configuration applies to. */
+#define WBM_PREC_EXT 0     /* WBM_FORM_FUSED / GRAPH, wbm_beamform_pairs, wbm_beamform_learned,
+                              wbm_profiles: extended-precision transforms and windows */
+#define WBM_PREC_F32 1     /* WBM_FORM_FUSED_F32 / GRAPH_F32, the mixed forms' transforms and the
+                              planar-array path */
+
+/* Launch configuration of the fused form in one precision.  Without a call to
+ * wbm_plan_set_tuning the first call of that precision times the candidates on the caller's
+ * data (FFT tiles of 2^11..2^13 complex per workgroup for the channelizer and the spatial DFT,
+ * 2^10..2^13 in extended precision; the pair kernels; the number of subband chunks over which
+ * the spatial DFT and the pair kernel overlap on two streams) and keeps the fastest, cached on
+ * disk per device, shape and precision.  Setting pins the choice and skips that search; every
+ * choice computes the same quantities (Eq. 4-20), differing only in rounding order.
+ *   precision                   WBM_PREC_EXT or WBM_PREC_F32.
+ *   chan_logtile, beam_logtile  11, 12 or 13 (WBM_PREC_EXT: 10 .. 13).
  *   pair_kernel                 WBM_PAIR_MFMA, WBM_PAIR_WAVE (needs w_max <= 40),
  *                               WBM_PAIR_BLOCK or WBM_PAIR_RESIDENT (needs
- *                               w_max * L and w_max * Lt <= 2304).
+ *                               w_max * L and w_max * Lt <= 2304); WBM_PREC_EXT takes
+ *                               WBM_PAIR_WAVE or WBM_PAIR_BLOCK only.
  *   overlap_chunks              1 (no overlap), 2, 4 or 8; K must be a multiple of 8 x chunks.
  * Errors: WBM_ERR_ARG for a NULL plan or a value outside those sets, WBM_ERR_UNSUPPORTED for
- * WBM_PAIR_WAVE or WBM_PAIR_RESIDENT beyond their limits or a chunk count K does not allow.
- * A pinned choice drops a captured graph (recaptured on the next graph call) and also fixes
- * the pair kernel of the planar-array path (wbm_beamform_upa).  wbm_plan_get_tuning writes the current
- * choice (NULL pointers skipped). */
-wbm_status wbm_plan_set_tuning(wbm_plan* plan, int32_t chan_logtile, int32_t beam_logtile,
-                               int32_t pair_kernel, int32_t overlap_chunks);
-wbm_status wbm_plan_get_tuning(const wbm_plan* plan, int32_t* chan_logtile,
+ * a pair kernel the precision or the shape does not allow or a chunk count K does not allow.
+ * A pinned choice drops a captured graph (recaptured on the next graph call); the WBM_PREC_F32
+ * choice also fixes the pair kernel of the planar-array path (wbm_beamform_upa).
+ * wbm_plan_get_tuning writes the current choice of a precision (NULL pointers skipped). */
+wbm_status wbm_plan_set_tuning(wbm_plan* plan, int32_t precision, int32_t chan_logtile,
+                               int32_t beam_logtile, int32_t pair_kernel,
+                               int32_t overlap_chunks);
+wbm_status wbm_plan_get_tuning(const wbm_plan* plan, int32_t precision, int32_t* chan_logtile,
                                int32_t* beam_logtile, int32_t* pair_kernel,
                                int32_t* overlap_chunks);
 
@@ -140,7 +160,7 @@ wbm_status wbm_plan_get_tuning(const wbm_plan* plan, int32_t* chan_logtile,
  *   win     host [T] window width W_t per target, 1 <= W_t <= w_max.
  *   T       number of targets, 1 <= T <= max_targets.
  *   loading diagonal loading delta >= 0 added to the 1/L-scaled covariance.
- *   form    WBM_FORM_PLAIN / FUSED / GRAPH / MIXED / MIXED_BF16.
+ *   form    WBM_FORM_PLAIN / FUSED / GRAPH / MIXED / MIXED_BF16 / FUSED_F32 / GRAPH_F32.
  *   out     device [T][K][Lt] wbm_c32: beam outputs c^H y on test snapshots L..L+Lt-1.
  *   weights device [T][K][w_max] wbm_c32 or NULL: correlators c~ in window-bin order
  *           (bins (s + i) mod M, i < W_t), zero padded to w_max.
@@ -312,13 +332,14 @@ wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                          void* stream);
 
 /* Per-stage timing of the fused sequence (same arguments as wbm_beamform with
- * form = WBM_FORM_FUSED, outputs go to plan-internal scratch): launches each kernel of it
- * (steer, channelize, windowed beamspace, fused MVDR, in that order) once untimed and then
- * `reps` times back to back on `stream` between two HIP events, and writes the average
- * milliseconds per launch to stage_ms (host [4]).  Blocks until the stream has drained. */
+ * form = WBM_FORM_FUSED for precision WBM_PREC_EXT, WBM_FORM_FUSED_F32 for WBM_PREC_F32;
+ * outputs go to plan-internal scratch): launches each kernel of it (steer, channelize,
+ * windowed beamspace, fused MVDR, in that order) once untimed and then `reps` times back to
+ * back on `stream` between two HIP events, and writes the average milliseconds per launch to
+ * stage_ms (host [4]).  Blocks until the stream has drained. */
 wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
-                           const int32_t* win, int32_t T, double loading, int32_t reps,
-                           double* stage_ms, void* stream);
+                           const int32_t* win, int32_t T, double loading, int32_t precision,
+                           int32_t reps, double* stage_ms, void* stream);
 
 /* ------------------------------------------------------------------------------------
  * Loading / window predictor.  The paper fixes the diagonal loading and the window width;

@@ -260,8 +260,10 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
     (zero padded), ``a`` [T, nk, Wmax] (windowed steering), ``z`` [T, nk, Lt],
     ``R`` list-of-lists of the loaded covariances, ``subbands``, and with
     ``return_windows`` ``Yw`` list-of-lists of the windowed snapshots [W, L + Lt].
+    ``X`` may be given instead of ``x`` (channelized [N, B, K], or [N, B, len(subbands)] with
+    the listed subbands' columns in that order).
     """
-    N = x.shape[0]
+    N = x.shape[0] if x is not None else X.shape[0]
     T = len(sin_az)
     win = [int(v) for v in win]
     Wmax = max(win)
@@ -269,6 +271,8 @@ def windowed_mvdr(x: np.ndarray, *, M: int, K: int, L: int, Lt: int,
     if X is None:
         X = channelize(x, K, half_bin) if subbands is None else channelize_bins(x, K, ks, half_bin)
         kcol = {k: (k if subbands is None else i) for i, k in enumerate(ks)}
+    elif subbands is not None and X.shape[2] == len(ks) != K:
+        kcol = {k: i for i, k in enumerate(ks)}      # X holds only the listed subbands
     else:
         kcol = {k: k for k in ks}
     ratio = subband_freq_ratio(K, beta, half_bin)

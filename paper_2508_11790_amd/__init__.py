@@ -23,7 +23,11 @@ __all__ = ["Plan", "Mlp", "WbmError", "FORM_PLAIN", "FORM_FUSED", "FORM_GRAPH", 
 MLP_PARAMS = _lib.MLP_PARAMS
 
 _FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH,
-          "mixed": _lib.FORM_MIXED, "mixed_bf16": _lib.FORM_MIXED_BF16}
+          "mixed": _lib.FORM_MIXED, "mixed_bf16": _lib.FORM_MIXED_BF16,
+          "fused_f32": _lib.FORM_FUSED_F32, "graph_f32": _lib.FORM_GRAPH_F32}
+# precision of the fused sequence a launch configuration applies to: "ext" (fused / graph /
+# learned forms) or "f32" (fused_f32 / graph_f32, the mixed forms' transforms, planar array)
+_PRECS = {"ext": _lib.PREC_EXT, "f32": _lib.PREC_F32}
 INFO_ROUTED = _lib.INFO_ROUTED
 
 
@@ -87,23 +91,30 @@ class Plan:
                      "resident": _lib.PAIR_RESIDENT}
 
     def set_tuning(self, chan_logtile: int, beam_logtile: int, pair_kernel: str = "block",
-                   overlap: int = 1):
-        """Pin the fused form's FFT tiles (log2 complex per workgroup: 11..13), pair kernel
-        ("mfma", "wave", "block" or "resident") and subband chunks overlapping the spatial DFT with the pair
-        kernel (1, 2, 4, 8); skips the first call's timing search."""
+                   overlap: int = 1, precision: str = "ext"):
+        """Pin the fused sequence's FFT tiles (log2 complex per workgroup: 11..13, or 10..13 in
+        extended precision), pair kernel ("mfma", "wave", "block" or "resident"; extended
+        precision: "wave" or "block") and subband chunks overlapping the spatial DFT with the
+        pair kernel (1, 2, 4, 8) for one precision ("ext" or "f32"); skips that precision's
+        first-call timing search."""
         if pair_kernel not in self._PAIR_KERNELS:
             raise ValueError(f"pair_kernel must be one of {sorted(self._PAIR_KERNELS)}")
-        _lib.check(_lib.load().wbm_plan_set_tuning(self._h, int(chan_logtile), int(beam_logtile),
+        _lib.check(_lib.load().wbm_plan_set_tuning(self._h, _PRECS[precision], int(chan_logtile),
+                                                   int(beam_logtile),
                                                    self._PAIR_KERNELS[pair_kernel], int(overlap)))
+
+    def get_tuning(self, precision: str = "ext"):
+        """(chan_logtile, beam_logtile, pair_kernel name, overlap chunks) of one precision."""
+        c, b, p, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.load().wbm_plan_get_tuning(self._h, _PRECS[precision], C.byref(c),
+                                                   C.byref(b), C.byref(p), C.byref(o)))
+        name = {v: k for k, v in self._PAIR_KERNELS.items()}[p.value]
+        return int(c.value), int(b.value), name, int(o.value)
 
     @property
     def tuning(self):
-        """(chan_logtile, beam_logtile, pair_kernel name, overlap chunks) currently in use."""
-        c, b, p, o = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
-        _lib.check(_lib.load().wbm_plan_get_tuning(self._h, C.byref(c), C.byref(b), C.byref(p),
-                                                   C.byref(o)))
-        name = {v: k for k, v in self._PAIR_KERNELS.items()}[p.value]
-        return int(c.value), int(b.value), name, int(o.value)
+        """Launch configuration of the extended-precision fused sequence (get_tuning("ext"))."""
+        return self.get_tuning("ext")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -369,15 +380,17 @@ class Plan:
 
     STAGES = ("steer", "channelize", "beamspace", "mvdr")
 
-    def stage_times(self, x, az_rad, win, loading: float, reps: int = 20, stream=None):
-        """Average milliseconds per kernel of the fused sequence, timed with HIP events."""
+    def stage_times(self, x, az_rad, win, loading: float, reps: int = 20, stream=None,
+                    precision: str = "ext"):
+        """Average milliseconds per kernel of the fused sequence in one precision ("ext": the
+        fused form, "f32": fused_f32), timed with HIP events."""
         self._x(x)
         az, w, T = self._targets(az_rad, win)
         ms = np.zeros(4, dtype=np.float64)
         _lib.check(_lib.load().wbm_stage_times(self._h, _ptr(x), az.ctypes.data,
                                                None if w is None else w.ctypes.data, T,
-                                               float(loading), int(reps), ms.ctypes.data,
-                                               _stream(stream)))
+                                               float(loading), _PRECS[precision], int(reps),
+                                               ms.ctypes.data, _stream(stream)))
         return dict(zip(self.STAGES, ms.tolist()))
 
     # ------------------------------------------------------------------ loading / window predictor

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(_PKG, "libwbmvdr.so")
 
 WBM_HALF_BIN = 1
 FORM_PLAIN, FORM_FUSED, FORM_GRAPH, FORM_MIXED, FORM_MIXED_BF16 = 0, 1, 2, 3, 4
+FORM_FUSED_F32, FORM_GRAPH_F32 = 5, 6
+PREC_EXT, PREC_F32 = 0, 1
 INFO_ROUTED = 1 << 30
 PAIR_MFMA, PAIR_RESIDENT, PAIR_WAVE, PAIR_BLOCK = 1, 2, 64, 256
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "out of memory",
@@ -59,14 +61,14 @@ def load() -> C.CDLL:
     lib.wbm_plan_destroy.argtypes = [P]
     lib.wbm_plan_workspace_bytes.argtypes = [P]
     lib.wbm_plan_workspace_bytes.restype = I64
-    lib.wbm_plan_set_tuning.argtypes = [P, I32, I32, I32, I32]
-    lib.wbm_plan_get_tuning.argtypes = [P, P, P, P, P]
+    lib.wbm_plan_set_tuning.argtypes = [P, I32, I32, I32, I32, I32]
+    lib.wbm_plan_get_tuning.argtypes = [P, I32, P, P, P, P]
     lib.wbm_beamform.argtypes = [P, P, P, P, I32, D, I32, P, P, P, P, P]
     lib.wbm_channelize.argtypes = [P, P, P, P]
     lib.wbm_beamspace.argtypes = [P, P, P, P]
     lib.wbm_steer.argtypes = [P, P, P, I32, P, P, P]
     lib.wbm_full_mvdr.argtypes = [P, P, P, I32, D, P, P, P, P]
-    lib.wbm_stage_times.argtypes = [P, P, P, P, I32, D, I32, P, P]
+    lib.wbm_stage_times.argtypes = [P, P, P, P, I32, D, I32, I32, P, P]
     lib.wbm_profiles.argtypes = [P, P, P, I32, D, P, P]
     lib.wbm_beamform_pairs.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P]
     lib.wbm_beamform_learned.argtypes = [P, P, P, I32, P, D, I32, D, P, P, P, P, P, P, P, P]

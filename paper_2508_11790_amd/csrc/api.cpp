@@ -48,6 +48,7 @@ int ilog2i(int v) {
 constexpr int kMaxOverlap = 8;
 
 struct GraphKey {
+  int prec = 0;
   const void* x = nullptr;
   void* out = nullptr;
   void* weights = nullptr;
@@ -57,22 +58,31 @@ struct GraphKey {
   double loading = 0.0;
   bool valid = false;
   bool operator==(const GraphKey& o) const {
-    return valid && o.valid && x == o.x && out == o.out && weights == o.weights && info == o.info &&
+    return valid && o.valid && prec == o.prec && x == o.x && out == o.out && weights == o.weights && info == o.info &&
            starts == o.starts && T == o.T && sumW == o.sumW && loading == o.loading;
   }
 };
 
 }  // namespace
 
+// Precision of the fused sequence's intermediates: extended (FP64 transforms, hi + lo storage
+// of X and the windows) or FP32.
+constexpr int kExt = 0, kF32 = 1;
+
+// Launch configuration of the fused sequence in one precision.
+struct Tuning {
+  int chan_logtile = 12, beam_logtile = 12;
+  int logTB = 0, TB = 0, nbt = 0;     // beamspace tile (snapshots per workgroup)
+  int pair_threads = WBM_PAIR_BLOCK;  // pair kernel: WBM_PAIR_*
+  int overlap = 1;                    // subband chunks overlapping beamspace and pair kernels
+  bool tuned = false;                 // timed by the autotuner or pinned
+};
+
 struct wbm_plan {
   wbm_config cfg;
   int B = 0;
   int64_t S = 0;
-  int logTB = 0, TB = 0, nbt = 0;     // beamspace tile (snapshots per workgroup) of the fused form
-  int chan_logtile = 12, beam_logtile = 12;
-  int pair_threads = WBM_PAIR_MFMA;   // fused MVDR pair kernel: WBM_PAIR_*
-  int overlap = 1;                    // subband chunks overlapping beamspace and pair kernels
-  bool tuned = false;
+  Tuning tune[2];                     // [kExt], [kF32]
   int upa_pair = WBM_PAIR_MFMA;       // pair kernel of the planar-array path (timed on first use)
   bool upa_tuned = false;
   // second stream of the overlapped fused sequence and its fork / join events
@@ -83,6 +93,9 @@ struct wbm_plan {
   float2* twK = nullptr;
   float2* twM = nullptr;
   float2* hb = nullptr;
+  double2* twK64 = nullptr;  // FP64 tables of the extended-precision transforms (first use)
+  double2* twM64 = nullptr;
+  double2* hb64 = nullptr;
   // per-call target description: device copy + pinned staging
   unsigned char* desc_dev = nullptr;
   unsigned char* desc_host = nullptr;
@@ -95,8 +108,10 @@ struct wbm_plan {
   hipStream_t desc_stream = nullptr;
   wbm::DevDesc dd{};
   // workspace
-  float2* X = nullptr;       // [K][B][N]
-  float2* Yw = nullptr;      // [K][nbt][T_max*w_max][TB]
+  float2* X = nullptr;       // [K][B][N] (extended precision: the FP32 hi part)
+  float2* Yw = nullptr;      // [K][nbt][T_max*w_max][TB] (extended precision: hi part)
+  uint32_t* Xl = nullptr;    // [K][B][N] BF16 remainders of X (extended precision, first use)
+  uint32_t* Ywl = nullptr;   // BF16 remainders of the windows, Yw's layout (first use)
   float2* Y = nullptr;       // [K][M][B]      (plain form, allocated on first use)
   float2* R32 = nullptr;     // [T_max*K][w_max^2] (plain form)
   float2* w32 = nullptr;     // [T_max*K][w_max]   (plain form)
@@ -107,6 +122,7 @@ struct wbm_plan {
   int* full_info = nullptr;  // [K]
   int nk_full = 0;
   int64_t ws_bytes = 0;
+  size_t yw_elems = 0;       // complex entries of Yw (and of Ywl)
   // graph replay of the fused sequence
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -166,6 +182,18 @@ wbm_status upload_twiddles(float2* dst, int n, double sign_frac) {
     h[q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
   }
   WBM_HIP(hipMemcpy(dst, h.data(), sizeof(float2) * n, hipMemcpyHostToDevice), "twiddle upload");
+  return WBM_OK;
+}
+
+wbm_status upload_twiddles64(double2* dst, int n, double sign_frac) {
+  // the FP64 tables of the extended-precision transforms, from long double sin / cos
+  std::vector<double2> h(n);
+  for (int q = 0; q < n; ++q) {
+    const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)q /
+                            (long double)n * (long double)sign_frac;
+    h[q] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+  }
+  WBM_HIP(hipMemcpy(dst, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice), "twiddle upload");
   return WBM_OK;
 }
 
@@ -344,7 +372,7 @@ wbm_status ensure_prof(wbm_plan* p) {
   return dev_alloc(p, &p->prof_info, pairs, "timing info");
 }
 
-wbm::PairArgs pair_args(const wbm_plan* p, int T, int sumW, double loading) {
+wbm::PairArgs pair_args(const wbm_plan* p, int prec, int T, int sumW, double loading) {
   wbm::PairArgs a;
   a.T = T;
   a.K = p->cfg.k_sub;
@@ -353,10 +381,11 @@ wbm::PairArgs pair_args(const wbm_plan* p, int T, int sumW, double loading) {
   a.Lt = p->cfg.l_test;
   a.B = p->B;
   a.wmax = p->cfg.w_max;
-  a.logTB = p->logTB;
-  a.nbt = p->nbt;
+  a.logTB = p->tune[prec].logTB;
+  a.nbt = p->tune[prec].nbt;
   a.sumW = sumW;
   a.delta = loading;
+  a.ywl = prec == kExt ? p->Ywl : nullptr;
   return a;
 }
 
@@ -397,23 +426,61 @@ bool resident_ok(const wbm_plan* p) {
   return wbm::mvdr_resident_supported(p->cfg.w_max, p->cfg.l_train, p->cfg.l_test);
 }
 
-void set_beam_tile(wbm_plan* p, int logtile) {
-  p->beam_logtile = logtile;
-  p->logTB = wbm::beamspace_tile_log(p->cfg.m_fft, logtile);
-  p->TB = 1 << p->logTB;
-  p->nbt = (p->B + p->TB - 1) / p->TB;
+void set_beam_tile(wbm_plan* p, int prec, int logtile) {
+  Tuning& t = p->tune[prec];
+  t.beam_logtile = logtile;
+  t.logTB = wbm::beamspace_tile_log(p->cfg.m_fft, logtile);
+  t.TB = 1 << t.logTB;
+  t.nbt = (p->B + t.TB - 1) / t.TB;
 }
 
-hipError_t enqueue_channelize(wbm_plan* p, const float2* x, hipStream_t st) {
-  const wbm_config& c = p->cfg;
-  return wbm::launch_channelize(x, p->X, c.n_elem, c.k_sub, p->B, p->twK,
-                                (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, p->chan_logtile, st);
+bool logtile_ok(int prec, int logtile) {
+  return prec == kExt ? wbm::fft_x_logtile_supported(logtile)
+                      : wbm::fft_logtile_supported(logtile);
 }
 
-hipError_t enqueue_beamspace_windows(wbm_plan* p, int T, int sumW, hipStream_t st) {
+// Workspace of the extended-precision intermediates: the BF16 remainder planes of X and the
+// windows, and the FP64 twiddle tables.
+wbm_status ensure_ext(wbm_plan* p) {
+  if (p->Xl) return WBM_OK;
   const wbm_config& c = p->cfg;
-  return wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
-                               p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st);
+  wbm_status s;
+  if ((s = dev_alloc(p, &p->twK64, c.k_sub, "FP64 twiddles K"))) return s;
+  if ((s = dev_alloc(p, &p->twM64, c.m_fft, "FP64 twiddles M"))) return s;
+  if ((s = dev_alloc(p, &p->hb64, c.k_sub, "FP64 half-bin twiddles"))) return s;
+  if ((s = upload_twiddles64(p->twK64, c.k_sub, 1.0))) return s;
+  if ((s = upload_twiddles64(p->twM64, c.m_fft, 1.0))) return s;
+  if ((s = upload_twiddles64(p->hb64, c.k_sub, 0.5))) return s;
+  if ((s = dev_alloc(p, &p->Ywl, p->yw_elems, "window remainders"))) return s;
+  return dev_alloc(p, &p->Xl, (size_t)c.n_elem * p->S, "X remainders");
+}
+
+hipError_t enqueue_channelize(wbm_plan* p, int prec, const float2* x, hipStream_t st) {
+  const wbm_config& c = p->cfg;
+  const bool hb = (c.flags & WBM_HALF_BIN) != 0;
+  if (prec == kExt)
+    return wbm::launch_channelize_x(x, p->X, p->Xl, c.n_elem, c.k_sub, p->B, p->twK64,
+                                    hb ? p->hb64 : nullptr, p->tune[kExt].chan_logtile, st);
+  return wbm::launch_channelize(x, p->X, c.n_elem, c.k_sub, p->B, p->twK, hb ? p->hb : nullptr,
+                                p->tune[kF32].chan_logtile, st);
+}
+
+// Windowed spatial DFT of subbands k0 .. k0 + kc - 1 (kc < 0: all), optionally with the
+// training power-profile partials (prof, G workgroups per subband).
+hipError_t enqueue_beamspace_windows(wbm_plan* p, int prec, int T, int sumW, hipStream_t st,
+                                     int k0 = 0, int kc = -1, bool windows = true,
+                                     float* prof = nullptr, int G = 0) {
+  const wbm_config& c = p->cfg;
+  const Tuning& t = p->tune[prec];
+  const int L = prof ? c.l_train : 0;
+  if (prec == kExt)
+    return wbm::launch_beamspace_x(p->X, p->Xl, windows ? p->Yw : nullptr,
+                                   windows ? p->Ywl : nullptr, c.n_elem, c.m_fft, p->B, c.k_sub,
+                                   p->twM64, p->dd.rowtab, sumW, geom(p, T), t.beam_logtile, st,
+                                   prof, L, G, k0, kc);
+  return wbm::launch_beamspace(p->X, nullptr, windows ? p->Yw : nullptr, c.n_elem, c.m_fft, p->B,
+                               c.k_sub, p->twM, p->dd.rowtab, sumW, geom(p, T), t.beam_logtile,
+                               st, prof, L, G, k0, kc);
 }
 
 bool overlap_supported(const wbm_plan* p, int chunks) {
@@ -421,45 +488,38 @@ bool overlap_supported(const wbm_plan* p, int chunks) {
                          p->cfg.k_sub % (8 * chunks) == 0);
 }
 
-hipError_t ensure_side_stream(wbm_plan* p) {
-  if (p->side_stream) return hipSuccess;
-  hipError_t e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
-  for (int i = 0; i <= kMaxOverlap && e == hipSuccess; ++i)
-    e = hipEventCreateWithFlags(&p->chunk_evt[i], hipEventDisableTiming);
-  return e;
-}
 
 // Channelize -> windowed beamspace -> fused MVDR on stream st (the beamspace and pair
 // kernels place the windows themselves).  With C > 1 overlap chunks the subbands are split in
 // C ranges: the pair kernel of range c runs on the plan's second stream while the beamspace
 // kernel of range c + 1 streams on st (the first is HBM-bound, the second latency- or
 // FP64-bound), joined back into st at the end; under graph capture this becomes a fork / join.
-hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
-                         float2* out, float2* wout, int* starts, int* info, hipStream_t st,
-                         int chunks) {
-  hipError_t e = enqueue_channelize(p, x, st);
+hipError_t enqueue_fused(wbm_plan* p, int prec, const float2* x, int T, int sumW,
+                         double loading, float2* out, float2* wout, int* starts, int* info,
+                         hipStream_t st, int chunks) {
+  hipError_t e = enqueue_channelize(p, prec, x, st);
   if (e != hipSuccess) return e;
   const wbm_config& c = p->cfg;
+  const int thr = p->tune[prec].pair_threads;
   if (chunks <= 1 || !overlap_supported(p, chunks)) {
-    e = enqueue_beamspace_windows(p, T, sumW, st);
+    e = enqueue_beamspace_windows(p, prec, T, sumW, st);
     if (e != hipSuccess) return e;
-    return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, out,
-                                  wout, starts, info, p->pair_threads, st);
+    return wbm::launch_mvdr_fused(pair_args(p, prec, T, sumW, loading), geom(p, T), p->dd, p->Yw,
+                                  out, wout, starts, info, thr, st);
   }
-  if ((e = ensure_side_stream(p)) != hipSuccess) return e;
+  // the side stream and its events exist from plan creation on: nothing is created here, where
+  // st may be capturing
   const int kc = c.k_sub / chunks;
   for (int ch = 0; ch < chunks && e == hipSuccess; ++ch) {
-    e = wbm::launch_beamspace(p->X, nullptr, p->Yw, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
-                              p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st, nullptr, 0, 0,
-                              ch * kc, kc);
+    e = enqueue_beamspace_windows(p, prec, T, sumW, st, ch * kc, kc);
     if (e == hipSuccess) e = hipEventRecord(p->chunk_evt[ch], st);
     if (e == hipSuccess) e = hipStreamWaitEvent(p->side_stream, p->chunk_evt[ch], 0);
     if (e == hipSuccess) {
-      wbm::PairArgs a = pair_args(p, T, sumW, loading);
+      wbm::PairArgs a = pair_args(p, prec, T, sumW, loading);
       a.k0 = ch * kc;
       a.kc = kc;
-      e = wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, out, wout, starts, info,
-                                 p->pair_threads, p->side_stream);
+      e = wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, out, wout, starts, info, thr,
+                                 p->side_stream);
     }
   }
   if (e == hipSuccess) e = hipEventRecord(p->chunk_evt[chunks], p->side_stream);
@@ -467,9 +527,11 @@ hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double l
   return e;
 }
 
-hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double loading,
-                         float2* out, float2* wout, int* starts, int* info, hipStream_t st) {
-  return enqueue_fused(p, x, T, sumW, loading, out, wout, starts, info, st, p->overlap);
+hipError_t enqueue_fused(wbm_plan* p, int prec, const float2* x, int T, int sumW,
+                         double loading, float2* out, float2* wout, int* starts, int* info,
+                         hipStream_t st) {
+  return enqueue_fused(p, prec, x, T, sumW, loading, out, wout, starts, info, st,
+                       p->tune[prec].overlap);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -479,7 +541,7 @@ hipError_t enqueue_fused(wbm_plan* p, const float2* x, int T, int sumW, double l
 // shape ($WBM_AUTOTUNE_CACHE, default ~/.cache/wbmvdr/autotune.json); WBM_AUTOTUNE=0
 // disables tuning (tile 2^12).
 
-std::string tune_key(const wbm_plan* p) {
+std::string tune_key(const wbm_plan* p, int prec) {
   hipDeviceProp_t prop;
   std::string arch = "gpu";
   if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
@@ -488,7 +550,8 @@ std::string tune_key(const wbm_plan* p) {
   const wbm_config& c = p->cfg;
   std::ostringstream os;
   os << arch << "/N" << c.n_elem << "/M" << c.m_fft << "/K" << c.k_sub << "/B" << p->B << "/L"
-     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max << "/p6";
+     << c.l_train << "/T" << c.max_targets << "/W" << c.w_max
+     << (prec == kExt ? "/x1" : "/f7");
   return os.str();
 }
 
@@ -503,7 +566,7 @@ std::string cache_path() {
 // {"key": [chan_logtile, beam_logtile, pair_kernel, overlap_chunks], ...}
 // (pair_kernel: 1 = FP64 matrix-core kernel, 2 = LDS-resident kernel, 64 / 256 = vector kernel
 // with that many threads).
-bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr, int* ovl) {
+bool cache_lookup(const std::string& key, int prec, int* chan, int* beam, int* thr, int* ovl) {
   std::ifstream f(cache_path());
   if (!f) return false;
   std::stringstream ss;
@@ -515,9 +578,9 @@ bool cache_lookup(const std::string& key, int* chan, int* beam, int* thr, int* o
   int a = 0, b = 0, c = 0, o = 0;
   if (std::sscanf(txt.c_str() + pos + pat.size(), "%d, %d, %d, %d", &a, &b, &c, &o) != 4)
     return false;
-  if (!wbm::fft_logtile_supported(a) || !wbm::fft_logtile_supported(b)) return false;
-  if (c != WBM_PAIR_MFMA && c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK &&
-      c != WBM_PAIR_RESIDENT)
+  if (!logtile_ok(prec, a) || !logtile_ok(prec, b)) return false;
+  if (c != WBM_PAIR_WAVE && c != WBM_PAIR_BLOCK &&
+      (prec == kExt || (c != WBM_PAIR_MFMA && c != WBM_PAIR_RESIDENT)))
     return false;
   *chan = a;
   *beam = b;
@@ -583,52 +646,62 @@ hipError_t time_best(F launch, hipStream_t st, float* best_ms) {
   return e;
 }
 
-hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loading,
+// Pair kernels each precision can run: the extended-precision windows need the vector kernels.
+bool pair_ok(const wbm_plan* p, int prec, int thr) {
+  if (thr == WBM_PAIR_WAVE) return wbm::mvdr_wave_supported(p->cfg.w_max);
+  if (thr == WBM_PAIR_BLOCK) return true;
+  if (prec == kExt) return false;
+  if (thr == WBM_PAIR_RESIDENT) return resident_ok(p);
+  return thr == WBM_PAIR_MFMA;
+}
+
+hipError_t autotune(wbm_plan* p, int prec, const float2* x, int T, int sumW, double loading,
                     hipStream_t st) {
-  p->tuned = true;
+  Tuning& tn = p->tune[prec];
+  tn.tuned = true;
   const char* env = std::getenv("WBM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
-  const std::string key = tune_key(p);
-  int chan = 12, beam = 12, thr = WBM_PAIR_MFMA, ovl = 1;
-  if (cache_lookup(key, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl) &&
-      (thr != WBM_PAIR_RESIDENT || resident_ok(p))) {
-    p->chan_logtile = chan;
-    set_beam_tile(p, beam);
-    p->pair_threads = thr;
-    p->overlap = ovl;
+  const std::string key = tune_key(p, prec);
+  int chan = 12, beam = 12, thr = WBM_PAIR_BLOCK, ovl = 1;
+  if (cache_lookup(key, prec, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl) &&
+      pair_ok(p, prec, thr)) {
+    tn.chan_logtile = chan;
+    set_beam_tile(p, prec, beam);
+    tn.pair_threads = thr;
+    tn.overlap = ovl;
     return hipSuccess;
   }
   float best_c = 1e30f, best_b = 1e30f;
-  for (int lt = 11; lt <= 13; ++lt) {
+  const int lt0 = prec == kExt ? 10 : 11;
+  for (int lt = lt0; lt <= 13; ++lt) {
     float ms;
-    p->chan_logtile = lt;
-    hipError_t e = time_best([&]() { return enqueue_channelize(p, x, st); }, st, &ms);
+    tn.chan_logtile = lt;
+    hipError_t e = time_best([&]() { return enqueue_channelize(p, prec, x, st); }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_c) {
       best_c = ms;
       chan = lt;
     }
-    set_beam_tile(p, lt);
-    e = time_best([&]() { return enqueue_beamspace_windows(p, T, sumW, st); }, st, &ms);
+    set_beam_tile(p, prec, lt);
+    e = time_best([&]() { return enqueue_beamspace_windows(p, prec, T, sumW, st); }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_b) {
       best_b = ms;
       beam = lt;
     }
   }
-  p->chan_logtile = chan;
-  set_beam_tile(p, beam);
+  tn.chan_logtile = chan;
+  set_beam_tile(p, prec, beam);
   // pair kernel: each candidate timed in the whole fused sequence (channelize, windows, pair
   // kernel), where it reads windows the spatial DFT has just written
   hipError_t e = hipSuccess;
   float best_p = 1e30f;
   for (int thr_c : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
-    if (thr_c == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max)) continue;
-    if (thr_c == WBM_PAIR_RESIDENT && !resident_ok(p)) continue;
+    if (!pair_ok(p, prec, thr_c)) continue;
     float ms;
-    p->pair_threads = thr_c;
+    tn.pair_threads = thr_c;
     e = time_best([&]() {
-      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
+      return enqueue_fused(p, prec, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
                            p->prof_info, st, 1);
     }, st, &ms);
     if (e != hipSuccess) return e;
@@ -637,15 +710,15 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
       thr = thr_c;
     }
   }
-  p->pair_threads = thr;
+  tn.pair_threads = thr;
   // subband chunks overlapping the beamspace and pair kernels: the whole fused sequence
   float best_o = 1e30f;
   for (int ch = 1; ch <= kMaxOverlap; ch <<= 1) {
     if (!overlap_supported(p, ch)) continue;
     float ms;
     e = time_best([&]() {
-      return enqueue_fused(p, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr, p->prof_info,
-                           st, ch);
+      return enqueue_fused(p, prec, x, T, sumW, loading, p->prof_out, p->prof_w, nullptr,
+                           p->prof_info, st, ch);
     }, st, &ms);
     if (e != hipSuccess) return e;
     if (ms < best_o) {
@@ -653,9 +726,22 @@ hipError_t autotune(wbm_plan* p, const float2* x, int T, int sumW, double loadin
       ovl = ch;
     }
   }
-  p->overlap = ovl;
+  tn.overlap = ovl;
   cache_store(key, chan, beam, thr, ovl);
   return hipSuccess;
+}
+
+// The workspace and the launch configuration of the fused sequence in precision prec, tuned
+// on this call's data on first use.
+wbm_status ready_fused(wbm_plan* p, int prec, const float2* x, int T, int sumW, double loading,
+                       hipStream_t st) {
+  wbm_status s;
+  if (prec == kExt && (s = ensure_ext(p))) return s;
+  if (!p->tune[prec].tuned) {
+    if ((s = ensure_prof(p))) return s;
+    WBM_HIP(autotune(p, prec, x, T, sumW, loading, st), "autotune");
+  }
+  return WBM_OK;
 }
 
 static_assert(WBM_PAIR_MFMA == wbm::kPairMfma && WBM_PAIR_RESIDENT == wbm::kPairResident,
@@ -690,11 +776,15 @@ const char* wbm_status_str(wbm_status s) {
 
 int64_t wbm_plan_workspace_bytes(const wbm_plan* p) { return p ? p->ws_bytes : 0; }
 
-wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t pair,
-                               int32_t overlap) {
+wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t precision, int32_t chan, int32_t beam,
+                               int32_t pair, int32_t overlap) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
-  if (!wbm::fft_logtile_supported(chan) || !wbm::fft_logtile_supported(beam))
-    return fail(WBM_ERR_ARG, "FFT tile log2 must be 11, 12 or 13");
+  if (precision != WBM_PREC_EXT && precision != WBM_PREC_F32)
+    return fail(WBM_ERR_ARG, "precision must be WBM_PREC_EXT or WBM_PREC_F32");
+  const int prec = precision == WBM_PREC_EXT ? kExt : kF32;
+  if (!logtile_ok(prec, chan) || !logtile_ok(prec, beam))
+    return fail(WBM_ERR_ARG, prec == kExt ? "FFT tile log2 must be 10, 11, 12 or 13"
+                                          : "FFT tile log2 must be 11, 12 or 13");
   if (pair != WBM_PAIR_MFMA && pair != WBM_PAIR_WAVE && pair != WBM_PAIR_BLOCK &&
       pair != WBM_PAIR_RESIDENT)
     return fail(WBM_ERR_ARG,
@@ -702,6 +792,9 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
                 "WBM_PAIR_RESIDENT");
   if (pair == WBM_PAIR_WAVE && !wbm::mvdr_wave_supported(p->cfg.w_max))
     return fail(WBM_ERR_UNSUPPORTED, "the one-wave pair kernel needs w_max <= 40");
+  if (prec == kExt && (pair == WBM_PAIR_MFMA || pair == WBM_PAIR_RESIDENT))
+    return fail(WBM_ERR_UNSUPPORTED,
+                "the extended-precision windows run on WBM_PAIR_BLOCK or WBM_PAIR_WAVE");
   if (pair == WBM_PAIR_RESIDENT && !resident_ok(p))
     return fail(WBM_ERR_UNSUPPORTED,
                 "the resident pair kernel needs w_max * L <= 2304 and w_max * Lt <= 2304");
@@ -709,24 +802,30 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t chan, int32_t beam, int32_t 
     return fail(WBM_ERR_ARG, "overlap_chunks must be 1, 2, 4 or 8");
   if (!overlap_supported(p, overlap))
     return fail(WBM_ERR_UNSUPPORTED, "overlap_chunks needs K to be a multiple of 8 * chunks");
-  p->chan_logtile = chan;
-  set_beam_tile(p, beam);
-  p->pair_threads = pair;
-  p->overlap = overlap;
-  p->tuned = true;
-  p->upa_pair = pair;
-  p->upa_tuned = true;
+  Tuning& tn = p->tune[prec];
+  tn.chan_logtile = chan;
+  set_beam_tile(p, prec, beam);
+  tn.pair_threads = pair;
+  tn.overlap = overlap;
+  tn.tuned = true;
+  if (prec == kF32) {
+    p->upa_pair = pair;
+    p->upa_tuned = true;
+  }
   p->gkey.valid = false;
   return WBM_OK;
 }
 
-wbm_status wbm_plan_get_tuning(const wbm_plan* p, int32_t* chan, int32_t* beam, int32_t* pair,
-                               int32_t* overlap) {
+wbm_status wbm_plan_get_tuning(const wbm_plan* p, int32_t precision, int32_t* chan,
+                               int32_t* beam, int32_t* pair, int32_t* overlap) {
   if (!p) return fail(WBM_ERR_ARG, "plan is NULL");
-  if (chan) *chan = p->chan_logtile;
-  if (beam) *beam = p->beam_logtile;
-  if (pair) *pair = p->pair_threads;
-  if (overlap) *overlap = p->overlap;
+  if (precision != WBM_PREC_EXT && precision != WBM_PREC_F32)
+    return fail(WBM_ERR_ARG, "precision must be WBM_PREC_EXT or WBM_PREC_F32");
+  const Tuning& tn = p->tune[precision == WBM_PREC_EXT ? kExt : kF32];
+  if (chan) *chan = tn.chan_logtile;
+  if (beam) *beam = tn.beam_logtile;
+  if (pair) *pair = tn.pair_threads;
+  if (overlap) *overlap = tn.overlap;
   return WBM_OK;
 }
 
@@ -743,7 +842,8 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   if (p->desc_host) (void)hipHostFree(p->desc_host);
   if (p->jam_evt) (void)hipEventDestroy(p->jam_evt);
   if (p->jam_host) (void)hipHostFree(p->jam_host);
-  void* bufs[] = {p->twK, p->twM, p->hb, p->desc_dev, p->X, p->Yw, p->Y, p->R32,
+  void* bufs[] = {p->twK, p->twM, p->hb, p->twK64, p->twM64, p->hb64, p->Xl, p->Ywl,
+                  p->desc_dev, p->X, p->Yw, p->Y, p->R32,
                   p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
                   p->prof_out, p->prof_w, p->prof_info, p->pprof, p->feat, p->nnout,
                   p->pw, p->pdelta, p->jam_dev, p->route, p->upa_rows};
@@ -793,7 +893,9 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   (void)hipGetDevice(&p->device);
   p->B = (int)B;
   p->S = B * c.k_sub;
-  set_beam_tile(p, 12);
+  set_beam_tile(p, kExt, 12);
+  set_beam_tile(p, kF32, 12);
+  p->tune[kF32].pair_threads = WBM_PAIR_MFMA;
 
   auto bail = [&](wbm_status s) {
     std::string keep = g_err;
@@ -833,8 +935,8 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   // room for the snapshot padding of the largest beamspace tile the autotuner may pick
   const size_t tb_max = (size_t)1 << wbm::beamspace_tile_log(c.m_fft, 13);
   const size_t b_pad = ((size_t)p->B + tb_max - 1) / tb_max * tb_max;
-  if ((s = dev_alloc(p, &p->Yw, (size_t)c.k_sub * b_pad * (size_t)Tm * c.w_max, "windows Yw")))
-    return bail(s);
+  p->yw_elems = (size_t)c.k_sub * b_pad * (size_t)Tm * c.w_max;
+  if ((s = dev_alloc(p, &p->Yw, p->yw_elems, "windows Yw"))) return bail(s);
   if ((s = dev_alloc(p, &p->starts, (size_t)Tm * c.k_sub, "starts"))) return bail(s);
   if ((s = dev_alloc(p, &p->abar, (size_t)Tm * c.k_sub * c.w_max, "steering"))) return bail(s);
   if ((s = dev_alloc(p, &p->full_info, (size_t)c.k_sub, "full info"))) return bail(s);
@@ -847,6 +949,13 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   if (he != hipSuccess) return bail(hip_fail(he, "hipFuncSetAttribute (full-dimensional kernels)"));
   if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(WBM_ERR_HIP, "capture stream creation failed"));
+  // the overlapped fused sequence's second stream and its fork / join events: created here,
+  // never while a stream may be capturing
+  if (hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(WBM_ERR_HIP, "side stream creation failed"));
+  for (int i = 0; i <= kMaxOverlap; ++i)
+    if (hipEventCreateWithFlags(&p->chunk_evt[i], hipEventDisableTiming) != hipSuccess)
+      return bail(fail(WBM_ERR_HIP, "event creation failed"));
   *out = p;
   return WBM_OK;
 }
@@ -871,8 +980,8 @@ wbm_status wbm_channelize(wbm_plan* p, const wbm_c32* x, wbm_c32* X, void* strea
   const wbm_config& c = p->cfg;
   WBM_HIP(wbm::launch_channelize(reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(X),
                                  c.n_elem, c.k_sub, p->B, p->twK,
-                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr, p->chan_logtile,
-                                 static_cast<hipStream_t>(stream)),
+                                 (c.flags & WBM_HALF_BIN) ? p->hb : nullptr,
+                                 p->tune[kF32].chan_logtile, static_cast<hipStream_t>(stream)),
           "channelize launch");
   return WBM_OK;
 }
@@ -899,7 +1008,8 @@ wbm_status wbm_apply_lifted(wbm_plan* p, const wbm_c32* x, const wbm_c32* c_hat,
   const wbm_config& c = p->cfg;
   if (T < 1 || T > c.max_targets) return fail(WBM_ERR_ARG, "T outside [1, max_targets]");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  WBM_HIP(enqueue_channelize(p, reinterpret_cast<const float2*>(x), st), "channelize launch");
+  WBM_HIP(enqueue_channelize(p, kF32, reinterpret_cast<const float2*>(x), st),
+          "channelize launch");
   WBM_HIP(wbm::launch_lift_apply(p->X, reinterpret_cast<const float2*>(c_hat),
                                  reinterpret_cast<float2*>(out), c.n_elem, c.k_sub, p->B,
                                  c.l_train, c.l_test, T, st),
@@ -999,7 +1109,8 @@ wbm_status wbm_beamspace(wbm_plan* p, const wbm_c32* X, wbm_c32* Y, void* stream
   const wbm_config& c = p->cfg;
   WBM_HIP(wbm::launch_beamspace(reinterpret_cast<const float2*>(X), reinterpret_cast<float2*>(Y),
                                 nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM, nullptr, 0,
-                                geom(p, 0), p->beam_logtile, static_cast<hipStream_t>(stream)),
+                                geom(p, 0), p->tune[kF32].beam_logtile,
+                                static_cast<hipStream_t>(stream)),
           "beamspace launch");
   return WBM_OK;
 }
@@ -1013,46 +1124,47 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
   if (!x) return fail(WBM_ERR_ARG, "x is NULL");
   if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
-  if (form < WBM_FORM_PLAIN || form > WBM_FORM_MIXED_BF16) return fail(WBM_ERR_ARG, "unknown form");
+  if (form < WBM_FORM_PLAIN || form > WBM_FORM_GRAPH_F32) return fail(WBM_ERR_ARG, "unknown form");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
   float2* o = reinterpret_cast<float2*>(out);
   float2* w = reinterpret_cast<float2*>(weights);
   const float2* xx = reinterpret_cast<const float2*>(x);
-  if (form != WBM_FORM_PLAIN && !p->tuned) {
-    if ((s = ensure_prof(p))) return s;
-    WBM_HIP(autotune(p, xx, T, sumW, loading, st), "autotune");
-  }
+  // the fused forms' intermediates: extended precision, or FP32 (the *_F32 forms and the mixed
+  // forms, whose covariance is formed at lower precision still)
+  const int prec = (form == WBM_FORM_FUSED || form == WBM_FORM_GRAPH) ? kExt : kF32;
+  if (form != WBM_FORM_PLAIN && (s = ready_fused(p, prec, xx, T, sumW, loading, st))) return s;
   if (form == WBM_FORM_PLAIN) {
     if ((s = ensure_plain(p))) return s;
     WBM_HIP(wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st), "steer launch");
-    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
+    WBM_HIP(enqueue_channelize(p, kF32, xx, st), "channelize launch");
     WBM_HIP(wbm::launch_beamspace(p->X, p->Y, nullptr, c.n_elem, c.m_fft, p->B, c.k_sub, p->twM,
                                   nullptr, 0, geom(p, T), 12, st),
             "beamspace launch");
-    WBM_HIP(wbm::launch_mvdr_plain(pair_args(p, T, sumW, loading), p->dd, p->Y, p->starts, p->abar,
-                                   p->R32, p->w32, o, w, info, st),
+    WBM_HIP(wbm::launch_mvdr_plain(pair_args(p, kF32, T, sumW, loading), p->dd, p->Y, p->starts,
+                                   p->abar, p->R32, p->w32, o, w, info, st),
             "plain MVDR launch");
     if (starts) {
       WBM_HIP(hipMemcpyAsync(starts, p->starts, sizeof(int) * (size_t)T * c.k_sub,
                              hipMemcpyDeviceToDevice, st),
               "starts copy");
     }
-  } else if (form == WBM_FORM_FUSED) {
-    WBM_HIP(enqueue_fused(p, xx, T, sumW, loading, o, w, starts, info, st), "fused launch");
+  } else if (form == WBM_FORM_FUSED || form == WBM_FORM_FUSED_F32) {
+    WBM_HIP(enqueue_fused(p, prec, xx, T, sumW, loading, o, w, starts, info, st), "fused launch");
   } else if (form == WBM_FORM_MIXED || form == WBM_FORM_MIXED_BF16) {
-    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
-    WBM_HIP(enqueue_beamspace_windows(p, T, sumW, st), "beamspace launch");
+    WBM_HIP(enqueue_channelize(p, kF32, xx, st), "channelize launch");
+    WBM_HIP(enqueue_beamspace_windows(p, kF32, T, sumW, st), "beamspace launch");
     if (!p->route) {
       wbm_status rs = dev_alloc(p, &p->route, (size_t)c.max_targets * c.k_sub, "route flags");
       if (rs) return rs;
     }
-    WBM_HIP(wbm::launch_mvdr_mixed(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw, o, w,
-                                   starts, info, p->route, form == WBM_FORM_MIXED, st),
+    WBM_HIP(wbm::launch_mvdr_mixed(pair_args(p, kF32, T, sumW, loading), geom(p, T), p->dd, p->Yw,
+                                   o, w, starts, info, p->route, form == WBM_FORM_MIXED, st),
             "mixed MVDR launch");
   } else {
     GraphKey key;
+    key.prec = prec;
     key.x = x;
     key.out = out;
     key.weights = weights;
@@ -1070,7 +1182,8 @@ wbm_status wbm_beamform(wbm_plan* p, const wbm_c32* x, const double* az_rad, con
       p->gkey.valid = false;
       hipGraph_t g = nullptr;
       WBM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-      hipError_t le = enqueue_fused(p, xx, T, sumW, loading, o, w, starts, info, p->cap_stream);
+      hipError_t le = enqueue_fused(p, prec, xx, T, sumW, loading, o, w, starts, info,
+                                    p->cap_stream);
       hipError_t ce = hipStreamEndCapture(p->cap_stream, &g);
       if (le != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -1113,7 +1226,8 @@ wbm_status wbm_beamspace_upa(wbm_plan* p, const wbm_c32* X, int32_t nz, int32_t 
   if ((s = check_upa_shape(p, nz, mz))) return s;
   WBM_HIP(wbm::launch_beamspace_upa(reinterpret_cast<const float2*>(X),
                                     reinterpret_cast<float2*>(Y), nullptr, p->B, p->twM, nullptr,
-                                    0, upa_geom(p, 0, nz, mz), p->logTB, p->nbt,
+                                    0, upa_geom(p, 0, nz, mz), p->tune[kF32].logTB,
+                                    p->tune[kF32].nbt,
                                     static_cast<hipStream_t>(stream)),
           "planar beamspace launch");
   return WBM_OK;
@@ -1126,10 +1240,10 @@ namespace {
 // Channelize -> planar beamspace windows for the uploaded targets (steering already in abar).
 hipError_t enqueue_upa_windows(wbm_plan* p, const float2* x, int T, int sumW,
                                const wbm::UpaGeom& g, hipStream_t st) {
-  hipError_t e = enqueue_channelize(p, x, st);
+  hipError_t e = enqueue_channelize(p, kF32, x, st);
   if (e != hipSuccess) return e;
   return wbm::launch_beamspace_upa(p->X, nullptr, p->Yw, p->B, p->twM, p->dd.rowtab, sumW, g,
-                                   p->logTB, p->nbt, st);
+                                   p->tune[kF32].logTB, p->tune[kF32].nbt, st);
 }
 
 // First planar-array call of a plan: the channelizer tile (unless already tuned or pinned)
@@ -1142,22 +1256,23 @@ hipError_t tune_upa(wbm_plan* p, const float2* x, int T, int sumW, const wbm::Up
   const char* env = std::getenv("WBM_AUTOTUNE");
   if (env && std::strcmp(env, "0") == 0) return hipSuccess;
   hipError_t e = hipSuccess;
-  if (!p->tuned) {
+  Tuning& tn = p->tune[kF32];
+  if (!tn.tuned) {
     float best_c = 1e30f;
-    int chan = p->chan_logtile;
+    int chan = tn.chan_logtile;
     for (int lt = 11; lt <= 13; ++lt) {
       float ms;
-      p->chan_logtile = lt;
-      e = time_best([&]() { return enqueue_channelize(p, x, st); }, st, &ms);
+      tn.chan_logtile = lt;
+      e = time_best([&]() { return enqueue_channelize(p, kF32, x, st); }, st, &ms);
       if (e != hipSuccess) return e;
       if (ms < best_c) {
         best_c = ms;
         chan = lt;
       }
     }
-    p->chan_logtile = chan;
+    tn.chan_logtile = chan;
   }
-  wbm::PairArgs pa = pair_args(p, T, sumW, loading);
+  wbm::PairArgs pa = pair_args(p, kF32, T, sumW, loading);
   pa.abar = p->abar;
   float best = 1e30f;
   for (int thr : {WBM_PAIR_MFMA, WBM_PAIR_BLOCK, WBM_PAIR_WAVE, WBM_PAIR_RESIDENT}) {
@@ -1215,11 +1330,11 @@ wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t m
       return s;
     WBM_HIP(wbm::launch_steer_upa(g, c.w_max, starts, p->abar, st, p->upa_rows),
             "planar steer launch");
-    WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
-    WBM_HIP(wbm::launch_beamspace_upa(p->X, p->Y, nullptr, p->B, p->twM, nullptr, 0, g, p->logTB,
-                                      p->nbt, st),
+    WBM_HIP(enqueue_channelize(p, kF32, xx, st), "channelize launch");
+    WBM_HIP(wbm::launch_beamspace_upa(p->X, p->Y, nullptr, p->B, p->twM, nullptr, 0, g,
+                                      p->tune[kF32].logTB, p->tune[kF32].nbt, st),
             "planar beamspace launch");
-    wbm::PairArgs pp = pair_args(p, T, sumW, loading);
+    wbm::PairArgs pp = pair_args(p, kF32, T, sumW, loading);
     pp.rows = p->upa_rows;
     WBM_HIP(wbm::launch_mvdr_plain(pp, p->dd, p->Y, p->starts, p->abar, p->R32, p->w32, o, w, info,
                                    st),
@@ -1232,7 +1347,7 @@ wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t m
     WBM_HIP(tune_upa(p, xx, T, sumW, g, loading, st), "planar pair kernel tuning");
   }
   WBM_HIP(enqueue_upa_windows(p, xx, T, sumW, g, st), "planar beamspace launch");
-  wbm::PairArgs pa = pair_args(p, T, sumW, loading);
+  wbm::PairArgs pa = pair_args(p, kF32, T, sumW, loading);
   pa.abar = p->abar;
   if (form == WBM_FORM_FUSED) {
     WBM_HIP(wbm::launch_mvdr_fused(pa, geom(p, T), p->dd, p->Yw, o, w, nullptr, info, p->upa_pair,
@@ -1251,8 +1366,8 @@ wbm_status wbm_beamform_upa(wbm_plan* p, const wbm_c32* x, int32_t nz, int32_t m
 }
 
 wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
-                           const int32_t* win, int32_t T, double loading, int32_t reps,
-                           double* stage_ms, void* stream) {
+                           const int32_t* win, int32_t T, double loading, int32_t precision,
+                           int32_t reps, double* stage_ms, void* stream) {
   wbm_status s = check_plan(p);
   if (s) return s;
   const wbm_config& c = p->cfg;
@@ -1261,10 +1376,13 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
+  if (precision != WBM_PREC_EXT && precision != WBM_PREC_F32)
+    return fail(WBM_ERR_ARG, "precision must be WBM_PREC_EXT or WBM_PREC_F32");
+  const int prec = precision == WBM_PREC_EXT ? kExt : kF32;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
   if ((s = ensure_prof(p))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
-  if (!p->tuned) WBM_HIP(autotune(p, xx, T, sumW, loading, st), "autotune");
+  if ((s = ready_fused(p, prec, xx, T, sumW, loading, st))) return s;
   hipEvent_t ev[2];
   for (int i = 0; i < 2; ++i) WBM_HIP(hipEventCreate(&ev[i]), "event create");
   // each stage launched `reps` times back to back between two events (every launch rewrites
@@ -1273,12 +1391,12 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   auto stage = [&](int i) -> hipError_t {
     switch (i) {
       case 0: return wbm::launch_steer(geom(p, T), c.w_max, p->starts, p->abar, st);
-      case 1: return enqueue_channelize(p, xx, st);
-      case 2: return enqueue_beamspace_windows(p, T, sumW, st);
+      case 1: return enqueue_channelize(p, prec, xx, st);
+      case 2: return enqueue_beamspace_windows(p, prec, T, sumW, st);
       default:
-        return wbm::launch_mvdr_fused(pair_args(p, T, sumW, loading), geom(p, T), p->dd, p->Yw,
-                                      p->prof_out, p->prof_w, nullptr, p->prof_info,
-                                      p->pair_threads, st);
+        return wbm::launch_mvdr_fused(pair_args(p, prec, T, sumW, loading), geom(p, T), p->dd,
+                                      p->Yw, p->prof_out, p->prof_w, nullptr, p->prof_info,
+                                      p->tune[prec].pair_threads, st);
     }
   };
   for (int i = 0; i < 4 && e == hipSuccess; ++i) {
@@ -1319,7 +1437,8 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
     if ((s = dev_alloc(p, &p->fullR, nk * NN, "full covariance"))) return s;
     if ((s = dev_alloc(p, &p->fullW, nk * (size_t)c.max_targets * c.n_elem, "full weights"))) return s;
   }
-  WBM_HIP(enqueue_channelize(p, reinterpret_cast<const float2*>(x), st), "channelize launch");
+  WBM_HIP(enqueue_channelize(p, kF32, reinterpret_cast<const float2*>(x), st),
+          "channelize launch");
   int* inf = info ? info : p->full_info;
   for (int k0 = 0; k0 < c.k_sub; k0 += p->nk_full) {
     wbm::FullArgs a;
@@ -1376,13 +1495,11 @@ wbm_status ensure_learned(wbm_plan* p) {
 hipError_t enqueue_profiles(wbm_plan* p, const float2* x, int T, int sumW, bool windows,
                             float noise, float* feat, hipStream_t st) {
   const wbm_config& c = p->cfg;
-  hipError_t e = enqueue_channelize(p, x, st);
+  hipError_t e = enqueue_channelize(p, kExt, x, st);
   if (e != hipSuccess) return e;
-  const int nbt = wbm::beamspace_tiles(c.m_fft, p->B, p->beam_logtile);
+  const int nbt = p->tune[kExt].nbt;
   const int G = p->prof_G < nbt ? p->prof_G : nbt;
-  e = wbm::launch_beamspace(p->X, nullptr, windows ? p->Yw : nullptr, c.n_elem, c.m_fft, p->B,
-                            c.k_sub, p->twM, p->dd.rowtab, sumW, geom(p, T), p->beam_logtile, st,
-                            p->pprof, c.l_train, G);
+  e = enqueue_beamspace_windows(p, kExt, T, sumW, st, 0, -1, windows, p->pprof, G);
   if (e != hipSuccess) return e;
   return wbm::launch_features(p->pprof, T, c.k_sub, G, c.l_train, noise, feat, st);
 }
@@ -1409,6 +1526,7 @@ wbm_status wbm_profiles(wbm_plan* p, const wbm_c32* x, const double* az_rad, int
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, nullptr, T, st, &sumW))) return s;
   if ((s = ensure_learned(p))) return s;
+  if ((s = ensure_ext(p))) return s;
   WBM_HIP(enqueue_profiles(p, reinterpret_cast<const float2*>(x), T, sumW, false,
                            (float)noise_power, feat, st),
           "profile launch");
@@ -1429,18 +1547,15 @@ wbm_status wbm_beamform_pairs(wbm_plan* p, const wbm_c32* x, const double* az_ra
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
-  if (!p->tuned) {
-    if ((s = ensure_prof(p))) return s;
-    WBM_HIP(autotune(p, xx, T, sumW, 0.0, st), "autotune");
-  }
-  WBM_HIP(enqueue_channelize(p, xx, st), "channelize launch");
-  WBM_HIP(enqueue_beamspace_windows(p, T, sumW, st), "beamspace launch");
-  wbm::PairArgs a = pair_args(p, T, sumW, 0.0);
+  if ((s = ready_fused(p, kExt, xx, T, sumW, 0.0, st))) return s;
+  WBM_HIP(enqueue_channelize(p, kExt, xx, st), "channelize launch");
+  WBM_HIP(enqueue_beamspace_windows(p, kExt, T, sumW, st), "beamspace launch");
+  wbm::PairArgs a = pair_args(p, kExt, T, sumW, 0.0);
   a.pw = pair_win;
   a.pdelta = pair_loading;
   WBM_HIP(wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, reinterpret_cast<float2*>(out),
-                                 reinterpret_cast<float2*>(weights), starts, info, p->pair_threads,
-                                 st),
+                                 reinterpret_cast<float2*>(weights), starts, info,
+                                 p->tune[kExt].pair_threads, st),
           "pair MVDR launch");
   return WBM_OK;
 }
@@ -1470,10 +1585,7 @@ wbm_status wbm_beamform_learned(wbm_plan* p, const wbm_c32* x, const double* az_
   if ((s = upload_desc(p, az_rad, win.data(), T, st, &sumW))) return s;
   if ((s = ensure_learned(p))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
-  if (!p->tuned) {
-    if ((s = ensure_prof(p))) return s;
-    WBM_HIP(autotune(p, xx, T, sumW, fallback_loading, st), "autotune");
-  }
+  if ((s = ready_fused(p, kExt, xx, T, sumW, fallback_loading, st))) return s;
   const int n = T * c.k_sub;
   int* pw = pair_win ? pair_win : p->pw;
   float* pd = pair_loading ? pair_loading : p->pdelta;
@@ -1482,12 +1594,12 @@ wbm_status wbm_beamform_learned(wbm_plan* p, const wbm_c32* x, const double* az_
   WBM_HIP(wbm::launch_decide(p->nnout, n, (float)noise_power, (float)fallback_loading,
                              fallback_win, pw, pd, fallback, st),
           "decision");
-  wbm::PairArgs a = pair_args(p, T, sumW, fallback_loading);
+  wbm::PairArgs a = pair_args(p, kExt, T, sumW, fallback_loading);
   a.pw = pw;
   a.pdelta = pd;
   WBM_HIP(wbm::launch_mvdr_fused(a, geom(p, T), p->dd, p->Yw, reinterpret_cast<float2*>(out),
-                                 reinterpret_cast<float2*>(weights), starts, info, p->pair_threads,
-                                 st),
+                                 reinterpret_cast<float2*>(weights), starts, info,
+                                 p->tune[kExt].pair_threads, st),
           "pair MVDR launch");
   return WBM_OK;
 }

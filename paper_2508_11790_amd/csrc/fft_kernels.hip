@@ -229,6 +229,195 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace(
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Extended-precision forms of the channelizer and the windowed spatial DFT.  Same transforms,
+// tiles and data layouts as k_channelize / k_beamspace, with FP64 arithmetic (FP64 twiddle
+// tables, FP32 inputs converted exactly) and every intermediate stored as hi (FP32) + lo
+// (BF16 remainder, ext_split): X as Xh [K][B][N] float2 + Xl [K][B][N] uint32, the windows
+// as Ywh [K][nbt][sumW][TB] float2 + Ywl (same layout) uint32.  Rounding in these stages then
+// stays near 2^-33 of each value instead of the FP32 transforms' few 2^-24, which is what
+// keeps the MVDR weights of scenes with strong interferers within the FP32 weight tolerance.
+
+template <int LOGK, int LOGT>
+__global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize_x(
+    const float2* __restrict__ x, float2* __restrict__ Xh, uint32_t* __restrict__ Xl, int N,
+    int B, int64_t S, const double2* __restrict__ twK, const double2* __restrict__ hb,
+    double scale) {
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK), double2>;
+  constexpr int K = F::n, TE = F::rows;
+  constexpr int LOGTE = fft_tile(LOGK, LOGT) - LOGK;
+  extern __shared__ double2 lds_x[];
+  double2* lds = lds_x;
+  const int e0 = blockIdx.x * TE;
+  double2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twK);
+  auto fetch = [&](int b, float2 (&v)[8]) {
+#pragma unroll
+    for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+      for (int r = 0; r < F::R0; ++r) {
+        int row, tau;
+        F::first_input(p, r, row, tau);
+        float2 val = make_float2(0.f, 0.f);
+        if (e0 + row < N) val = x[(int64_t)(e0 + row) * S + (int64_t)b * K + tau];
+        v[p * F::R0 + r] = val;
+      }
+    }
+  };
+  float2 nv[8];
+  int b = blockIdx.y;
+  if (b < B) fetch(b, nv);
+  for (; b < B; b += gridDim.y) {
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = make_double2((double)nv[q].x, (double)nv[q].y);
+    if (b + (int)gridDim.y < B) fetch(b + gridDim.y, nv);
+    if (hb) {
+#pragma unroll
+      for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+        for (int r = 0; r < F::R0; ++r) {
+          int row, tau;
+          F::first_input(p, r, row, tau);
+          v[p * F::R0 + r] = cmul(v[p * F::R0 + r], hb[tau]);
+        }
+      }
+    }
+    F::run(v, lds, tr);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = threadIdx.x + q * F::threads;
+      const int k = idx >> LOGTE, e = idx & (TE - 1);
+      if (e0 + e < N) {
+        float2 hi;
+        uint32_t lo;
+        ext_split(cscale(lds[F::addr(e, k)], scale), hi, lo);
+        const int64_t o = ((int64_t)k * B + b) * N + e0 + e;
+        Xh[o] = hi;
+        Xl[o] = lo;
+      }
+    }
+    __syncthreads();   // the next block's first pass overwrites lds
+  }
+}
+
+// Windowed spatial DFT in extended precision (windows and training power profiles as in
+// k_beamspace; no full-beamspace output).
+template <int LOGM, int LOGT, bool ZH>
+__global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace_x(
+    const float2* __restrict__ Xh, const uint32_t* __restrict__ Xl, float2* __restrict__ Ywh,
+    uint32_t* __restrict__ Ywl, int N, int B, int K, const double2* __restrict__ twM,
+    double scale, const int* __restrict__ rowtab, int sumW, WindowGeom g, float* __restrict__ prof,
+    int L, int k0) {
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM), double2>;
+  constexpr int M = F::n, TB = F::rows;
+  constexpr int LOGTB = fft_tile(LOGM, LOGT) - LOGM;
+  extern __shared__ double2 lds_x[];
+  double2* lds = lds_x;
+  int* s_dyn = reinterpret_cast<int*>(lds_x + F::lds_complex);
+  int* s_start = s_dyn;                                    // [T] window starts of subband k
+  int* s_center = s_dyn + g.T;                             // [T] beam bins (profile centre)
+  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);  // [T][64] profile sums (prof)
+  int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);      // [sumW] bin of window row r
+  const int k = k0 + blockIdx.y;
+  const int nbt = (B + TB - 1) / TB;
+  double2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twM);
+  // first-pass inputs at the same element offset in every tile (see k_beamspace)
+  uint32_t foff[8];
+  int frow[8];
+  bool fok[8];
+#pragma unroll
+  for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      int row, e;
+      F::first_input(p, r, row, e);
+      const int q = p * F::R0 + r;
+      frow[q] = row;
+      fok[q] = e < N;
+      foff[q] = (uint32_t)(row * N + e);
+    }
+  }
+  const bool dense = N >= (ZH ? M / 2 : M);
+  auto fetch = [&](int j, float2 (&vh)[8], uint32_t (&vl)[8]) {
+    const int b0 = j * TB;
+    const int64_t base = ((int64_t)k * B + b0) * N;
+    const float2* bh = Xh + base;
+    const uint32_t* bl = Xl + base;
+    const bool full = dense && b0 + TB <= B;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      vh[q] = make_float2(0.f, 0.f);
+      vl[q] = 0u;
+      const bool zero_half = ZH && 2 * (q % F::R0) >= F::R0;
+      if (!zero_half && (full || (fok[q] && b0 + frow[q] < B))) {
+        vh[q] = bh[foff[q]];
+        vl[q] = bl[foff[q]];
+      }
+    }
+  };
+  float2 nh[8];
+  uint32_t nl[8];
+  if ((int)blockIdx.x < nbt) fetch(blockIdx.x, nh, nl);
+  if (Ywh || prof) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) {
+      double u;
+      int s;
+      window_of(g, t, k, &u, &s);
+      s_start[t] = s;
+      if (prof) s_center[t] = (int)floor(u + 0.5);
+    }
+    if (prof)
+      for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
+    if (Ywh) {
+      __syncthreads();
+      for (int r = threadIdx.x; r < sumW; r += F::threads) {
+        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+        s_bin[r] = (s_start[t] + i) & (M - 1);
+      }
+    }
+  }
+  for (int j = blockIdx.x; j < nbt; j += gridDim.x) {
+    const int b0 = j * TB;
+    double2 v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = ext_join(nh[q], nl[q]);
+    if (j + (int)gridDim.x < nbt) fetch(j + gridDim.x, nh, nl);
+    F::template run<ZH>(v, lds, tr);
+    if (Ywh) {
+      const int64_t o0 = ((int64_t)k * nbt + j) * sumW * TB;
+      const int tot = sumW * TB;
+      for (int idx = threadIdx.x; idx < tot; idx += F::threads) {
+        const int r = idx >> LOGTB, b = idx & (TB - 1);
+        float2 hi;
+        uint32_t lo;
+        ext_split(cscale(lds[F::addr(b, s_bin[r])], scale), hi, lo);
+        Ywh[o0 + idx] = hi;
+        Ywl[o0 + idx] = lo;
+      }
+    }
+    if (prof && b0 < L) {
+      const int nb = min(TB, L - b0);
+      for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) {
+        const int t = idx >> 6, jj = idx & 63;
+        const int m = (s_center[t] - 32 + jj) & (M - 1);
+        float acc = 0.f;
+        for (int b = 0; b < nb; ++b) {
+          const double2 y = cscale(lds[F::addr(b, m)], scale);
+          acc += (float)(y.x * y.x + y.y * y.y);
+        }
+        s_acc[idx] += acc;
+      }
+    }
+    __syncthreads();   // the next tile's first pass overwrites lds
+  }
+  if (prof) {
+    float* dst = prof + ((int64_t)k * gridDim.x + blockIdx.x) * g.T * 64;
+    for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) dst[idx] = s_acc[idx];
+  }
+}
+
 // Subband synthesis, the inverse of the channelizer per block: Z [T][K][Lt] (beam outputs of
 // every subband on the test blocks) -> z [T][Lt*K], z[t][b K + tau] = K^-1/2 conj(h[tau])
 // sum_k Z[t][k][b] exp(+j 2 pi tau k / K), computed as the conjugate of the forward transform
@@ -504,6 +693,70 @@ static hipError_t beam_launch(const float2* X, float2* Y, float2* Yw, int N, int
                                            k0, kc, s);
 }
 
+template <int LOGK, int LOGT>
+static hipError_t chan_launch_x(const float2* x, float2* Xh, uint32_t* Xl, int N, int B,
+                                const double2* twK, const double2* hb, hipStream_t s) {
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK), double2>;
+  const size_t shm = sizeof(double2) * (size_t)F::lds_complex;
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_channelize_x<LOGK, LOGT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  static int resident = 0;
+  const int gx = (N + F::rows - 1) / F::rows;
+  const int cap = resident_blocks(k_channelize_x<LOGK, LOGT>, F::threads, shm, &resident);
+  int gy = (cap + gx - 1) / gx;
+  if (gy > B) gy = B;
+  if (gy < 1) gy = 1;
+  hipLaunchKernelGGL((k_channelize_x<LOGK, LOGT>), dim3(gx, gy), dim3(F::threads), shm, s, x, Xh,
+                     Xl, N, B, (int64_t)B * F::n, twK, hb, 1.0 / sqrt((double)F::n));
+  return hipGetLastError();
+}
+
+template <int LOGM, int LOGT, bool ZH>
+static hipError_t beam_launch_x_zh(const float2* Xh, const uint32_t* Xl, float2* Ywh,
+                                   uint32_t* Ywl, int N, int B, int K, const double2* twM,
+                                   const int* rowtab, int sumW, const WindowGeom& g, float* prof,
+                                   int L, int G, int k0, int kc, hipStream_t s) {
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM), double2>;
+  const int nbt = (B + F::rows - 1) / F::rows;
+  if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
+  size_t shm = sizeof(double2) * (size_t)F::lds_complex;
+  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
+  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
+  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x<LOGM, LOGT, ZH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  int gx = G;
+  if (!prof) {
+    static int resident = 0;
+    const int cap = resident_blocks(k_beamspace_x<LOGM, LOGT, ZH>, F::threads, shm, &resident);
+    gx = (cap + kc - 1) / kc;
+    if (gx > nbt) gx = nbt;
+    if (gx < 1) gx = 1;
+  }
+  hipLaunchKernelGGL((k_beamspace_x<LOGM, LOGT, ZH>), dim3(gx, kc), dim3(F::threads), shm, s, Xh,
+                     Xl, Ywh, Ywl, N, B, K, twM, 1.0 / sqrt((double)F::n), rowtab, sumW, g, prof,
+                     L, k0);
+  return hipGetLastError();
+}
+
+template <int LOGM, int LOGT>
+static hipError_t beam_launch_x(const float2* Xh, const uint32_t* Xl, float2* Ywh, uint32_t* Ywl,
+                                int N, int B, int K, const double2* twM, const int* rowtab,
+                                int sumW, const WindowGeom& g, float* prof, int L, int G, int k0,
+                                int kc, hipStream_t s) {
+  if (2 * N <= (1 << LOGM))
+    return beam_launch_x_zh<LOGM, LOGT, true>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g,
+                                              prof, L, G, k0, kc, s);
+  return beam_launch_x_zh<LOGM, LOGT, false>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g,
+                                             prof, L, G, k0, kc, s);
+}
+
 // Planar-array beamspace (Eq. 16-17): X [K][B][N], N = Nz Nx (element ix Nz + iz) ->
 //   full  : Y [K][Mz Mx][B], beam mx Mz + mz                              (stage output), and/or
 //   window: Yw [K][nbt][sumW][TB] in the layout of the linear-array kernel (TB = 2^logTB
@@ -689,6 +942,62 @@ hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, co
       break;
     case 13:
       switch (lk) { WBM_LOG_CASES(C, 13) }
+      break;
+  }
+#undef C
+  return hipErrorInvalidValue;
+}
+
+bool fft_x_logtile_supported(int logtile) { return logtile >= 10 && logtile <= 13; }
+
+hipError_t launch_channelize_x(const float2* x, float2* Xh, uint32_t* Xl, int N, int K, int B,
+                               const double2* twK, const double2* hb, int logtile,
+                               hipStream_t s) {
+  const int lk = ilog2(K);
+#define C(L, T)                                     \
+  case L:                                           \
+    return chan_launch_x<L, T>(x, Xh, Xl, N, B, twK, hb, s);
+  switch (logtile) {
+    case 10:
+      switch (lk) { WBM_LOG_CASES(C, 10) }
+      break;
+    case 11:
+      switch (lk) { WBM_LOG_CASES(C, 11) }
+      break;
+    case 12:
+      switch (lk) { WBM_LOG_CASES(C, 12) }
+      break;
+    case 13:
+      switch (lk) { WBM_LOG_CASES(C, 13) }
+      break;
+  }
+#undef C
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_beamspace_x(const float2* Xh, const uint32_t* Xl, float2* Ywh, uint32_t* Ywl,
+                              int N, int M, int B, int K, const double2* twM, const int* rowtab,
+                              int sumW, const WindowGeom& g, int logtile, hipStream_t s,
+                              float* prof, int L, int G, int k0, int kc) {
+  const int lm = ilog2(M);
+  if (kc < 0) kc = K - k0;
+  if (k0 < 0 || kc < 1 || k0 + kc > K) return hipErrorInvalidValue;
+#define C(LG, T)                                                                           \
+  case LG:                                                                                 \
+    return beam_launch_x<LG, T>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g, prof, L, G, \
+                                k0, kc, s);
+  switch (logtile) {
+    case 10:
+      switch (lm) { WBM_LOG_CASES(C, 10) }
+      break;
+    case 11:
+      switch (lm) { WBM_LOG_CASES(C, 11) }
+      break;
+    case 12:
+      switch (lm) { WBM_LOG_CASES(C, 12) }
+      break;
+    case 13:
+      switch (lm) { WBM_LOG_CASES(C, 13) }
       break;
   }
 #undef C

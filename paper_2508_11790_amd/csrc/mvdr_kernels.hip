@@ -16,6 +16,8 @@
 #include "wbm_dev.h"
 #include "wbm_launch.h"
 
+#include <type_traits>
+
 namespace wbm {
 
 template <typename T>
@@ -374,6 +376,7 @@ hipError_t launch_mvdr_resident(const PairArgs& a, const WindowGeom& g, const De
 hipError_t launch_mvdr_fused(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                              const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                              int threads, hipStream_t s) {
+  if (a.ywl && threads != 256 && threads != 64) return hipErrorInvalidValue;
   if (threads == kPairMfma) return launch_mvdr_mfma(a, g, d, Yw, out, wout, starts, info, s);
   if (threads == kPairResident)
     return launch_mvdr_resident(a, g, d, Yw, out, wout, starts, info, s);
@@ -421,7 +424,7 @@ struct XLds {
 // cores) and the complex R, then the pivots, weights, steering vector and the apply's partial
 // sums.
 template <bool MF, int TH, int CH>
-__host__ __device__ inline XLds x_lds_layout(int wmax) {
+__host__ __device__ inline XLds x_lds_layout(int wmax, bool ext = false) {
   constexpr int NG = TH / CH > 0 ? TH / CH : 1;   // row groups of the apply
   XLds p;
   p.RS = wmax + 1;
@@ -435,7 +438,9 @@ __host__ __device__ inline XLds x_lds_layout(int wmax) {
     if (z > big) big = z;
     if (gram > big) big = gram;
   } else {
-    const size_t zf = sizeof(float2) * (size_t)((wmax + 3) / 4 * 4) * (CH + 1);
+    // staged chunk rows: FP32 complex, or FP64 complex (hi + lo joined) in extended precision
+    const size_t zf = (ext ? sizeof(double2) : sizeof(float2)) * (size_t)((wmax + 3) / 4 * 4) *
+                      (CH + 1);
     if (zf > big) big = zf;
   }
   p.region = 0;
@@ -502,27 +507,34 @@ __device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, in
 }
 
 // Snapshots c0 + (mapped snapshot) of the window rows (zero at b >= lim) into registers.  With
-// aligned chunks (c0 a multiple of CH) one add per element; otherwise the full address.
-template <int PRE>
+// aligned chunks (c0 a multiple of CH) one add per element; otherwise the full address.  EXT:
+// also the BF16 remainders of the extended-precision windows (a.ywl, same layout) into prel.
+template <int PRE, bool EXT = false>
 __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const PairArgs& a,
                                             int k, int woff, const int* map, const int* off,
-                                            bool aligned, int c0, int lim, float2* pre) {
+                                            bool aligned, int c0, int lim, float2* pre,
+                                            uint32_t* prel = nullptr) {
   const int TB = 1 << a.logTB;
-  const float2* base = Yw + (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
+  const int64_t ebase = (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
+  const float2* base = Yw + ebase;
   if (aligned) {
     // the chunk base is uniform; each element adds a 32-bit byte offset, kept opaque (empty
     // register constraint) so that the compiler does not hoist PRE 64-bit addresses out of
     // the chunk loops, where they would be spilled to scratch
-    const char* cb = reinterpret_cast<const char*>(
-        base + (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1)));
+    const int64_t cofs = (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1));
+    const char* cb = reinterpret_cast<const char*>(base + cofs);
+    const char* cl = EXT ? reinterpret_cast<const char*>(a.ywl + ebase + cofs) : nullptr;
     const int rem = lim - c0;
 #pragma unroll
     for (int m = 0; m < PRE; ++m) {
       pre[m] = make_float2(0.f, 0.f);
+      if constexpr (EXT) prel[m] = 0u;
       uint32_t o = (uint32_t)off[m] << 3;
       asm volatile("" : "+v"(o));
-      if (map[m] >= 0 && (map[m] & 255) < rem)
+      if (map[m] >= 0 && (map[m] & 255) < rem) {
         pre[m] = *reinterpret_cast<const float2*>(cb + o);
+        if constexpr (EXT) prel[m] = *reinterpret_cast<const uint32_t*>(cl + (o >> 1));
+      }
     }
   } else {
 #pragma unroll
@@ -531,8 +543,12 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const
       int mm = map[m];
       asm volatile("" : "+v"(mm));   // as above: no hoisted per-element addresses
       const int i = mm >> 8, b = c0 + (mm & 255);
-      if (mm >= 0 && b < lim)
-        pre[m] = base[((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1))];
+      if constexpr (EXT) prel[m] = 0u;
+      if (mm >= 0 && b < lim) {
+        const int64_t o = ((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1));
+        pre[m] = base[o];
+        if constexpr (EXT) prel[m] = a.ywl[ebase + o];
+      }
     }
   }
 }
@@ -550,14 +566,29 @@ __device__ __forceinline__ void store_planes(int W, const int* map, const float2
   }
 }
 
-// Registers -> LDS complex rows, zf[i * RSF + snapshot].
-template <int PRE, int RSF>
-__device__ __forceinline__ void store_rows(const int* map, const float2* pre, float2* zf) {
+// Registers -> LDS complex rows, zf[i * RSF + snapshot]: FP32 complex, or with EXT the FP64
+// complex hi + lo.
+template <int PRE, int RSF, bool EXT = false>
+__device__ __forceinline__ void store_rows(const int* map, const float2* pre, void* zf,
+                                           const uint32_t* prel = nullptr) {
 #pragma unroll
   for (int m = 0; m < PRE; ++m) {
-    if (map[m] >= 0) zf[(map[m] >> 8) * RSF + (map[m] & 255)] = pre[m];
+    if (map[m] >= 0) {
+      const int o = (map[m] >> 8) * RSF + (map[m] & 255);
+      if constexpr (EXT)
+        static_cast<double2*>(zf)[o] = ext_join(pre[m], prel[m]);
+      else
+        static_cast<float2*>(zf)[o] = pre[m];
+    }
   }
 }
+
+// Staged snapshot element -> FP64 complex.
+__device__ __forceinline__ double2 staged_c64(const float2* zf, int o) {
+  const float2 v = zf[o];
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ double2 staged_c64(const double2* zf, int o) { return zf[o]; }
 
 struct GramArgs {
   int W, woff, k, ntiles, TG, tg, kq, lane;
@@ -632,12 +663,14 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
 // (LDS, row stride RS).  A thread owns a BS x BS block of the lower triangle and a slice of S
 // interleaved snapshots (S a power of two; the S slices of a block on consecutive lanes,
 // summed by shuffles in a fixed order).  Requires nblk <= TH.
-template <int BS, int PRE, int TH, int CH>
+template <int BS, int PRE, int TH, int CH, bool EXT = false>
 __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const PairArgs& a,
                                          const GramArgs& ga, const int* map, const int* off,
-                                         float2* pre, float2* zf, C2<double>* R, int RS,
-                                         double delta) {
+                                         float2* pre, void* zfv, C2<double>* R, int RS,
+                                         double delta, uint32_t* prel = nullptr) {
   constexpr int RSF = CH + 1;
+  using SV = typename std::conditional<EXT, double2, float2>::type;
+  SV* zf = static_cast<SV*>(zfv);
   const int W = ga.W;
   const int nb = (W + BS - 1) / BS, nblk = nb * (nb + 1) / 2;
   int S = 1;
@@ -647,8 +680,8 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
   const bool act = blk < nblk;
   int bi = 0, bj = 0;
   if (act) tri_index(blk, bi, bj);
-  const float2* yr0 = zf + bi * BS * RSF;
-  const float2* yc0 = zf + bj * BS * RSF;
+  const SV* yr0 = zf + bi * BS * RSF;
+  const SV* yc0 = zf + bj * BS * RSF;
   double ax[BS][BS], ay[BS][BS];
 #pragma unroll
   for (int u = 0; u < BS; ++u)
@@ -656,18 +689,19 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
     for (int v = 0; v < BS; ++v) ax[u][v] = ay[u][v] = 0.0;
   for (int c0 = 0; c0 < a.L; c0 += CH) {
     __syncthreads();   // previous chunk consumed
-    store_rows<PRE, RSF>(map, pre, zf);
+    store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel);
     else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
+                            prel);
     if (act) {
       for (int bb = sg; bb < CH; bb += S) {
         double rx[BS], ry[BS], cx[BS], cy[BS];
 #pragma unroll
         for (int u = 0; u < BS; ++u) {
-          const float2 yr = yr0[u * RSF + bb], yc = yc0[u * RSF + bb];
+          const double2 yr = staged_c64(yr0, u * RSF + bb), yc = staged_c64(yc0, u * RSF + bb);
           rx[u] = yr.x;
           ry[u] = yr.y;
           cx[u] = yc.x;
@@ -888,13 +922,16 @@ __device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowG
 // the first test chunk on entry): thread (row group q = tid / CH, snapshot l = tid % CH) sums
 // window rows i = q mod NG in FP64, then the NG partials are added in order.  Zero outputs
 // when fail.
-template <int PRE, int TH, int CH, bool PLANES>
+template <int PRE, int TH, int CH, bool PLANES, bool EXT = false>
 __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, const PairArgs& a,
                                              int k, int woff, int W, const int* map,
                                              const int* off, bool aligned, float2* pre, float* z,
-                                             float2* zf, const C2<double>* wv, double2* red,
-                                             int fail, float2* __restrict__ o) {
+                                             void* zfv, const C2<double>* wv, double2* red,
+                                             int fail, float2* __restrict__ o,
+                                             uint32_t* prel = nullptr) {
   constexpr int NG = TH / CH, RSF = CH + 1;
+  using SV = typename std::conditional<EXT, double2, float2>::type;
+  SV* zf = static_cast<SV*>(zfv);
   const int tid = threadIdx.x;
   const int rg = tid / CH, ls = tid % CH;
   const int nch = (a.Lt + CH - 1) / CH;
@@ -903,10 +940,11 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
     if constexpr (PLANES)
       store_planes<PRE>(W, map, pre, z);
     else
-      store_rows<PRE, RSF>(map, pre, zf);
+      store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c + 1 < nch)
-      fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt, pre);
+      fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
+                            pre, prel);
     double zx = 0.0, zy = 0.0;
     if (!fail) {
       for (int i = rg; i < W; i += NG) {
@@ -915,7 +953,7 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
           yr = z[i * kXRSP + ls];
           yi = z[(W + i) * kXRSP + ls];
         } else {
-          const float2 y = zf[i * RSF + ls];
+          const double2 y = staged_c64(zf, i * RSF + ls);
           yr = y.x;
           yi = y.y;
         }
@@ -939,7 +977,7 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
   }
 }
 
-template <int WCAP, bool MF, int TH, int CHUNK>
+template <int WCAP, bool MF, int TH, int CHUNK, bool EXT = false>
 __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom& g,
                                             const DevDesc& d, const float2* __restrict__ Yw,
                                             float2* __restrict__ out, float2* __restrict__ wout,
@@ -949,8 +987,9 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   constexpr int NG = TH / CH;   // row groups of the apply
   static_assert(TH % CH == 0 && CH <= 256, "chunk: a divisor of the workgroup, at most 256");
   static_assert(!MF || CH == 64, "the matrix-core Gram steps through 64-snapshot chunks");
+  static_assert(!(MF && EXT), "extended-precision windows use the vector Gram");
   extern __shared__ __align__(16) unsigned char smem[];
-  const XLds lay = x_lds_layout<MF, TH, CH>(a.wmax);
+  const XLds lay = x_lds_layout<MF, TH, CH>(a.wmax, EXT);
   float* z = reinterpret_cast<float*>(smem + lay.region);
   float2* zf = reinterpret_cast<float2*>(smem + lay.region);
   double* P = reinterpret_cast<double*>(smem + lay.region);
@@ -972,7 +1011,8 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   chunk_map<PRE, TH, CH>(a, W, map, off);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
-  fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
+  uint32_t prel[EXT ? PRE : 1];
+  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre, prel);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
@@ -982,12 +1022,12 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if constexpr (TH >= 256) {
       // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
       if (WCAP <= 44 || W <= 44)
-        gram_vec<2, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+        gram_vec<2, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
       else if constexpr (WCAP > 44)
-        gram_vec<4, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+        gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
     } else {
       // one wave: 4 x 4 blocks (at most 55 blocks for 40 bins)
-      gram_vec<4, PRE, TH, CH>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta);
+      gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
     }
   } else {
     static_assert(!MF || TH == 256, "the matrix-core form runs four waves");
@@ -1060,8 +1100,8 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     fail = ldl_lds<TH>(R, lay.RS, W);
     if (!fail) ldl_solve(R, lay.RS, W, av, wv);
   }
-  apply_chunks<PRE, TH, CH, MF>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red, fail,
-                                out + pair * a.Lt);
+  apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red,
+                                     fail, out + pair * a.Lt, prel);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
       float2 v = make_float2(0.f, 0.f);
@@ -1085,28 +1125,33 @@ __global__ __launch_bounds__(256) void k_mvdr_xm(PairArgs a, WindowGeom g, DevDe
   mvdr_x_body<WCAP, true, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
+// EXT: the windows are the extended-precision hi + lo planes (a.ywl), staged as FP64.
+template <bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv16(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<16, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<16, false, 256, 64, EXT>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
+template <bool EXT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mvdr_xv40(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<40, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<40, false, 256, 64, EXT>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
+template <bool EXT>
 __global__ __launch_bounds__(256) void k_mvdr_xv64(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<64, false, 256, 64>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<64, false, 256, 64, EXT>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
+template <bool EXT>
 __global__ __launch_bounds__(64) void k_mvdr_xw40(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
-  mvdr_x_body<40, false, 64, 16>(a, g, d, Yw, out, wout, starts_out, info);
+  mvdr_x_body<40, false, 64, 16, EXT>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
 hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
@@ -1122,31 +1167,36 @@ hipError_t launch_mvdr_mfma(const PairArgs& a, const WindowGeom& g, const DevDes
   return hipGetLastError();
 }
 
+template <bool EXT>
+static hipError_t vector_launch(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
+                                const float2* Yw, float2* out, float2* wout, int* starts,
+                                int* info, int threads, hipStream_t s) {
+  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K));
+  if (threads == 64) {
+    const XLds lay = x_lds_layout<false, 64, 16>(a.wmax, EXT);
+    hipLaunchKernelGGL(k_mvdr_xw40<EXT>, grid, dim3(64), lay.total, s, a, g, d, Yw, out, wout,
+                       starts, info);
+    return hipGetLastError();
+  }
+  const XLds lay = x_lds_layout<false, 256, 64>(a.wmax, EXT);
+  if (a.wmax <= 16)
+    hipLaunchKernelGGL(k_mvdr_xv16<EXT>, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout,
+                       starts, info);
+  else if (a.wmax <= 40)
+    hipLaunchKernelGGL(k_mvdr_xv40<EXT>, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout,
+                       starts, info);
+  else
+    hipLaunchKernelGGL(k_mvdr_xv64<EXT>, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout,
+                       starts, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_mvdr_vector(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
                               const float2* Yw, float2* out, float2* wout, int* starts, int* info,
                               int threads, hipStream_t s) {
   if (a.wmax > 64 || (threads == 64 && a.wmax > 40)) return hipErrorInvalidValue;
-  const dim3 grid(a.T * (a.kc > 0 ? a.kc : a.K));
-  if (threads == 64) {
-    const XLds lay = x_lds_layout<false, 64, 16>(a.wmax);
-    hipLaunchKernelGGL(k_mvdr_xw40, grid, dim3(64), lay.total, s, a, g, d, Yw, out, wout, starts,
-                       info);
-    return hipGetLastError();
-  }
-  if (a.wmax <= 16) {
-    const XLds l16 = x_lds_layout<false, 256, 64>(a.wmax);
-    hipLaunchKernelGGL(k_mvdr_xv16, grid, dim3(256), l16.total, s, a, g, d, Yw, out, wout, starts,
-                       info);
-    return hipGetLastError();
-  }
-  const XLds lay = x_lds_layout<false, 256, 64>(a.wmax);
-  if (a.wmax <= 40)
-    hipLaunchKernelGGL(k_mvdr_xv40, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
-                       info);
-  else
-    hipLaunchKernelGGL(k_mvdr_xv64, grid, dim3(256), lay.total, s, a, g, d, Yw, out, wout, starts,
-                       info);
-  return hipGetLastError();
+  if (a.ywl) return vector_launch<true>(a, g, d, Yw, out, wout, starts, info, threads, s);
+  return vector_launch<false>(a, g, d, Yw, out, wout, starts, info, threads, s);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1479,8 +1529,17 @@ hipError_t set_pair_attributes() {
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)x_lds_layout<true, 256, 64>(64).total);
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_mvdr_xv64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)x_lds_layout<false, 256, 64>(64).total);
+  e = hipFuncSetAttribute((const void*)k_mvdr_xv64<false>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)x_lds_layout<false, 256, 64>(64).total);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_mvdr_xv40<true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)x_lds_layout<false, 256, 64>(40, true).total);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_mvdr_xv64<true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)x_lds_layout<false, 256, 64>(64, true).total);
 }
 
 }  // namespace wbm

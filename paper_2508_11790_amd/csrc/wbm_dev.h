@@ -112,44 +112,77 @@ __device__ __forceinline__ double2 axis_steering(int N, int M, double u, int m) 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Small DFTs in registers, forward sign: X[k] = sum_r v[r] exp(-2 pi i r k / R).
+// Small DFTs in registers, forward sign: X[k] = sum_r v[r] exp(-2 pi i r k / R).  V is float2
+// (the FP32 kernels) or double2 (the extended-precision kernels); the operations and their
+// order are the same for both.
 
-__device__ __forceinline__ void dft2(float2* v) {
-  float2 a = v[0], b = v[1];
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cmul_mj(double2 a) { return make_double2(a.y, -a.x); }
+
+template <typename V>
+struct Cplx;
+template <>
+struct Cplx<float2> {
+  using S = float;
+  __device__ __forceinline__ static float2 make(float a, float b) { return make_float2(a, b); }
+};
+template <>
+struct Cplx<double2> {
+  using S = double;
+  __device__ __forceinline__ static double2 make(double a, double b) { return make_double2(a, b); }
+};
+
+template <typename V>
+__device__ __forceinline__ void dft2(V* v) {
+  V a = v[0], b = v[1];
   v[0] = cadd(a, b);
   v[1] = csub(a, b);
 }
 
-__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
-  float2 t2 = cadd(a1, a3), t3 = cmul_mj(csub(a1, a3));
+template <typename V>
+__device__ __forceinline__ void dft4(V& a0, V& a1, V& a2, V& a3) {
+  V t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  V t2 = cadd(a1, a3), t3 = cmul_mj(csub(a1, a3));
   a0 = cadd(t0, t2);
   a2 = csub(t0, t2);
   a1 = cadd(t1, t3);
   a3 = csub(t1, t3);
 }
 
-__device__ __forceinline__ void dft4(float2* v) { dft4(v[0], v[1], v[2], v[3]); }
+template <typename V>
+__device__ __forceinline__ void dft4(V* v) { dft4(v[0], v[1], v[2], v[3]); }
 
-__device__ __forceinline__ void dft8(float2* v) {
-  // even / odd split: E = DFT4(v0, v2, v4, v6), O = DFT4(v1, v3, v5, v7)
-  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
-  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
-  dft4(e0, e1, e2, e3);
-  dft4(o0, o1, o2, o3);
-  const float r = 0.70710678118654752440f;
-  // O[k] * exp(-2 pi i k / 8)
-  float2 w1 = make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);     // (1 - i)/sqrt2
-  float2 w2 = cmul_mj(o2);                                            // -i
-  float2 w3 = make_float2((o3.y - o3.x) * r, -(o3.x + o3.y) * r);     // (-1 - i)/sqrt2
-  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
-  v[1] = cadd(e1, w1); v[5] = csub(e1, w1);
-  v[2] = cadd(e2, w2); v[6] = csub(e2, w2);
-  v[3] = cadd(e3, w3); v[7] = csub(e3, w3);
+// odd outputs of the radix-8 split times exp(-2 pi i k / 8), k = 1, 2, 3
+template <typename V>
+__device__ __forceinline__ void rot8(V& o1, V& o2, V& o3) {
+  using S = typename Cplx<V>::S;
+  const S r = (S)0.70710678118654752440;
+  o1 = Cplx<V>::make((o1.x + o1.y) * r, (o1.y - o1.x) * r);     // (1 - i)/sqrt2
+  o2 = cmul_mj(o2);                                             // -i
+  o3 = Cplx<V>::make((o3.y - o3.x) * r, -(o3.x + o3.y) * r);    // (-1 - i)/sqrt2
 }
 
-template <int R>
-__device__ __forceinline__ void dftR(float2* v) {
+template <typename V>
+__device__ __forceinline__ void dft8(V* v) {
+  // even / odd split: E = DFT4(v0, v2, v4, v6), O = DFT4(v1, v3, v5, v7)
+  V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  V o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  rot8(o1, o2, o3);
+  v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+template <int R, typename V>
+__device__ __forceinline__ void dftR(V* v) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 4) dft4(v);
   else dft8(v);
@@ -157,31 +190,30 @@ __device__ __forceinline__ void dftR(float2* v) {
 
 // The same DFTs when the upper half of the inputs is zero (v[R/2 .. R-1] = 0, not read): the
 // additions of those zeros are left out, which changes no value.
-__device__ __forceinline__ void dft4_zh(float2& a0, float2& a1, float2& a2, float2& a3) {
-  const float2 x0 = a0, x1 = a1, t3 = cmul_mj(x1);
+template <typename V>
+__device__ __forceinline__ void dft4_zh(V& a0, V& a1, V& a2, V& a3) {
+  const V x0 = a0, x1 = a1, t3 = cmul_mj(x1);
   a0 = cadd(x0, x1);
   a2 = csub(x0, x1);
   a1 = cadd(x0, t3);
   a3 = csub(x0, t3);
 }
 
-__device__ __forceinline__ void dft8_zh(float2* v) {
-  float2 e0 = v[0], e1 = v[2], e2, e3;
-  float2 o0 = v[1], o1 = v[3], o2, o3;
+template <typename V>
+__device__ __forceinline__ void dft8_zh(V* v) {
+  V e0 = v[0], e1 = v[2], e2, e3;
+  V o0 = v[1], o1 = v[3], o2, o3;
   dft4_zh(e0, e1, e2, e3);
   dft4_zh(o0, o1, o2, o3);
-  const float r = 0.70710678118654752440f;
-  float2 w1 = make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);     // (1 - i)/sqrt2
-  float2 w2 = cmul_mj(o2);                                            // -i
-  float2 w3 = make_float2((o3.y - o3.x) * r, -(o3.x + o3.y) * r);     // (-1 - i)/sqrt2
+  rot8(o1, o2, o3);
   v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
-  v[1] = cadd(e1, w1); v[5] = csub(e1, w1);
-  v[2] = cadd(e2, w2); v[6] = csub(e2, w2);
-  v[3] = cadd(e3, w3); v[7] = csub(e3, w3);
+  v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
-template <int R>
-__device__ __forceinline__ void dftR_zh(float2* v) {
+template <int R, typename V>
+__device__ __forceinline__ void dftR_zh(V* v) {
   if constexpr (R == 2) {
     v[1] = v[0];
   } else if constexpr (R == 4) {
@@ -189,6 +221,28 @@ __device__ __forceinline__ void dftR_zh(float2* v) {
   } else {
     dft8_zh(v);
   }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Extended-precision storage of a complex FP64 value in 12 bytes: hi = its FP32 rounding
+// (float2), lo = the remainder v - hi (exact in FP64) rounded to BF16, real part in the low
+// half of a 32-bit word, imaginary part in the high half.  hi + lo carries the value to a
+// relative error of at most about 2^-33 (lo <= 2^-25 |v|, BF16 keeps 8 significant bits),
+// against 2^-25 for FP32 alone.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ void ext_split(double2 v, float2& hi, uint32_t& lo) {
+  hi = make_float2((float)v.x, (float)v.y);
+  const float rx = (float)(v.x - (double)hi.x), ry = (float)(v.y - (double)hi.y);
+  lo = bf16_rne_bits(rx) | (bf16_rne_bits(ry) << 16);
+}
+
+__device__ __forceinline__ double2 ext_join(float2 hi, uint32_t lo) {
+  return make_double2((double)hi.x + (double)__uint_as_float(lo << 16),
+                      (double)hi.y + (double)__uint_as_float(lo & 0xFFFF0000u));
 }
 
 // Batched forward DFT of `rows` rows of n = 2^LOGN points held across a workgroup of
@@ -200,7 +254,7 @@ __device__ __forceinline__ void dftR_zh(float2* v) {
 // element i ^ ((i >> 3) & 31) (bits 0-4 XORed with bits 3-7: the stride-8 butterfly writes,
 // the contiguous reads and the stride-64 blocks all land on distinct banks), and rows are PAD
 // slots apart beyond n, chosen per shape for the kernel's output gather.
-template <int LOGN, int LOGTILE, int PAD>
+template <int LOGN, int LOGTILE, int PAD, typename V = float2>
 struct Fft {
   static constexpr int n = 1 << LOGN;
   static constexpr int tile = 1 << LOGTILE;
@@ -239,8 +293,8 @@ struct Fft {
 
   // tw[q * stride] = exp(-2 pi i q / n): an n-point table, or every stride-th entry of a
   // larger one.
-  __device__ __forceinline__ static void load_twiddles(float2 (&tr)[NPA][NTW],
-                                                       const float2* __restrict__ tw,
+  __device__ __forceinline__ static void load_twiddles(V (&tr)[NPA][NTW],
+                                                       const V* __restrict__ tw,
                                                        int stride = 1) {
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -260,23 +314,23 @@ struct Fft {
   }
 
   template <int R, int LOGR, int LOGNS, bool ZH = false>
-  __device__ __forceinline__ static void compute_write(float2 (&v)[8], float2* lds,
-                                                       const float2 (&tr)[NPA][NTW]) {
+  __device__ __forceinline__ static void compute_write(V (&v)[8], V* lds,
+                                                       const V (&tr)[NPA][NTW]) {
 #pragma unroll
     for (int p = 0; p < 8 / R; ++p) {
       int row, j;
       bf<LOGR>(p, row, j);
-      float2* b = v + p * R;
+      V* b = v + p * R;
       const int k = j & ((1 << LOGNS) - 1);
       if constexpr (LOGNS > 0) {
         // only radix-8 passes follow the first (LOGNS == 0) pass: one butterfly per thread
         constexpr int q = (LOGNS - LOGR0) / 3;
         if constexpr (kCompact) {
-          float2 w1 = tr[q][0], w2 = tr[q][1], w4 = tr[q][2];
+          V w1 = tr[q][0], w2 = tr[q][1], w4 = tr[q][2];
           // empty register constraint: keeps the derived twiddles inside the tile loop (the
           // compiler would otherwise hoist them out and hold all seven per pass again)
           asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y), "+v"(w4.x), "+v"(w4.y));
-          const float2 w3 = cmul(w2, w1);
+          const V w3 = cmul(w2, w1);
           b[1] = cmul(b[1], w1);
           b[2] = cmul(b[2], w2);
           b[3] = cmul(b[3], w3);
@@ -299,7 +353,7 @@ struct Fft {
     }
   }
 
-  __device__ __forceinline__ static void read8(float2 (&v)[8], const float2* lds) {
+  __device__ __forceinline__ static void read8(V (&v)[8], const V* lds) {
     constexpr int LOGQ = LOGN - 3;
     int row, j;
     bf<3>(0, row, j);
@@ -308,8 +362,8 @@ struct Fft {
   }
 
   template <int LOGNS>
-  __device__ __forceinline__ static void rest(float2 (&v)[8], float2* lds,
-                                              const float2 (&tr)[NPA][NTW]) {
+  __device__ __forceinline__ static void rest(V (&v)[8], V* lds,
+                                              const V (&tr)[NPA][NTW]) {
     if constexpr (LOGNS < LOGN) {
       __syncthreads();
       read8(v, lds);
@@ -331,8 +385,8 @@ struct Fft {
   // (addr(row, i)), visible to all threads.  ZH: the inputs at positions >= n/2 are zero (the
   // slots r >= R0/2 are not read).
   template <bool ZH = false>
-  __device__ __forceinline__ static void run(float2 (&v)[8], float2* lds,
-                                             const float2 (&tr)[NPA][NTW]) {
+  __device__ __forceinline__ static void run(V (&v)[8], V* lds,
+                                             const V (&tr)[NPA][NTW]) {
     compute_write<R0, LOGR0, 0, ZH>(v, lds, tr);
     rest<LOGR0>(v, lds, tr);
     __syncthreads();

@@ -39,6 +39,19 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
 // Snapshot tiles of the beamspace kernel for M, B at a tile size.
 int beamspace_tiles(int M, int B, int logtile);
 
+// Extended-precision channelizer and windowed spatial DFT (FP64 arithmetic, hi + lo storage:
+// X as Xh / Xl [K][B][N], windows as Ywh / Ywl [K][nbt][sumW][TB]); tiles of 2^10 .. 2^13
+// complex (fft_x_logtile_supported), the beamspace tile in snapshots as for launch_beamspace.
+bool fft_x_logtile_supported(int logtile);
+hipError_t launch_channelize_x(const float2* x, float2* Xh, uint32_t* Xl, int N, int K, int B,
+                               const double2* twK, const double2* hb, int logtile,
+                               hipStream_t s);
+hipError_t launch_beamspace_x(const float2* Xh, const uint32_t* Xl, float2* Ywh, uint32_t* Ywl,
+                              int N, int M, int B, int K, const double2* twM, const int* rowtab,
+                              int sumW, const WindowGeom& g, int logtile, hipStream_t s,
+                              float* prof = nullptr, int L = 0, int G = 0, int k0 = 0,
+                              int kc = -1);
+
 // Window starts [T][K] and windowed steering abar [T][K][wmax] (FP64).
 hipError_t launch_steer(const WindowGeom& g, int wmax, int* starts, double2* abar, hipStream_t s);
 
@@ -72,6 +85,9 @@ struct PairArgs {
   // plain form on the planar array: beam index of every window cell [T][K][wmax] in the full
   // beamspace (nullptr = bins (s + i) mod M)
   const int* rows = nullptr;
+  // extended-precision windows: the BF16 remainder plane of the windows (same layout as the
+  // FP32 plane passed as Yw); nullptr = FP32 windows.  Vector pair kernels only.
+  const uint32_t* ywl = nullptr;
 };
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> LDL^H (FP64) -> solve
 // -> apply, reading the window rows written by the beamspace kernel.

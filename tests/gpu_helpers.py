@@ -47,18 +47,30 @@ def weight_tol(kappa: float, plain: bool = False, dr: float = 1.0, unit: float =
 
 
 def windowed_interference(scene, k, bins, ratio):
+    """S D R_in D^H S^T of one window: sigma^2 (S D)(S D)^H + sum_j INR_j (S D a_j)(S D a_j)^H,
+    the same matrix as forming the N x N R_in first, in O(W^2 N) (the N x N form takes seconds
+    per window at N = 4096)."""
     cfg = scene.cfg
-    Rin = oracle.interference_covariance(cfg.N, np.sin(scene.jammer_az), scene.jammer_inr,
-                                         ratio, cfg.dl, cfg.noise_var)
     D = np.exp(-2j * np.pi * np.outer(np.asarray(bins, dtype=np.float64), np.arange(cfg.N)) / cfg.M)
     D /= math.sqrt(cfg.M)
-    return D @ Rin @ D.conj().T
+    R = cfg.noise_var * (D @ D.conj().T)
+    for s, p in zip(np.sin(scene.jammer_az), scene.jammer_inr):
+        a = D @ oracle.steering(cfg.N, oracle.spatial_frequency(float(s), ratio, cfg.dl))
+        R += p * np.outer(a, a.conj())
+    return R
+
+
+NORTH_STAR_WEIGHT_ERR = 1e-5
 
 
 def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.1,
-                     check_sinr=True, fp32_fft=True, tol_scale=1.0, unit=EPS32):
+                     check_sinr=True, fp32_fft=True, tol_scale=1.0, unit=EPS32, ext=False):
     """Check GPU outputs ``res`` (tensors) against oracle dict ``ref`` (windowed_mvdr with
-    return_windows).  Returns a dict of error statistics."""
+    return_windows).  Returns a dict of error statistics.
+
+    ext: the extended-precision forms (fused / graph / learned): every pair's relative weight
+    error must be <= 1e-5 and its SINR loss <= 0.1 dB, with no widening; the FP32 bound of
+    weight_tol is still computed and logged (max_err_over_f32_tol) for comparison."""
     cfg = scene.cfg
     T, K = len(scene.win), cfg.K
     ks = list(range(K)) if subbands is None else list(subbands)
@@ -81,7 +93,10 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
             kappa = float(np.linalg.cond(R))
             err = oracle.rel_weight_error(wg, wo)
             tol = weight_tol(kappa, plain, dr, unit)
-            if tol_scale is not None:   # None: the error is reported, not bounded
+            if ext:
+                assert err <= NORTH_STAR_WEIGHT_ERR, \
+                    f"pair t={t} k={k}: weight error {err:.3e} > 1e-5 (kappa {kappa:.3e})"
+            elif tol_scale is not None:   # None: the error is reported, not bounded
                 assert err <= tol * tol_scale, \
                     f"pair t={t} k={k}: weight error {err:.3e} > {tol:.3e} (kappa {kappa:.3e})"
             worst_w = max(worst_w, err)
@@ -103,5 +118,6 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
                 loss = abs(oracle.sinr_loss_db(wg, wo, a, Rin))
                 assert loss <= sinr_bar_db, f"pair t={t} k={k}: SINR loss {loss:.3e} dB"
                 worst_loss = max(worst_loss, loss)
-    return dict(max_weight_err=worst_w, max_err_over_tol=worst_ratio, max_out_err=worst_z,
-                max_sinr_loss_db=worst_loss)
+    key = "max_err_over_f32_tol" if ext else "max_err_over_tol"
+    return {"max_weight_err": worst_w, key: worst_ratio, "max_out_err": worst_z,
+            "max_sinr_loss_db": worst_loss}

@@ -76,8 +76,8 @@ def test_null_arguments_are_rejected(lib):
     assert lib.wbm_full_mvdr(None, None, None, 1, 10.0, None, None, None, None) == 1
     assert lib.wbm_plan_destroy(None) == 0
     assert lib.wbm_plan_workspace_bytes(None) == 0
-    assert lib.wbm_plan_set_tuning(None, 12, 12, 1, 1) == 1
-    assert lib.wbm_plan_get_tuning(None, None, None, None, None) == 1
+    assert lib.wbm_plan_set_tuning(None, 0, 12, 12, 1, 1) == 1
+    assert lib.wbm_plan_get_tuning(None, 0, None, None, None, None) == 1
 
 
 def test_header_is_plain_c(tmp_path):

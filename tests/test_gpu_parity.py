@@ -106,7 +106,10 @@ def test_window_starts_bit_exact_and_steering(torch, wb, N, M, K, wmax, half_bin
 
 # ----------------------------------------------------------------------------- end to end
 
-@pytest.mark.parametrize("form", ["plain", "fused", "graph"])
+EXT_FORMS = ("fused", "graph")   # extended-precision transforms: held to 1e-5 and 0.1 dB
+
+
+@pytest.mark.parametrize("form", ["plain", "fused", "graph", "fused_f32", "graph_f32"])
 @pytest.mark.parametrize("half_bin", [False, True])
 def test_small_config_end_to_end(torch, wb, form, half_bin):
     cfg = scenes.SMALL.replace(half_bin=half_bin)
@@ -117,13 +120,13 @@ def test_small_config_end_to_end(torch, wb, form, half_bin):
     plan = _plan(wb, cfg, sc)
     res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
-    st = compare_beamform(sc, ref, res, plain=(form == "plain"))
+    st = compare_beamform(sc, ref, res, plain=(form == "plain"), ext=form in EXT_FORMS)
     log(f"  {st}")
     assert st["max_weight_err"] < 1e-5
     plan.close()
 
 
-@pytest.mark.parametrize("form", ["plain", "fused"])
+@pytest.mark.parametrize("form", ["plain", "fused", "graph", "fused_f32"])
 def test_gpu_config_all_pairs(torch, wb, form):
     cfg = scenes.GPU
     log(f"gpu config (N=256 M=512 K=128 W=9 L=256) all 1024 pairs form={form}")
@@ -133,49 +136,106 @@ def test_gpu_config_all_pairs(torch, wb, form):
     plan = _plan(wb, cfg, sc)
     res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
-    st = compare_beamform(sc, ref, res, plain=(form == "plain"))
+    st = compare_beamform(sc, ref, res, plain=(form == "plain"), ext=form in EXT_FORMS)
     log(f"  {st}")
     assert st["max_weight_err"] < 1e-5       # seeded scene: every window is well conditioned
     plan.close()
 
 
 def test_batch_config_full_size_sampled_subbands(torch, wb):
+    """Batching workload at full size (N=1024, M=2048, K=256, L=Lt=512, 64 targets, W in
+    {5, 9, 17, 33}, 6 jammers up to 50 dB): fused and graph forms within 1e-5 / 0.1 dB of the
+    oracle on six subbands (every target); the FP32-transform form within its derived bound."""
     cfg = scenes.BATCH
     log("batch config (N=1024 M=2048 K=256 L=512, W in {5,9,17,33}, 64 targets): generating")
     sc = scenes.make_scene(cfg)
     x32 = _x32(sc)
     plan = _plan(wb, cfg, sc)
     xd = torch.from_numpy(x32).cuda()
-    res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form="fused")
-    torch.cuda.synchronize()
     ks = [0, 1, 77, 128, 200, 255]
     log("  oracle on sampled subbands")
     ref = _oracle(sc, x32, subbands=ks)
-    st = compare_beamform(sc, ref, res, subbands=ks)
-    log(f"  {st}")
+    for form in ("fused", "graph", "fused_f32"):
+        res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS)
+        log(f"  {form}: {st}")
     del xd
     plan.close()
 
 
-def _pin(plan, pair, overlap=1):
-    chan, beam, _, _ = plan.tuning
-    plan.set_tuning(chan, beam, pair, overlap)
-    assert plan.tuning[2] == pair and plan.tuning[3] == overlap
+def _host_channelize_bins(x, K, ks, half_bin, chunk=64):
+    """Oracle channelizer (direct DFT at the listed bins) of a device-resident x, copied to the
+    host in chunks of elements: [N, B, len(ks)] complex128."""
+    parts = []
+    for e0 in range(0, x.shape[0], chunk):
+        parts.append(oracle.channelize_bins(x[e0:e0 + chunk].cpu().numpy(), K, ks, half_bin))
+    return np.concatenate(parts, axis=0)
 
 
-@pytest.mark.parametrize("pair", ["mfma", "wave", "block", "resident"])
+@pytest.mark.timeout(1200)
+def test_precision_config_full_size_sampled_subbands(torch, wb):
+    """Precision workload at full size (N=4096, M=8192, K=512, L=Lt=1024, W=64, 32 targets,
+    8 jammers of 20-60 dB; 34 GB of samples generated on the device): on four subbands, every
+    target, against the FP64 oracle on the same complex64 samples -- the fused and graph forms
+    within 1e-5 relative weight error and 0.1 dB SINR loss; the mixed forms (BF16 covariance)
+    and the FP32-transform form within 0.1 dB, their weight errors stated."""
+    cfg = scenes.PRECISION
+    log("precision config (N=4096 M=8192 K=512 L=Lt=1024 W=64, 32 targets): generating")
+    sc, x = scenes.make_scene_torch(cfg, cfg.seed)
+    torch.cuda.synchronize()
+    ks = [0, 129, 256, 511]
+    log(f"  oracle channelizer on subbands {ks} (host)")
+    X = _host_channelize_bins(x, cfg.K, ks, cfg.half_bin)
+    ref = oracle.windowed_mvdr(None, X=X, M=cfg.M, K=cfg.K, L=cfg.L, Lt=cfg.Lt,
+                               sin_az=[math.sin(a) for a in sc.target_az], win=sc.win,
+                               delta=cfg.delta, beta=cfg.beta, dl=cfg.dl, half_bin=cfg.half_bin,
+                               subbands=ks, return_windows=True)
+    del X
+    plan = _plan(wb, cfg, sc)
+    for form in ("fused", "graph", "fused_f32", "mixed", "mixed_bf16"):
+        log(f"  form {form}")
+        res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        res = dict(res)
+        if form.startswith("mixed"):
+            info = res["info"].cpu().numpy()
+            assert np.all((info & ~wb.INFO_ROUTED) == 0), "Cholesky failures"
+            log(f"    routed to FP64: {int(((info & wb.INFO_ROUTED) != 0).sum())}")
+            res["info"] = torch.zeros_like(res["info"])
+        st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
+                              tol_scale=1.0 if form in EXT_FORMS else None)
+        log(f"    {st}")
+    del x
+    plan.close()
+
+
+def _pin(plan, pair, overlap=1, precision="ext"):
+    chan, beam, _, _ = plan.get_tuning(precision)
+    plan.set_tuning(chan, beam, pair, overlap, precision=precision)
+    assert plan.get_tuning(precision)[2:] == (pair, overlap)
+
+
+# pair kernels each precision of the fused sequence runs: the extended-precision windows are
+# staged as FP64 by the vector kernels; the FP64 matrix-core and LDS-resident kernels read FP32
+PAIR_FORMS = [("fused", "ext", "wave"), ("fused", "ext", "block"),
+              ("fused_f32", "f32", "mfma"), ("fused_f32", "f32", "wave"),
+              ("fused_f32", "f32", "block"), ("fused_f32", "f32", "resident")]
+
+
+@pytest.mark.parametrize("form,precision,pair", PAIR_FORMS)
 @pytest.mark.parametrize("name", ["small", "gpu"])
-def test_pair_kernels_match_oracle(torch, wb, name, pair):
+def test_pair_kernels_match_oracle(torch, wb, name, form, precision, pair):
     cfg = scenes.config_by_name(name)
-    log(f"pair kernel {pair} on the {name} config, all pairs")
+    log(f"pair kernel {pair} ({form}) on the {name} config, all pairs")
     sc = scenes.make_scene(cfg)
     x32 = _x32(sc)
     ref = _oracle(sc, x32)
     plan = _plan(wb, cfg, sc)
-    _pin(plan, pair)
-    res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form="fused")
+    _pin(plan, pair, precision=precision)
+    res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
-    st = compare_beamform(sc, ref, res)
+    st = compare_beamform(sc, ref, res, ext=form in EXT_FORMS)
     log(f"  {st}")
     assert st["max_weight_err"] < 1e-5
     plan.close()
@@ -195,7 +255,7 @@ def test_overlapped_subband_chunks_match_oracle(torch, wb, overlap, form):
     x = torch.from_numpy(x32).cuda()
     res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
-    st = compare_beamform(sc, ref, res)
+    st = compare_beamform(sc, ref, res, ext=True)
     log(f"  {st}")
     assert st["max_weight_err"] < 1e-5
     # same results as the unchunked sequence, every replay
@@ -210,20 +270,23 @@ def test_overlapped_subband_chunks_match_oracle(torch, wb, overlap, form):
     plan.close()
 
 
-@pytest.mark.parametrize("pair", ["mfma", "block"])
-def test_pair_kernels_batch_config_sampled_subbands(torch, wb, pair):
+@pytest.mark.parametrize("form,precision,pair", [("fused_f32", "f32", "mfma"),
+                                                  ("fused_f32", "f32", "block"),
+                                                  ("fused", "ext", "wave")])
+def test_pair_kernels_batch_config_sampled_subbands(torch, wb, form, precision, pair):
     cfg = scenes.BATCH
-    log(f"pair kernel {pair}, batch config (W in {{5,9,17,33}}, 64 targets), sampled subbands")
+    log(f"pair kernel {pair} ({form}), batch config (W in {{5,9,17,33}}, 64 targets), "
+        f"sampled subbands")
     sc = scenes.make_scene(cfg)
     x32 = _x32(sc)
     plan = _plan(wb, cfg, sc)
-    _pin(plan, pair)
+    _pin(plan, pair, precision=precision)
     xd = torch.from_numpy(x32).cuda()
-    res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form="fused")
+    res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
     ks = [0, 3, 130, 255]
     ref = _oracle(sc, x32, subbands=ks)
-    st = compare_beamform(sc, ref, res, subbands=ks)
+    st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS)
     log(f"  {st}")
     del xd
     plan.close()
@@ -275,15 +338,16 @@ def test_edge_shapes(torch, wb, case):
     x32 = _x32(sc)
     ref = _oracle(sc, x32)
     plan = _plan(wb, cfg, sc)
-    runs = [("plain", None), ("fused", "mfma"), ("fused", "block"), ("fused", "resident")]
+    runs = [("plain", None, None), ("fused", "block", "ext"), ("fused_f32", "mfma", "f32"),
+            ("fused_f32", "block", "f32"), ("fused_f32", "resident", "f32")]
     if max(W) <= 40:
-        runs.append(("fused", "wave"))
-    for form, pair in runs:
+        runs += [("fused", "wave", "ext"), ("fused_f32", "wave", "f32")]
+    for form, pair, precision in runs:
         if pair:
-            _pin(plan, pair)
+            _pin(plan, pair, precision=precision)
         res = plan.beamform(torch.from_numpy(x32).cuda(), sc.target_az, sc.win, cfg.delta, form=form)
         torch.cuda.synchronize()
-        compare_beamform(sc, ref, res, plain=(form == "plain"))
+        compare_beamform(sc, ref, res, plain=(form == "plain"), ext=form in EXT_FORMS)
     plan.close()
 
 
@@ -316,14 +380,14 @@ def test_rejects_bad_targets(torch, wb):
     plan.close()
 
 
-@pytest.mark.parametrize("form", ["plain", "fused-mfma", "fused-block", "fused-wave",
-                                  "fused-resident"])
+@pytest.mark.parametrize("form", ["plain", "fused_f32-mfma", "fused-block", "fused-wave",
+                                  "fused_f32-block", "fused_f32-wave", "fused_f32-resident"])
 def test_zero_loading_singular_reports_info(torch, wb, form):
     # silent input and no loading: the window covariance is 0, the first pivot fails (info = 1)
     plan = wb.Plan(16, 32, 4, 3, 2, 1, 9)
     if form.startswith("fused"):
         form, pair = form.split("-")
-        _pin(plan, pair)
+        _pin(plan, pair, precision="f32" if form.endswith("f32") else "ext")
     x = torch.zeros((16, 5 * 4), dtype=torch.complex64, device="cuda")
     res = plan.beamform(x, [0.2], [9], 0.0, form=form)
     torch.cuda.synchronize()
@@ -413,7 +477,8 @@ def test_full_dimensional_mvdr_matches_oracle(torch, wb, name, subbands):
 def test_mixed_forms_route_ill_conditioned_windows_to_fp64(torch, wb, form):
     """A 60 dB jammer inside a target's window drives its covariance past the routing threshold
     (condition estimate 1e4): those windows must be flagged (info bit 30) and solved by the exact
-    FP64 kernel (bit-identical to the fused form on the same vector kernel); the others stay on
+    FP64 kernel (bit-identical to the fused_f32 form on the same vector kernel, both reading the
+    FP32 transforms' windows); the others stay on
     the mixed path within its bound."""
     cfg = scenes.SceneConfig(name="route", N=32, M=64, K=16, L=64, Lt=32, T=4, W=9,
                              W_choices=(9,), n_jammers=2,
@@ -423,9 +488,9 @@ def test_mixed_forms_route_ill_conditioned_windows_to_fp64(torch, wb, form):
     x32 = _x32(sc)
     ref = _oracle(sc, x32)
     plan = _plan(wb, cfg, sc)
-    _pin(plan, "block")
+    _pin(plan, "block", precision="f32")
     x = torch.from_numpy(x32).cuda()
-    exact = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    exact = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused_f32")
     res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
     torch.cuda.synchronize()
     info = res["info"].cpu().numpy()

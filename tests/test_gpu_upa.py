@@ -125,8 +125,8 @@ def _run(torch, wb, cfg, pair=None, form="fused", subbands=None, plain_bound=Fal
         f"Lt{cfg.Lt} T{cfg.T} pair={pair} form={form}")
     plan = _plan(wb, cfg, sc)
     if pair is not None:
-        chan, beam, _, _ = plan.tuning
-        plan.set_tuning(chan, beam, pair, 1)
+        chan, beam, _, _ = plan.get_tuning("f32")
+        plan.set_tuning(chan, beam, pair, 1, precision="f32")
     x = torch.from_numpy(x32).cuda()
     res = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
                             cfg.delta, form=form)
@@ -266,7 +266,7 @@ def test_one_row_planar_equals_linear_path(torch, wb):
     sc = scenes.make_upa_scene(cfg)
     x = torch.from_numpy(sc.x.astype(np.complex64)).cuda()
     plan = _plan(wb, cfg, sc)
-    plan.set_tuning(12, 12, "block", 1)
+    plan.set_tuning(12, 12, "block", 1, precision="f32")
     r2 = plan.beamform_upa(x, 1, 1, sc.target_az, sc.target_el, sc.win_z, sc.win_x, cfg.delta)
     r1 = plan.beamform(x, sc.target_az, sc.win_x, cfg.delta, form="fused")
     torch.cuda.synchronize()
@@ -283,7 +283,7 @@ def test_linear_and_planar_calls_interleave(torch, wb):
     x32 = sc.x.astype(np.complex64)
     x = torch.from_numpy(x32).cuda()
     plan = _plan(wb, cfg, sc)
-    plan.set_tuning(12, 12, "block", 1)
+    plan.set_tuning(12, 12, "block", 1, precision="f32")
     win = np.full(cfg.T, 9, dtype=np.int32)
     kw = dict(form="fused")
     a = plan.beamform_upa(x, cfg.Nz, cfg.Mz, sc.target_az, sc.target_el, sc.win_z, sc.win_x,
