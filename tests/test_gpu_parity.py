@@ -170,6 +170,8 @@ def _host_channelize_bins(x, K, ks, half_bin, chunk=64):
     parts = []
     for e0 in range(0, x.shape[0], chunk):
         parts.append(oracle.channelize_bins(x[e0:e0 + chunk].cpu().numpy(), K, ks, half_bin))
+        if (e0 // chunk) % 16 == 15:
+            log(f"    elements {e0 + chunk}/{x.shape[0]}")
     return np.concatenate(parts, axis=0)
 
 
