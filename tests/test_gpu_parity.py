@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 import scenes
-from gpu_helpers import compare_beamform, log, snapshot_dynamic_range, weight_tol
+from gpu_helpers import (compare_beamform, log, loss_by_pivot_ratio, snapshot_dynamic_range,
+                         weight_tol)
 
 pytestmark = pytest.mark.gpu
 
@@ -155,11 +156,22 @@ def test_batch_config_full_size_sampled_subbands(torch, wb):
     ks = [0, 1, 77, 128, 200, 255]
     log("  oracle on sampled subbands")
     ref = _oracle(sc, x32, subbands=ks)
-    for form in ("fused", "graph", "fused_f32"):
-        res = plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form=form)
+    for form in ("fused", "graph", "fused_f32", "mixed", "mixed_bf16"):
+        res = dict(plan.beamform(xd, sc.target_az, sc.win, cfg.delta, form=form))
         torch.cuda.synchronize()
-        st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS)
+        mixed = form.startswith("mixed")
+        if mixed:
+            info = res["info"].cpu().numpy()
+            assert np.all((info & ~wb.INFO_ROUTED) == 0), "Cholesky failures"
+            log(f"  {form}: routed to FP64: {int(((info & wb.INFO_ROUTED) != 0).sum())}")
+            res["info"] = torch.zeros_like(res["info"])
+        st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
+                              tol_scale=None if mixed else 1.0,
+                              sinr_bar_db=None if form == "mixed_bf16" else 0.1, pairs=True)
+        pp = st.pop("per_pair")
         log(f"  {form}: {st}")
+        if mixed:
+            log(f"    by pivot ratio (oracle LDL^H): {loss_by_pivot_ratio(pp)}")
     del xd
     plan.close()
 
@@ -206,8 +218,12 @@ def test_precision_config_full_size_sampled_subbands(torch, wb):
             log(f"    routed to FP64: {int(((info & wb.INFO_ROUTED) != 0).sum())}")
             res["info"] = torch.zeros_like(res["info"])
         st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
-                              tol_scale=1.0 if form in EXT_FORMS else None)
+                              tol_scale=1.0 if form in EXT_FORMS else None,
+                              sinr_bar_db=None if form == "mixed_bf16" else 0.1, pairs=True)
+        pp = st.pop("per_pair")
         log(f"    {st}")
+        if form.startswith("mixed"):
+            log(f"    by pivot ratio (oracle LDL^H): {loss_by_pivot_ratio(pp)}")
     del x
     plan.close()
 
