@@ -77,10 +77,11 @@ typedef enum {
                                snapshot split into BF16 hi + lo (three BF16 products, FP32
                                accumulation), FP32 LDL^H and solves, one FP64-residual
                                refinement step and FP64 normalisation a^H R^-1 a; windows whose
-                               LDL^H pivots span a condition estimate above 1e4 take the
-                               FP64 path instead and report info bit 30 (info & (1 << 30)) */
+                               LDL^H pivots span a ratio max d / min d above 1e4 take the FP64
+                               path instead and report info bit 30 (info & (1 << 30)) */
 #define WBM_FORM_MIXED_BF16 4  /* as WBM_FORM_MIXED with one BF16 product per step (snapshots
-                               rounded to BF16) */
+                               rounded to BF16); windows are routed to the FP64 path above a
+                               pivot ratio of 1e2 (one BF16 product keeps 8 significant bits) */
 #define WBM_FORM_FUSED_F32 5   /* WBM_FORM_FUSED with FP32 transforms and FP32 X and windows
                                (fewer bytes; the transforms' rounding then moves the weights
                                by about 0.1 eps32 times the input's dynamic range over the

@@ -1552,9 +1552,10 @@ hipError_t set_pair_attributes() {
 // step) or with each FP32 snapshot split into BF16 hi + lo parts (hi*hi + hi*lo + lo*hi, three
 // products).  The LDL^H factorisation and both triangular solves run in FP32; the residual of
 // the iterative-refinement step and the normalisation a^H R^-1 a run in FP64.  A window whose
-// pivots span more than kRouteKappa (condition-number estimate) is routed to the exact path
-// instead: a second launch runs the exact vector pair kernel on the flagged windows only (FP64
-// accumulation of the FP32 snapshots, FP64 LDL^H); their info entry carries bit 30.  Staging,
+// FP32 LDL^H pivots span more than a per-form ratio (max d_j / min d_j above kRouteKappaSplit or
+// kRouteKappaBf16, a condition-number estimate) is routed to the exact path instead: a second
+// launch runs the exact vector pair kernel on the flagged windows only (FP64 accumulation of the
+// FP32 snapshots, FP64 LDL^H); their info entry carries bit 30.  Staging,
 // prefetch, pair order and the apply are those of the fused pair kernels above.
 namespace wbm {
 
@@ -1562,7 +1563,14 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kMixRS = 64 + 8;             // bf16 row stride of a staged plane (144 B)
-constexpr double kRouteKappa = 1.0e4;
+// Routing thresholds.  One BF16 product rounds every snapshot to 8 significant bits, the split
+// hi + lo products to about 16: the pivot ratio up to which the mixed solve stays within 0.1 dB
+// of the FP64 oracle's output SINR is correspondingly smaller for the single product.  Measured
+// on the batching and precision workloads (largest SINR loss of the windows kept on the mixed
+// path, by the oracle covariance's pivot ratio): one BF16 product 0.036 / 0.065 / 0.21 dB below
+// 10 / 100 / 1000, split products at most 0.032 dB below 1e4.
+constexpr double kRouteKappaSplit = 1.0e4;
+constexpr double kRouteKappaBf16 = 1.0e2;
 constexpr int kInfoRouted = 1 << 30;
 
 __device__ __forceinline__ __bf16 to_bf16(float f) {
@@ -1775,7 +1783,7 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
       dmax = fmaxf(dmax, R32[j * RS + j].x);
       dmin = fminf(dmin, R32[j * RS + j].x);
     }
-    route = (double)dmax > kRouteKappa * (double)dmin;
+    route = (double)dmax > (SPLIT ? kRouteKappaSplit : kRouteKappaBf16) * (double)dmin;
   }
   __syncthreads();
   if (!route) {

@@ -167,7 +167,7 @@ def test_batch_config_full_size_sampled_subbands(torch, wb):
             res["info"] = torch.zeros_like(res["info"])
         st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
                               tol_scale=None if mixed else 1.0,
-                              sinr_bar_db=None if form == "mixed_bf16" else 0.1, pairs=True)
+                              pairs=True)
         pp = st.pop("per_pair")
         log(f"  {form}: {st}")
         if mixed:
@@ -218,8 +218,7 @@ def test_precision_config_full_size_sampled_subbands(torch, wb):
             log(f"    routed to FP64: {int(((info & wb.INFO_ROUTED) != 0).sum())}")
             res["info"] = torch.zeros_like(res["info"])
         st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
-                              tol_scale=1.0 if form in EXT_FORMS else None,
-                              sinr_bar_db=None if form == "mixed_bf16" else 0.1, pairs=True)
+                              tol_scale=1.0 if form in EXT_FORMS else None, pairs=True)
         pp = st.pop("per_pair")
         log(f"    {st}")
         if form.startswith("mixed"):
@@ -525,8 +524,8 @@ def test_mixed_forms_route_ill_conditioned_windows_to_fp64(torch, wb, form):
     res = dict(res)
     res["info"] = torch.zeros_like(res["info"])
     unit = 2.0 ** -16 if form == "mixed" else 2.0 ** -8
-    st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit,
-                          check_sinr=(form == "mixed"))
+    # bar: a tenth of the derived 4 u kappa bound (measured at most 0.007 of the full bound)
+    st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit, tol_scale=0.1)
     log(f"  {st}")
     plan.close()
 
@@ -550,6 +549,8 @@ def test_mixed_precision_forms(torch, wb, name):
         res = dict(res)
         res["info"] = torch.zeros_like(res["info"])
         unit = 2.0 ** -16 if form == "mixed" else 2.0 ** -8
-        st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit)
+        # bar: a tenth of the derived 4 u kappa bound (measured at most 0.028 of the full bound)
+        st = compare_beamform(sc, ref, res, plain=True, sinr_bar_db=0.1, unit=unit,
+                              tol_scale=0.1)
         log(f"  {name} {form}: routed {int(routed.sum())}/{routed.size} {st}")
     plan.close()
