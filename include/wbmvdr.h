@@ -326,11 +326,13 @@ wbm_status wbm_beam_pattern_upa(wbm_plan* plan, const wbm_c32* c, int32_t pairs,
  * comparison method.  R = (1/L) sum_{b<L} X_b X_b^H + loading I_N (N x N, FP64
  * accumulation), c_t = R^-1 a_t / (a_t^H R^-1 a_t) with a_t the element steering
  * vector of target t at the subband centre (Eq. 7-8), out = c_t^H X_b for the Lt
- * test blocks.  N <= 4096.
- *   out device [T][K][Lt]; weights device [T][K][N] or NULL; info device [K] or NULL. */
+ * test blocks.  N <= 4096.  Subbands k0 .. k0 + nk - 1 only (nk = 0: all of them; the
+ * channelizer still runs over every subband); entries of other subbands are not written.
+ *   out device [T][K][Lt]; weights device [T][K][N] or NULL; info device [K] or NULL.
+ * Errors: WBM_ERR_ARG for NULL x / out or a subband range outside [0, K). */
 wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad, int32_t T,
-                         double loading, wbm_c32* out, wbm_c32* weights, int32_t* info,
-                         void* stream);
+                         double loading, int32_t k0, int32_t nk, wbm_c32* out,
+                         wbm_c32* weights, int32_t* info, void* stream);
 
 /* Per-stage timing of the fused sequence (same arguments as wbm_beamform with
  * form = WBM_FORM_FUSED for precision WBM_PREC_EXT, WBM_FORM_FUSED_F32 for WBM_PREC_F32;

@@ -464,18 +464,21 @@ class Plan:
             _stream(stream)))
         return out
 
-    def full_mvdr(self, x, az_rad, loading: float, want_weights: bool = True, stream=None):
+    def full_mvdr(self, x, az_rad, loading: float, want_weights: bool = True, stream=None,
+                  subbands=None):
         """Full-dimensional element-space MVDR per subband: out [T, K, Lt], weights [T, K, N],
-        info [K]."""
+        info [K]; subbands = (k0, nk) restricts it to k0 .. k0 + nk - 1 (other entries are
+        left unwritten)."""
         torch = _torch()
         self._x(x)
         az, _, T = self._targets(az_rad, None)
-        out = torch.empty((T, self.K, self.Lt), dtype=torch.complex64, device=self.device)
-        weights = (torch.empty((T, self.K, self.N), dtype=torch.complex64, device=self.device)
+        k0, nk = (0, 0) if subbands is None else (int(subbands[0]), int(subbands[1]))
+        out = torch.zeros((T, self.K, self.Lt), dtype=torch.complex64, device=self.device)
+        weights = (torch.zeros((T, self.K, self.N), dtype=torch.complex64, device=self.device)
                    if want_weights else None)
-        info = torch.empty((self.K,), dtype=torch.int32, device=self.device)
+        info = torch.zeros((self.K,), dtype=torch.int32, device=self.device)
         _lib.check(_lib.load().wbm_full_mvdr(self._h, _ptr(x), az.ctypes.data, T, float(loading),
-                                             _ptr(out), _ptr(weights), _ptr(info),
+                                             k0, nk, _ptr(out), _ptr(weights), _ptr(info),
                                              _stream(stream)))
         return dict(out=out, weights=weights, info=info)
 

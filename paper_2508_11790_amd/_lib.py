@@ -67,7 +67,7 @@ def load() -> C.CDLL:
     lib.wbm_channelize.argtypes = [P, P, P, P]
     lib.wbm_beamspace.argtypes = [P, P, P, P]
     lib.wbm_steer.argtypes = [P, P, P, I32, P, P, P]
-    lib.wbm_full_mvdr.argtypes = [P, P, P, I32, D, P, P, P, P]
+    lib.wbm_full_mvdr.argtypes = [P, P, P, I32, D, I32, I32, P, P, P, P]
     lib.wbm_stage_times.argtypes = [P, P, P, P, I32, D, I32, I32, P, P]
     lib.wbm_profiles.argtypes = [P, P, P, I32, D, P, P]
     lib.wbm_beamform_pairs.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P]

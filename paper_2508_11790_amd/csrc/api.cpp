@@ -1415,8 +1415,8 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
 }
 
 wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, int32_t T,
-                         double loading, wbm_c32* out, wbm_c32* weights, int32_t* info,
-                         void* stream) {
+                         double loading, int32_t k_first, int32_t nk_req, wbm_c32* out,
+                         wbm_c32* weights, int32_t* info, void* stream) {
   wbm_status s = check_plan(p);
   if (s) return s;
   const wbm_config& c = p->cfg;
@@ -1424,6 +1424,13 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
   if (!out && c.l_test > 0) return fail(WBM_ERR_ARG, "out is NULL");
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
   if (c.n_elem > 4096) return fail(WBM_ERR_UNSUPPORTED, "full-dimensional MVDR supports N <= 4096");
+  if (nk_req == 0) {
+    k_first = 0;
+    nk_req = c.k_sub;
+  }
+  if (k_first < 0 || nk_req < 0 || k_first + nk_req > c.k_sub)
+    return fail(WBM_ERR_ARG, "subband range outside [0, K)");
+  const int k_end = k_first + nk_req;
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
   if ((s = upload_desc(p, az_rad, nullptr, T, st, &sumW))) return s;
@@ -1440,7 +1447,7 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
   WBM_HIP(enqueue_channelize(p, kF32, reinterpret_cast<const float2*>(x), st),
           "channelize launch");
   int* inf = info ? info : p->full_info;
-  for (int k0 = 0; k0 < c.k_sub; k0 += p->nk_full) {
+  for (int k0 = k_first; k0 < k_end; k0 += p->nk_full) {
     wbm::FullArgs a;
     a.N = c.n_elem;
     a.K = c.k_sub;
@@ -1449,7 +1456,7 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
     a.B = p->B;
     a.T = T;
     a.k0 = k0;
-    a.nk = std::min(p->nk_full, c.k_sub - k0);
+    a.nk = std::min(p->nk_full, k_end - k0);
     a.delta = loading;
     a.beta = c.beta;
     a.dl = c.d_over_lambda;

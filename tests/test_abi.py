@@ -73,7 +73,7 @@ def test_null_arguments_are_rejected(lib):
     assert lib.wbm_plan_create(None, C.byref(h)) == 1
     assert lib.wbm_beamform(None, None, None, None, 1, 10.0, 1, None, None, None, None, None) == 1
     assert lib.wbm_channelize(None, None, None, None) == 1
-    assert lib.wbm_full_mvdr(None, None, None, 1, 10.0, None, None, None, None) == 1
+    assert lib.wbm_full_mvdr(None, None, None, 1, 10.0, 0, 0, None, None, None, None) == 1
     assert lib.wbm_plan_destroy(None) == 0
     assert lib.wbm_plan_workspace_bytes(None) == 0
     assert lib.wbm_plan_set_tuning(None, 0, 12, 12, 1, 1) == 1
