@@ -264,14 +264,15 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize_x(
       }
     }
   };
-  float2 nv[8];
-  int b = blockIdx.y;
-  if (b < B) fetch(b, nv);
-  for (; b < B; b += gridDim.y) {
+  // no register prefetch of the next block here (unlike the FP32 kernel): it would hold 16 more
+  // registers, and at 2^13-complex tiles (16 elements, 128-byte output runs: the fastest tile
+  // for this kernel) the workgroup's 1024 threads are held to 128 registers each
+  for (int b = blockIdx.y; b < B; b += gridDim.y) {
+    float2 nv[8];
+    fetch(b, nv);
     double2 v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = make_double2((double)nv[q].x, (double)nv[q].y);
-    if (b + (int)gridDim.y < B) fetch(b + gridDim.y, nv);
     if (hb) {
 #pragma unroll
       for (int p = 0; p < 8 / F::R0; ++p) {
@@ -411,6 +412,125 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace_x(
       }
     }
     __syncthreads();   // the next tile's first pass overwrites lds
+  }
+  if (prof) {
+    float* dst = prof + ((int64_t)k * gridDim.x + blockIdx.x) * g.T * 64;
+    for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) dst[idx] = s_acc[idx];
+  }
+}
+
+// Windowed spatial DFT in extended precision for M >= 8192 with N <= M / 2 (the upper half of
+// every zero-padded row is zero).  The M-point transform of such a row splits into two
+// H = M/2-point transforms, Y[2 m'] = sum_{e<N} X[e] w_H^(m' e) and Y[2 m' + 1] = sum_{e<N}
+// (X[e] w_M^e) w_H^(m' e), computed one after the other in a 64 KiB FP64 tile (one snapshot per
+// iteration, 512 threads at H = 4096): the even bins' window rows are written after the first,
+// the odd bins' after the second.  The full M-point row would need a 128 KiB tile and 1024
+// threads, one workgroup per compute unit.  Outputs as k_beamspace_x with one snapshot per tile
+// (TB = 1).
+template <int LOGH>
+__global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
+    const float2* __restrict__ Xh, const uint32_t* __restrict__ Xl, float2* __restrict__ Ywh,
+    uint32_t* __restrict__ Ywl, int N, int B, int K, const double2* __restrict__ twM,
+    double scale, const int* __restrict__ rowtab, int sumW, WindowGeom g, float* __restrict__ prof,
+    int L, int k0) {
+  using F = Fft<LOGH, LOGH, beam_pad(LOGH, LOGH), double2>;
+  constexpr int H = F::n, M = 2 * H;
+  extern __shared__ double2 lds_x[];
+  double2* lds = lds_x;
+  int* s_dyn = reinterpret_cast<int*>(lds_x + F::lds_complex);
+  int* s_start = s_dyn;
+  int* s_center = s_dyn + g.T;
+  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);
+  int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);
+  const int k = k0 + blockIdx.y;
+  double2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twM, 2);   // the H-point twiddles: every second entry of the M table
+  int fpos[8];
+#pragma unroll
+  for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      int row, e;
+      F::first_input(p, r, row, e);
+      fpos[p * F::R0 + r] = e;
+    }
+  }
+  auto fetch = [&](int b, float2 (&vh)[8], uint32_t (&vl)[8]) {
+    const int64_t base = ((int64_t)k * B + b) * N;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      vh[q] = make_float2(0.f, 0.f);
+      vl[q] = 0u;
+      if (fpos[q] < N) {
+        vh[q] = Xh[base + fpos[q]];
+        vl[q] = Xl[base + fpos[q]];
+      }
+    }
+  };
+  float2 nh[8];
+  uint32_t nl[8];
+  if ((int)blockIdx.x < B) fetch(blockIdx.x, nh, nl);
+  if (Ywh || prof) {
+    for (int t = threadIdx.x; t < g.T; t += F::threads) {
+      double u;
+      int s;
+      window_of(g, t, k, &u, &s);
+      s_start[t] = s;
+      if (prof) s_center[t] = (int)floor(u + 0.5);
+    }
+    if (prof)
+      for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
+    if (Ywh) {
+      __syncthreads();
+      for (int r = threadIdx.x; r < sumW; r += F::threads) {
+        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+        s_bin[r] = (s_start[t] + i) & (M - 1);
+      }
+    }
+  }
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    float2 ch[8];
+    uint32_t cl[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      ch[q] = nh[q];
+      cl[q] = nl[q];
+    }
+    if (b + (int)gridDim.x < B) fetch(b + gridDim.x, nh, nl);
+    const int64_t o0 = ((int64_t)k * B + b) * sumW;
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {
+      double2 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        v[q] = ext_join(ch[q], cl[q]);
+        if (par) v[q] = cmul(v[q], twM[fpos[q]]);   // X[e] w_M^e for the odd bins
+      }
+      F::template run<false>(v, lds, tr);
+      if (Ywh) {
+        for (int r = threadIdx.x; r < sumW; r += F::threads) {
+          const int m = s_bin[r];
+          if ((m & 1) == par) {
+            float2 hi;
+            uint32_t lo;
+            ext_split(cscale(lds[F::addr(0, m >> 1)], scale), hi, lo);
+            Ywh[o0 + r] = hi;
+            Ywl[o0 + r] = lo;
+          }
+        }
+      }
+      if (prof && b < L) {
+        for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) {
+          const int t = idx >> 6, jj = idx & 63;
+          const int m = (s_center[t] - 32 + jj) & (M - 1);
+          if ((m & 1) == par) {
+            const double2 y = cscale(lds[F::addr(0, m >> 1)], scale);
+            s_acc[idx] += (float)(y.x * y.x + y.y * y.y);
+          }
+        }
+      }
+      __syncthreads();   // the next transform overwrites lds
+    }
   }
   if (prof) {
     float* dst = prof + ((int64_t)k * gridDim.x + blockIdx.x) * g.T * 64;
@@ -745,11 +865,48 @@ static hipError_t beam_launch_x_zh(const float2* Xh, const uint32_t* Xl, float2*
   return hipGetLastError();
 }
 
+// Split-half form (k_beamspace_x2) for M = 2^(LOGH + 1), one snapshot per tile.
+template <int LOGH>
+static hipError_t beam_launch_x2(const float2* Xh, const uint32_t* Xl, float2* Ywh,
+                                 uint32_t* Ywl, int N, int B, int K, const double2* twM,
+                                 const int* rowtab, int sumW, const WindowGeom& g, float* prof,
+                                 int L, int G, int k0, int kc, hipStream_t s) {
+  using F = Fft<LOGH, LOGH, beam_pad(LOGH, LOGH), double2>;
+  if (prof && (G < 1 || G > B)) return hipErrorInvalidValue;
+  size_t shm = sizeof(double2) * (size_t)F::lds_complex;
+  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
+  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
+  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x2<LOGH>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  int gx = G;
+  if (!prof) {
+    static int resident = 0;
+    const int cap = resident_blocks(k_beamspace_x2<LOGH>, F::threads, shm, &resident);
+    gx = (cap + kc - 1) / kc;
+    if (gx > B) gx = B;
+    if (gx < 1) gx = 1;
+  }
+  hipLaunchKernelGGL((k_beamspace_x2<LOGH>), dim3(gx, kc), dim3(F::threads), shm, s, Xh, Xl, Ywh,
+                     Ywl, N, B, K, twM, 1.0 / sqrt((double)(2 * F::n)), rowtab, sumW, g, prof, L,
+                     k0);
+  return hipGetLastError();
+}
+
 template <int LOGM, int LOGT>
 static hipError_t beam_launch_x(const float2* Xh, const uint32_t* Xl, float2* Ywh, uint32_t* Ywl,
                                 int N, int B, int K, const double2* twM, const int* rowtab,
                                 int sumW, const WindowGeom& g, float* prof, int L, int G, int k0,
                                 int kc, hipStream_t s) {
+  if constexpr (LOGM >= 13) {
+    // a full FP64 row no longer fits a 64 KiB tile: split halves whenever the upper half is zero
+    if (2 * N <= (1 << LOGM))
+      return beam_launch_x2<LOGM - 1>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g, prof, L,
+                                      G, k0, kc, s);
+  }
   if (2 * N <= (1 << LOGM))
     return beam_launch_x_zh<LOGM, LOGT, true>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g,
                                               prof, L, G, k0, kc, s);

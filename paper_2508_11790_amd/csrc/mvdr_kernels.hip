@@ -1140,8 +1140,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   mvdr_x_body<40, false, 256, 64, EXT>(a, g, d, Yw, out, wout, starts_out, info);
 }
 
+// two waves per SIMD: the extended-precision build would otherwise take 256 VGPRs + 48 AGPRs
+// (one wave per SIMD); held to 256 registers it spills some staging registers and runs 1.6x
+// faster at 64-bin windows
 template <bool EXT>
-__global__ __launch_bounds__(256) void k_mvdr_xv64(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_mvdr_xv64(
     PairArgs a, WindowGeom g, DevDesc d, const float2* __restrict__ Yw, float2* __restrict__ out,
     float2* __restrict__ wout, int* __restrict__ starts_out, int* __restrict__ info) {
   mvdr_x_body<64, false, 256, 64, EXT>(a, g, d, Yw, out, wout, starts_out, info);

@@ -288,7 +288,8 @@ struct Fft {
   // w^7 = w^4 w^3) so that the large transforms stay within their register budget.
   static constexpr int NP = (LOGN - LOGR0) / 3;
   static constexpr int NPA = NP > 0 ? NP : 1;
-  static constexpr bool kCompact = NP >= 3;
+  // FP64 values: always the three-twiddle form (register budget)
+  static constexpr bool kCompact = NP >= 3 || sizeof(V) == sizeof(double2);
   static constexpr int NTW = kCompact ? 3 : 7;
 
   // tw[q * stride] = exp(-2 pi i q / n): an n-point table, or every stride-th entry of a
