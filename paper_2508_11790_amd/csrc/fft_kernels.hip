@@ -538,6 +538,193 @@ __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// 4096-point FP64 transform of one LDS-resident row by 256 threads, 16 values each: three
+// radix-16 Stockham passes (sub-lengths Ns = 1, 16, 256).  Butterfly j of a pass takes
+// x[j + 256 r], multiplies input r by w^(r (j mod Ns)), w = exp(-2 pi i / (16 Ns)), applies the
+// 16-point DFT and stores output r at (j div Ns) 16 Ns + (j mod Ns) + r Ns.  LDS position of
+// element e: e ^ ((e >> 4) & 15), so that the stride-16 stores of a pass and the stride-1 loads
+// of the next each put 16 consecutive lanes on 16 distinct 16-byte bank groups.
+struct Fft4k {
+  static constexpr int n = 4096, threads = 256;
+  __device__ __forceinline__ static int pos(int e) { return e ^ ((e >> 4) & 15); }
+
+  // 16-point DFT in place, 4 x 4: DFT4 over p of v[q + 4p] (outputs k1 at v[q + 4 k1]),
+  // twiddle by exp(-2 pi i q k1 / 16), DFT4 over q (output k1 + 4 k2 at v[4 k1 + k2]).
+  __device__ __forceinline__ static void dft16(double2 (&v)[16]) {
+    constexpr double c = 0.92387953251128675613, sn = 0.38268343236508977173,
+                     h = 0.70710678118654752440;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dft4(v[q], v[q + 4], v[q + 8], v[q + 12]);
+    v[5] = cmul(v[5], make_double2(c, -sn));      // w^1
+    v[6] = cmul(v[6], make_double2(h, -h));       // w^2
+    v[7] = cmul(v[7], make_double2(sn, -c));      // w^3
+    v[9] = cmul(v[9], make_double2(h, -h));       // w^2
+    v[10] = cmul_mj(v[10]);                       // w^4 = -i
+    v[11] = cmul(v[11], make_double2(-h, -h));    // w^6
+    v[13] = cmul(v[13], make_double2(sn, -c));    // w^3
+    v[14] = cmul(v[14], make_double2(-h, -h));    // w^6
+    v[15] = cmul(v[15], make_double2(-c, sn));    // w^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  }
+
+  // output r of the butterfly (natural order) to LDS element base + r ns
+  __device__ __forceinline__ static void store(const double2 (&v)[16], double2* lds, int base,
+                                               int ns) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) lds[pos(base + r * ns)] = v[4 * (r & 3) + (r >> 2)];
+  }
+
+  __device__ __forceinline__ static void load(double2 (&v)[16], const double2* lds, int j) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = lds[pos(j + 256 * r)];
+  }
+
+  // input r times w^r, the powers formed by repeated products (FP64).  The empty register
+  // constraint keeps the powers inside the caller's loop (hoisted out of it, as loop
+  // invariants, they would take 60 registers per pass).
+  __device__ __forceinline__ static void twiddle(double2 (&v)[16], double2 w) {
+    asm volatile("" : "+v"(w.x), "+v"(w.y));
+    double2 t = w;
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+      v[r] = cmul(v[r], t);
+      if (r < 15) t = cmul(t, w);
+    }
+  }
+
+  // v = this thread's inputs x[j + 256 r]; w1 = exp(-2 pi i (j mod 16) / 256), w2 =
+  // exp(-2 pi i (j mod 256) / 4096).  On return lds holds the transform in natural order
+  // (position pos(m)), visible to every thread.
+  __device__ __forceinline__ static void run(double2 (&v)[16], double2* lds, double2 w1,
+                                             double2 w2) {
+    const int j = threadIdx.x;
+    dft16(v);
+    store(v, lds, 16 * j, 1);
+    __syncthreads();
+    load(v, lds, j);
+    __syncthreads();
+    twiddle(v, w1);
+    dft16(v);
+    store(v, lds, (j >> 4) * 256 + (j & 15), 16);
+    __syncthreads();
+    load(v, lds, j);
+    __syncthreads();
+    twiddle(v, w2);
+    dft16(v);
+    store(v, lds, j, 256);
+    __syncthreads();
+  }
+};
+
+// Windowed spatial DFT in extended precision at M = 8192, N <= 4096: the split-half scheme of
+// k_beamspace_x2 (even bins from the 4096-point transform of X, odd bins from that of
+// X[e] w_M^e) on the Fft4k engine.  256 threads: two 64 KiB workgroups per compute unit.  The
+// next snapshot's inputs are fetched into the registers of the current one as soon as the odd
+// half's inputs have been formed.  Outputs as k_beamspace_x with one snapshot per tile.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_beamspace_x16(
+    const float2* __restrict__ Xh, const uint32_t* __restrict__ Xl, float2* __restrict__ Ywh,
+    uint32_t* __restrict__ Ywl, int N, int B, int K, const double2* __restrict__ twM,
+    double scale, const int* __restrict__ rowtab, int sumW, WindowGeom g, float* __restrict__ prof,
+    int L, int k0) {
+  constexpr int M = 8192;
+  extern __shared__ double2 lds_x[];
+  double2* lds = lds_x;
+  int* s_dyn = reinterpret_cast<int*>(lds_x + Fft4k::n);
+  int* s_start = s_dyn;
+  int* s_center = s_dyn + g.T;
+  float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);
+  int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);
+  const int k = k0 + blockIdx.y;
+  const int j = threadIdx.x;
+  const double2 w1 = twM[(j & 15) * 32];
+  const double2 w2 = twM[(j & 255) * 2];
+  const double2 w0 = twM[j], w256 = twM[256];
+  auto fetch = [&](int b, float2 (&vh)[16], uint32_t (&vl)[16]) {
+    const int64_t base = ((int64_t)k * B + b) * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = j + 256 * r;
+      vh[r] = make_float2(0.f, 0.f);
+      vl[r] = 0u;
+      if (e < N) {
+        vh[r] = Xh[base + e];
+        vl[r] = Xl[base + e];
+      }
+    }
+  };
+  float2 rh[16];
+  uint32_t rl[16];
+  if ((int)blockIdx.x < B) fetch(blockIdx.x, rh, rl);
+  if (Ywh || prof) {
+    for (int t = threadIdx.x; t < g.T; t += Fft4k::threads) {
+      double u;
+      int s;
+      window_of(g, t, k, &u, &s);
+      s_start[t] = s;
+      if (prof) s_center[t] = (int)floor(u + 0.5);
+    }
+    if (prof)
+      for (int i = threadIdx.x; i < g.T * 64; i += Fft4k::threads) s_acc[i] = 0.f;
+    if (Ywh) {
+      __syncthreads();
+      for (int r = threadIdx.x; r < sumW; r += Fft4k::threads) {
+        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+        s_bin[r] = (s_start[t] + i) & (M - 1);
+      }
+    }
+  }
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    const int64_t o0 = ((int64_t)k * B + b) * sumW;
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {
+      double2 v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = ext_join(rh[r], rl[r]);
+      if (par) {
+        // X[e] w_M^e for the odd bins, e = j + 256 r: w_M^j times the powers of w_M^256
+        double2 t = w0, ws = w256;
+        asm volatile("" : "+v"(t.x), "+v"(t.y), "+v"(ws.x), "+v"(ws.y));
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          v[r] = cmul(v[r], t);
+          if (r < 15) t = cmul(t, ws);
+        }
+      }
+      if (par && b + (int)gridDim.x < B) fetch(b + gridDim.x, rh, rl);
+      Fft4k::run(v, lds, w1, w2);
+      if (Ywh) {
+        for (int r = threadIdx.x; r < sumW; r += Fft4k::threads) {
+          const int m = s_bin[r];
+          if ((m & 1) == par) {
+            float2 hi;
+            uint32_t lo;
+            ext_split(cscale(lds[Fft4k::pos(m >> 1)], scale), hi, lo);
+            Ywh[o0 + r] = hi;
+            Ywl[o0 + r] = lo;
+          }
+        }
+      }
+      if (prof && b < L) {
+        for (int idx = threadIdx.x; idx < g.T * 64; idx += Fft4k::threads) {
+          const int t = idx >> 6, jj = idx & 63;
+          const int m = (s_center[t] - 32 + jj) & (M - 1);
+          if ((m & 1) == par) {
+            const double2 y = cscale(lds[Fft4k::pos(m >> 1)], scale);
+            s_acc[idx] += (float)(y.x * y.x + y.y * y.y);
+          }
+        }
+      }
+      __syncthreads();   // the next transform overwrites lds
+    }
+  }
+  if (prof) {
+    float* dst = prof + ((int64_t)k * gridDim.x + blockIdx.x) * g.T * 64;
+    for (int idx = threadIdx.x; idx < g.T * 64; idx += Fft4k::threads) dst[idx] = s_acc[idx];
+  }
+}
+
 // Subband synthesis, the inverse of the channelizer per block: Z [T][K][Lt] (beam outputs of
 // every subband on the test blocks) -> z [T][Lt*K], z[t][b K + tau] = K^-1/2 conj(h[tau])
 // sum_k Z[t][k][b] exp(+j 2 pi tau k / K), computed as the conjugate of the forward transform
@@ -896,6 +1083,34 @@ static hipError_t beam_launch_x2(const float2* Xh, const uint32_t* Xl, float2* Y
   return hipGetLastError();
 }
 
+static hipError_t beam_launch_x16(const float2* Xh, const uint32_t* Xl, float2* Ywh,
+                                  uint32_t* Ywl, int N, int B, int K, const double2* twM,
+                                  const int* rowtab, int sumW, const WindowGeom& g, float* prof,
+                                  int L, int G, int k0, int kc, hipStream_t s) {
+  if (N > 4096) return hipErrorInvalidValue;
+  if (prof && (G < 1 || G > B)) return hipErrorInvalidValue;
+  size_t shm = sizeof(double2) * (size_t)Fft4k::n;
+  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
+  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
+  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (shm > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x16,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  int gx = G;
+  if (!prof) {
+    static int resident = 0;
+    const int cap = resident_blocks(k_beamspace_x16, Fft4k::threads, shm, &resident);
+    gx = (cap + kc - 1) / kc;
+    if (gx > B) gx = B;
+    if (gx < 1) gx = 1;
+  }
+  hipLaunchKernelGGL(k_beamspace_x16, dim3(gx, kc), dim3(Fft4k::threads), shm, s, Xh, Xl, Ywh,
+                     Ywl, N, B, K, twM, 1.0 / sqrt(8192.0), rowtab, sumW, g, prof, L, k0);
+  return hipGetLastError();
+}
+
 template <int LOGM, int LOGT>
 static hipError_t beam_launch_x(const float2* Xh, const uint32_t* Xl, float2* Ywh, uint32_t* Ywl,
                                 int N, int B, int K, const double2* twM, const int* rowtab,
@@ -903,9 +1118,15 @@ static hipError_t beam_launch_x(const float2* Xh, const uint32_t* Xl, float2* Yw
                                 int kc, hipStream_t s) {
   if constexpr (LOGM >= 13) {
     // a full FP64 row no longer fits a 64 KiB tile: split halves whenever the upper half is zero
-    if (2 * N <= (1 << LOGM))
+    if (2 * N <= (1 << LOGM)) {
+      if constexpr (LOGM == 13) {
+        if (LOGT == 13)   // the radix-16 engine (tile 2^13: both halves of one snapshot)
+          return beam_launch_x16(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g, prof, L, G, k0,
+                                 kc, s);
+      }
       return beam_launch_x2<LOGM - 1>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g, prof, L,
                                       G, k0, kc, s);
+    }
   }
   if (2 * N <= (1 << LOGM))
     return beam_launch_x_zh<LOGM, LOGT, true>(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g,

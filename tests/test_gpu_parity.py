@@ -368,6 +368,31 @@ def test_edge_shapes(torch, wb, case):
     plan.close()
 
 
+@pytest.mark.parametrize("beam_tile", [12, 13])
+def test_extended_precision_spatial_dft_at_8192_bins(torch, wb, beam_tile):
+    """M = 8192 with N <= 4096: the extended-precision spatial DFT splits every row into its
+    even- and odd-bin 4096-point halves (tile 2^13: the radix-16 engine, 256 threads; below:
+    the radix-8 engine, 512 threads); windows of 64, 5 and 33 bins, one next to the wrap, the
+    others at the band centre and edge; N not a multiple of the thread count."""
+    cfg = scenes.SceneConfig(name="m8192", N=300, M=8192, K=4, L=50, Lt=10, T=3, W=None,
+                             W_choices=(1,), n_jammers=1, target_az_deg=(-89.0, 0.0, 55.0),
+                             target_snr_db=(5.0, 0.0, 10.0), jammer_az_deg=(20.0,),
+                             jammer_inr_db=(40.0,), seed=31)
+    sc = scenes.make_scene(cfg)
+    sc.win = np.asarray((64, 5, 33), dtype=np.int32)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    plan.set_tuning(11, beam_tile, "block", 1, precision="ext")
+    x = torch.from_numpy(x32).cuda()
+    for form in ("fused", "graph"):
+        res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        st = compare_beamform(sc, ref, res, ext=True)
+        log(f"  tile {beam_tile} {form}: {st}")
+    plan.close()
+
+
 def test_identity_windowed_equals_full_dimensional(torch, wb):
     # W = M = N: the windowed beamspace MVDR equals element-space MVDR (Eq. 13 vs Eq. 20-21)
     cfg = scenes.SMALL.replace(M=16, W=16)
