@@ -58,8 +58,13 @@ def dispatch_name(stage: str, cfg, tuning, wmax: int, ext: bool) -> str:
     if stage == "channelize":
         return f"k_channelize{'_x' if ext else ''}<{lk}, {max(tuning[0], lk)}>"
     if stage == "beamspace":
-        zh = "true" if 2 * cfg.N <= cfg.M else "false"
-        return f"k_beamspace{'_x' if ext else ''}<{lm}, {max(tuning[1], lm)}, {zh}>"
+        zh = 2 * cfg.N <= cfg.M
+        if ext and zh and lm >= 13:
+            # split-half forms: the radix-16 engine at tile 2^13 and M = 8192, else radix 8
+            return ("k_beamspace_x16" if lm == 13 and tuning[1] == 13
+                    else f"k_beamspace_x2<{lm - 1}>")
+        return f"k_beamspace{'_x' if ext else ''}<{lm}, {max(tuning[1], lm)}, " \
+               f"{'true' if zh else 'false'}>"
     pair = tuning[2]
     if pair == "resident":
         return "k_mvdr_res"

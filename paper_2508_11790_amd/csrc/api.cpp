@@ -386,6 +386,7 @@ wbm::PairArgs pair_args(const wbm_plan* p, int prec, int T, int sumW, double loa
   a.sumW = sumW;
   a.delta = loading;
   a.ywl = prec == kExt ? p->Ywl : nullptr;
+  a.split_rows = (prec == kExt && wbm::beamspace_x_split_rows(p->cfg.n_elem, p->cfg.m_fft)) ? 1 : 0;
   return a;
 }
 

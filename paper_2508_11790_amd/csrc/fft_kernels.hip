@@ -426,7 +426,8 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace_x(
 // iteration, 512 threads at H = 4096): the even bins' window rows are written after the first,
 // the odd bins' after the second.  The full M-point row would need a 128 KiB tile and 1024
 // threads, one workgroup per compute unit.  Outputs as k_beamspace_x with one snapshot per tile
-// (TB = 1).
+// (TB = 1), except that each window's rows are stored in split order: its even-bin rows first,
+// then the odd ones (each half then writes whole runs of rows).
 template <int LOGH>
 __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
     const float2* __restrict__ Xh, const uint32_t* __restrict__ Xl, float2* __restrict__ Ywh,
@@ -482,9 +483,11 @@ __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
       for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
     if (Ywh) {
       __syncthreads();
+      // window rows in split order: each window's even-bin rows first, then the odd ones
       for (int r = threadIdx.x; r < sumW; r += F::threads) {
         const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-        s_bin[r] = (s_start[t] + i) & (M - 1);
+        const int st = s_start[t], ne = (g.win[t] + ((st & 1) ? 0 : 1)) >> 1;
+        s_bin[r - i + ((((st + i) & 1) ? ne : 0) + (i >> 1))] = (st + i) & (M - 1);
       }
     }
   }
@@ -622,7 +625,8 @@ struct Fft4k {
 // k_beamspace_x2 (even bins from the 4096-point transform of X, odd bins from that of
 // X[e] w_M^e) on the Fft4k engine.  256 threads: two 64 KiB workgroups per compute unit.  The
 // next snapshot's inputs are fetched into the registers of the current one as soon as the odd
-// half's inputs have been formed.  Outputs as k_beamspace_x with one snapshot per tile.
+// half's inputs have been formed.  Outputs as k_beamspace_x2 (one snapshot per tile, window
+// rows in split order).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_beamspace_x16(
     const float2* __restrict__ Xh, const uint32_t* __restrict__ Xl, float2* __restrict__ Ywh,
     uint32_t* __restrict__ Ywl, int N, int B, int K, const double2* __restrict__ twM,
@@ -669,9 +673,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int i = threadIdx.x; i < g.T * 64; i += Fft4k::threads) s_acc[i] = 0.f;
     if (Ywh) {
       __syncthreads();
+      // window rows in split order: each window's even-bin rows first, then the odd ones, so
+      // that each half writes whole runs of rows
       for (int r = threadIdx.x; r < sumW; r += Fft4k::threads) {
         const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-        s_bin[r] = (s_start[t] + i) & (M - 1);
+        const int st = s_start[t], ne = (g.win[t] + ((st & 1) ? 0 : 1)) >> 1;
+        s_bin[r - i + ((((st + i) & 1) ? ne : 0) + (i >> 1))] = (st + i) & (M - 1);
       }
     }
   }
@@ -1118,7 +1125,7 @@ static hipError_t beam_launch_x(const float2* Xh, const uint32_t* Xl, float2* Yw
                                 int kc, hipStream_t s) {
   if constexpr (LOGM >= 13) {
     // a full FP64 row no longer fits a 64 KiB tile: split halves whenever the upper half is zero
-    if (2 * N <= (1 << LOGM)) {
+    if (beamspace_x_split_rows(N, 1 << LOGM)) {
       if constexpr (LOGM == 13) {
         if (LOGT == 13)   // the radix-16 engine (tile 2^13: both halves of one snapshot)
           return beam_launch_x16(Xh, Xl, Ywh, Ywl, N, B, K, twM, rowtab, sumW, g, prof, L, G, k0,
@@ -1327,6 +1334,8 @@ hipError_t launch_channelize(const float2* x, float2* X, int N, int K, int B, co
 }
 
 bool fft_x_logtile_supported(int logtile) { return logtile >= 10 && logtile <= 13; }
+
+bool beamspace_x_split_rows(int N, int M) { return M >= 8192 && 2 * N <= M; }
 
 hipError_t launch_channelize_x(const float2* x, float2* Xh, uint32_t* Xl, int N, int K, int B,
                                const double2* twK, const double2* hb, int logtile,

@@ -485,12 +485,28 @@ __device__ __forceinline__ void chunk_elem(const PairArgs& a, int W, int e, int&
   }
 }
 
+// Storage order of a pair's window rows in the window layout, relative to the first row of the
+// window its target gathered: natural (row i at i), or, after the split-half spatial DFT
+// (a.split_rows), the rows whose bin is even first in ascending order, then the odd ones --
+// slot(i) = ((s + i) odd ? ne : 0) + i / 2 for row i of the gathered window (start s, ne
+// even-bin rows).  so: offset of the pair's (sub-)window inside the gathered one.
+struct RowOrder {
+  int split = 0, so = 0, s = 0, ne = 0;
+};
+__device__ __forceinline__ int row_slot(const RowOrder& ro, int i) {
+  if (!ro.split) return i;
+  const int ii = i + ro.so;
+  return (((ro.s + ii) & 1) ? ro.ne : 0) + (ii >> 1);
+}
+
 // This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end, and
 // their offsets from the chunk's first element in the window layout (valid when chunks start
 // at multiples of CH: then a chunk never splits a tile block differently).  The mapping is the
-// same for every chunk.
+// same for every chunk.  Offsets count from the first row of the gathered window when rows
+// are in split order (ro.split), else from the pair's own first row.
 template <int PRE, int TH, int CH>
-__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off) {
+__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off,
+                                          const RowOrder& ro = RowOrder()) {
   const int TB = 1 << a.logTB;
 #pragma unroll
   for (int m = 0; m < PRE; ++m) {
@@ -501,7 +517,7 @@ __device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, in
       int i, bb;
       chunk_elem<CH>(a, W, e, i, bb);
       map[m] = (i << 8) | bb;
-      off[m] = ((bb >> a.logTB) * a.sumW + i) * TB + (bb & (TB - 1));
+      off[m] = ((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1));
     }
   }
 }
@@ -513,7 +529,8 @@ template <int PRE, bool EXT = false>
 __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const PairArgs& a,
                                             int k, int woff, const int* map, const int* off,
                                             bool aligned, int c0, int lim, float2* pre,
-                                            uint32_t* prel = nullptr) {
+                                            uint32_t* prel = nullptr,
+                                            const RowOrder& ro = RowOrder()) {
   const int TB = 1 << a.logTB;
   const int64_t ebase = (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
   const float2* base = Yw + ebase;
@@ -545,7 +562,8 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const
       const int i = mm >> 8, b = c0 + (mm & 255);
       if constexpr (EXT) prel[m] = 0u;
       if (mm >= 0 && b < lim) {
-        const int64_t o = ((int64_t)(b >> a.logTB) * a.sumW + i) * TB + (b & (TB - 1));
+        const int64_t o =
+            ((int64_t)(b >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (b & (TB - 1));
         pre[m] = base[o];
         if constexpr (EXT) prel[m] = a.ywl[ebase + o];
       }
@@ -593,6 +611,7 @@ __device__ __forceinline__ double2 staged_c64(const double2* zf, int o) { return
 struct GramArgs {
   int W, woff, k, ntiles, TG, tg, kq, lane;
   bool aligned;
+  RowOrder ro;
 };
 
 // Matrix-core Gram (TH = 256, CH = 64) into the tile-packed P[tile][16][16] (FP64): NT tiles
@@ -692,10 +711,11 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel);
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
+                            ga.ro);
     else if (a.Lt > 0)
       fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
-                            prel);
+                            prel, ga.ro);
     if (act) {
       for (int bb = sg; bb < CH; bb += S) {
         double rx[BS], ry[BS], cx[BS], cy[BS];
@@ -928,7 +948,8 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
                                              const int* off, bool aligned, float2* pre, float* z,
                                              void* zfv, const C2<double>* wv, double2* red,
                                              int fail, float2* __restrict__ o,
-                                             uint32_t* prel = nullptr) {
+                                             uint32_t* prel = nullptr,
+                                             const RowOrder& ro = RowOrder()) {
   constexpr int NG = TH / CH, RSF = CH + 1;
   using SV = typename std::conditional<EXT, double2, float2>::type;
   SV* zf = static_cast<SV*>(zfv);
@@ -944,7 +965,7 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
     __syncthreads();
     if (c + 1 < nch)
       fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
-                            pre, prel);
+                            pre, prel, ro);
     double zx = 0.0, zy = 0.0;
     if (!fail) {
       for (int i = rg; i < W; i += NG) {
@@ -1002,23 +1023,33 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const PairSetup ps = pair_setup(a, g, d);
-  const int k = ps.k, W = ps.W, woff = ps.woff;
+  const int k = ps.k, W = ps.W;
   const int64_t pair = ps.pair;
   const double delta = ps.delta;
   if (a.route && !a.route[pair]) return;   // solved by the mixed-precision launch
 
+  // rows in split order: address from the gathered window's first row (see row_slot)
+  RowOrder ro;
+  int woff = ps.woff;
+  if (a.split_rows) {
+    ro.split = 1;
+    ro.so = ps.woff - d.woff[ps.t];
+    ro.s = ps.s - ro.so;
+    ro.ne = (d.win[ps.t] + ((ro.s & 1) ? 0 : 1)) >> 1;
+    woff = ps.woff - ro.so;
+  }
   int map[PRE], off[PRE];
-  chunk_map<PRE, TH, CH>(a, W, map, off);
+  chunk_map<PRE, TH, CH>(a, W, map, off, ro);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   uint32_t prel[EXT ? PRE : 1];
-  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre, prel);
+  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre, prel, ro);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
 
   if constexpr (!MF) {
-    GramArgs ga{W, woff, k, 0, 0, 0, 0, lane, aligned};
+    GramArgs ga{W, woff, k, 0, 0, 0, 0, lane, aligned, ro};
     if constexpr (TH >= 256) {
       // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
       if (WCAP <= 44 || W <= 44)
@@ -1101,7 +1132,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if (!fail) ldl_solve(R, lay.RS, W, av, wv);
   }
   apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red,
-                                     fail, out + pair * a.Lt, prel);
+                                     fail, out + pair * a.Lt, prel, ro);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
       float2 v = make_float2(0.f, 0.f);

@@ -88,7 +88,13 @@ struct PairArgs {
   // extended-precision windows: the BF16 remainder plane of the windows (same layout as the
   // FP32 plane passed as Yw); nullptr = FP32 windows.  Vector pair kernels only.
   const uint32_t* ywl = nullptr;
+  // window rows stored in the split-half spatial DFT's order (even-bin rows of each gathered
+  // window first, then the odd ones; beamspace_x_split_rows)
+  int split_rows = 0;
 };
+// Whether the extended-precision spatial DFT at this N, M runs its split-half form, which
+// stores every window's rows in split order (even bins first).
+bool beamspace_x_split_rows(int N, int M);
 // Fused per-pair window/steering -> covariance (FP64 accumulation) -> LDL^H (FP64) -> solve
 // -> apply, reading the window rows written by the beamspace kernel.
 // threads = kPairMfma (four waves, FP64 matrix-core covariance), kPairResident (below), 64 (one

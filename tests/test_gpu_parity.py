@@ -390,6 +390,17 @@ def test_extended_precision_spatial_dft_at_8192_bins(torch, wb, beam_tile):
         torch.cuda.synchronize()
         st = compare_beamform(sc, ref, res, ext=True)
         log(f"  tile {beam_tile} {form}: {st}")
+    # per-pair sub-windows of the gathered ones (the learned form's path): rows 16..47 of the
+    # 64-bin window, 1..3 of the 5-bin one, 8..24 of the 33-bin one -- the oracle at those widths
+    sub = np.asarray((32, 3, 17), dtype=np.int32)
+    pw = torch.from_numpy(np.repeat(sub[:, None], cfg.K, axis=1)).cuda()
+    pd = torch.full((cfg.T, cfg.K), cfg.delta, dtype=torch.float32, device="cuda")
+    res = plan.beamform_pairs(x, sc.target_az, sc.win, pw, pd)
+    torch.cuda.synchronize()
+    sc_sub = scenes.make_scene(cfg)
+    sc_sub.win = sub
+    st = compare_beamform(sc_sub, _oracle(sc_sub, x32), res, ext=True)
+    log(f"  tile {beam_tile} sub-windows: {st}")
     plan.close()
 
 
