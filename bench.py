@@ -482,6 +482,34 @@ def main():
                     stage_gbs_f32={n: round(bytes_f32[n] / (st32[n] * 1e-3) / 1e9, 1)
                                    for n in bytes_f32})
 
+    # the covariance engines: BF16 MFMA utilisation of the mixed forms' pair stage (MFMA kernel
+    # plus the FP64 re-solve of routed windows) against the 2.5 PFLOP/s dense BF16 peak, and
+    # the exact path's FP64 vector Gram beside the FP64 matrix-core Gram on the same windows
+    cov_flops = 8.0 * float(np.sum(np.asarray(win, dtype=np.float64) ** 2)) * cfg.L * K
+    covariance = {"algorithmic_tflop_per_step": cov_flops / 1e12,
+                  "flops_per_pair": "8 W^2 L (real Gram of [Re y; Im y], 2W x L)"}
+    if not args.no_mixed:
+        for form, prods in (("mixed", 3), ("mixed_bf16", 1)):
+            stm = plan.stage_times(x, az, win, delta, reps=max(5, args.steps // 4),
+                                   precision=form)
+            ms = stm["mvdr"]
+            covariance[form] = {
+                "pair_stage_ms": round(ms, 4), "mfma": "v_mfma_f32_32x32x16_bf16",
+                "bf16_products_per_entry": prods, "peak_tflops": 2500.0,
+                "achieved_tflops_algorithmic": round(cov_flops / (ms * 1e-3) / 1e12, 2),
+                "frac_algorithmic": round(cov_flops / (ms * 1e-3) / 2.5e15, 5),
+                "frac_executed": round(prods * cov_flops / (ms * 1e-3) / 2.5e15, 5),
+                "routed_pairs": mixed.get(form, {}).get("routed_pairs")}
+    tun32 = plan.get_tuning("f32")
+    for pair in ("block", "mfma"):
+        plan.set_tuning(tun32[0], tun32[1], pair, 1, precision="f32")
+        ms = plan.stage_times(x, az, win, delta, reps=max(5, args.steps // 4),
+                              precision="f32")["mvdr"]
+        covariance["fp64_" + ("vector" if pair == "block" else "mfma") + "_pair_kernel"] = {
+            "ms": round(ms, 4), "achieved_tflops": round(cov_flops / (ms * 1e-3) / 1e12, 2),
+            "peak_tflops": 78.6, "frac": round(cov_flops / (ms * 1e-3) / 78.6e12, 4)}
+    plan.set_tuning(*tun32, precision="f32")
+
     learned_res = None
     if args.predictor and os.path.exists(args.predictor):
         from paper_2508_11790_amd import learned as wlearned
@@ -585,6 +613,7 @@ def main():
         **beside,
         "upa": upa_res,
         "roofline": roofline,
+        "covariance": covariance,
     }
     plan.close()
     del out, wts, info

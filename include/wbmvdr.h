@@ -128,6 +128,8 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
                               wbm_profiles: extended-precision transforms and windows */
 #define WBM_PREC_F32 1     /* WBM_FORM_FUSED_F32 / GRAPH_F32, the mixed forms' transforms and the
                               planar-array path */
+#define WBM_PREC_MIXED 2      /* wbm_stage_times only: the WBM_FORM_MIXED sequence */
+#define WBM_PREC_MIXED_BF16 3 /* wbm_stage_times only: the WBM_FORM_MIXED_BF16 sequence */
 
 /* Launch configuration of the fused form in one precision.  Without a call to
  * wbm_plan_set_tuning the first call of that precision times the candidates on the caller's
@@ -335,11 +337,13 @@ wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                          wbm_c32* weights, int32_t* info, void* stream);
 
 /* Per-stage timing of the fused sequence (same arguments as wbm_beamform with
- * form = WBM_FORM_FUSED for precision WBM_PREC_EXT, WBM_FORM_FUSED_F32 for WBM_PREC_F32;
- * outputs go to plan-internal scratch): launches each kernel of it (steer, channelize,
- * windowed beamspace, fused MVDR, in that order) once untimed and then `reps` times back to
- * back on `stream` between two HIP events, and writes the average milliseconds per launch to
- * stage_ms (host [4]).  Blocks until the stream has drained. */
+ * form = WBM_FORM_FUSED for precision WBM_PREC_EXT, WBM_FORM_FUSED_F32 for WBM_PREC_F32,
+ * WBM_FORM_MIXED / MIXED_BF16 for WBM_PREC_MIXED / MIXED_BF16; outputs go to plan-internal
+ * scratch): launches each stage of it (steer, channelize, windowed beamspace, pair kernel --
+ * for the mixed forms the MFMA pair kernel and the FP64 re-solve of the routed windows) once
+ * untimed and then `reps` times back to back on `stream` between two HIP events, and writes the
+ * average milliseconds per launch to stage_ms (host [4]).  Blocks until the stream has
+ * drained. */
 wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                            const int32_t* win, int32_t T, double loading, int32_t precision,
                            int32_t reps, double* stage_ms, void* stream);

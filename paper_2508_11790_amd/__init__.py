@@ -27,7 +27,8 @@ _FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH,
           "fused_f32": _lib.FORM_FUSED_F32, "graph_f32": _lib.FORM_GRAPH_F32}
 # precision of the fused sequence a launch configuration applies to: "ext" (fused / graph /
 # learned forms) or "f32" (fused_f32 / graph_f32, the mixed forms' transforms, planar array)
-_PRECS = {"ext": _lib.PREC_EXT, "f32": _lib.PREC_F32}
+_PRECS = {"ext": _lib.PREC_EXT, "f32": _lib.PREC_F32, "mixed": _lib.PREC_MIXED,
+          "mixed_bf16": _lib.PREC_MIXED_BF16}
 INFO_ROUTED = _lib.INFO_ROUTED
 
 
@@ -383,7 +384,8 @@ class Plan:
     def stage_times(self, x, az_rad, win, loading: float, reps: int = 20, stream=None,
                     precision: str = "ext"):
         """Average milliseconds per kernel of the fused sequence in one precision ("ext": the
-        fused form, "f32": fused_f32), timed with HIP events."""
+        fused form, "f32": fused_f32, "mixed" / "mixed_bf16": the mixed forms, whose pair stage
+        is the MFMA kernel plus the FP64 re-solve of routed windows), timed with HIP events."""
         self._x(x)
         az, w, T = self._targets(az_rad, win)
         ms = np.zeros(4, dtype=np.float64)

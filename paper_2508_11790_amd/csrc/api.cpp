@@ -1377,11 +1377,15 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
   if (!(loading >= 0.0 && std::isfinite(loading))) return fail(WBM_ERR_ARG, "loading must be finite and >= 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
   int sumW = 0;
-  if (precision != WBM_PREC_EXT && precision != WBM_PREC_F32)
-    return fail(WBM_ERR_ARG, "precision must be WBM_PREC_EXT or WBM_PREC_F32");
+  if (precision < WBM_PREC_EXT || precision > WBM_PREC_MIXED_BF16)
+    return fail(WBM_ERR_ARG, "precision must be WBM_PREC_EXT, _F32, _MIXED or _MIXED_BF16");
   const int prec = precision == WBM_PREC_EXT ? kExt : kF32;
+  const bool mixed = precision == WBM_PREC_MIXED || precision == WBM_PREC_MIXED_BF16;
   if ((s = upload_desc(p, az_rad, win, T, st, &sumW))) return s;
   if ((s = ensure_prof(p))) return s;
+  if (mixed && !p->route &&
+      (s = dev_alloc(p, &p->route, (size_t)c.max_targets * c.k_sub, "route flags")))
+    return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
   if ((s = ready_fused(p, prec, xx, T, sumW, loading, st))) return s;
   hipEvent_t ev[2];
@@ -1395,6 +1399,10 @@ wbm_status wbm_stage_times(wbm_plan* p, const wbm_c32* x, const double* az_rad,
       case 1: return enqueue_channelize(p, prec, xx, st);
       case 2: return enqueue_beamspace_windows(p, prec, T, sumW, st);
       default:
+        if (mixed)
+          return wbm::launch_mvdr_mixed(pair_args(p, kF32, T, sumW, loading), geom(p, T), p->dd,
+                                        p->Yw, p->prof_out, p->prof_w, nullptr, p->prof_info,
+                                        p->route, precision == WBM_PREC_MIXED, st);
         return wbm::launch_mvdr_fused(pair_args(p, prec, T, sumW, loading), geom(p, T), p->dd,
                                       p->Yw, p->prof_out, p->prof_w, nullptr, p->prof_info,
                                       p->tune[prec].pair_threads, st);
