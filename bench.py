@@ -39,16 +39,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_sources_sha256() -> str:
+def kernel_source_hashes() -> dict:
+    """SHA-256 of each kernel source file and header of the library."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2508_11790_amd", "csrc")
-    h = hashlib.sha256()
+    out = {}
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(f.encode())
+        if f.endswith((".hip", ".h")):
             with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()
+                out[f] = hashlib.sha256(fh.read()).hexdigest()
+    return out
+
+
+def kernel_source_file(name: str) -> str:
+    """The source file that defines a kernel of the fused sequence."""
+    return "mvdr_kernels.hip" if name.startswith("k_mvdr") else "fft_kernels.hip"
 
 
 def dispatch_name(stage: str, cfg, tuning, wmax: int, ext: bool) -> str:
@@ -77,17 +82,21 @@ def dispatch_name(stage: str, cfg, tuning, wmax: int, ext: bool) -> str:
 
 def counter_traffic(workload: str, name: str):
     """HBM bytes per launch of the named kernel from the committed FETCH_SIZE / WRITE_SIZE
-    record of this workload, or None when there is none, the kernel is not in it or the
-    kernel sources changed since it was taken."""
+    record of this workload, or None when there is none, the kernel is not in it, or the
+    kernel's source file or any header changed since the counters were taken."""
     path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("kernel_sources_sha256") != kernel_sources_sha256():
-        return None
     k = rec.get("dispatches", {}).get(name)
-    return None if k is None else k["hbm_bytes"]
+    if k is None:
+        return None
+    now, then = kernel_source_hashes(), rec.get("sources", {})
+    deps = [f for f in now if f.endswith(".h")] + [kernel_source_file(name)]
+    if any(then.get(f) != now[f] for f in deps):
+        return None
+    return k["hbm_bytes"]
 
 
 def timed_steps(torch, fn, steps, warmup):
