@@ -410,6 +410,19 @@ wbm_status wbm_mlp_forward(wbm_mlp* mlp, const float* params, const float* in, i
  * samples and both outputs against target device [n][2]; deterministic reduction order. */
 wbm_status wbm_mlp_grad(wbm_mlp* mlp, const float* params, const float* in, const float* target,
                         int32_t n, float* grad, float* loss, void* stream);
+/* wbm_mlp_grad without a network workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * gradient and loss partials live in a static device array of the library (about 25.7 MB
+ * per device, held until the process ends) instead of a wbm_mlp.  No allocation happens in
+ * the call; the first call on a device looks up the array's address there (not a stream
+ * operation; make that first call before capturing).  Same kernels and reduction order as
+ * wbm_mlp_grad, so the same results bit for bit.  loss may be NULL.  Calls that overlap on
+ * one device (other streams, other threads) share the array and race: serialise them.
+ * Errors: WBM_ERR_ARG for NULL params / in / target / grad, WBM_ERR_SHAPE for n outside
+ * [1, WBM_MLP_STATIC_MAX_BATCH]; nothing is enqueued then. */
+#define WBM_MLP_STATIC_MAX_BATCH 4096
+wbm_status wbm_mlp_grad_static(const float* params, const float* in, const float* target,
+                               int32_t n, float* grad, float* loss, void* stream);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on params with moment
  * arrays m, v (device [WBM_MLP_PARAMS]). */
 wbm_status wbm_mlp_adam(wbm_mlp* mlp, float* params, float* m, float* v, const float* grad,

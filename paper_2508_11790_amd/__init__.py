@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import FORM_FUSED, FORM_GRAPH, FORM_PLAIN, WbmError  # noqa: F401
 
 __all__ = ["Plan", "Mlp", "WbmError", "FORM_PLAIN", "FORM_FUSED", "FORM_GRAPH", "version",
-           "MLP_PARAMS"]
+           "MLP_PARAMS", "MLP_STATIC_MAX_BATCH", "mlp_grad_static"]
 
 MLP_PARAMS = _lib.MLP_PARAMS
 
@@ -545,3 +545,25 @@ class Mlp:
                                                 w.ctypes.data, w.size, float(noise_power),
                                                 _ptr(label), _stream(stream)))
         return label
+
+
+MLP_STATIC_MAX_BATCH = _lib.MLP_STATIC_MAX_BATCH
+
+
+def mlp_grad_static(params, inp, target, grad, loss=None, stream=None):
+    """Gradient and loss of the predictor network as Mlp.grad, through the library's static
+    device scratch instead of an Mlp workspace: nothing is allocated, so the caller passes the
+    outputs (grad [MLP_PARAMS] float32, loss [1] float32 or None).  n <= MLP_STATIC_MAX_BATCH;
+    calls that overlap on one GPU share the scratch and must be serialised."""
+    torch = _torch()
+    n = int(inp.shape[0])
+    dev = params.device
+    _check_tensor(params, "params", (MLP_PARAMS,), torch.float32, dev)
+    _check_tensor(inp, "in", (n, 64), torch.float32, dev)
+    _check_tensor(target, "target", (n, 2), torch.float32, dev)
+    _check_tensor(grad, "grad", (MLP_PARAMS,), torch.float32, dev)
+    if loss is not None:
+        _check_tensor(loss, "loss", (1,), torch.float32, dev)
+    _lib.check(_lib.load().wbm_mlp_grad_static(_ptr(params), _ptr(inp), _ptr(target), n,
+                                               _ptr(grad), _ptr(loss), _stream(stream)))
+    return grad, loss

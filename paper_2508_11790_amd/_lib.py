@@ -39,10 +39,11 @@ EXPORTS = ("wbm_plan_create", "wbm_plan_destroy", "wbm_plan_workspace_bytes",
            "wbm_channelize", "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times",
            "wbm_profiles", "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr",
            "wbm_mlp_create", "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
-           "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
+           "wbm_mlp_grad_static", "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
            "wbm_beam_pattern", "wbm_range_doppler", "wbm_beamform_upa", "wbm_beamspace_upa",
            "wbm_steer_upa", "wbm_lift_upa", "wbm_beam_pattern_upa", "wbm_status_str", "wbm_last_error", "wbm_version")
 MLP_PARAMS = 25090
+MLP_STATIC_MAX_BATCH = 4096
 PROFILE_BINS = 64
 
 _lib = None
@@ -78,6 +79,7 @@ def load() -> C.CDLL:
     lib.wbm_mlp_forward.argtypes = [P, P, P, I32, P, P]
     lib.wbm_mlp_grad.argtypes = [P, P, P, P, I32, P, P, P]
     lib.wbm_mlp_adam.argtypes = [P, P, P, P, P, I32, D, P]
+    lib.wbm_mlp_grad_static.argtypes = [P, P, P, I32, P, P, P]
     lib.wbm_sweep_labels.argtypes = [P, P, I32, P, I32, P, I32, D, P, P]
     lib.wbm_lift.argtypes = [P, P, P, I32, P, P]
     lib.wbm_apply_lifted.argtypes = [P, P, P, I32, P, P]
@@ -99,7 +101,7 @@ def load() -> C.CDLL:
                  "wbm_beamspace", "wbm_steer", "wbm_full_mvdr", "wbm_stage_times", "wbm_profiles",
                  "wbm_beamform_pairs", "wbm_beamform_learned", "wbm_sinr", "wbm_mlp_create",
                  "wbm_mlp_destroy", "wbm_mlp_forward", "wbm_mlp_grad", "wbm_mlp_adam",
-                 "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
+                 "wbm_mlp_grad_static", "wbm_sweep_labels", "wbm_lift", "wbm_apply_lifted", "wbm_synthesize",
                  "wbm_beam_pattern", "wbm_range_doppler", "wbm_beamform_upa",
                  "wbm_beamspace_upa", "wbm_steer_upa", "wbm_lift_upa",
                  "wbm_beam_pattern_upa"):

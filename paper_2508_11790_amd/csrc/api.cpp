@@ -1723,6 +1723,21 @@ wbm_status wbm_mlp_grad(wbm_mlp* m, const float* params, const float* in, const 
   return WBM_OK;
 }
 
+wbm_status wbm_mlp_grad_static(const float* params, const float* in, const float* target,
+                               int32_t n, float* grad, float* loss, void* stream) {
+  if (!params || !in || !target || !grad) return fail(WBM_ERR_ARG, "NULL argument");
+  if (n < 1 || n > WBM_MLP_STATIC_MAX_BATCH)
+    return fail(WBM_ERR_SHAPE, "n outside [1, WBM_MLP_STATIC_MAX_BATCH = " +
+                                   std::to_string(WBM_MLP_STATIC_MAX_BATCH) + "]");
+  float* part = nullptr;
+  float* loss_part = nullptr;
+  WBM_HIP(wbm::mlp_static_scratch(&part, &loss_part), "static scratch address");
+  WBM_HIP(wbm::launch_mlp_backward(params, in, target, n, part, loss_part, grad, loss,
+                                   static_cast<hipStream_t>(stream)),
+          "backward");
+  return WBM_OK;
+}
+
 wbm_status wbm_mlp_adam(wbm_mlp* m, float* params, float* mom, float* var, const float* grad,
                         int32_t step, double lr, void* stream) {
   wbm_status s = check_mlp(m);

@@ -8,8 +8,11 @@
 // interference-plus-noise covariance of the synthetic scene.
 #include <math.h>
 
+#include <mutex>
+
 #include "wbm_dev.h"
 #include "wbm_learned.h"
+#include "wbmvdr.h"
 
 namespace wbm {
 
@@ -378,6 +381,40 @@ hipError_t launch_mlp_backward(const float* P, const float* in, const float* tgt
   hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, s, part, loss_part,
                      nwg, grad, loss);
   return hipGetLastError();
+}
+
+// Device scratch of the allocation-free gradient entry point: the gradient and loss partials
+// of up to WBM_MLP_STATIC_MAX_BATCH samples (kStaticWG workgroups of kBwdSB samples).  Every
+// call on a device overwrites the rows it uses before reading them, so nothing is cleared
+// between calls; calls that overlap on one device race on it.
+constexpr int kStaticWG = WBM_MLP_STATIC_MAX_BATCH / kBwdSB;
+static_assert(WBM_MLP_STATIC_MAX_BATCH % kBwdSB == 0, "static batch limit");
+static __device__ __align__(256) float scratch[(size_t)kStaticWG * kParams + kStaticWG];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+float* g_scratch_dev[kMaxDevices] = {};  // the array's device address, per device
+}  // namespace
+
+hipError_t mlp_static_scratch(float** part, float** loss_part) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    // each device holds its own copy of the array: look up its address with that device
+    // current, once, and use only that address from the host
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *part = g_scratch_dev[dev];
+  *loss_part = g_scratch_dev[dev] + (size_t)kStaticWG * kParams;
+  return hipSuccess;
 }
 
 hipError_t launch_adam(float* P, float* m, float* v, const float* grad, float lr, float beta1,

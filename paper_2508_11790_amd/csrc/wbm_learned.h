@@ -14,6 +14,9 @@ int mlp_param_count();
 hipError_t launch_mlp_backward(const float* P, const float* in, const float* tgt, int n,
                                float* part, float* loss_part, float* grad, float* loss,
                                hipStream_t s);
+// Device addresses (current device) of the static scratch of wbm_mlp_grad_static: gradient
+// partials [WBM_MLP_STATIC_MAX_BATCH / 16][params] and loss partials after them.
+hipError_t mlp_static_scratch(float** part, float** loss_part);
 hipError_t launch_adam(float* P, float* m, float* v, const float* grad, float lr, float beta1,
                        float beta2, float eps, float c1, float c2, hipStream_t s);
 hipError_t launch_decide(const float* out, int n, float noise, float fb_delta, int fb_win, int* pw,
