@@ -56,6 +56,21 @@ def kernel_source_file(name: str) -> str:
     return "mvdr_kernels.hip" if name.startswith("k_mvdr") else "fft_kernels.hip"
 
 
+def kernel_source_deps(fname: str) -> list:
+    """The source file and the library headers it includes, directly or through others."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2508_11790_amd", "csrc")
+    seen, todo = [], [fname]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        seen.append(f)
+        with open(os.path.join(csrc, f)) as fh:
+            todo += re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), re.M)
+    return seen
+
+
 def dispatch_name(stage: str, cfg, tuning, wmax: int, ext: bool) -> str:
     """Kernel name (as the profiler lists it, without arguments) a stage of the fused sequence
     launches for the plan's tuning."""
@@ -83,7 +98,7 @@ def dispatch_name(stage: str, cfg, tuning, wmax: int, ext: bool) -> str:
 def counter_traffic(workload: str, name: str):
     """HBM bytes per launch of the named kernel from the committed FETCH_SIZE / WRITE_SIZE
     record of this workload, or None when there is none, the kernel is not in it, or the
-    kernel's source file or any header changed since the counters were taken."""
+    kernel's source file or a header it includes changed since the counters were taken."""
     path = os.path.join(TRAFFIC_DIR, f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -93,8 +108,7 @@ def counter_traffic(workload: str, name: str):
     if k is None:
         return None
     now, then = kernel_source_hashes(), rec.get("sources", {})
-    deps = [f for f in now if f.endswith(".h")] + [kernel_source_file(name)]
-    if any(then.get(f) != now[f] for f in deps):
+    if any(then.get(f) != now.get(f) for f in kernel_source_deps(kernel_source_file(name))):
         return None
     return k["hbm_bytes"]
 
