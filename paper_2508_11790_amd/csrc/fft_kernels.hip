@@ -49,15 +49,14 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
   const int e0 = blockIdx.x * TE;
   float2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twK);
-  float2 hv[8];
+  // half-bin pre-twiddle: one table value per first-pass butterfly (its input r = 0), the
+  // other inputs' values being that times exp(-i pi r / R0)
+  float2 hv[8 / F::R0];
 #pragma unroll
   for (int p = 0; p < 8 / F::R0; ++p) {
-#pragma unroll
-    for (int r = 0; r < F::R0; ++r) {
-      int row, tau;
-      F::first_input(p, r, row, tau);
-      hv[p * F::R0 + r] = hb ? hb[tau] : make_float2(1.f, 0.f);
-    }
+    int row, tau;
+    F::first_input(p, 0, row, tau);
+    hv[p] = hb ? hb[tau] : make_float2(1.f, 0.f);
   }
   auto fetch = [&](int b, float2 (&v)[8]) {
 #pragma unroll
@@ -82,7 +81,11 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize(
     if (b + (int)gridDim.y < B) fetch(b + gridDim.y, nv);
     if (hb) {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = cmul(v[q], hv[q]);
+      for (int p = 0; p < 8 / F::R0; ++p) {
+#pragma unroll
+        for (int r = 0; r < F::R0; ++r)
+          v[p * F::R0 + r] = rot_pi8(cmul(v[p * F::R0 + r], hv[p]), r * (8 / F::R0));
+      }
     }
     F::run(v, lds, tr);
 #pragma unroll
@@ -249,8 +252,6 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize_x(
   extern __shared__ double2 lds_x[];
   double2* lds = lds_x;
   const int e0 = blockIdx.x * TE;
-  double2 tr[F::NPA][F::NTW];
-  F::load_twiddles(tr, twK);
   auto fetch = [&](int b, float2 (&v)[8]) {
 #pragma unroll
     for (int p = 0; p < 8 / F::R0; ++p) {
@@ -264,30 +265,42 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize_x(
       }
     }
   };
-  // no register prefetch of the next block here (unlike the FP32 kernel): it would hold 16 more
-  // registers, and at 2^13-complex tiles (16 elements, 128-byte output runs: the fastest tile
-  // for this kernel) the workgroup's 1024 threads are held to 128 registers each
-  for (int b = blockIdx.y; b < B; b += gridDim.y) {
-    float2 nv[8];
-    fetch(b, nv);
+  // the next block's samples are fetched into registers while the current block is
+  // transformed (16 registers; the kernel stays within the 128 per thread that a 1024-thread
+  // workgroup allows, so nothing spills)
+  double2 tr[F::NPA][F::NTW];
+  F::load_twiddles(tr, twK);
+  float2 nv[8];
+  int b = blockIdx.y;
+  if (b < B) fetch(b, nv);
+  for (; b < B; b += gridDim.y) {
     double2 v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) v[q] = make_double2((double)nv[q].x, (double)nv[q].y);
+    if (b + (int)gridDim.y < B) fetch(b + gridDim.y, nv);
+    double2 hv[8 / F::R0];     // half-bin pre-twiddle, factored as in k_channelize
+#pragma unroll
+    for (int p = 0; p < 8 / F::R0; ++p) {
+      int row, tau;
+      F::first_input(p, 0, row, tau);
+      hv[p] = hb ? hb[tau] : make_double2(1.0, 0.0);
+    }
     if (hb) {
 #pragma unroll
       for (int p = 0; p < 8 / F::R0; ++p) {
 #pragma unroll
-        for (int r = 0; r < F::R0; ++r) {
-          int row, tau;
-          F::first_input(p, r, row, tau);
-          v[p * F::R0 + r] = cmul(v[p * F::R0 + r], hb[tau]);
-        }
+        for (int r = 0; r < F::R0; ++r)
+          v[p * F::R0 + r] = rot_pi8(cmul(v[p * F::R0 + r], hv[p]), r * (8 / F::R0));
       }
     }
     F::run(v, lds, tr);
+    // output offsets from an opaque copy of the thread index: hoisted out of the loop they
+    // are 64-bit values the 128-register budget spills, and the reloads miss the cache
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int idx = threadIdx.x + q * F::threads;
+      const int idx = tid + q * F::threads;
       const int k = idx >> LOGTE, e = idx & (TE - 1);
       if (e0 + e < N) {
         float2 hi;

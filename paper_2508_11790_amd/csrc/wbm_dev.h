@@ -137,6 +137,24 @@ struct Cplx<double2> {
   __device__ __forceinline__ static double2 make(double a, double b) { return make_double2(a, b); }
 };
 
+// v * exp(-i pi m / 8), m in [0, 8) (a compile-time constant once loops are unrolled): the
+// half-bin pre-twiddle h[tau] = exp(-i pi tau / n) at tau = j + r n / R factors into
+// h[j] exp(-i pi r / R), so a channelizer thread keeps one table value per first-pass
+// butterfly and applies these constant rotations to the rest of its inputs.
+template <typename V>
+__device__ __forceinline__ V rot_pi8(V v, int m) {
+  constexpr double c[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                           0.38268343236508977173, 0.0, -0.38268343236508977173,
+                           -0.70710678118654752440, -0.92387953251128675613};
+  constexpr double s[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                           0.92387953251128675613, 1.0, 0.92387953251128675613,
+                           0.70710678118654752440, 0.38268343236508977173};
+  using S = typename Cplx<V>::S;
+  if (m == 0) return v;
+  if (m == 4) return cmul_mj(v);
+  return cmul(v, Cplx<V>::make((S)c[m], (S)-s[m]));
+}
+
 template <typename V>
 __device__ __forceinline__ void dft2(V* v) {
   V a = v[0], b = v[1];
