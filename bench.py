@@ -226,7 +226,7 @@ def validity(scene, ref, ks, weights_by_form, info_by_form):
     out = {}
     for form, w in weights_by_form.items():
         loss_max, err_max, failed, nonfinite = 0.0, 0.0, 0, 0
-        pivots = info_by_form[form] & ~(1 << 30)      # bit 30: the mixed forms' FP64 route
+        pivots = info_by_form[form] & ((1 << 29) - 1)   # bits 29, 30: width / FP64-route flags
         for ik, k in enumerate(ks):
             for t in range(cfg.T):
                 W = int(scene.win[t])

@@ -90,6 +90,7 @@ typedef enum {
                                these FP32 transforms. */
 #define WBM_FORM_GRAPH_F32 6   /* WBM_FORM_FUSED_F32 replayed from a HIP graph */
 #define WBM_INFO_ROUTED (1 << 30)
+#define WBM_INFO_WIDTH (1 << 29)   /* wbm_beamform_pairs: the pair's per-pair width was rejected */
 
 typedef struct {
   int32_t n_elem;           /* N >= 1 */
@@ -371,8 +372,10 @@ wbm_status wbm_profiles(wbm_plan* plan, const wbm_c32* x, const double* az_rad, 
 
 /* Windowed MVDR with a window width and a loading per pair.  Target t's window of win[t]
  * bins (host, as in wbm_beamform) is gathered once; pair (t, k) uses its centred sub-window
- * of pair_win[t][k] bins (device int32; same parity as win[t], else the full window) and the
- * loading pair_loading[t][k] (device float, >= 0).  Outputs as in wbm_beamform. */
+ * of pair_win[t][k] bins (device int32) and the loading pair_loading[t][k] (device float,
+ * >= 0).  A width outside [1, win[t]] or of the other parity than win[t] is rejected: that
+ * pair solves the full window of win[t] bins and its info entry carries WBM_INFO_WIDTH.
+ * Outputs as in wbm_beamform. */
 wbm_status wbm_beamform_pairs(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                               const int32_t* win, int32_t T, const int32_t* pair_win,
                               const float* pair_loading, wbm_c32* out, wbm_c32* weights,
@@ -391,7 +394,8 @@ wbm_status wbm_beamform_learned(wbm_plan* plan, const wbm_c32* x, const double* 
                                 void* stream);
 
 /* Output SINR of weights (device [T][K][w_max], window-bin order starting at starts[t][k],
- * width pair_win[t][k] or win[t] if pair_win is NULL) against the exact covariance of white
+ * width pair_win[t][k] or win[t] if pair_win is NULL; a width wbm_beamform_pairs rejects
+ * counts as win[t], and no width counts past w_max) against the exact covariance of white
  * noise sigma^2 plus J white jammers (host jam_az [J] radians, jam_inr [J] linear per
  * element): |w^H a~|^2 / (w^H (S D R_in D^H S^T) w).  sinr device [T][K] float. */
 wbm_status wbm_sinr(wbm_plan* plan, const double* az_rad, const int32_t* win, int32_t T,

@@ -30,6 +30,7 @@ _FORMS = {"plain": FORM_PLAIN, "fused": FORM_FUSED, "graph": FORM_GRAPH,
 _PRECS = {"ext": _lib.PREC_EXT, "f32": _lib.PREC_F32, "mixed": _lib.PREC_MIXED,
           "mixed_bf16": _lib.PREC_MIXED_BF16}
 INFO_ROUTED = _lib.INFO_ROUTED
+INFO_WIDTH = _lib.INFO_WIDTH
 
 
 def version() -> str:

@@ -16,6 +16,7 @@ FORM_PLAIN, FORM_FUSED, FORM_GRAPH, FORM_MIXED, FORM_MIXED_BF16 = 0, 1, 2, 3, 4
 FORM_FUSED_F32, FORM_GRAPH_F32 = 5, 6
 PREC_EXT, PREC_F32, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2, 3
 INFO_ROUTED = 1 << 30
+INFO_WIDTH = 1 << 29
 PAIR_MFMA, PAIR_RESIDENT, PAIR_WAVE, PAIR_BLOCK = 1, 2, 64, 256
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "out of memory",
           4: "HIP runtime error", 5: "unsupported"}

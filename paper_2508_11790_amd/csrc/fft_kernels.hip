@@ -1244,18 +1244,19 @@ __global__ __launch_bounds__(fft_threads(LOGMX, kUpaLogTile)) void k_beamspace_u
     }
   }
   __syncthreads();
-  // beam m of tile snapshot bb: the z-DFT of the x-transformed rows, the twiddles
-  // exp(-j 2 pi mz iz / Mz) as powers of the one for iz = 1 (one table read per beam)
+  // beam m of tile snapshot bb: the z-DFT of the x-transformed rows, each twiddle
+  // exp(-j 2 pi mz iz / Mz) read from the table (index mz iz mod Mz), so that its error does
+  // not grow with Nz as powers formed by repeated products would
   auto beam = [&](int m, int bb) {
     const int mx = m >> logMz, mz = m & (Mz - 1);
-    const float2 w1 = s_twz[mz];
     float2 acc = lds[F::addr(bb << logPz, mx)];
-    float2 w = w1;
+    int q = mz;
     for (int iz = 1; iz < Nz; ++iz) {
       const float2 v = lds[F::addr((bb << logPz) + iz, mx)];
+      const float2 w = s_twz[q];
       acc.x += v.x * w.x - v.y * w.y;
       acc.y += v.x * w.y + v.y * w.x;
-      w = cmul(w, w1);
+      q = (q + mz) & (Mz - 1);
     }
     return cscale(acc, scale);
   };

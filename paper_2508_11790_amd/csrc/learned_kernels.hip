@@ -275,7 +275,14 @@ __global__ void k_sinr(WindowGeom g, const float2* __restrict__ w, int wmax,
   const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (pair >= (int64_t)g.T * g.K) return;
   const int t = (int)(pair / g.K), k = (int)(pair % g.K);
-  const int W = pw ? pw[pair] : g.win[t];
+  // the width the pair kernels solved: a per-pair width outside [1, W_t] or of the other
+  // parity was rejected for the gathered window W_t; never more than the weight row holds
+  int W = g.win[t];
+  if (pw) {
+    const int Wp = pw[pair];
+    if (Wp >= 1 && Wp <= W && ((W - Wp) & 1) == 0) W = Wp;
+  }
+  W = W < wmax ? W : wmax;
   const int s = starts[pair];
   const float2* wp = w + pair * wmax;
   double u;

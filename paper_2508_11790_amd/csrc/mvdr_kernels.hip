@@ -908,8 +908,12 @@ __device__ __forceinline__ int ldl_reg_solve_w(const C2<double>* R, int RS, int 
   return ldl_reg_solve<16>(R, RS, W, av, wv);
 }
 
+// info bit of a pair whose per-pair width was rejected (the gathered window was solved)
+constexpr int kInfoWidth = 1 << 29;
+
 struct PairSetup {
   int t, k, W, woff, s;
+  int wflag;        // kInfoWidth when the pair's per-pair width was rejected, else 0
   int64_t pair;
   double u, delta;
 };
@@ -925,6 +929,7 @@ __device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowG
   ps.woff = d.woff[ps.t];
   ps.pair = (int64_t)ps.t * a.K + ps.k;
   window_of(g, ps.t, ps.k, &ps.u, &ps.s);
+  ps.wflag = 0;
   if (a.pw) {
     const int Wp = a.pw[ps.pair];
     if (Wp >= 1 && Wp <= ps.W && ((ps.W - Wp) & 1) == 0) {
@@ -932,6 +937,8 @@ __device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowG
       ps.woff += off;
       ps.s += off;
       ps.W = Wp;
+    } else {
+      ps.wflag = kInfoWidth;
     }
   }
   ps.delta = a.pdelta ? (double)a.pdelta[ps.pair] : a.delta;
@@ -1140,7 +1147,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
       wout[pair * a.wmax + i] = v;
     }
   }
-  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0);
+  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0) | ps.wflag;
 }
 
 // Matrix-core form, vector form with four waves (held to 128 VGPRs up to 40 bins: four
@@ -1445,7 +1452,7 @@ __global__ __launch_bounds__(256) void k_mvdr_res(PairArgs a, WindowGeom g, DevD
       wout[pair * a.wmax + i] = vv;
     }
   }
-  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0);
+  if (info && tid == 0) info[pair] = fail | (a.route ? (1 << 30) : 0) | ps.wflag;
 }
 
 hipError_t launch_mvdr_resident(const PairArgs& a, const WindowGeom& g, const DevDesc& d,
@@ -1880,7 +1887,7 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
     // the exact FP64 path solves this window in the second launch
     if (tid == 0) {
       flags[pair] = 1;
-      if (info) info[pair] = kInfoRouted;
+      if (info) info[pair] = kInfoRouted | ps.wflag;
     }
     return;
   }
@@ -1894,7 +1901,7 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
       wout[pair * a.wmax + i] = v;
     }
   }
-  if (info && tid == 0) info[pair] = fail;
+  if (info && tid == 0) info[pair] = fail | ps.wflag;
 }
 
 template <int WCAP, bool SPLIT>

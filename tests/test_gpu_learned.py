@@ -98,6 +98,39 @@ def test_pair_windows_and_loadings_match_oracle(torch, wb):
     plan.close()
 
 
+def test_rejected_pair_widths_solve_the_full_window(torch, wb):
+    cfg = SMALL_MULTI
+    sc = scenes.make_scene(cfg)
+    x = torch.from_numpy(sc.x.astype(np.complex64)).cuda()
+    rng = np.random.default_rng(11)
+    pw = rng.choice([5, 9, 17, 33], size=(cfg.T, cfg.K)).astype(np.int32)
+    pd = np.full((cfg.T, cfg.K), 10.0, dtype=np.float32)
+    bad = {(0, 0): 8, (1, 2): 35, (2, 3): 0, (2, 7): -5}     # other parity, too wide, < 1
+    fixed = pw.copy()
+    for (t, k), v in bad.items():
+        pw[t, k] = v
+        fixed[t, k] = 33
+    plan = _plan(wb, cfg)
+    win = [33] * cfg.T
+    r_bad = plan.beamform_pairs(x, sc.target_az, win, torch.from_numpy(pw).cuda(),
+                                torch.from_numpy(pd).cuda())
+    r_fix = plan.beamform_pairs(x, sc.target_az, win, torch.from_numpy(fixed).cuda(),
+                                torch.from_numpy(pd).cuda())
+    info = r_bad["info"].cpu().numpy()
+    for t in range(cfg.T):
+        for k in range(cfg.K):
+            assert info[t, k] == (wb.INFO_WIDTH if (t, k) in bad else 0), (t, k, info[t, k])
+    assert int(r_fix["info"].abs().sum()) == 0
+    assert torch.equal(r_bad["weights"], r_fix["weights"])
+    assert torch.equal(r_bad["starts"], r_fix["starts"])
+    s_bad = plan.sinr(sc.target_az, win, r_bad["weights"], r_bad["starts"], sc.jammer_az,
+                      sc.jammer_inr, 1.0, pair_win=torch.from_numpy(pw).cuda())
+    s_fix = plan.sinr(sc.target_az, win, r_fix["weights"], r_fix["starts"], sc.jammer_az,
+                      sc.jammer_inr, 1.0, pair_win=torch.from_numpy(fixed).cuda())
+    assert torch.equal(s_bad, s_fix)
+    plan.close()
+
+
 def test_sweep_labels_match_oracle(torch, wb):
     from paper_2508_11790_amd import learned
     cfg = SMALL_MULTI
@@ -154,17 +187,18 @@ def test_mlp_forward_gradients_and_adam_match_oracle(torch, wb):
     scale = np.max(np.abs(ref_g))
     assert np.max(np.abs(grad - ref_g)) < 1e-4 * scale
     assert abs(float(loss.item()) - omlp.loss(pr, x, y)) < 1e-4 * omlp.loss(pr, x, y)
-    # Adam step against the oracle's
+    # three Adam steps (bias correction past the first step) against the oracle's
     m = torch.zeros_like(P)
     v = torch.zeros_like(P)
-    g_t = torch.from_numpy(ref_g.astype(np.float32)).cuda()
     P2 = P.clone()
-    mlp.adam(P2, m, v, g_t, 1, 1e-3)
     pp = omlp.unflatten(flat.astype(np.float64))
     mm = {k2: np.zeros_like(a) for k2, a in pp.items()}
     vv = {k2: np.zeros_like(a) for k2, a in pp.items()}
-    omlp.adam_step(pp, omlp.unflatten(ref_g.astype(np.float32).astype(np.float64)), mm, vv, 1, 1e-3)
-    assert np.max(np.abs(P2.cpu().numpy() - omlp.flatten(pp))) < 1e-6
+    for step in (1, 2, 3):
+        g_np = (ref_g * (1.0 + 0.5 * step) + r.standard_normal(ref_g.size) * scale).astype(np.float32)
+        mlp.adam(P2, m, v, torch.from_numpy(g_np).cuda(), step, 1e-3)
+        omlp.adam_step(pp, omlp.unflatten(g_np.astype(np.float64)), mm, vv, step, 1e-3)
+        assert np.max(np.abs(P2.cpu().numpy() - omlp.flatten(pp))) < 1e-6 * step, step
     mlp.close()
 
 
@@ -225,3 +259,83 @@ def test_trained_network_gains_over_fixed_method(torch, wb):
     assert ev["learned_mean_sinr_db"] <= ev["best_mean_sinr_db"] + 1e-3
     plan.close()
     mlp.close()
+
+
+def test_learned_form_at_evaluation_shape(torch, wb):
+    """The committed network at its evaluation shape (batch-sized array: N = 1024, M = 2048,
+    K = 256, 64 targets, L = Lt = 512): per-pair profiles, network outputs and (W, delta)
+    decisions, then the resulting weights, against the oracle on sampled subbands; and the
+    held-out SINR gain over the fixed method."""
+    import os
+    from paper_2508_11790_amd import learned
+    from paper_2508_11790_amd.train_predictor import evaluate
+    cfg = scenes.LEARNED_EVAL
+    path = os.path.join(os.path.dirname(learned.__file__), "predictor_params.npz")
+    flat = learned.load_params(path)
+    P = torch.from_numpy(flat).cuda()
+    sc, x = scenes.make_scene_torch(cfg, cfg.seed + 77)
+    plan = wb.Plan(cfg.N, cfg.M, cfg.K, cfg.L, cfg.Lt, cfg.T, 33, beta=cfg.beta,
+                   d_over_lambda=cfg.dl)
+    mlp = wb.Mlp(cfg.T * cfg.K)
+    lr = plan.beamform_learned(x, sc.target_az, P, cfg.noise_var, 9, cfg.delta)
+    feat = plan.profiles(x, sc.target_az, cfg.noise_var)
+    out = mlp.forward(P, feat.reshape(-1, 64)).reshape(cfg.T, cfg.K, 2).cpu().numpy()
+    feat = feat.cpu().numpy()
+    pw = lr["pair_win"].cpu().numpy()
+    pd = lr["pair_loading"].cpu().numpy()
+    w = lr["weights"].cpu().numpy().astype(np.complex128)
+    starts = lr["starts"].cpu().numpy()
+    assert int(lr["fallback"].sum()) == 0 and int(lr["info"].abs().sum()) == 0
+    x128 = x.cpu().numpy().astype(np.complex128)
+    del x
+    torch.cuda.empty_cache()
+    ks = [0, 101, 255]
+    log(f"  oracle on subbands {ks}, all {cfg.T} targets")
+    Xs = oracle.channelize_bins(x128, cfg.K, ks)                     # [N, B, len(ks)]
+    del x128
+    ratio = oracle.subband_freq_ratio(cfg.K, cfg.beta)
+    pr = omlp.unflatten(olearned.bf16_round(flat))
+    n_boundary, err_max, loss_max = 0, 0.0, 0.0
+    for ik, k in enumerate(ks):
+        Yk = oracle.beamspace(Xs[:, :cfg.L, ik], cfg.M)               # training beamspace [M, L]
+        for t in range(cfg.T):
+            u = oracle.beam_position(_sin(sc)[t], ratio[k], cfg.M, cfg.dl)
+            f_ref = olearned.power_profile(Yk, u, cfg.noise_var)
+            assert np.max(np.abs(feat[t, k] - f_ref)) < 2e-4, (t, k)
+            o_ref = omlp.forward(pr, f_ref[None, :])["out"][0]
+            assert np.max(np.abs(out[t, k] - o_ref)) < 1e-3, (t, k, out[t, k], o_ref)
+            W_ref, d_ref = olearned.decision(float(o_ref[0]), float(o_ref[1]), cfg.noise_var)
+            assert abs(pd[t, k] / d_ref - 1) < 1e-3, (t, k, pd[t, k], d_ref)
+            # a width decided within the two networks' rounding of a rint() boundary may
+            # differ; every other decision is the oracle's
+            frac = abs(float(o_ref[1]) - math.floor(float(o_ref[1])) - 0.5)
+            if frac < 1e-3 and 2.0 < o_ref[1] < 5.0:
+                n_boundary += 1
+                assert pw[t, k] in (W_ref, 2 * W_ref - 1, (W_ref + 1) // 2)
+            else:
+                assert pw[t, k] == W_ref, (t, k, pw[t, k], W_ref, o_ref)
+            # weights of the GPU's decision against the oracle's MVDR with that (W, delta)
+            W, d = int(pw[t, k]), float(pd[t, k])
+            ref = oracle.windowed_mvdr(None, X=Xs[:, :, ik:ik + 1], M=cfg.M, K=cfg.K, L=cfg.L,
+                                       Lt=cfg.Lt, sin_az=[_sin(sc)[t]], win=[W], delta=d,
+                                       beta=cfg.beta, dl=cfg.dl, subbands=[k])
+            assert starts[t, k] == ref["start"][0, 0]
+            err = oracle.rel_weight_error(w[t, k, :W], ref["w"][0, 0, :W])
+            bins = oracle.window_bins(int(starts[t, k]), W, cfg.M)
+            s_g = olearned.pair_sinr(w[t, k, :W], ref["a"][0, 0, :W], bins, cfg.N, cfg.M,
+                                     np.sin(sc.jammer_az), sc.jammer_inr, ratio[k], cfg.dl,
+                                     cfg.noise_var)
+            s_o = olearned.pair_sinr(ref["w"][0, 0, :W], ref["a"][0, 0, :W], bins, cfg.N, cfg.M,
+                                     np.sin(sc.jammer_az), sc.jammer_inr, ratio[k], cfg.dl,
+                                     cfg.noise_var)
+            err_max = max(err_max, err)
+            loss_max = max(loss_max, abs(10 * math.log10(s_o / s_g)))
+    log(f"  max weight error {err_max:.3g}, max SINR loss {loss_max:.3g} dB, "
+        f"{n_boundary} width decisions at a rounding boundary")
+    assert err_max <= 1e-5 and loss_max <= 0.1
+    plan.close()
+    mlp.close()
+    ev = evaluate(wb, learned, scenes, cfg, 2, cfg.seed + 500, P, with_ceiling=False)
+    log(f"  held-out: {ev}")
+    assert ev["fallback_pairs"] == 0
+    assert ev["gain_db"] > 0.0

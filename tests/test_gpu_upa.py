@@ -153,6 +153,8 @@ BEAM_SHAPES = [
     dict(Nz=8, Nx=1, Mz=16, Mx=2, K=2, L=7, Lt=2),       # one column
     dict(Nz=4, Nx=4, Mz=4, Mx=4, K=4, L=3, Lt=2),        # no zero padding
     dict(Nz=2, Nx=300, Mz=2, Mx=1024, K=2, L=3, Lt=2),   # widest x-FFT of a two-row array
+    dict(Nz=64, Nx=8, Mz=64, Mx=16, K=2, L=5, Lt=3),     # long z-DFT: table twiddles per term
+    dict(Nz=100, Nx=4, Mz=128, Mx=16, K=2, L=4, Lt=2),   # longest z-DFT the tile allows
 ]
 
 
