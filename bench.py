@@ -378,7 +378,9 @@ def upa_leg(torch, wb, scenes, steps, warmup):
 
 
 def extra_leg(torch, wb, scenes, name, steps, warmup):
-    """Another configuration at full size: the chosen form and the FP32-transform form."""
+    """Another configuration at full size: the chosen form, the FP32-transform form, the mixed
+    forms (with their routed pairs) and the plain form, and the per-stage times of both
+    transform precisions."""
     cfg = scenes.config_by_name(name)
     if cfg.N >= 1024:
         sc, x = scenes.make_scene_torch(cfg, cfg.seed)
@@ -393,15 +395,23 @@ def extra_leg(torch, wb, scenes, name, steps, warmup):
     info = torch.empty((cfg.T, cfg.K), dtype=torch.int32, device=x.device)
     res = {"workload": f"{cfg.name}: ULA N={cfg.N}, M={cfg.M}, K={cfg.K}, W<={wmax}, L={cfg.L}, "
                        f"Lt={cfg.Lt}, T={cfg.T}, {cfg.n_jammers} jammers"}
-    for form in ("graph", "graph_f32"):
+    for form in ("graph", "graph_f32", "mixed", "mixed_bf16", "plain"):
         ms = timed_steps(torch, lambda: plan.beamform(x, sc.target_az, sc.win, cfg.delta,
                                                       form=form, out=out, weights=wts,
                                                       info=info, want_starts=False),
                          steps, warmup)
-        assert int(info.abs().sum()) == 0
+        inf = info.cpu().numpy()
         res[form] = {"value": cfg.T * cfg.K / (ms * 1e-3), "ms_per_step": ms}
-    st = plan.stage_times(x, sc.target_az, sc.win, cfg.delta, reps=20)
-    res["stage_ms_ext"] = {k: round(v, 5) for k, v in st.items()}
+        if form.startswith("mixed"):
+            res[form]["routed_pairs"] = int(((inf & wb.INFO_ROUTED) != 0).sum())
+        failed = int(((inf & ((1 << 29) - 1)) != 0).sum())
+        if form.startswith("graph"):
+            assert failed == 0
+        else:
+            res[form]["failed_pairs"] = failed
+    for prec in ("ext", "f32"):
+        st = plan.stage_times(x, sc.target_az, sc.win, cfg.delta, reps=20, precision=prec)
+        res["stage_ms_" + prec] = {k: round(v, 5) for k, v in st.items()}
     plan.close()
     del x
     torch.cuda.empty_cache()
