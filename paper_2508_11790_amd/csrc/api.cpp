@@ -119,6 +119,8 @@ struct wbm_plan {
   double2* abar = nullptr;   // [T_max][K][w_max]
   double2* fullR = nullptr;  // [nk_full][N][N] (full-dimensional MVDR, first use)
   double2* fullW = nullptr;  // [nk_full][T_max][N]
+  double2* fullV = nullptr;  // [nk_full][N][T_max] (blocked solves)
+  double* fullQ = nullptr;   // [nk_full][T_max]
   int* full_info = nullptr;  // [K]
   int nk_full = 0;
   int64_t ws_bytes = 0;
@@ -845,7 +847,7 @@ wbm_status wbm_plan_destroy(wbm_plan* p) {
   if (p->jam_host) (void)hipHostFree(p->jam_host);
   void* bufs[] = {p->twK, p->twM, p->hb, p->twK64, p->twM64, p->hb64, p->Xl, p->Ywl,
                   p->desc_dev, p->X, p->Yw, p->Y, p->R32,
-                  p->w32, p->starts, p->abar, p->fullR, p->fullW, p->full_info,
+                  p->w32, p->starts, p->abar, p->fullR, p->fullW, p->fullV, p->fullQ, p->full_info,
                   p->prof_out, p->prof_w, p->prof_info, p->pprof, p->feat, p->nnout,
                   p->pw, p->pdelta, p->jam_dev, p->route, p->upa_rows};
   for (void* b : bufs)
@@ -1452,6 +1454,8 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
     p->nk_full = (int)nk;
     if ((s = dev_alloc(p, &p->fullR, nk * NN, "full covariance"))) return s;
     if ((s = dev_alloc(p, &p->fullW, nk * (size_t)c.max_targets * c.n_elem, "full weights"))) return s;
+    if ((s = dev_alloc(p, &p->fullV, nk * (size_t)c.max_targets * c.n_elem, "full solves"))) return s;
+    if ((s = dev_alloc(p, &p->fullQ, nk * (size_t)c.max_targets, "full norms"))) return s;
   }
   WBM_HIP(enqueue_channelize(p, kF32, reinterpret_cast<const float2*>(x), st),
           "channelize launch");
@@ -1470,7 +1474,7 @@ wbm_status wbm_full_mvdr(wbm_plan* p, const wbm_c32* x, const double* az_rad, in
     a.beta = c.beta;
     a.dl = c.d_over_lambda;
     a.half_bin = (c.flags & WBM_HALF_BIN) ? 1 : 0;
-    WBM_HIP(wbm::launch_full_mvdr(a, p->dd, p->X, p->fullR, p->fullW,
+    WBM_HIP(wbm::launch_full_mvdr(a, p->dd, p->X, p->fullR, p->fullV, p->fullQ, p->fullW,
                                   reinterpret_cast<float2*>(out), reinterpret_cast<float2*>(weights),
                                   inf, st),
             "full MVDR launch");

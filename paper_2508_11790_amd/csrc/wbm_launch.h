@@ -127,9 +127,11 @@ struct FullArgs {
   double delta, beta, dl;
   int half_bin;
 };
-// Full-dimensional element-space MVDR for subbands k0..k0+nk-1 (R workspace [nk][N][N] FP64).
+// Full-dimensional element-space MVDR for subbands k0..k0+nk-1 (workspace: R [nk][N][N],
+// V [nk][N][T], q [nk][T], wtmp [nk][T][N], FP64).
 hipError_t launch_full_mvdr(const FullArgs& a, const DevDesc& d, const float2* X, double2* R,
-                            double2* wtmp, float2* out, float2* wout, int* info, hipStream_t s);
+                            double2* V, double* q, double2* wtmp, float2* out, float2* wout,
+                            int* info, hipStream_t s);
 
 // Subband synthesis (inverse channelizer per block): Z [T][K][Lt] -> z [T][Lt*K].
 hipError_t launch_synth(const float2* Z, float2* z, int K, int Lt, int T, const float2* twK,

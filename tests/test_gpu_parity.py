@@ -491,10 +491,16 @@ def test_pair_kernel_limits_rejected(torch, wb):
     plan.close()
 
 
-@pytest.mark.parametrize("name,subbands", [("small", None), ("gpu", [0, 5, 64, 127])])
+# N = 200: the blocked Cholesky's 64-column panels end in a ragged one of 8 columns
+FULL_RAGGED = scenes.GPU.replace(name="full_ragged", N=200, K=16, L=256, Lt=32, T=4,
+                                 seed=4242)
+
+
+@pytest.mark.parametrize("name,subbands", [("small", None), ("gpu", [0, 5, 64, 127]),
+                                           ("full_ragged", [0, 3, 15])])
 def test_full_dimensional_mvdr_matches_oracle(torch, wb, name, subbands):
-    cfg = scenes.config_by_name(name)
-    log(f"full-dimensional MVDR, {name} config")
+    cfg = FULL_RAGGED if name == "full_ragged" else scenes.config_by_name(name)
+    log(f"full-dimensional MVDR, {name} config (N={cfg.N})")
     sc = scenes.make_scene(cfg)
     x32 = _x32(sc)
     plan = _plan(wb, cfg, sc)
