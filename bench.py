@@ -595,14 +595,14 @@ def main():
 
     ms_full = None
     if not args.no_full:
-        # element-space N x N MVDR per subband: about K * 8 N^2 L flops of covariance plus the
-        # Cholesky factorisations (160 TFLOP at N = 4096), so few steps at large N
-        # (160 TFLOP at N = 4096: there it runs on eight subbands, ks, and is scaled per pair)
+        # element-space N x N MVDR per subband over the whole workload: about 8 N^2 L flops of
+        # covariance and 4 N^3 / 3 of Cholesky per subband (117 TFLOP per step at N = 4096), so
+        # few steps at large N
         full_sub = None
         nfs = max(2, min(args.steps // 20, 20))
         full_k = cfg.K
         if cfg.N >= 2048:
-            full_sub, full_k, nfs = (ks[len(ks) // 2], 8), 8, 1
+            nfs = 2
         log(f"timing full-dimensional element-space MVDR on {full_k} subbands ({nfs} step(s))")
         ms_full = timed_steps(torch, lambda: plan.full_mvdr(x, az, delta, want_weights=False,
                                                             subbands=full_sub), nfs, 1)
@@ -654,8 +654,9 @@ def main():
         "full_dim": (None if ms_full is None else
                      {"value": T * full_k / (ms_full * 1e-3), "ms_per_step": ms_full,
                       "subbands_per_step": full_k,
-                      "form": f"element-space {cfg.N}x{cfg.N} MVDR per subband, FP64 (a step "
-                              f"channelizes every subband and solves {full_k} of {K})"}),
+                      "form": f"element-space {cfg.N}x{cfg.N} MVDR per subband, FP64 "
+                              f"(covariance, blocked Cholesky, blocked solves, apply; "
+                              f"{full_k} of {K} subbands per step)"}),
         **beside,
         "upa": upa_res,
         "roofline": roofline,
