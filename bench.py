@@ -633,12 +633,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 transforms (f32+bf16 storage), f64 covariance/solve",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: ULA N={cfg.N}, M={cfg.M}, K={cfg.K}, W={wmax}, "
                                f"L={cfg.L}, Lt={cfg.Lt}, T={T}, {cfg.n_jammers} jammers "
                                f"(INR {cfg.inr_range_db[0]:.0f}-{cfg.inr_range_db[1]:.0f} dB)",
                    "form": "fused + HIP graph, extended-precision transforms",
+                   "precision": "FP64 transforms, covariance, LDL^H and normalisation; X and "
+                                "the windows stored as FP32 + BF16 remainder",
                    "pairs_per_step": beams,
                    "tuning": dict(zip(("chan_logtile", "beam_logtile", "pair_kernel",
                                        "overlap_chunks"), tun)),
