@@ -94,7 +94,7 @@ typedef enum {
 
 typedef struct {
   int32_t n_elem;           /* N >= 1 */
-  int32_t m_fft;            /* M: power of two, N <= M <= 8192 */
+  int32_t m_fft;            /* M: power of two, max(2, N) <= M <= 8192 */
   int32_t k_sub;            /* K: power of two, 2 <= K <= 8192 */
   int32_t l_train;          /* L >= 1 training snapshots per subband */
   int32_t l_test;           /* Lt >= 0 test snapshots per subband */

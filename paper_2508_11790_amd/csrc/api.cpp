@@ -862,8 +862,8 @@ wbm_status wbm_plan_create(const wbm_config* cfg, wbm_plan** out) {
   if (!cfg) return fail(WBM_ERR_ARG, "cfg is NULL");
   const wbm_config& c = *cfg;
   if (c.n_elem < 1) return fail(WBM_ERR_ARG, "n_elem must be >= 1");
-  if (!is_pow2(c.m_fft) || c.m_fft < c.n_elem || c.m_fft > 8192)
-    return fail(WBM_ERR_ARG, "m_fft must be a power of two with n_elem <= m_fft <= 8192");
+  if (!is_pow2(c.m_fft) || c.m_fft < 2 || c.m_fft < c.n_elem || c.m_fft > 8192)
+    return fail(WBM_ERR_ARG, "m_fft must be a power of two with max(2, n_elem) <= m_fft <= 8192");
   if (!is_pow2(c.k_sub) || c.k_sub < 2 || c.k_sub > 8192)
     return fail(WBM_ERR_ARG, "k_sub must be a power of two in [2, 8192]");
   if (c.l_train < 1 || c.l_test < 0) return fail(WBM_ERR_ARG, "need l_train >= 1 and l_test >= 0");

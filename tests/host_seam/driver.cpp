@@ -15,6 +15,9 @@
 
 #include "wbmvdr.h"
 
+#pragma clang diagnostic ignored "-Wunused-value"
+#pragma clang diagnostic ignored "-Wunused-result"
+
 extern "C" long hip_stub_launches();
 extern "C" int hip_stub_open_captures();
 
@@ -244,6 +247,59 @@ static void planar_plan(hipStream_t st) {
     hipFree(q);
 }
 
+// Extreme and unusual shapes: every form once (no autotuning), full-dimensional MVDR where
+// N <= 4096, so that each launcher's grid, block and LDS request is checked at the limits.
+static void shape_sweep(hipStream_t st) {
+  struct Shape { int N, M, K, L, Lt, T, W; };
+  const Shape shapes[] = {
+      {1, 2, 2, 1, 1, 1, 1},            // one element, the smallest spatial DFT
+      {2, 2, 2, 1, 1, 2, 2},            // W = M = N = 2
+      {3, 4, 2, 2, 0, 2, 3},            // no test snapshots
+      {5, 8, 4, 3, 1, 3, 8},            // windows as wide as M
+      {33, 64, 8192, 1, 1, 2, 5},       // the most subbands
+      {100, 128, 16, 5, 3, 7, 33},      // N not a power of two
+      {2048, 8192, 2, 2, 2, 2, 64},     // split-half extended spatial DFT (2N <= M = 8192)
+      {4096, 8192, 2, 1, 1, 2, 64},     // the largest array
+      {3000, 4096, 4, 2, 1, 3, 17},     // N > M / 2: no zero-half skip
+      {64, 64, 32, 4, 4, 40, 64},       // many targets, W = M = N
+  };
+  setenv("WBM_AUTOTUNE", "0", 1);
+  for (const Shape& sh : shapes) {
+    const int fail_before = g_fail;
+    g_fail = 0;
+    wbm_config cfg = config(sh.N, sh.M, sh.K, sh.L, sh.Lt, sh.T, sh.W, 0);
+    wbm_plan* p = nullptr;
+    EXPECT(wbm_plan_create(&cfg, &p), WBM_OK);
+    if (!p) continue;
+    const long S = (long)(sh.L + sh.Lt) * sh.K;
+    auto* x = dev<wbm_c32>((size_t)sh.N * S);
+    auto* out = dev<wbm_c32>((size_t)sh.T * sh.K * (sh.Lt ? sh.Lt : 1));
+    auto* w = dev<wbm_c32>((size_t)sh.T * sh.K * sh.W);
+    auto* starts = dev<int32_t>((size_t)sh.T * sh.K);
+    auto* info = dev<int32_t>((size_t)sh.T * sh.K);
+    std::vector<double> az(sh.T);
+    std::vector<int32_t> win(sh.T);
+    for (int t = 0; t < sh.T; ++t) {
+      az[t] = -1.2 + 2.4 * t / (sh.T > 1 ? sh.T - 1 : 1);
+      win[t] = 1 + (t * 7) % sh.W;
+    }
+    win[0] = sh.W;
+    for (int form = 0; form <= 6; ++form)
+      EXPECT(wbm_beamform(p, x, az.data(), win.data(), sh.T, 10.0, form, out, w, starts, info, st), WBM_OK);
+    auto* fw = dev<wbm_c32>((size_t)sh.T * sh.K * sh.N);
+    auto* finfo = dev<int32_t>(sh.K);
+    EXPECT(wbm_full_mvdr(p, x, az.data(), sh.T, 10.0, 0, sh.K < 4 ? sh.K : 4, out, fw, finfo, st), WBM_OK);
+    EXPECT(wbm_plan_destroy(p), WBM_OK);
+    for (void* q : {(void*)x, (void*)out, (void*)w, (void*)starts, (void*)info, (void*)fw, (void*)finfo})
+      hipFree(q);
+    if (g_fail)
+      std::fprintf(stderr, "  (shape N=%d M=%d K=%d L=%d Lt=%d T=%d W=%d)\n", sh.N, sh.M, sh.K,
+                   sh.L, sh.Lt, sh.T, sh.W);
+    g_fail |= fail_before;
+  }
+  unsetenv("WBM_AUTOTUNE");
+}
+
 // Self-checks of the seam itself (each must end the process with a report): a stream created
 // while a capture is open, and a write one element past a buffer from hipMalloc.
 static int plant(const char* what) {
@@ -270,11 +326,14 @@ int main(int argc, char** argv) {
   wbm_config bad = config(16, 24, 16, 8, 8, 4, 9, 0);          // M not a power of two
   wbm_plan* none = nullptr;
   EXPECT(wbm_plan_create(&bad, &none), WBM_ERR_ARG);
+  bad = config(1, 1, 2, 1, 1, 1, 1, 0);                         // a one-point spatial DFT
+  EXPECT(wbm_plan_create(&bad, &none), WBM_ERR_ARG);
   EXPECT(wbm_plan_create(nullptr, &none), WBM_ERR_ARG);
   linear_plan(0, st);
   linear_plan(WBM_HALF_BIN, st);
   learned_plan(st);
   planar_plan(st);
+  shape_sweep(st);
   EXPECT(wbm_plan_destroy(nullptr), WBM_OK);
   hipStreamDestroy(st);
   if (hip_stub_open_captures() != 0) {
