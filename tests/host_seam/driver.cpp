@@ -300,6 +300,59 @@ static void shape_sweep(hipStream_t st) {
   unsetenv("WBM_AUTOTUNE");
 }
 
+// Planar geometries at their limits: one row, one column, the longest z-DFT, the widest x-FFT.
+static void planar_sweep(hipStream_t st) {
+  struct Geo { int Nz, Nx, Mz, Mx, K, T, Wz, Wx; };
+  const Geo geos[] = {
+      {1, 16, 1, 32, 4, 2, 1, 5},       // one row
+      {8, 1, 16, 2, 2, 2, 3, 1},        // one column
+      {100, 4, 128, 16, 2, 2, 4, 3},    // longest z-DFT the tile allows
+      {2, 300, 2, 1024, 2, 2, 2, 8},    // widest x-FFT of a two-row array
+      {4, 4, 4, 4, 8, 3, 4, 4},         // no zero padding, window = whole grid
+  };
+  setenv("WBM_AUTOTUNE", "0", 1);
+  for (const Geo& g : geos) {
+    const int fail_before = g_fail;
+    g_fail = 0;
+    const int N = g.Nz * g.Nx, M = g.Mz * g.Mx, L = 3, Lt = 2, W = g.Wz * g.Wx;
+    wbm_config cfg = config(N, M, g.K, L, Lt, g.T, W, 0);
+    wbm_plan* p = nullptr;
+    EXPECT(wbm_plan_create(&cfg, &p), WBM_OK);
+    if (!p) continue;
+    const long S = (long)(L + Lt) * g.K;
+    auto* x = dev<wbm_c32>((size_t)N * S);
+    auto* out = dev<wbm_c32>((size_t)g.T * g.K * Lt);
+    auto* w = dev<wbm_c32>((size_t)g.T * g.K * W);
+    auto* starts = dev<int32_t>((size_t)g.T * g.K * 2);
+    auto* info = dev<int32_t>((size_t)g.T * g.K);
+    std::vector<double> az(g.T), el(g.T);
+    std::vector<int32_t> wz(g.T, g.Wz), wx(g.T, g.Wx);
+    for (int t = 0; t < g.T; ++t) {
+      az[t] = -0.8 + 1.6 * t / (g.T - 1);
+      el[t] = 0.1 * t;
+    }
+    for (int form : {WBM_FORM_PLAIN, WBM_FORM_FUSED, WBM_FORM_MIXED, WBM_FORM_MIXED_BF16})
+      EXPECT(wbm_beamform_upa(p, x, g.Nz, g.Mz, az.data(), el.data(), wz.data(), wx.data(), g.T,
+                              10.0, form, out, w, starts, info, st), WBM_OK);
+    auto* wzd = dev<int32_t>(g.T);
+    hipMemcpy(wzd, wz.data(), sizeof(int32_t) * g.T, hipMemcpyHostToDevice);
+    auto* chat = dev<wbm_c32>((size_t)g.T * g.K * N);
+    EXPECT(wbm_lift_upa(p, w, starts, g.Nz, g.Mz, wzd, g.T, chat, st), WBM_OK);
+    auto* omega = dev<double>(2 * 8);
+    auto* pat = dev<float>((size_t)g.T * g.K * 8);
+    EXPECT(wbm_beam_pattern_upa(p, chat, g.T * g.K, g.Nz, omega, 8, pat, st), WBM_OK);
+    EXPECT(wbm_apply_lifted(p, x, chat, g.T, out, st), WBM_OK);
+    EXPECT(wbm_plan_destroy(p), WBM_OK);
+    for (void* q : {(void*)x, (void*)out, (void*)w, (void*)starts, (void*)info, (void*)wzd,
+                    (void*)chat, (void*)omega, (void*)pat})
+      hipFree(q);
+    if (g_fail)
+      std::fprintf(stderr, "  (planar Nz=%d Nx=%d Mz=%d Mx=%d K=%d)\n", g.Nz, g.Nx, g.Mz, g.Mx, g.K);
+    g_fail |= fail_before;
+  }
+  unsetenv("WBM_AUTOTUNE");
+}
+
 // Self-checks of the seam itself (each must end the process with a report): a stream created
 // while a capture is open, and a write one element past a buffer from hipMalloc.
 static int plant(const char* what) {
@@ -334,6 +387,7 @@ int main(int argc, char** argv) {
   learned_plan(st);
   planar_plan(st);
   shape_sweep(st);
+  planar_sweep(st);
   EXPECT(wbm_plan_destroy(nullptr), WBM_OK);
   hipStreamDestroy(st);
   if (hip_stub_open_captures() != 0) {
