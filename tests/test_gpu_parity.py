@@ -227,6 +227,34 @@ def test_precision_config_full_size_sampled_subbands(torch, wb):
     plan.close()
 
 
+@pytest.mark.timeout(900)
+def test_precision_config_every_jammer_at_60db(torch, wb):
+    """The precision workload's array and targets with all eight jammers at the workload's
+    largest INR (60 dB): the extended-precision forms still within 1e-5 relative weight error
+    and 0.1 dB SINR loss on three subbands (every target); the FP32-transform error logged."""
+    cfg = scenes.PRECISION.replace(name="precision_60dB", inr_range_db=(60.0, 60.0), seed=777)
+    log("precision config with 8 jammers at 60 dB: generating")
+    sc, x = scenes.make_scene_torch(cfg, cfg.seed)
+    torch.cuda.synchronize()
+    ks = [0, 200, 400]
+    X = _host_channelize_bins(x, cfg.K, ks, cfg.half_bin)
+    ref = oracle.windowed_mvdr(None, X=X, M=cfg.M, K=cfg.K, L=cfg.L, Lt=cfg.Lt,
+                               sin_az=[math.sin(a) for a in sc.target_az], win=sc.win,
+                               delta=cfg.delta, beta=cfg.beta, dl=cfg.dl, half_bin=cfg.half_bin,
+                               subbands=ks, return_windows=True)
+    del X
+    plan = _plan(wb, cfg, sc)
+    for form in ("graph", "graph_f32"):
+        res = dict(plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form))
+        torch.cuda.synchronize()
+        ext = form == "graph"
+        st = compare_beamform(sc, ref, res, subbands=ks, ext=ext,
+                              tol_scale=1.0 if ext else None)
+        log(f"  {form}: {st}")
+    del x
+    plan.close()
+
+
 def _pin(plan, pair, overlap=1, precision="ext"):
     chan, beam, _, _ = plan.get_tuning(precision)
     plan.set_tuning(chan, beam, pair, overlap, precision=precision)
