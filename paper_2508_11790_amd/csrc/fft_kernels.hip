@@ -432,6 +432,41 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace_x(
   }
 }
 
+// Half-bin index field of a window-row list entry of the split-half kernels (M <= 8192).
+constexpr int kHalfBinBits = 12;
+
+// Window rows of subband k for the split-half kernels, as two lists in LDS: lst[0, ne) holds
+// the even-bin rows and lst[ne, sumW) the odd-bin rows, each entry (row << kHalfBinBits) |
+// (bin / 2), where row is the window row in split order (each window's even-bin rows first,
+// then its odd-bin ones) and ne = ebase[T] the number of even-bin rows; ebase[t] counts the
+// even-bin rows of the windows before t (rowtab lists the windows in target order).  Each half
+// transform then stores its own rows with every lane active.  Requires s_start filled and
+// visible; ends with lst and ebase written but not yet synchronised.
+template <int M>
+__device__ void split_row_lists(const WindowGeom& g, const int* s_start,
+                                const int* __restrict__ rowtab, int sumW, int* lst, int* ebase,
+                                int nthreads) {
+  static_assert(M / 2 <= (1 << kHalfBinBits), "half-bin field too narrow");
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int t = 0; t < g.T; ++t) {
+      ebase[t] = acc;
+      acc += (g.win[t] + ((s_start[t] & 1) ? 0 : 1)) >> 1;
+    }
+    ebase[g.T] = acc;
+  }
+  __syncthreads();
+  const int ne_all = ebase[g.T];
+  for (int r = threadIdx.x; r < sumW; r += nthreads) {
+    const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
+    const int st = s_start[t], m = (st + i) & (M - 1), base = r - i;
+    const int ne = (g.win[t] + ((st & 1) ? 0 : 1)) >> 1;
+    const int row = base + ((m & 1) ? ne : 0) + (i >> 1);
+    const int at = (m & 1) ? ne_all + (base - ebase[t]) + (i >> 1) : ebase[t] + (i >> 1);
+    lst[at] = (row << kHalfBinBits) | (m >> 1);
+  }
+}
+
 // Windowed spatial DFT in extended precision for M >= 8192 with N <= M / 2 (the upper half of
 // every zero-padded row is zero).  The M-point transform of such a row splits into two
 // H = M/2-point transforms, Y[2 m'] = sum_{e<N} X[e] w_H^(m' e) and Y[2 m' + 1] = sum_{e<N}
@@ -456,6 +491,7 @@ __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
   int* s_center = s_dyn + g.T;
   float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);
   int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);
+  int* s_ebase = s_bin + sumW;
   const int k = k0 + blockIdx.y;
   double2 tr[F::NPA][F::NTW];
   F::load_twiddles(tr, twM, 2);   // the H-point twiddles: every second entry of the M table
@@ -496,12 +532,7 @@ __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
       for (int i = threadIdx.x; i < g.T * 64; i += F::threads) s_acc[i] = 0.f;
     if (Ywh) {
       __syncthreads();
-      // window rows in split order: each window's even-bin rows first, then the odd ones
-      for (int r = threadIdx.x; r < sumW; r += F::threads) {
-        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-        const int st = s_start[t], ne = (g.win[t] + ((st & 1) ? 0 : 1)) >> 1;
-        s_bin[r - i + ((((st + i) & 1) ? ne : 0) + (i >> 1))] = (st + i) & (M - 1);
-      }
+      split_row_lists<M>(g, s_start, rowtab, sumW, s_bin, s_ebase, F::threads);
     }
   }
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -524,15 +555,15 @@ __global__ __launch_bounds__(fft_threads(LOGH, LOGH)) void k_beamspace_x2(
       }
       F::template run<false>(v, lds, tr);
       if (Ywh) {
-        for (int r = threadIdx.x; r < sumW; r += F::threads) {
-          const int m = s_bin[r];
-          if ((m & 1) == par) {
-            float2 hi;
-            uint32_t lo;
-            ext_split(cscale(lds[F::addr(0, m >> 1)], scale), hi, lo);
-            Ywh[o0 + r] = hi;
-            Ywl[o0 + r] = lo;
-          }
+        const int ne = s_ebase[g.T], cnt = par ? sumW - ne : ne;
+        const int* lst = s_bin + (par ? ne : 0);
+        for (int q = threadIdx.x; q < cnt; q += F::threads) {
+          const int pk = lst[q], r = pk >> kHalfBinBits;
+          float2 hi;
+          uint32_t lo;
+          ext_split(cscale(lds[F::addr(0, pk & ((1 << kHalfBinBits) - 1))], scale), hi, lo);
+          Ywh[o0 + r] = hi;
+          Ywl[o0 + r] = lo;
         }
       }
       if (prof && b < L) {
@@ -610,9 +641,34 @@ struct Fft4k {
     }
   }
 
+  // input r times exp(-i pi r / 16): the first pass's share of the half-bin shift (below)
+  __device__ __forceinline__ static void shift_first(double2 (&v)[16]) {
+    constexpr double c[9] = {1.0, 0.98078528040323044913, 0.92387953251128675613,
+                             0.83146961230254523708, 0.70710678118654752440,
+                             0.55557023301960222474, 0.38268343236508977173,
+                             0.19509032201612826785, 0.0};
+#pragma unroll
+    for (int r = 1; r < 16; ++r) {
+      if (r == 8) {
+        v[r] = cmul_mj(v[r]);
+      } else {
+        // cos(pi r / 16) and sin(pi r / 16) from the first quadrant
+        const double cr = r < 8 ? c[r] : -c[16 - r], sr = r < 8 ? c[8 - r] : c[r - 8];
+        v[r] = cmul(v[r], make_double2(cr, -sr));
+      }
+    }
+  }
+
   // v = this thread's inputs x[j + 256 r]; w1 = exp(-2 pi i (j mod 16) / 256), w2 =
   // exp(-2 pi i (j mod 256) / 4096).  On return lds holds the transform in natural order
   // (position pos(m)), visible to every thread.
+  //
+  // Half-bin shift: the transform at frequencies m + 1/2, sum_e x[e] exp(-2 pi i e (m + 1/2) /
+  // 4096), is the same three passes with input r of the first pass times exp(-i pi r / 16)
+  // (shift_first) and the bases w1 = exp(-2 pi i (2 (j mod 16) + 1) / 512), w2 = exp(-2 pi i
+  // (2 (j mod 256) + 1) / 8192): the factor exp(-i pi e / 4096) of element e = j + 256 r splits
+  // into exp(-i pi r / 16) and a factor common to butterfly j, which commutes with its DFT and
+  // moves into the next pass's twiddle base, where it leaves no common factor after the third.
   __device__ __forceinline__ static void run(double2 (&v)[16], double2* lds, double2 w1,
                                              double2 w2) {
     const int j = threadIdx.x;
@@ -653,11 +709,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   int* s_center = s_dyn + g.T;
   float* s_acc = reinterpret_cast<float*>(s_dyn + 2 * g.T);
   int* s_bin = s_dyn + 2 * g.T + (prof ? 64 * g.T : 0);
+  int* s_ebase = s_bin + sumW;
   const int k = k0 + blockIdx.y;
   const int j = threadIdx.x;
-  const double2 w1 = twM[(j & 15) * 32];
-  const double2 w2 = twM[(j & 255) * 2];
-  const double2 w0 = twM[j], w256 = twM[256];
+  // twiddle bases of the even-bin transform and of the odd-bin one (half-bin shift)
+  const double2 w1e = twM[(j & 15) * 32], w2e = twM[(j & 255) * 2];
+  const double2 w1o = twM[(2 * (j & 15) + 1) * 16], w2o = twM[2 * (j & 255) + 1];
   auto fetch = [&](int b, float2 (&vh)[16], uint32_t (&vl)[16]) {
     const int64_t base = ((int64_t)k * B + b) * N;
 #pragma unroll
@@ -686,13 +743,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       for (int i = threadIdx.x; i < g.T * 64; i += Fft4k::threads) s_acc[i] = 0.f;
     if (Ywh) {
       __syncthreads();
-      // window rows in split order: each window's even-bin rows first, then the odd ones, so
-      // that each half writes whole runs of rows
-      for (int r = threadIdx.x; r < sumW; r += Fft4k::threads) {
-        const int t = rowtab[r] >> 8, i = rowtab[r] & 255;
-        const int st = s_start[t], ne = (g.win[t] + ((st & 1) ? 0 : 1)) >> 1;
-        s_bin[r - i + ((((st + i) & 1) ? ne : 0) + (i >> 1))] = (st + i) & (M - 1);
-      }
+      split_row_lists<M>(g, s_start, rowtab, sumW, s_bin, s_ebase, Fft4k::threads);
     }
   }
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
@@ -702,28 +753,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       double2 v[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) v[r] = ext_join(rh[r], rl[r]);
-      if (par) {
-        // X[e] w_M^e for the odd bins, e = j + 256 r: w_M^j times the powers of w_M^256
-        double2 t = w0, ws = w256;
-        asm volatile("" : "+v"(t.x), "+v"(t.y), "+v"(ws.x), "+v"(ws.y));
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          v[r] = cmul(v[r], t);
-          if (r < 15) t = cmul(t, ws);
-        }
-      }
+      if (par) Fft4k::shift_first(v);
       if (par && b + (int)gridDim.x < B) fetch(b + gridDim.x, rh, rl);
-      Fft4k::run(v, lds, w1, w2);
+      Fft4k::run(v, lds, par ? w1o : w1e, par ? w2o : w2e);
       if (Ywh) {
-        for (int r = threadIdx.x; r < sumW; r += Fft4k::threads) {
-          const int m = s_bin[r];
-          if ((m & 1) == par) {
-            float2 hi;
-            uint32_t lo;
-            ext_split(cscale(lds[Fft4k::pos(m >> 1)], scale), hi, lo);
-            Ywh[o0 + r] = hi;
-            Ywl[o0 + r] = lo;
-          }
+        const int ne = s_ebase[g.T], cnt = par ? sumW - ne : ne;
+        const int* lst = s_bin + (par ? ne : 0);
+        for (int q = threadIdx.x; q < cnt; q += Fft4k::threads) {
+          const int pk = lst[q], r = pk >> kHalfBinBits;
+          float2 hi;
+          uint32_t lo;
+          ext_split(cscale(lds[Fft4k::pos(pk & ((1 << kHalfBinBits) - 1))], scale), hi, lo);
+          Ywh[o0 + r] = hi;
+          Ywl[o0 + r] = lo;
         }
       }
       if (prof && b < L) {
@@ -1083,7 +1125,7 @@ static hipError_t beam_launch_x2(const float2* Xh, const uint32_t* Xl, float2* Y
   size_t shm = sizeof(double2) * (size_t)F::lds_complex;
   if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x2<LOGH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1112,7 +1154,7 @@ static hipError_t beam_launch_x16(const float2* Xh, const uint32_t* Xl, float2* 
   size_t shm = sizeof(double2) * (size_t)Fft4k::n;
   if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x16,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -247,15 +247,15 @@ __device__ __forceinline__ void dftR_zh(V* v) {
 // half of a 32-bit word, imaginary part in the high half.  hi + lo carries the value to a
 // relative error of at most about 2^-33 (lo <= 2^-25 |v|, BF16 keeps 8 significant bits),
 // against 2^-25 for FP32 alone.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-}
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
+// hi = v rounded to FP32, lo = the two remainders rounded to BF16 (nearest, ties to even; the
+// real part in the low half): one packed conversion instruction on gfx950
 __device__ __forceinline__ void ext_split(double2 v, float2& hi, uint32_t& lo) {
   hi = make_float2((float)v.x, (float)v.y);
-  const float rx = (float)(v.x - (double)hi.x), ry = (float)(v.y - (double)hi.y);
-  lo = bf16_rne_bits(rx) | (bf16_rne_bits(ry) << 16);
+  const f32x2_t r = {(float)(v.x - (double)hi.x), (float)(v.y - (double)hi.y)};
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2_t));
 }
 
 __device__ __forceinline__ double2 ext_join(float2 hi, uint32_t lo) {
