@@ -308,7 +308,10 @@ __global__ __launch_bounds__(fft_threads(LOGK, LOGT)) void k_channelize_x(
         ext_split(cscale(lds[F::addr(e, k)], scale), hi, lo);
         const int64_t o = ((int64_t)k * B + b) * N + e0 + e;
         Xh[o] = hi;
-        Xl[o] = lo;
+        // a workgroup's remainders of one (subband, block) row are 4 TE bytes, half a cache
+        // line when TE = 16: streamed past the cache (non-temporal) these partial-line writes
+        // cost less than through it
+        __builtin_nontemporal_store(lo, &Xl[o]);
       }
     }
     __syncthreads();   // the next block's first pass overwrites lds
@@ -431,6 +434,10 @@ __global__ __launch_bounds__(fft_threads(LOGM, LOGT)) void k_beamspace_x(
     for (int idx = threadIdx.x; idx < g.T * 64; idx += F::threads) dst[idx] = s_acc[idx];
   }
 }
+
+// Fourth word of a raw (untyped, stride 0) buffer descriptor on gfx9-family chips: 32-bit data
+// format; the record count is then in bytes and a load past it returns zero.
+constexpr int kRawBufferFlags = 0x00020000;
 
 // Half-bin index field of a window-row list entry of the split-half kernels (M <= 8192).
 constexpr int kHalfBinBits = 12;
@@ -628,16 +635,23 @@ struct Fft4k {
     for (int r = 0; r < 16; ++r) v[r] = lds[pos(j + 256 * r)];
   }
 
-  // input r times w^r, the powers formed by repeated products (FP64).  The empty register
-  // constraint keeps the powers inside the caller's loop (hoisted out of it, as loop
-  // invariants, they would take 60 registers per pass).
+  // input r times w^r (FP64).  The powers follow the three-term recurrence w^r = 2 Re(w)
+  // w^(r-1) - w^(r-2) of cos and sin, applied to the real and imaginary parts alike (two FMAs
+  // per power against four for a complex product; for r <= 15 its rounding error stays near
+  // r^2 / 2 units in the last place).  The empty register constraint keeps the powers inside
+  // the caller's loop (hoisted out of it, as loop invariants, they would take 60 registers
+  // per pass).
   __device__ __forceinline__ static void twiddle(double2 (&v)[16], double2 w) {
     asm volatile("" : "+v"(w.x), "+v"(w.y));
-    double2 t = w;
+    const double c2 = 2.0 * w.x;
+    double2 t0 = make_double2(1.0, 0.0), t1 = w;
+    v[1] = cmul(v[1], t1);
 #pragma unroll
-    for (int r = 1; r < 16; ++r) {
-      v[r] = cmul(v[r], t);
-      if (r < 15) t = cmul(t, w);
+    for (int r = 2; r < 16; ++r) {
+      const double2 t2 = make_double2(fma(c2, t1.x, -t0.x), fma(c2, t1.y, -t0.y));
+      v[r] = cmul(v[r], t2);
+      t0 = t1;
+      t1 = t2;
     }
   }
 
@@ -715,17 +729,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   // twiddle bases of the even-bin transform and of the odd-bin one (half-bin shift)
   const double2 w1e = twM[(j & 15) * 32], w2e = twM[(j & 255) * 2];
   const double2 w1o = twM[(2 * (j & 15) + 1) * 16], w2o = twM[2 * (j & 255) + 1];
+  // one snapshot row x[e], e = j + 256 r, through buffer descriptors bounded at the row's N
+  // elements: the hardware returns zero for e >= N (the zero padding), with no branch
   auto fetch = [&](int b, float2 (&vh)[16], uint32_t (&vl)[16]) {
     const int64_t base = ((int64_t)k * B + b) * N;
+    const __amdgpu_buffer_rsrc_t dh =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(Xh + base), 0, N * 8, kRawBufferFlags);
+    const __amdgpu_buffer_rsrc_t dl =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(Xl + base), 0, N * 4, kRawBufferFlags);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int e = j + 256 * r;
-      vh[r] = make_float2(0.f, 0.f);
-      vl[r] = 0u;
-      if (e < N) {
-        vh[r] = Xh[base + e];
-        vl[r] = Xl[base + e];
-      }
+      vh[r] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(dh, e * 8, 0, 0));
+      vl[r] = __builtin_amdgcn_raw_buffer_load_b32(dl, e * 4, 0, 0);
     }
   };
   float2 rh[16];
