@@ -147,7 +147,11 @@ int64_t wbm_plan_workspace_bytes(const wbm_plan* plan);
  *                               WBM_PAIR_WAVE or WBM_PAIR_BLOCK only.
  *   overlap_chunks              1 (no overlap), 2, 4 or 8; K must be a multiple of 8 x chunks.
  * Errors: WBM_ERR_ARG for a NULL plan or a value outside those sets, WBM_ERR_UNSUPPORTED for
- * a pair kernel the precision or the shape does not allow or a chunk count K does not allow.
+ * a pair kernel the precision or the shape does not allow, a chunk count K does not allow, or
+ * a tile whose transform needs more than the 160 KiB of LDS of a compute unit at this K or M
+ * (the extended channelizer's 2^13 tile at K = 2).  A call whose window rows do not fit beside
+ * the pinned spatial-DFT tile runs at, and moves the plan to, the largest smaller tile where
+ * they do (see wbm_beamform).
  * A pinned choice drops a captured graph (recaptured on the next graph call); the WBM_PREC_F32
  * choice also fixes the pair kernel of the planar-array path (wbm_beamform_upa).
  * wbm_plan_get_tuning writes the current choice of a precision (NULL pointers skipped). */
@@ -172,7 +176,15 @@ wbm_status wbm_plan_get_tuning(const wbm_plan* plan, int32_t precision, int32_t*
  *           negative; the bins are taken mod M).
  *   info    device [T][K] int32 or NULL: 0, or j > 0 when the pair's factorisation failed at
  *           pivot j-1 (mixed forms: plus WBM_INFO_ROUTED when the FP64 path was taken).
- *   stream  hipStream_t or NULL. */
+ *   stream  hipStream_t or NULL.
+ * Window rows: the windowed spatial DFT of every form but WBM_FORM_PLAIN holds the call's
+ * window-row tables in LDS beside its transform tile (4 bytes per window row, 8 per target, 4
+ * more per target with M = 8192, N <= 4096 in extended precision; 256 more per target for the
+ * learned form's profiles).  A call whose tables do not fit beside the tuned tile runs at, and
+ * moves the plan to, the largest smaller tile where they do; at M = 8192 (FP32, or extended
+ * with N <= 4096) every tile is 64 KiB, which leaves room for about 24 000 rows.
+ * Errors: WBM_ERR_ARG for NULL pointers or a value outside the ranges above, WBM_ERR_SHAPE for T
+ * outside [1, max_targets] or window rows that fit no tile (nothing is launched). */
 wbm_status wbm_beamform(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                         const int32_t* win, int32_t T, double loading, int32_t form,
                         wbm_c32* out, wbm_c32* weights, int32_t* starts, int32_t* info,
@@ -344,7 +356,7 @@ wbm_status wbm_full_mvdr(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
  * for the mixed forms the MFMA pair kernel and the FP64 re-solve of the routed windows) once
  * untimed and then `reps` times back to back on `stream` between two HIP events, and writes the
  * average milliseconds per launch to stage_ms (host [4]).  Blocks until the stream has
- * drained. */
+ * drained.  Window rows as in wbm_beamform (WBM_ERR_SHAPE when they fit no tile). */
 wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                            const int32_t* win, int32_t T, double loading, int32_t precision,
                            int32_t reps, double* stage_ms, void* stream);
@@ -366,7 +378,8 @@ wbm_status wbm_stage_times(wbm_plan* plan, const wbm_c32* x, const double* az_ra
 #define WBM_PROFILE_BINS 64
 
 /* Training power profiles of every pair: feat device [T][K][64] float (the network input).
- * noise_power = sigma^2 > 0. */
+ * noise_power = sigma^2 > 0.  The spatial DFT keeps 264 bytes per target in LDS beside its
+ * tile; WBM_ERR_SHAPE, with nothing launched, when they fit no tile (as in wbm_beamform). */
 wbm_status wbm_profiles(wbm_plan* plan, const wbm_c32* x, const double* az_rad, int32_t T,
                         double noise_power, float* feat, void* stream);
 
@@ -375,7 +388,7 @@ wbm_status wbm_profiles(wbm_plan* plan, const wbm_c32* x, const double* az_rad, 
  * of pair_win[t][k] bins (device int32) and the loading pair_loading[t][k] (device float,
  * >= 0).  A width outside [1, win[t]] or of the other parity than win[t] is rejected: that
  * pair solves the full window of win[t] bins and its info entry carries WBM_INFO_WIDTH.
- * Outputs as in wbm_beamform. */
+ * Outputs, window rows and errors as in wbm_beamform. */
 wbm_status wbm_beamform_pairs(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                               const int32_t* win, int32_t T, const int32_t* pair_win,
                               const float* pair_loading, wbm_c32* out, wbm_c32* weights,
@@ -385,7 +398,8 @@ wbm_status wbm_beamform_pairs(wbm_plan* plan, const wbm_c32* x, const double* az
  * Needs w_max >= 33.  params device [WBM_MLP_PARAMS].  A pair whose network output is not
  * finite uses fallback_win / fallback_loading (odd fallback_win <= 33).  pair_win,
  * pair_loading (device [T][K], may be NULL) receive the decisions; fallback (device [T][K]
- * int32, may be NULL) is 1 where the fallback was used. */
+ * int32, may be NULL) is 1 where the fallback was used.  Window rows (33 per target) and the
+ * profiles' LDS as in wbm_beamform and wbm_profiles: WBM_ERR_SHAPE when they fit no tile. */
 wbm_status wbm_beamform_learned(wbm_plan* plan, const wbm_c32* x, const double* az_rad,
                                 int32_t T, const float* params, double noise_power,
                                 int32_t fallback_win, double fallback_loading, wbm_c32* out,

@@ -437,6 +437,30 @@ void set_beam_tile(wbm_plan* p, int prec, int logtile) {
   t.nbt = (p->B + t.TB - 1) / t.TB;
 }
 
+// LDS of the windowed spatial DFT at this tile for a call with T targets and sumW window rows.
+size_t beam_lds(const wbm_plan* p, int prec, int logtile, int T, int sumW, bool windows,
+                bool prof) {
+  return wbm::beamspace_lds_bytes(prec == kExt, p->cfg.n_elem, p->cfg.m_fft, logtile, T, sumW,
+                                  windows, prof);
+}
+
+// The spatial DFT holds a call's window-row tables in LDS beside its transform tile: keep the
+// tuned tile if they fit there, else move the plan to the largest smaller tile where they do
+// (the pair kernels follow the tile's window layout); WBM_ERR_SHAPE if none does.
+wbm_status fit_beam_tile(wbm_plan* p, int prec, int T, int sumW, bool windows, bool prof) {
+  const int cur = p->tune[prec].beam_logtile;
+  if (beam_lds(p, prec, cur, T, sumW, windows, prof) <= wbm::kLdsBytes) return WBM_OK;
+  for (int lt = cur - 1; lt >= (prec == kExt ? 10 : 11); --lt) {
+    if (beam_lds(p, prec, lt, T, sumW, windows, prof) <= wbm::kLdsBytes) {
+      set_beam_tile(p, prec, lt);
+      return WBM_OK;
+    }
+  }
+  return fail(WBM_ERR_SHAPE, "the window rows of this call (" + std::to_string(sumW) +
+                                 " rows of " + std::to_string(T) +
+                                 " targets) do not fit the spatial DFT's LDS at any tile");
+}
+
 bool logtile_ok(int prec, int logtile) {
   return prec == kExt ? wbm::fft_x_logtile_supported(logtile)
                       : wbm::fft_logtile_supported(logtile);
@@ -667,7 +691,8 @@ hipError_t autotune(wbm_plan* p, int prec, const float2* x, int T, int sumW, dou
   const std::string key = tune_key(p, prec);
   int chan = 12, beam = 12, thr = WBM_PAIR_BLOCK, ovl = 1;
   if (cache_lookup(key, prec, &chan, &beam, &thr, &ovl) && overlap_supported(p, ovl) &&
-      pair_ok(p, prec, thr)) {
+      pair_ok(p, prec, thr) &&
+      wbm::channelize_lds_bytes(prec == kExt, p->cfg.k_sub, chan) <= wbm::kLdsBytes) {
     tn.chan_logtile = chan;
     set_beam_tile(p, prec, beam);
     tn.pair_threads = thr;
@@ -676,21 +701,28 @@ hipError_t autotune(wbm_plan* p, int prec, const float2* x, int T, int sumW, dou
   }
   float best_c = 1e30f, best_b = 1e30f;
   const int lt0 = prec == kExt ? 10 : 11;
+  // tiles beyond the LDS at this shape (the extended channelizer at K = 2; a spatial DFT whose
+  // tile leaves no room for this call's window rows) are not candidates
   for (int lt = lt0; lt <= 13; ++lt) {
     float ms;
-    tn.chan_logtile = lt;
-    hipError_t e = time_best([&]() { return enqueue_channelize(p, prec, x, st); }, st, &ms);
-    if (e != hipSuccess) return e;
-    if (ms < best_c) {
-      best_c = ms;
-      chan = lt;
+    if (wbm::channelize_lds_bytes(prec == kExt, p->cfg.k_sub, lt) <= wbm::kLdsBytes) {
+      tn.chan_logtile = lt;
+      hipError_t e = time_best([&]() { return enqueue_channelize(p, prec, x, st); }, st, &ms);
+      if (e != hipSuccess) return e;
+      if (ms < best_c) {
+        best_c = ms;
+        chan = lt;
+      }
     }
-    set_beam_tile(p, prec, lt);
-    e = time_best([&]() { return enqueue_beamspace_windows(p, prec, T, sumW, st); }, st, &ms);
-    if (e != hipSuccess) return e;
-    if (ms < best_b) {
-      best_b = ms;
-      beam = lt;
+    if (beam_lds(p, prec, lt, T, sumW, true, false) <= wbm::kLdsBytes) {
+      set_beam_tile(p, prec, lt);
+      hipError_t e =
+          time_best([&]() { return enqueue_beamspace_windows(p, prec, T, sumW, st); }, st, &ms);
+      if (e != hipSuccess) return e;
+      if (ms < best_b) {
+        best_b = ms;
+        beam = lt;
+      }
     }
   }
   tn.chan_logtile = chan;
@@ -737,14 +769,15 @@ hipError_t autotune(wbm_plan* p, int prec, const float2* x, int T, int sumW, dou
 // The workspace and the launch configuration of the fused sequence in precision prec, tuned
 // on this call's data on first use.
 wbm_status ready_fused(wbm_plan* p, int prec, const float2* x, int T, int sumW, double loading,
-                       hipStream_t st) {
+                       hipStream_t st, bool prof = false) {
   wbm_status s;
   if (prec == kExt && (s = ensure_ext(p))) return s;
+  if ((s = fit_beam_tile(p, prec, T, sumW, true, prof))) return s;
   if (!p->tune[prec].tuned) {
     if ((s = ensure_prof(p))) return s;
     WBM_HIP(autotune(p, prec, x, T, sumW, loading, st), "autotune");
   }
-  return WBM_OK;
+  return fit_beam_tile(p, prec, T, sumW, true, prof);
 }
 
 static_assert(WBM_PAIR_MFMA == wbm::kPairMfma && WBM_PAIR_RESIDENT == wbm::kPairResident,
@@ -805,6 +838,10 @@ wbm_status wbm_plan_set_tuning(wbm_plan* p, int32_t precision, int32_t chan, int
     return fail(WBM_ERR_ARG, "overlap_chunks must be 1, 2, 4 or 8");
   if (!overlap_supported(p, overlap))
     return fail(WBM_ERR_UNSUPPORTED, "overlap_chunks needs K to be a multiple of 8 * chunks");
+  if (wbm::channelize_lds_bytes(prec == kExt, p->cfg.k_sub, chan) > wbm::kLdsBytes ||
+      beam_lds(p, prec, beam, 0, 0, false, false) > wbm::kLdsBytes)
+    return fail(WBM_ERR_UNSUPPORTED, "this FFT tile needs more LDS than a compute unit has at "
+                                     "this K / M and precision");
   Tuning& tn = p->tune[prec];
   tn.chan_logtile = chan;
   set_beam_tile(p, prec, beam);
@@ -1547,6 +1584,7 @@ wbm_status wbm_profiles(wbm_plan* p, const wbm_c32* x, const double* az_rad, int
   if ((s = upload_desc(p, az_rad, nullptr, T, st, &sumW))) return s;
   if ((s = ensure_learned(p))) return s;
   if ((s = ensure_ext(p))) return s;
+  if ((s = fit_beam_tile(p, kExt, T, sumW, false, true))) return s;
   WBM_HIP(enqueue_profiles(p, reinterpret_cast<const float2*>(x), T, sumW, false,
                            (float)noise_power, feat, st),
           "profile launch");
@@ -1605,7 +1643,7 @@ wbm_status wbm_beamform_learned(wbm_plan* p, const wbm_c32* x, const double* az_
   if ((s = upload_desc(p, az_rad, win.data(), T, st, &sumW))) return s;
   if ((s = ensure_learned(p))) return s;
   const float2* xx = reinterpret_cast<const float2*>(x);
-  if ((s = ready_fused(p, kExt, xx, T, sumW, fallback_loading, st))) return s;
+  if ((s = ready_fused(p, kExt, xx, T, sumW, fallback_loading, st, true))) return s;
   const int n = T * c.k_sub;
   int* pw = pair_win ? pair_win : p->pw;
   float* pd = pair_loading ? pair_loading : p->pdelta;

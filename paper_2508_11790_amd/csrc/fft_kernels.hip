@@ -1047,6 +1047,7 @@ static hipError_t beam_launch_zh(const float2* X, float2* Y, float2* Yw, int N, 
   if (Yw || prof) shm = sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
   if (Yw) shm += sizeof(int) * (size_t)sumW;
+  if (sizeof(float2) * (size_t)F::lds_complex + shm > kLdsBytes) return hipErrorInvalidValue;
   if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
     // beyond the default 64 KiB per workgroup: ask for exactly the dynamic part
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace<LOGM, LOGT, ZH>,
@@ -1083,6 +1084,7 @@ static hipError_t chan_launch_x(const float2* x, float2* Xh, uint32_t* Xl, int N
                                 const double2* twK, const double2* hb, hipStream_t s) {
   using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK), double2>;
   const size_t shm = sizeof(double2) * (size_t)F::lds_complex;
+  if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_channelize_x<LOGK, LOGT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1111,6 +1113,7 @@ static hipError_t beam_launch_x_zh(const float2* Xh, const uint32_t* Xl, float2*
   if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
   if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x<LOGM, LOGT, ZH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1142,6 +1145,7 @@ static hipError_t beam_launch_x2(const float2* Xh, const uint32_t* Xl, float2* Y
   if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
   if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
+  if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x2<LOGH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1171,6 +1175,7 @@ static hipError_t beam_launch_x16(const float2* Xh, const uint32_t* Xl, float2* 
   if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
   if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
   if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
+  if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x16,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -1552,6 +1557,119 @@ int beamspace_tile_log(int M, int logtile) { return fft_tile(ilog2(M), logtile) 
 int beamspace_tiles(int M, int B, int logtile) {
   const int tb = 1 << beamspace_tile_log(M, logtile);
   return (B + tb - 1) / tb;
+}
+
+template <int LOGK, int LOGT, typename V>
+static size_t chan_tile_bytes() {
+  using F = Fft<LOGK, fft_tile(LOGK, LOGT), chan_pad(fft_tile(LOGK, LOGT), LOGK), V>;
+  return sizeof(V) * (size_t)F::lds_complex;
+}
+
+size_t channelize_lds_bytes(bool ext, int K, int logtile) {
+  if (!(ext ? fft_x_logtile_supported(logtile) : fft_logtile_supported(logtile)) || K < 2 ||
+      K > 8192 || (K & (K - 1)))
+    return SIZE_MAX;
+  const int lk = ilog2(K);
+  size_t bytes = SIZE_MAX;
+#define C(LG, TT)                                                                     \
+  case LG:                                                                            \
+    bytes = ext ? chan_tile_bytes<LG, TT, double2>() : chan_tile_bytes<LG, TT, float2>(); \
+    break;
+  switch (logtile) {
+    case 10:
+      switch (lk) { WBM_LOG_CASES(C, 10) }
+      break;
+    case 11:
+      switch (lk) { WBM_LOG_CASES(C, 11) }
+      break;
+    case 12:
+      switch (lk) { WBM_LOG_CASES(C, 12) }
+      break;
+    case 13:
+      switch (lk) { WBM_LOG_CASES(C, 13) }
+      break;
+  }
+#undef C
+  return bytes;
+}
+
+template <int LOGM, int LOGT>
+static size_t beam_tile_bytes_f32() {
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
+  return sizeof(float2) * (size_t)F::lds_complex;
+}
+
+// the transform tile of the kernel beam_launch_x runs; *split: a split-half kernel, whose row
+// tables carry T + 1 more ints
+template <int LOGM, int LOGT>
+static size_t beam_tile_bytes_x(int N, bool* split) {
+  *split = false;
+  if constexpr (LOGM >= 13) {
+    if (beamspace_x_split_rows(N, 1 << LOGM)) {
+      *split = true;
+      if constexpr (LOGM == 13) {
+        if (LOGT == 13) return sizeof(double2) * (size_t)Fft4k::n;
+      }
+      using H = Fft<LOGM - 1, LOGM - 1, beam_pad(LOGM - 1, LOGM - 1), double2>;
+      return sizeof(double2) * (size_t)H::lds_complex;
+    }
+  }
+  using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM), double2>;
+  return sizeof(double2) * (size_t)F::lds_complex;
+}
+
+size_t beamspace_lds_bytes(bool ext, int N, int M, int logtile, int T, int sumW, bool windows,
+                           bool prof) {
+  if (!(ext ? fft_x_logtile_supported(logtile) : fft_logtile_supported(logtile)) || M < 2 ||
+      M > 8192 || (M & (M - 1)))
+    return SIZE_MAX;
+  const int lm = ilog2(M);
+  size_t tile = 0;
+  bool split = false;
+  if (ext) {
+#define C(LG, TT)                                \
+  case LG:                                       \
+    tile = beam_tile_bytes_x<LG, TT>(N, &split); \
+    break;
+    switch (logtile) {
+      case 10:
+        switch (lm) { WBM_LOG_CASES(C, 10) }
+        break;
+      case 11:
+        switch (lm) { WBM_LOG_CASES(C, 11) }
+        break;
+      case 12:
+        switch (lm) { WBM_LOG_CASES(C, 12) }
+        break;
+      case 13:
+        switch (lm) { WBM_LOG_CASES(C, 13) }
+        break;
+    }
+#undef C
+  } else {
+#define C(LG, TT)                              \
+  case LG:                                     \
+    tile = beam_tile_bytes_f32<LG, TT>();      \
+    break;
+    switch (logtile) {
+      case 11:
+        switch (lm) { WBM_LOG_CASES(C, 11) }
+        break;
+      case 12:
+        switch (lm) { WBM_LOG_CASES(C, 12) }
+        break;
+      case 13:
+        switch (lm) { WBM_LOG_CASES(C, 13) }
+        break;
+    }
+#undef C
+  }
+  if (!tile) return SIZE_MAX;
+  size_t tables = 0;
+  if (windows || prof) tables += sizeof(int) * 2 * (size_t)T;
+  if (prof) tables += sizeof(float) * 64 * (size_t)T;
+  if (windows) tables += sizeof(int) * ((size_t)sumW + (split ? (size_t)T + 1 : 0));
+  return tile + tables;
 }
 
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,

@@ -39,6 +39,18 @@ hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M
 // Snapshot tiles of the beamspace kernel for M, B at a tile size.
 int beamspace_tiles(int M, int B, int logtile);
 
+// LDS a workgroup may use (gfx950: 160 KiB per compute unit, all of it to one workgroup).
+constexpr size_t kLdsBytes = 160 * 1024;
+// LDS bytes of one workgroup of the channelizer (launch_channelize / _x) at this tile; SIZE_MAX
+// for a tile the precision does not support.
+size_t channelize_lds_bytes(bool ext, int K, int logtile);
+// LDS bytes of one workgroup of the spatial DFT that launch_beamspace (ext = false) or
+// launch_beamspace_x (ext = true) runs at this tile: the transform tile, and for a call with T
+// targets and sumW window rows the window-row tables (windows) and the profile accumulators
+// (prof).  SIZE_MAX for a tile the precision does not support.
+size_t beamspace_lds_bytes(bool ext, int N, int M, int logtile, int T, int sumW, bool windows,
+                           bool prof);
+
 // Extended-precision channelizer and windowed spatial DFT (FP64 arithmetic, hi + lo storage:
 // X as Xh / Xl [K][B][N], windows as Ywh / Ywl [K][nbt][sumW][TB]); tiles of 2^10 .. 2^13
 // complex (fft_x_logtile_supported), the beamspace tile in snapshots as for launch_beamspace.

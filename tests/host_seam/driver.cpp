@@ -371,6 +371,77 @@ static int plant(const char* what) {
   return 0;
 }
 
+// Calls whose window-row tables outgrow the spatial DFT's LDS: a call that fits only smaller
+// tiles than the tuned (or pinned) one runs at the largest that fits, and the plan reports it;
+// a call that fits none is rejected with WBM_ERR_SHAPE before any launch; the autotuner leaves
+// out the tiles that cannot hold the call's rows.
+static void window_row_limits(hipStream_t st) {
+  const int N = 64, M = 2048, K = 2, L = 2, Lt = 1, TMAX = 1100, W = 64;
+  const long S = (long)(L + Lt) * K;
+  for (int tuned = 0; tuned < 2; ++tuned) {
+    if (!tuned) setenv("WBM_AUTOTUNE", "0", 1);
+    wbm_config cfg = config(N, M, K, L, Lt, TMAX, W, 0);
+    wbm_plan* p = nullptr;
+    EXPECT(wbm_plan_create(&cfg, &p), WBM_OK);
+    if (!p) return;
+    auto* x = dev<wbm_c32>((size_t)N * S);
+    auto* out = dev<wbm_c32>((size_t)TMAX * K * Lt);
+    auto* w = dev<wbm_c32>((size_t)TMAX * K * W);
+    auto* starts = dev<int32_t>((size_t)TMAX * K);
+    auto* info = dev<int32_t>((size_t)TMAX * K);
+    auto* feat = dev<float>((size_t)TMAX * K * 64);
+    std::vector<double> az(TMAX);
+    std::vector<int32_t> win(TMAX, W);
+    for (int t = 0; t < TMAX; ++t) az[t] = -1.2 + 2.4 * t / (TMAX - 1);
+    // 320 targets x 64 bins = 20480 rows: the extended tile 2^13 (128 KiB transform tile) cannot
+    // hold them, 2^12 can
+    const int T1 = 320;
+    if (!tuned) {
+      // K = 2: the extended channelizer's 2^13 tile (4096 two-point rows, padded) exceeds 160 KiB
+      EXPECT(wbm_plan_set_tuning(p, WBM_PREC_EXT, 13, 12, WBM_PAIR_BLOCK, 1), WBM_ERR_UNSUPPORTED);
+      EXPECT(wbm_plan_set_tuning(p, WBM_PREC_EXT, 12, 13, WBM_PAIR_BLOCK, 1), WBM_OK);
+      EXPECT(wbm_plan_set_tuning(p, WBM_PREC_F32, 12, 13, WBM_PAIR_BLOCK, 1), WBM_OK);
+    }
+    for (int form : {WBM_FORM_FUSED, WBM_FORM_GRAPH, WBM_FORM_FUSED_F32, WBM_FORM_MIXED})
+      EXPECT(wbm_beamform(p, x, az.data(), win.data(), T1, 10.0, form, out, w, starts, info, st), WBM_OK);
+    int32_t chan = 0, beam = 0, pair = 0, ovl = 0;
+    EXPECT(wbm_plan_get_tuning(p, WBM_PREC_EXT, &chan, &beam, &pair, &ovl), WBM_OK);
+    if (beam > 12) {
+      std::fprintf(stderr, "line %d: extended beam tile %d holds 20480 window rows\n", __LINE__, beam);
+      g_fail = 1;
+    }
+    if (!tuned) {   // FP32 at 2^13 (64 KiB tile) holds them: the pinned tile stays
+      EXPECT(wbm_plan_get_tuning(p, WBM_PREC_F32, &chan, &beam, &pair, &ovl), WBM_OK);
+      if (beam != 13) {
+        std::fprintf(stderr, "line %d: FP32 beam tile moved to %d\n", __LINE__, beam);
+        g_fail = 1;
+      }
+    }
+    // 1100 x 64 = 70400 rows fit no tile: rejected, nothing launched
+    const long before = hip_stub_launches();
+    for (int form = WBM_FORM_FUSED; form <= WBM_FORM_GRAPH_F32; ++form)
+      EXPECT(wbm_beamform(p, x, az.data(), win.data(), TMAX, 10.0, form, out, w, starts, info, st),
+             WBM_ERR_SHAPE);
+    EXPECT(wbm_profiles(p, x, az.data(), TMAX, 1.0, feat, st), WBM_ERR_SHAPE);
+    std::vector<float> params(WBM_MLP_PARAMS, 0.f);
+    auto* dparams = dev<float>(WBM_MLP_PARAMS);
+    EXPECT(wbm_beamform_learned(p, x, az.data(), TMAX, dparams, 1.0, 9, 10.0, out, w, nullptr,
+                                nullptr, nullptr, starts, info, st),
+           WBM_ERR_SHAPE);
+    if (hip_stub_launches() != before) {
+      std::fprintf(stderr, "line %d: %ld launches for rejected calls\n", __LINE__,
+                   hip_stub_launches() - before);
+      g_fail = 1;
+    }
+    // and the plan still serves calls that fit
+    EXPECT(wbm_beamform(p, x, az.data(), win.data(), 8, 10.0, WBM_FORM_GRAPH, out, w, starts, info, st), WBM_OK);
+    EXPECT(wbm_plan_destroy(p), WBM_OK);
+    for (void* q : {(void*)x, (void*)out, (void*)w, (void*)starts, (void*)info, (void*)feat, (void*)dparams})
+      hipFree(q);
+    if (!tuned) unsetenv("WBM_AUTOTUNE");
+  }
+}
+
 int main(int argc, char** argv) {
   if (argc > 2 && std::string(argv[1]) == "--plant") return plant(argv[2]);
   if (argc > 1) setenv("WBM_AUTOTUNE_CACHE", argv[1], 1);
@@ -388,6 +459,7 @@ int main(int argc, char** argv) {
   planar_plan(st);
   shape_sweep(st);
   planar_sweep(st);
+  window_row_limits(st);
   EXPECT(wbm_plan_destroy(nullptr), WBM_OK);
   hipStreamDestroy(st);
   if (hip_stub_open_captures() != 0) {

@@ -7,6 +7,8 @@
 // into a capture is joined back before it ends.  Any violation prints a message and aborts.
 #include <hip/hip_runtime.h>
 
+#include <sanitizer/common_interface_defs.h>
+
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -43,6 +45,7 @@ std::set<ihipStream_t*> g_streams;
 
 [[noreturn]] void fail(const char* what) {
   std::fprintf(stderr, "hip stub: %s\n", what);
+  __sanitizer_print_stack_trace();   // the library call that broke the rule
   std::fflush(stderr);
   std::abort();
 }
