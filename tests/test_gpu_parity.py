@@ -432,6 +432,39 @@ def test_extended_precision_spatial_dft_at_8192_bins(torch, wb, beam_tile):
     plan.close()
 
 
+def test_window_rows_beyond_the_pinned_tile(torch, wb):
+    """320 targets of 64 bins at M = 2048 (20480 window rows): the extended spatial DFT's 2^13
+    tile (128 KiB of LDS) cannot hold their row table beside it, so a call with that tile pinned
+    runs at, and moves the plan to, 2^12, with the pair kernels following the smaller tile's
+    window layout; every target's weights on two subbands still match the oracle (fused, graph,
+    fused_f32 and mixed forms).  The FP32 2^13 tile (64 KiB) holds the table and stays."""
+    # jammer directions fixed: 320 targets leave no sin-space gap the random draw accepts
+    cfg = scenes.SceneConfig(name="rows", N=64, M=2048, K=4, L=160, Lt=16, T=320, W=64,
+                             n_jammers=2, jammer_az_deg=(20.0, -35.0),
+                             jammer_inr_db=(30.0, 40.0), seed=41)
+    sc = scenes.make_scene(cfg)
+    x32 = _x32(sc)
+    ks = [0, 3]
+    ref = _oracle(sc, x32, subbands=ks)
+    plan = _plan(wb, cfg, sc)
+    plan.set_tuning(12, 13, "block", 1, precision="ext")
+    plan.set_tuning(12, 13, "block", 1, precision="f32")
+    x = torch.from_numpy(x32).cuda()
+    for form in ("fused", "graph", "fused_f32", "mixed"):
+        res = dict(plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form))
+        torch.cuda.synchronize()
+        if form == "mixed":
+            info = res["info"].cpu().numpy()
+            assert np.all((info & ~wb.INFO_ROUTED) == 0), "Cholesky failures"
+            res["info"] = torch.zeros_like(res["info"])
+        st = compare_beamform(sc, ref, res, subbands=ks, ext=form in EXT_FORMS,
+                              tol_scale=None if form == "mixed" else 1.0)
+        log(f"  {form}: {st}")
+    assert plan.get_tuning("ext")[1] == 12
+    assert plan.get_tuning("f32")[1] == 13
+    plan.close()
+
+
 def test_identity_windowed_equals_full_dimensional(torch, wb):
     # W = M = N: the windowed beamspace MVDR equals element-space MVDR (Eq. 13 vs Eq. 20-21)
     cfg = scenes.SMALL.replace(M=16, W=16)
