@@ -93,6 +93,37 @@ def test_subband_ratio_half_bin_is_eq1(K):
     assert np.allclose(r - plain, beta / (2 * K), atol=1e-15)
 
 
+@pytest.mark.parametrize("K", [8, 32])
+@pytest.mark.parametrize("half_bin", [False, True])
+def test_subband_centre_is_the_frequency_of_a_tone_in_that_bin(K, half_bin):
+    # Sampling physics, not the oracle's formula: the complex baseband tone exp(j 2 pi nu n)
+    # with nu = (ks + off) / K cycles per sample (ks the bin's signed index, k - K above K/2
+    # with the Nyquist bin at -1/2; off = 1/2 for the half-bin centres of Eq. 1) is the RF
+    # frequency f_c + nu f_s, so a plane wave at that frequency advances by
+    # Omega = 2 pi (d / lambda_c) sin(az) (1 + beta nu) per element.  DFT orthogonality puts it
+    # wholly into bin k with value K^(1/2) exp(j Omega e); the oracle's steering at its subband
+    # ratio for bin k must carry the same phase progression.  Block b starts at sample bK, where
+    # the tone's phase is 2 pi nu K b (a multiple of pi: half-bin tones flip sign every block).
+    N, B, beta, dl, az = 6, 3, 0.2, 0.5, math.radians(25.0)
+    off = 0.5 if half_bin else 0.0
+    ratio = oracle.subband_freq_ratio(K, beta, half_bin)
+    n = np.arange(B * K)
+    for k in range(K):
+        ks = k if k < K // 2 else k - K
+        nu = (ks + off) / K
+        omega = 2.0 * math.pi * dl * math.sin(az) * (1.0 + beta * nu)
+        x = np.exp(1j * omega * np.arange(N))[:, None] * np.exp(2j * math.pi * nu * n)[None, :]
+        X = oracle.channelize(x, K, half_bin)
+        others = np.delete(X, k, axis=2)
+        assert np.max(np.abs(others)) < 1e-11
+        exact = math.sqrt(K) * np.exp(1j * omega * np.arange(N))
+        for b in range(B):
+            block = np.exp(2j * math.pi * nu * K * b)
+            assert np.max(np.abs(X[:, b, k] - block * exact)) < 1e-11
+        a = oracle.steering(N, oracle.spatial_frequency(math.sin(az), ratio[k], dl))
+        assert np.max(np.abs(math.sqrt(K) * a - exact)) < 1e-11
+
+
 @pytest.mark.parametrize("half_bin", [False, True])
 def test_generator_tone_lands_in_its_subband(half_bin):
     # A single noiseless source: channelized element 0 equals the generator's per-bin source
