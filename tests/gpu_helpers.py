@@ -60,7 +60,7 @@ def windowed_interference(scene, k, bins, ratio):
     return R
 
 
-NORTH_STAR_WEIGHT_ERR = 1e-5
+WEIGHT_ERR_BAR = 1e-5
 
 
 def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.1,
@@ -99,7 +99,7 @@ def compare_beamform(scene, ref, res, subbands=None, plain=False, sinr_bar_db=0.
             err = oracle.rel_weight_error(wg, wo)
             tol = weight_tol(kappa, plain, dr, unit)
             if ext:
-                assert err <= NORTH_STAR_WEIGHT_ERR, \
+                assert err <= WEIGHT_ERR_BAR, \
                     f"pair t={t} k={k}: weight error {err:.3e} > 1e-5 (kappa {kappa:.3e})"
             elif tol_scale is not None:   # None: the error is reported, not bounded
                 assert err <= tol * tol_scale, \
