@@ -60,6 +60,8 @@ def windowed_interference(scene, k, bins, ratio):
     return R
 
 
+# relative weight error ||w - w_oracle|| / ||w_oracle|| every pair of the extended-precision
+# forms must stay within (with SINR loss <= 0.1 dB)
 WEIGHT_ERR_BAR = 1e-5
 
 
