@@ -499,25 +499,20 @@ __device__ __forceinline__ int row_slot(const RowOrder& ro, int i) {
   return (((ro.s + ii) & 1) ? ro.ne : 0) + (ii >> 1);
 }
 
-// This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end, and
-// their offsets from the chunk's first element in the window layout (valid when chunks start
-// at multiples of CH: then a chunk never splits a tile block differently).  The mapping is the
-// same for every chunk.  Offsets count from the first row of the gathered window when rows
-// are in split order (ro.split), else from the pair's own first row.
+// This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end.  The
+// mapping is the same for every chunk.  fetch_chunk derives each element's offset in the
+// window layout from it (from the first row of the gathered window when rows are in split
+// order, ro.split, else from the pair's own first row).
 template <int PRE, int TH, int CH>
-__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off,
-                                          const RowOrder& ro = RowOrder()) {
-  const int TB = 1 << a.logTB;
+__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map) {
 #pragma unroll
   for (int m = 0; m < PRE; ++m) {
     const int e = threadIdx.x + m * TH;
     map[m] = -1;
-    off[m] = 0;
     if (e < W * CH) {
       int i, bb;
       chunk_elem<CH>(a, W, e, i, bb);
       map[m] = (i << 8) | bb;
-      off[m] = ((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1));
     }
   }
 }
@@ -527,17 +522,18 @@ __device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, in
 // also the BF16 remainders of the extended-precision windows (a.ywl, same layout) into prel.
 template <int PRE, bool EXT = false>
 __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const PairArgs& a,
-                                            int k, int woff, const int* map, const int* off,
-                                            bool aligned, int c0, int lim, float2* pre,
+                                            int k, int woff, const int* map, bool aligned,
+                                            int c0, int lim, float2* pre,
                                             uint32_t* prel = nullptr,
                                             const RowOrder& ro = RowOrder()) {
   const int TB = 1 << a.logTB;
   const int64_t ebase = (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
   const float2* base = Yw + ebase;
   if (aligned) {
-    // the chunk base is uniform; each element adds a 32-bit byte offset, kept opaque (empty
-    // register constraint) so that the compiler does not hoist PRE 64-bit addresses out of
-    // the chunk loops, where they would be spilled to scratch
+    // the chunk base is uniform; each element adds a 32-bit byte offset computed from an
+    // opaque copy (empty register constraint) of its packed position, so that the compiler
+    // neither hoists PRE addresses out of the chunk loops nor keeps PRE offsets live through
+    // them: registers the Gram needs
     const int64_t cofs = (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1));
     const char* cb = reinterpret_cast<const char*>(base + cofs);
     const char* cl = EXT ? reinterpret_cast<const char*>(a.ywl + ebase + cofs) : nullptr;
@@ -546,9 +542,12 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const
     for (int m = 0; m < PRE; ++m) {
       pre[m] = make_float2(0.f, 0.f);
       if constexpr (EXT) prel[m] = 0u;
-      uint32_t o = (uint32_t)off[m] << 3;
-      asm volatile("" : "+v"(o));
-      if (map[m] >= 0 && (map[m] & 255) < rem) {
+      int mm = map[m];
+      asm volatile("" : "+v"(mm));
+      if (mm >= 0 && (mm & 255) < rem) {
+        const int i = mm >> 8, bb = mm & 255;
+        const uint32_t o =
+            (uint32_t)(((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1))) << 3;
         pre[m] = *reinterpret_cast<const float2*>(cb + o);
         if constexpr (EXT) prel[m] = *reinterpret_cast<const uint32_t*>(cl + (o >> 1));
       }
@@ -620,7 +619,7 @@ struct GramArgs {
 // branch.
 template <int NT, int PRE>
 __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const PairArgs& a,
-                                          const GramArgs& ga, const int* map, const int* off,
+                                          const GramArgs& ga, const int* map,
                                           float2* pre, float* z, double* P) {
   constexpr int CH = 64;
   const int KS = 4 / ga.TG;
@@ -643,9 +642,9 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
     store_planes<PRE>(ga.W, map, pre, z);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre);
     else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre);
     for (int sb = ga.kq; sb < CH / 16; sb += KS) {
       float4 A[NT], Bv[NT];
 #pragma unroll
@@ -684,7 +683,7 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
 // summed by shuffles in a fixed order).  Requires nblk <= TH.
 template <int BS, int PRE, int TH, int CH, bool EXT = false>
 __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const PairArgs& a,
-                                         const GramArgs& ga, const int* map, const int* off,
+                                         const GramArgs& ga, const int* map,
                                          float2* pre, void* zfv, C2<double>* R, int RS,
                                          double delta, uint32_t* prel = nullptr) {
   constexpr int RSF = CH + 1;
@@ -711,10 +710,10 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre, prel,
                             ga.ro);
     else if (a.Lt > 0)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre,
                             prel, ga.ro);
     if (act) {
       for (int bb = sg; bb < CH; bb += S) {
@@ -764,6 +763,121 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
           R[i * RS + j] = r;
         }
       }
+  }
+  __syncthreads();
+}
+
+// Vector Gram for 61..64 bins (16 block rows of 4) on 256 threads.  Its 4 x 4 blocks of the
+// lower triangle number 136, so gram_vec<4> gives each one thread and leaves 120 idle; here the
+// 120 blocks below the diagonal take two snapshot slices each (threads 0..239, the slices on
+// adjacent lanes, summed by one shuffle), and the 160 entries of the 16 diagonal blocks' lower
+// triangles take one thread each over every snapshot (threads 0..159): about 36 instead of
+// 64 FMA-instructions per snapshot and wave.  Same sums as gram_vec (FP64 accumulation of
+// exact products), in another order.
+template <int PRE, int TH, int CH, bool EXT = false>
+__device__ __forceinline__ void gram_vec64(const float2* __restrict__ Yw, const PairArgs& a,
+                                           const GramArgs& ga, const int* map,
+                                           float2* pre, void* zfv, C2<double>* R, int RS,
+                                           double delta, uint32_t* prel = nullptr) {
+  static_assert(TH == 256, "two slices of the 120 off-diagonal blocks fill 240 threads");
+  constexpr int RSF = CH + 1, NB = 16, NOD = NB * (NB - 1) / 2;
+  using SV = typename std::conditional<EXT, double2, float2>::type;
+  SV* zf = static_cast<SV*>(zfv);
+  const int W = ga.W;
+  const int tid = threadIdx.x;
+  // phase 1: block (bi, bj), bi > bj, snapshots sg, sg + 2, ...
+  const int sg = tid & 1;
+  const bool act1 = (tid >> 1) < NOD;
+  int bi = 1, bj = 0;
+  if (act1) {
+    tri_index(tid >> 1, bi, bj);
+    bi += 1;
+  }
+  // phase 2: entry (4 d + u, 4 d + v), u >= v, of diagonal block d
+  const bool act2 = tid < NB * 10;
+  int d = 0, u2 = 0, v2 = 0;
+  if (act2) {
+    d = tid / 10;
+    tri_index(tid - 10 * d, u2, v2);
+  }
+  const int r2 = 4 * d + u2, c2r = 4 * d + v2;
+  const SV* yr0 = zf + bi * 4 * RSF;
+  const SV* yc0 = zf + bj * 4 * RSF;
+  const SV* yd0 = zf + r2 * RSF;
+  const SV* ye0 = zf + c2r * RSF;
+  double ax[4][4], ay[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ax[u][v] = ay[u][v] = 0.0;
+  double px = 0.0, py = 0.0;
+  for (int c0 = 0; c0 < a.L; c0 += CH) {
+    __syncthreads();   // previous chunk consumed
+    store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
+    __syncthreads();
+    if (c0 + CH < a.L)
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre, prel,
+                            ga.ro);
+    else if (a.Lt > 0)
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre,
+                            prel, ga.ro);
+    if (act1) {
+      for (int bb = sg; bb < CH; bb += 2) {
+        double rx[4], ry[4], cx[4], cy[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double2 yr = staged_c64(yr0, u * RSF + bb), yc = staged_c64(yc0, u * RSF + bb);
+          rx[u] = yr.x;
+          ry[u] = yr.y;
+          cx[u] = yc.x;
+          cy[u] = yc.y;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {   // y_i conj(y_j), two FMAs per part
+            ax[u][v] = fma(rx[u], cx[v], ax[u][v]);
+            ax[u][v] = fma(ry[u], cy[v], ax[u][v]);
+            ay[u][v] = fma(ry[u], cx[v], ay[u][v]);
+            ay[u][v] = fma(-rx[u], cy[v], ay[u][v]);
+          }
+      }
+    }
+    if (act2) {
+      for (int bb = 0; bb < CH; ++bb) {
+        const double2 yr = staged_c64(yd0, bb), yc = staged_c64(ye0, bb);
+        px = fma(yr.x, yc.x, px);
+        px = fma(yr.y, yc.y, px);
+        py = fma(yr.y, yc.x, py);
+        py = fma(-yr.x, yc.y, py);
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ax[u][v] += __shfl_xor(ax[u][v], 1);
+      ay[u][v] += __shfl_xor(ay[u][v], 1);
+    }
+  __syncthreads();   // staging no longer read: R aliases it
+  const double invL = 1.0 / (double)a.L;
+  if (act1 && sg == 0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = bi * 4 + u, j = bj * 4 + v;   // j < i: below the diagonal blocks
+        if (i < W) R[i * RS + j] = c2<double>(ax[u][v] * invL, ay[u][v] * invL);
+      }
+  }
+  if (act2 && r2 < W) {
+    C2<double> r = c2<double>(px * invL, py * invL);
+    if (r2 == c2r) {
+      r.x += delta;
+      r.y = 0.0;
+    }
+    R[r2 * RS + c2r] = r;
   }
   __syncthreads();
 }
@@ -952,7 +1066,7 @@ __device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowG
 template <int PRE, int TH, int CH, bool PLANES, bool EXT = false>
 __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, const PairArgs& a,
                                              int k, int woff, int W, const int* map,
-                                             const int* off, bool aligned, float2* pre, float* z,
+                                             bool aligned, float2* pre, float* z,
                                              void* zfv, const C2<double>* wv, double2* red,
                                              int fail, float2* __restrict__ o,
                                              uint32_t* prel = nullptr,
@@ -971,7 +1085,7 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
       store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c + 1 < nch)
-      fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
+      fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
                             pre, prel, ro);
     double zx = 0.0, zy = 0.0;
     if (!fail) {
@@ -1045,12 +1159,12 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     ro.ne = (d.win[ps.t] + ((ro.s & 1) ? 0 : 1)) >> 1;
     woff = ps.woff - ro.so;
   }
-  int map[PRE], off[PRE];
-  chunk_map<PRE, TH, CH>(a, W, map, off, ro);
+  int map[PRE];
+  chunk_map<PRE, TH, CH>(a, W, map);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   uint32_t prel[EXT ? PRE : 1];
-  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre, prel, ro);
+  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, aligned, 0, a.L, pre, prel, ro);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
@@ -1060,12 +1174,18 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if constexpr (TH >= 256) {
       // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
       if (WCAP <= 44 || W <= 44)
-        gram_vec<2, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
-      else if constexpr (WCAP > 44)
-        gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
+        gram_vec<2, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+      else if constexpr (WCAP > 60) {
+        // 16 block rows: gram_vec<4> would leave 120 of the 256 threads idle
+        if (W > 60)
+          gram_vec64<PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+        else
+          gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+      } else if constexpr (WCAP > 44)
+        gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
     } else {
       // one wave: 4 x 4 blocks (at most 55 blocks for 40 bins)
-      gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
+      gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
     }
   } else {
     static_assert(!MF || TH == 256, "the matrix-core form runs four waves");
@@ -1082,7 +1202,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     switch (NT) {
 #define WBM_GRAM_CASE(n) \
   case n:                \
-    if constexpr (n <= kXMaxT) gram_mfma<n, PRE>(Yw, a, ga, map, off, pre, z, P); \
+    if constexpr (n <= kXMaxT) gram_mfma<n, PRE>(Yw, a, ga, map, pre, z, P); \
     break;
       WBM_GRAM_CASE(1) WBM_GRAM_CASE(2) WBM_GRAM_CASE(3) WBM_GRAM_CASE(4) WBM_GRAM_CASE(5)
       WBM_GRAM_CASE(6) WBM_GRAM_CASE(7) WBM_GRAM_CASE(8) WBM_GRAM_CASE(9)
@@ -1138,7 +1258,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     fail = ldl_lds<TH>(R, lay.RS, W);
     if (!fail) ldl_solve(R, lay.RS, W, av, wv);
   }
-  apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red,
+  apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, aligned, pre, z, zf, wv, red,
                                      fail, out + pair * a.Lt, prel, ro);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
@@ -1682,7 +1802,7 @@ __device__ __forceinline__ void store_bf16(int W, int pad, const int* map, const
 template <int NT, int PRE, bool SPLIT>
 __device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const PairArgs& a,
                                           const GramArgs& ga, int pad, const int* map,
-                                          const int* off, float2* pre, __bf16* zh, float* P) {
+                                          float2* pre, __bf16* zh, float* P) {
   constexpr int CH = 64;
   const int KS = 4 / ga.TG;
   const __bf16* zl = zh + pad * kMixRS;
@@ -1703,9 +1823,9 @@ __device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const P
     store_bf16<PRE, SPLIT>(ga.W, pad, map, pre, zh);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre);
     else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre);
     for (int st = ga.kq; st < CH / 16; st += KS) {
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -1775,11 +1895,11 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
   const double delta = ps.delta;
   const int RS = lay.RS, pad = lay.pad;
 
-  int map[PRE], off[PRE];
-  chunk_map<PRE, TH, CH>(a, W, map, off);
+  int map[PRE];
+  chunk_map<PRE, TH, CH>(a, W, map);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
-  fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
+  fetch_chunk<PRE>(Yw, a, k, woff, map, aligned, 0, a.L, pre);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
@@ -1795,9 +1915,9 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
     if (SPLIT) zh[(pad + rows) * kMixRS + e] = to_bf16(0.f);
   }
   GramArgs ga{W, woff, k, ntiles, TG, wave % TG, wave / TG, lane, aligned};
-  if (NT == 1) gram_bf16<1, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
-  else if (NT == 2) gram_bf16<2, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
-  else if constexpr (kMaxT >= 3) gram_bf16<3, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
+  if (NT == 1) gram_bf16<1, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
+  else if (NT == 2) gram_bf16<2, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
+  else if constexpr (kMaxT >= 3) gram_bf16<3, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
   __syncthreads();
   // FP32 complex R (lower) from the Gram, scaled and loaded
   const float invL = 1.0f / (float)a.L;
@@ -1892,7 +2012,7 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
     return;
   }
   if (tid == 0) flags[pair] = 0;
-  apply_chunks<PRE, TH, CH, false>(Yw, a, k, woff, W, map, off, aligned, pre, nullptr, zf, wv,
+  apply_chunks<PRE, TH, CH, false>(Yw, a, k, woff, W, map, aligned, pre, nullptr, zf, wv,
                                    red, fail, out + pair * a.Lt);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
