@@ -499,20 +499,25 @@ __device__ __forceinline__ int row_slot(const RowOrder& ro, int i) {
   return (((ro.s + ii) & 1) ? ro.ne : 0) + (ii >> 1);
 }
 
-// This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end.  The
-// mapping is the same for every chunk.  fetch_chunk derives each element's offset in the
-// window layout from it (from the first row of the gathered window when rows are in split
-// order, ro.split, else from the pair's own first row).
+// This thread's elements of a chunk, packed as (row << 8) | snapshot, -1 past the end, and
+// their offsets from the chunk's first element in the window layout (valid when chunks start
+// at multiples of CH: then a chunk never splits a tile block differently).  The mapping is the
+// same for every chunk.  Offsets count from the first row of the gathered window when rows
+// are in split order (ro.split), else from the pair's own first row.
 template <int PRE, int TH, int CH>
-__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map) {
+__device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map, int* off,
+                                          const RowOrder& ro = RowOrder()) {
+  const int TB = 1 << a.logTB;
 #pragma unroll
   for (int m = 0; m < PRE; ++m) {
     const int e = threadIdx.x + m * TH;
     map[m] = -1;
+    off[m] = 0;
     if (e < W * CH) {
       int i, bb;
       chunk_elem<CH>(a, W, e, i, bb);
       map[m] = (i << 8) | bb;
+      off[m] = ((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1));
     }
   }
 }
@@ -522,18 +527,20 @@ __device__ __forceinline__ void chunk_map(const PairArgs& a, int W, int* map) {
 // also the BF16 remainders of the extended-precision windows (a.ywl, same layout) into prel.
 template <int PRE, bool EXT = false>
 __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const PairArgs& a,
-                                            int k, int woff, const int* map, bool aligned,
-                                            int c0, int lim, float2* pre,
+                                            int k, int woff, const int* map, const int* off,
+                                            bool aligned, int c0, int lim, float2* pre,
                                             uint32_t* prel = nullptr,
                                             const RowOrder& ro = RowOrder()) {
   const int TB = 1 << a.logTB;
   const int64_t ebase = (int64_t)k * a.nbt * a.sumW * TB + (int64_t)woff * TB;
   const float2* base = Yw + ebase;
   if (aligned) {
-    // the chunk base is uniform; each element adds a 32-bit byte offset computed from an
-    // opaque copy (empty register constraint) of its packed position, so that the compiler
-    // neither hoists PRE addresses out of the chunk loops nor keeps PRE offsets live through
-    // them: registers the Gram needs
+    // the chunk base is uniform; each element adds a 32-bit byte offset, kept opaque (empty
+    // register constraint) so that the compiler does not hoist PRE 64-bit addresses out of
+    // the chunk loops, where they would be spilled to scratch.  The 64-bin builds (PRE = 16)
+    // derive each offset from an opaque copy of the element's packed position instead of
+    // keeping PRE offsets live through the Gram: registers their Gram needs.
+    constexpr bool kDerive = PRE >= 16;
     const int64_t cofs = (int64_t)(c0 >> a.logTB) * a.sumW * TB + (c0 & (TB - 1));
     const char* cb = reinterpret_cast<const char*>(base + cofs);
     const char* cl = EXT ? reinterpret_cast<const char*>(a.ywl + ebase + cofs) : nullptr;
@@ -543,11 +550,16 @@ __device__ __forceinline__ void fetch_chunk(const float2* __restrict__ Yw, const
       pre[m] = make_float2(0.f, 0.f);
       if constexpr (EXT) prel[m] = 0u;
       int mm = map[m];
-      asm volatile("" : "+v"(mm));
-      if (mm >= 0 && (mm & 255) < rem) {
+      uint32_t o = 0;
+      if constexpr (kDerive) {
+        asm volatile("" : "+v"(mm));
         const int i = mm >> 8, bb = mm & 255;
-        const uint32_t o =
-            (uint32_t)(((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1))) << 3;
+        o = (uint32_t)(((bb >> a.logTB) * a.sumW + row_slot(ro, i)) * TB + (bb & (TB - 1))) << 3;
+      } else {
+        o = (uint32_t)off[m] << 3;
+        asm volatile("" : "+v"(o));
+      }
+      if (mm >= 0 && (mm & 255) < rem) {
         pre[m] = *reinterpret_cast<const float2*>(cb + o);
         if constexpr (EXT) prel[m] = *reinterpret_cast<const uint32_t*>(cl + (o >> 1));
       }
@@ -619,7 +631,7 @@ struct GramArgs {
 // branch.
 template <int NT, int PRE>
 __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const PairArgs& a,
-                                          const GramArgs& ga, const int* map,
+                                          const GramArgs& ga, const int* map, const int* off,
                                           float2* pre, float* z, double* P) {
   constexpr int CH = 64;
   const int KS = 4 / ga.TG;
@@ -642,9 +654,9 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
     store_planes<PRE>(ga.W, map, pre, z);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
     else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
     for (int sb = ga.kq; sb < CH / 16; sb += KS) {
       float4 A[NT], Bv[NT];
 #pragma unroll
@@ -683,7 +695,7 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
 // summed by shuffles in a fixed order).  Requires nblk <= TH.
 template <int BS, int PRE, int TH, int CH, bool EXT = false>
 __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const PairArgs& a,
-                                         const GramArgs& ga, const int* map,
+                                         const GramArgs& ga, const int* map, const int* off,
                                          float2* pre, void* zfv, C2<double>* R, int RS,
                                          double delta, uint32_t* prel = nullptr) {
   constexpr int RSF = CH + 1;
@@ -710,10 +722,10 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre, prel,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
                             ga.ro);
     else if (a.Lt > 0)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
                             prel, ga.ro);
     if (act) {
       for (int bb = sg; bb < CH; bb += S) {
@@ -777,7 +789,7 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
 template <int PRE, int TH, int CH, bool EXT = false>
 __device__ __forceinline__ void gram_vec64(const float2* __restrict__ Yw, const PairArgs& a,
                                            const GramArgs& ga, const int* map,
-                                           float2* pre, void* zfv, C2<double>* R, int RS,
+                                           const int* off, float2* pre, void* zfv, C2<double>* R, int RS,
                                            double delta, uint32_t* prel = nullptr) {
   static_assert(TH == 256, "two slices of the 120 off-diagonal blocks fill 240 threads");
   constexpr int RSF = CH + 1, NB = 16, NOD = NB * (NB - 1) / 2;
@@ -816,10 +828,10 @@ __device__ __forceinline__ void gram_vec64(const float2* __restrict__ Yw, const 
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre, prel,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
                             ga.ro);
     else if (a.Lt > 0)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre,
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
                             prel, ga.ro);
     if (act1) {
       for (int bb = sg; bb < CH; bb += 2) {
@@ -1066,7 +1078,7 @@ __device__ __forceinline__ PairSetup pair_setup(const PairArgs& a, const WindowG
 template <int PRE, int TH, int CH, bool PLANES, bool EXT = false>
 __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, const PairArgs& a,
                                              int k, int woff, int W, const int* map,
-                                             bool aligned, float2* pre, float* z,
+                                             const int* off, bool aligned, float2* pre, float* z,
                                              void* zfv, const C2<double>* wv, double2* red,
                                              int fail, float2* __restrict__ o,
                                              uint32_t* prel = nullptr,
@@ -1085,7 +1097,7 @@ __device__ __forceinline__ void apply_chunks(const float2* __restrict__ Yw, cons
       store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
     if (c + 1 < nch)
-      fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
+      fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, a.L + (c + 1) * CH, a.L + a.Lt,
                             pre, prel, ro);
     double zx = 0.0, zy = 0.0;
     if (!fail) {
@@ -1159,12 +1171,12 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     ro.ne = (d.win[ps.t] + ((ro.s & 1) ? 0 : 1)) >> 1;
     woff = ps.woff - ro.so;
   }
-  int map[PRE];
-  chunk_map<PRE, TH, CH>(a, W, map);
+  int map[PRE], off[PRE];
+  chunk_map<PRE, TH, CH>(a, W, map, off, ro);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
   uint32_t prel[EXT ? PRE : 1];
-  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, aligned, 0, a.L, pre, prel, ro);
+  fetch_chunk<PRE, EXT>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre, prel, ro);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
@@ -1174,18 +1186,18 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     if constexpr (TH >= 256) {
       // 2 x 2 blocks up to 44 bins (at most 253 blocks), 4 x 4 beyond
       if (WCAP <= 44 || W <= 44)
-        gram_vec<2, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+        gram_vec<2, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
       else if constexpr (WCAP > 60) {
         // 16 block rows: gram_vec<4> would leave 120 of the 256 threads idle
         if (W > 60)
-          gram_vec64<PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+          gram_vec64<PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
         else
-          gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+          gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
       } else if constexpr (WCAP > 44)
-        gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+        gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
     } else {
       // one wave: 4 x 4 blocks (at most 55 blocks for 40 bins)
-      gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, pre, zf, R, lay.RS, delta, prel);
+      gram_vec<4, PRE, TH, CH, EXT>(Yw, a, ga, map, off, pre, zf, R, lay.RS, delta, prel);
     }
   } else {
     static_assert(!MF || TH == 256, "the matrix-core form runs four waves");
@@ -1202,7 +1214,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     switch (NT) {
 #define WBM_GRAM_CASE(n) \
   case n:                \
-    if constexpr (n <= kXMaxT) gram_mfma<n, PRE>(Yw, a, ga, map, pre, z, P); \
+    if constexpr (n <= kXMaxT) gram_mfma<n, PRE>(Yw, a, ga, map, off, pre, z, P); \
     break;
       WBM_GRAM_CASE(1) WBM_GRAM_CASE(2) WBM_GRAM_CASE(3) WBM_GRAM_CASE(4) WBM_GRAM_CASE(5)
       WBM_GRAM_CASE(6) WBM_GRAM_CASE(7) WBM_GRAM_CASE(8) WBM_GRAM_CASE(9)
@@ -1258,7 +1270,7 @@ __device__ __forceinline__ void mvdr_x_body(const PairArgs& a, const WindowGeom&
     fail = ldl_lds<TH>(R, lay.RS, W);
     if (!fail) ldl_solve(R, lay.RS, W, av, wv);
   }
-  apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, aligned, pre, z, zf, wv, red,
+  apply_chunks<PRE, TH, CH, MF, EXT>(Yw, a, k, woff, W, map, off, aligned, pre, z, zf, wv, red,
                                      fail, out + pair * a.Lt, prel, ro);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
@@ -1802,7 +1814,7 @@ __device__ __forceinline__ void store_bf16(int W, int pad, const int* map, const
 template <int NT, int PRE, bool SPLIT>
 __device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const PairArgs& a,
                                           const GramArgs& ga, int pad, const int* map,
-                                          float2* pre, __bf16* zh, float* P) {
+                                          const int* off, float2* pre, __bf16* zh, float* P) {
   constexpr int CH = 64;
   const int KS = 4 / ga.TG;
   const __bf16* zl = zh + pad * kMixRS;
@@ -1823,9 +1835,9 @@ __device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const P
     store_bf16<PRE, SPLIT>(ga.W, pad, map, pre, zh);
     __syncthreads();
     if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, c0 + CH, a.L, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
     else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, ga.aligned, a.L, a.L + a.Lt, pre);
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
     for (int st = ga.kq; st < CH / 16; st += KS) {
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -1895,11 +1907,11 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
   const double delta = ps.delta;
   const int RS = lay.RS, pad = lay.pad;
 
-  int map[PRE];
-  chunk_map<PRE, TH, CH>(a, W, map);
+  int map[PRE], off[PRE];
+  chunk_map<PRE, TH, CH>(a, W, map, off);
   const bool aligned = (a.L % CH) == 0;
   float2 pre[PRE];
-  fetch_chunk<PRE>(Yw, a, k, woff, map, aligned, 0, a.L, pre);
+  fetch_chunk<PRE>(Yw, a, k, woff, map, off, aligned, 0, a.L, pre);
   for (int i = tid; i < W; i += TH)
     av[i] = a.abar ? a.abar[ps.pair * a.wmax + i] : window_steering(g, ps.u, ps.s, i);
   if (starts_out && tid == 0) starts_out[pair] = ps.s;
@@ -1915,9 +1927,9 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
     if (SPLIT) zh[(pad + rows) * kMixRS + e] = to_bf16(0.f);
   }
   GramArgs ga{W, woff, k, ntiles, TG, wave % TG, wave / TG, lane, aligned};
-  if (NT == 1) gram_bf16<1, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
-  else if (NT == 2) gram_bf16<2, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
-  else if constexpr (kMaxT >= 3) gram_bf16<3, PRE, SPLIT>(Yw, a, ga, pad, map, pre, zh, P);
+  if (NT == 1) gram_bf16<1, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
+  else if (NT == 2) gram_bf16<2, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
+  else if constexpr (kMaxT >= 3) gram_bf16<3, PRE, SPLIT>(Yw, a, ga, pad, map, off, pre, zh, P);
   __syncthreads();
   // FP32 complex R (lower) from the Gram, scaled and loaded
   const float invL = 1.0f / (float)a.L;
@@ -2012,7 +2024,7 @@ __device__ __forceinline__ void mvdr_mixed_body(const PairArgs& a, const WindowG
     return;
   }
   if (tid == 0) flags[pair] = 0;
-  apply_chunks<PRE, TH, CH, false>(Yw, a, k, woff, W, map, aligned, pre, nullptr, zf, wv,
+  apply_chunks<PRE, TH, CH, false>(Yw, a, k, woff, W, map, off, aligned, pre, nullptr, zf, wv,
                                    red, fail, out + pair * a.Lt);
   if (wout) {
     for (int i = tid; i < a.wmax; i += TH) {
