@@ -1035,6 +1035,18 @@ static hipError_t chan_launch(const float2* x, float2* X, int N, int B, const fl
   return hipGetLastError();
 }
 
+// LDS bytes of a spatial DFT launch's per-call tables beside its transform tile: window
+// starts and beam centres (2 ints per target), the profile accumulators (64 floats per target),
+// the window-row list (one int per row; the split-half kernels also the even-row offsets, T + 1
+// ints).  The launchers and beamspace_lds_bytes share it.
+static size_t beam_table_bytes(int T, int sumW, bool windows, bool prof, bool split) {
+  size_t b = 0;
+  if (windows || prof) b += sizeof(int) * 2 * (size_t)T;
+  if (prof) b += sizeof(float) * 64 * (size_t)T;
+  if (windows) b += sizeof(int) * ((size_t)sumW + (split ? (size_t)T + 1 : 0));
+  return b;
+}
+
 template <int LOGM, int LOGT, bool ZH>
 static hipError_t beam_launch_zh(const float2* X, float2* Y, float2* Yw, int N, int B, int K,
                                  const float2* twM, const int* rowtab, int sumW,
@@ -1043,10 +1055,7 @@ static hipError_t beam_launch_zh(const float2* X, float2* Y, float2* Yw, int N, 
   using F = Fft<LOGM, fft_tile(LOGM, LOGT), beam_pad(fft_tile(LOGM, LOGT), LOGM)>;
   const int nbt = (B + F::rows - 1) / F::rows;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
-  size_t shm = 0;
-  if (Yw || prof) shm = sizeof(int) * 2 * (size_t)g.T;
-  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Yw) shm += sizeof(int) * (size_t)sumW;
+  const size_t shm = beam_table_bytes(g.T, sumW, Yw != nullptr, prof != nullptr, false);
   if (sizeof(float2) * (size_t)F::lds_complex + shm > kLdsBytes) return hipErrorInvalidValue;
   if (sizeof(float2) * (size_t)F::lds_complex + shm > 64 * 1024) {
     // beyond the default 64 KiB per workgroup: ask for exactly the dynamic part
@@ -1110,9 +1119,7 @@ static hipError_t beam_launch_x_zh(const float2* Xh, const uint32_t* Xl, float2*
   const int nbt = (B + F::rows - 1) / F::rows;
   if (prof && (G < 1 || G > nbt)) return hipErrorInvalidValue;
   size_t shm = sizeof(double2) * (size_t)F::lds_complex;
-  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
-  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Ywh) shm += sizeof(int) * (size_t)sumW;
+  shm += beam_table_bytes(g.T, sumW, Ywh != nullptr, prof != nullptr, false);
   if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x<LOGM, LOGT, ZH>,
@@ -1142,9 +1149,7 @@ static hipError_t beam_launch_x2(const float2* Xh, const uint32_t* Xl, float2* Y
   using F = Fft<LOGH, LOGH, beam_pad(LOGH, LOGH), double2>;
   if (prof && (G < 1 || G > B)) return hipErrorInvalidValue;
   size_t shm = sizeof(double2) * (size_t)F::lds_complex;
-  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
-  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
+  shm += beam_table_bytes(g.T, sumW, Ywh != nullptr, prof != nullptr, true);
   if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x2<LOGH>,
@@ -1172,9 +1177,7 @@ static hipError_t beam_launch_x16(const float2* Xh, const uint32_t* Xl, float2* 
   if (N > 4096) return hipErrorInvalidValue;
   if (prof && (G < 1 || G > B)) return hipErrorInvalidValue;
   size_t shm = sizeof(double2) * (size_t)Fft4k::n;
-  if (Ywh || prof) shm += sizeof(int) * 2 * (size_t)g.T;
-  if (prof) shm += sizeof(float) * 64 * (size_t)g.T;
-  if (Ywh) shm += sizeof(int) * ((size_t)sumW + g.T + 1);
+  shm += beam_table_bytes(g.T, sumW, Ywh != nullptr, prof != nullptr, true);
   if (shm > kLdsBytes) return hipErrorInvalidValue;
   if (shm > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_beamspace_x16,
@@ -1665,11 +1668,7 @@ size_t beamspace_lds_bytes(bool ext, int N, int M, int logtile, int T, int sumW,
 #undef C
   }
   if (!tile) return SIZE_MAX;
-  size_t tables = 0;
-  if (windows || prof) tables += sizeof(int) * 2 * (size_t)T;
-  if (prof) tables += sizeof(float) * 64 * (size_t)T;
-  if (windows) tables += sizeof(int) * ((size_t)sumW + (split ? (size_t)T + 1 : 0));
-  return tile + tables;
+  return tile + beam_table_bytes(T, sumW, windows, prof, split);
 }
 
 hipError_t launch_beamspace(const float2* X, float2* Y, float2* Yw, int N, int M, int B, int K,
