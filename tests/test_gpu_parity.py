@@ -432,6 +432,33 @@ def test_extended_precision_spatial_dft_at_8192_bins(torch, wb, beam_tile):
     plan.close()
 
 
+def test_windows_of_61_to_64_bins(torch, wb):
+    """Windows of 61, 62, 63 and 64 bins, where the pair kernels' Gram works on 16 block rows
+    of 4 (the last one partly past W for 61..63): the four-wave vector kernel on extended
+    windows (fused and graph forms) and on FP32 windows, and the FP64 matrix-core kernel on FP32
+    windows, each against the oracle.  On FP32 windows the two pair kernels may return the same
+    weights bit for bit: both sum exact products in FP64, and the rounding to FP32 hides the
+    different summation orders."""
+    cfg = scenes.SceneConfig(name="w61", N=64, M=128, K=4, L=192, Lt=8, T=4, W=None,
+                             W_choices=(1,), n_jammers=2, target_az_deg=(-40.0, -5.0, 20.0, 55.0),
+                             target_snr_db=(0.0, 5.0, -5.0, 10.0), jammer_az_deg=(30.0, -20.0),
+                             jammer_inr_db=(35.0, 45.0), seed=61)
+    sc = scenes.make_scene(cfg)
+    sc.win = np.asarray((61, 62, 63, 64), dtype=np.int32)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    x = torch.from_numpy(x32).cuda()
+    for form, pk, prec in (("fused", "block", "ext"), ("graph", "block", "ext"),
+                           ("fused_f32", "block", "f32"), ("fused_f32", "mfma", "f32")):
+        _pin(plan, pk, precision=prec)
+        res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        st = compare_beamform(sc, ref, res, ext=form in EXT_FORMS)
+        log(f"  {form} ({pk}): {st}")
+    plan.close()
+
+
 def test_window_rows_beyond_the_pinned_tile(torch, wb):
     """320 targets of 64 bins at M = 2048 (20480 window rows): the extended spatial DFT's 2^13
     tile (128 KiB of LDS) cannot hold their row table beside it, so a call with that tile pinned
