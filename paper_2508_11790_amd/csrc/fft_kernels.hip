@@ -638,11 +638,8 @@ struct Fft4k {
   // input r times w^r (FP64).  The powers follow the three-term recurrence w^r = 2 Re(w)
   // w^(r-1) - w^(r-2) of cos and sin, applied to the real and imaginary parts alike (two FMAs
   // per power against four for a complex product; for r <= 15 its rounding error stays near
-  // r^2 / 2 units in the last place).  The empty register constraint keeps the powers inside
-  // the caller's loop (hoisted out of it, as loop invariants, they would take 60 registers
-  // per pass).
+  // r^2 / 2 units in the last place).
   __device__ __forceinline__ static void twiddle(double2 (&v)[16], double2 w) {
-    asm volatile("" : "+v"(w.x), "+v"(w.y));
     const double c2 = 2.0 * w.x;
     double2 t0 = make_double2(1.0, 0.0), t1 = w;
     v[1] = cmul(v[1], t1);
@@ -675,7 +672,11 @@ struct Fft4k {
 
   // v = this thread's inputs x[j + 256 r]; w1 = exp(-2 pi i (j mod 16) / 256), w2 =
   // exp(-2 pi i (j mod 256) / 4096).  On return lds holds the transform in natural order
-  // (position pos(m)), visible to every thread.
+  // (position pos(m)), visible to every thread; on entry other threads may still be reading
+  // lds (the previous transform's outputs).  Each barrier sits just before the stores it
+  // protects, not after the loads of the pass before: a wave then works on its first loaded
+  // values while the rest are still arriving, and waves that receive theirs early do not wait
+  // for the others before computing.
   //
   // Half-bin shift: the transform at frequencies m + 1/2, sum_e x[e] exp(-2 pi i e (m + 1/2) /
   // 4096), is the same three passes with input r of the first pass times exp(-i pi r / 16)
@@ -685,20 +686,26 @@ struct Fft4k {
   // moves into the next pass's twiddle base, where it leaves no common factor after the third.
   __device__ __forceinline__ static void run(double2 (&v)[16], double2* lds, double2 w1,
                                              double2 w2) {
+    // The empty register constraint makes the bases opaque, which keeps their powers inside
+    // the caller's loop (hoisted out of it as loop invariants they would take 60 registers per
+    // pass).  It stands here, before any LDS load is in flight, because in the middle of a
+    // pass it makes the compiler wait for all sixteen loads before the first product.
+    asm volatile("" : "+v"(w1.x), "+v"(w1.y), "+v"(w2.x), "+v"(w2.y));
     const int j = threadIdx.x;
     dft16(v);
+    __syncthreads();   // every thread is done reading lds
     store(v, lds, 16 * j, 1);
     __syncthreads();
     load(v, lds, j);
-    __syncthreads();
     twiddle(v, w1);
     dft16(v);
+    __syncthreads();
     store(v, lds, (j >> 4) * 256 + (j & 15), 16);
     __syncthreads();
     load(v, lds, j);
-    __syncthreads();
     twiddle(v, w2);
     dft16(v);
+    __syncthreads();
     store(v, lds, j, 256);
     __syncthreads();
   }
@@ -794,7 +801,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           }
         }
       }
-      __syncthreads();   // the next transform overwrites lds
     }
   }
   if (prof) {
