@@ -59,6 +59,38 @@ def test_profiles_match_oracle(torch, wb):
     plan.close()
 
 
+@pytest.mark.parametrize("beam_tile", [13, 12])
+def test_profiles_at_8192_bins_match_oracle(torch, wb, beam_tile):
+    """Training power profiles at M = 8192 with N <= 4096, where the extended-precision spatial
+    DFT computes each row's even and odd bins as two 4096-point transforms (tile 2^13: the
+    radix-16 kernel; 2^12: the radix-8 split-half kernel) and accumulates each parity's profile
+    bins in its own half: every profile against the oracle's, one target next to the wrap, N not
+    a multiple of the thread count."""
+    cfg = scenes.SceneConfig(name="prof8192", N=300, M=8192, K=4, L=40, Lt=8, T=3, W=9,
+                             n_jammers=2, target_az_deg=(-89.0, 3.0, 41.0),
+                             target_snr_db=(5.0, 0.0, 10.0), jammer_az_deg=(-30.0, 20.0),
+                             jammer_inr_db=(40.0, 30.0), seed=37)
+    sc = scenes.make_scene(cfg)
+    x32 = sc.x.astype(np.complex64)
+    plan = _plan(wb, cfg)
+    chan = plan.get_tuning("ext")[0]
+    plan.set_tuning(chan, beam_tile, "block", 1, precision="ext")
+    feat = plan.profiles(torch.from_numpy(x32).cuda(), sc.target_az, 1.0).cpu().numpy()
+    X = oracle.channelize(x32.astype(np.complex128), cfg.K)
+    ratio = oracle.subband_freq_ratio(cfg.K, cfg.beta)
+    worst = 0.0
+    for k in range(cfg.K):
+        Yk = oracle.beamspace(X[:, :cfg.L, k][:, :, None], cfg.M)[:, :, 0]
+        for t in range(cfg.T):
+            u = oracle.beam_position(_sin(sc)[t], ratio[k], cfg.M, cfg.dl)
+            ref = olearned.power_profile(Yk, u, 1.0)
+            err = float(np.max(np.abs(feat[t, k] - ref)))
+            assert err < 2e-4, (t, k, err)
+            worst = max(worst, err)
+    log(f"  tile {beam_tile}: worst profile error {worst:.2e} (log10 units)")
+    plan.close()
+
+
 def _pair_oracle(x128, cfg, s_az, k, W, d):
     return oracle.windowed_mvdr(x128, M=cfg.M, K=cfg.K, L=cfg.L, Lt=cfg.Lt, sin_az=[s_az], win=[W],
                                 delta=d, beta=cfg.beta, dl=cfg.dl, subbands=[k])
