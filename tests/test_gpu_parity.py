@@ -432,6 +432,35 @@ def test_extended_precision_spatial_dft_at_8192_bins(torch, wb, beam_tile):
     plan.close()
 
 
+@pytest.mark.parametrize("beam_tile,form", [(13, "fused"), (13, "graph"), (12, "graph")])
+def test_overlapped_chunks_at_8192_bins(torch, wb, beam_tile, form):
+    """Two overlapped subband chunks at M = 8192 with N <= 4096: the split-half spatial DFTs
+    (tile 2^13: radix-16, 2^12: radix-8) start each chunk at its first subband and the pair
+    kernel of one chunk runs beside the transform of the next; every pair against the oracle,
+    and the same outputs as the unchunked sequence bit for bit."""
+    cfg = scenes.SceneConfig(name="m8192k16", N=300, M=8192, K=16, L=40, Lt=8, T=3, W=None,
+                             W_choices=(1,), n_jammers=1, target_az_deg=(-60.0, 0.0, 35.0),
+                             target_snr_db=(5.0, 0.0, 10.0), jammer_az_deg=(20.0,),
+                             jammer_inr_db=(40.0,), seed=43)
+    sc = scenes.make_scene(cfg)
+    sc.win = np.asarray((64, 9, 33), dtype=np.int32)
+    x32 = _x32(sc)
+    ref = _oracle(sc, x32)
+    plan = _plan(wb, cfg, sc)
+    plan.set_tuning(11, beam_tile, "block", 1, precision="ext")
+    x = torch.from_numpy(x32).cuda()
+    one = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form="fused")
+    plan.set_tuning(11, beam_tile, "block", 2, precision="ext")
+    for rep in range(2):
+        res = plan.beamform(x, sc.target_az, sc.win, cfg.delta, form=form)
+        torch.cuda.synchronize()
+        st = compare_beamform(sc, ref, res, ext=True)
+        log(f"  tile {beam_tile} {form} two chunks, call {rep}: {st}")
+        assert torch.equal(res["out"], one["out"]), rep
+        assert torch.equal(res["weights"], one["weights"]), rep
+    plan.close()
+
+
 def test_windows_of_61_to_64_bins(torch, wb):
     """Windows of 61, 62, 63 and 64 bins, where the pair kernels' Gram works on 16 block rows
     of 4 (the last one partly past W for 61..63): the four-wave vector kernel on extended
