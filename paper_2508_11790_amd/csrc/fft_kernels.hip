@@ -782,13 +782,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
       if (Ywh) {
         const int ne = s_ebase[g.T], cnt = par ? sumW - ne : ne;
         const int* lst = s_bin + (par ? ne : 0);
-        for (int q = threadIdx.x; q < cnt; q += Fft4k::threads) {
-          const int pk = lst[q], r = pk >> kHalfBinBits;
-          float2 hi;
-          uint32_t lo;
-          ext_split(cscale(lds[Fft4k::pos(pk & ((1 << kHalfBinBits) - 1))], scale), hi, lo);
-          Ywh[o0 + r] = hi;
-          Ywl[o0 + r] = lo;
+        // GB = 2 list entries per thread and pass, each pass's LDS reads issued together (the
+        // entries, then the bins they name): two LDS round trips per pass instead of two per
+        // entry, in registers the transform no longer holds (256 per thread; four entries per
+        // pass spill)
+        constexpr int GB = 2;
+        for (int q0 = 0; q0 < cnt; q0 += GB * Fft4k::threads) {
+          int pk[GB];
+#pragma unroll
+          for (int i = 0; i < GB; ++i) {
+            const int q = q0 + i * Fft4k::threads + (int)threadIdx.x;
+            pk[i] = q < cnt ? lst[q] : -1;
+          }
+          double2 y[GB];
+#pragma unroll
+          for (int i = 0; i < GB; ++i)
+            if (pk[i] >= 0) y[i] = lds[Fft4k::pos(pk[i] & ((1 << kHalfBinBits) - 1))];
+#pragma unroll
+          for (int i = 0; i < GB; ++i) {
+            if (pk[i] >= 0) {
+              const int r = pk[i] >> kHalfBinBits;
+              float2 hi;
+              uint32_t lo;
+              ext_split(cscale(y[i], scale), hi, lo);
+              Ywh[o0 + r] = hi;
+              Ywl[o0 + r] = lo;
+            }
+          }
         }
       }
       if (prof && b < L) {
