@@ -531,9 +531,13 @@ def main():
     # the covariance engines: BF16 MFMA utilisation of the mixed forms' pair stage (MFMA kernel
     # plus the FP64 re-solve of routed windows) against the 2.5 PFLOP/s dense BF16 peak, and
     # the exact path's FP64 vector Gram beside the FP64 matrix-core Gram on the same windows
-    cov_flops = 8.0 * float(np.sum(np.asarray(win, dtype=np.float64) ** 2)) * cfg.L * K
+    # algorithmic flops: the lower triangle (with the diagonal) of each pair's Hermitian W x W
+    # covariance, W (W + 1) / 2 complex entries of L complex products (8 real flops each) --
+    # what every engine forms (the matrix-core ones as lower tiles of the real 2W x 2W Gram)
+    wv = np.asarray(win, dtype=np.float64)
+    cov_flops = 4.0 * float(np.sum(wv * (wv + 1.0))) * cfg.L * K
     covariance = {"algorithmic_tflop_per_step": cov_flops / 1e12,
-                  "flops_per_pair": "8 W^2 L (real Gram of [Re y; Im y], 2W x L)"}
+                  "flops_per_pair": "4 W (W + 1) L (lower triangle of the Hermitian covariance)"}
     if not args.no_mixed:
         for form, prods in (("mixed", 3), ("mixed_bf16", 1)):
             stm = plan.stage_times(x, az, win, delta, reps=max(5, args.steps // 4),
@@ -544,7 +548,6 @@ def main():
                 "bf16_products_per_entry": prods, "peak_tflops": 2500.0,
                 "achieved_tflops_algorithmic": round(cov_flops / (ms * 1e-3) / 1e12, 2),
                 "frac_algorithmic": round(cov_flops / (ms * 1e-3) / 2.5e15, 5),
-                "frac_executed": round(prods * cov_flops / (ms * 1e-3) / 2.5e15, 5),
                 "routed_pairs": mixed.get(form, {}).get("routed_pairs")}
     tun32 = plan.get_tuning("f32")
     for pair in ("block", "mfma"):
@@ -595,9 +598,9 @@ def main():
 
     ms_full = None
     if not args.no_full:
-        # element-space N x N MVDR per subband over the whole workload: about 8 N^2 L flops of
-        # covariance and 4 N^3 / 3 of Cholesky per subband (117 TFLOP per step at N = 4096), so
-        # few steps at large N
+        # element-space N x N MVDR per subband over the whole workload: 4 N (N + 1) L flops of
+        # covariance (its lower triangle) and 4 N^3 / 3 of Cholesky per subband (82 TFLOP per
+        # step at N = 4096), so few steps at large N
         full_sub = None
         nfs = max(2, min(args.steps // 20, 20))
         full_k = cfg.K
