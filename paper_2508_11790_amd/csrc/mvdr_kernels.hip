@@ -653,10 +653,14 @@ __device__ __forceinline__ void gram_mfma(const float2* __restrict__ Yw, const P
     __syncthreads();   // previous chunk consumed
     store_planes<PRE>(ga.W, map, pre, z);
     __syncthreads();
-    if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
-    else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+    // the next training chunk, or after the last one the first test chunk: one call site,
+    // so that the loads stay in flight through this chunk's Gram (two calls made the
+    // compiler merge their results with copies that wait for the loads)
+    if (c0 + CH < a.L || a.Lt > 0) {
+      const bool more = c0 + CH < a.L;
+      const int from = more ? c0 + CH : a.L, to = more ? a.L : a.L + a.Lt;
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, from, to, pre);
+    }
     for (int sb = ga.kq; sb < CH / 16; sb += KS) {
       float4 A[NT], Bv[NT];
 #pragma unroll
@@ -721,12 +725,14 @@ __device__ __forceinline__ void gram_vec(const float2* __restrict__ Yw, const Pa
     __syncthreads();   // previous chunk consumed
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
-    if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
-                            ga.ro);
-    else if (a.Lt > 0)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
-                            prel, ga.ro);
+    // the next training chunk, or after the last one the first test chunk: one call site,
+    // so that the loads stay in flight through this chunk's Gram (two calls made the
+    // compiler merge their results with copies that wait for the loads)
+    if (c0 + CH < a.L || a.Lt > 0) {
+      const bool more = c0 + CH < a.L;
+      const int from = more ? c0 + CH : a.L, to = more ? a.L : a.L + a.Lt;
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, from, to, pre, prel, ga.ro);
+    }
     if (act) {
       for (int bb = sg; bb < CH; bb += S) {
         double rx[BS], ry[BS], cx[BS], cy[BS];
@@ -827,12 +833,14 @@ __device__ __forceinline__ void gram_vec64(const float2* __restrict__ Yw, const 
     __syncthreads();   // previous chunk consumed
     store_rows<PRE, RSF, EXT>(map, pre, zf, prel);
     __syncthreads();
-    if (c0 + CH < a.L)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre, prel,
-                            ga.ro);
-    else if (a.Lt > 0)
-      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre,
-                            prel, ga.ro);
+    // the next training chunk, or after the last one the first test chunk: one call site,
+    // so that the loads stay in flight through this chunk's Gram (two calls made the
+    // compiler merge their results with copies that wait for the loads)
+    if (c0 + CH < a.L || a.Lt > 0) {
+      const bool more = c0 + CH < a.L;
+      const int from = more ? c0 + CH : a.L, to = more ? a.L : a.L + a.Lt;
+      fetch_chunk<PRE, EXT>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, from, to, pre, prel, ga.ro);
+    }
     if (act1) {
       for (int bb = sg; bb < CH; bb += 2) {
         double rx[4], ry[4], cx[4], cy[4];
@@ -1834,10 +1842,14 @@ __device__ __forceinline__ void gram_bf16(const float2* __restrict__ Yw, const P
     __syncthreads();   // previous chunk consumed
     store_bf16<PRE, SPLIT>(ga.W, pad, map, pre, zh);
     __syncthreads();
-    if (c0 + CH < a.L)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, c0 + CH, a.L, pre);
-    else if (a.Lt > 0)
-      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, a.L, a.L + a.Lt, pre);
+    // the next training chunk, or after the last one the first test chunk: one call site,
+    // so that the loads stay in flight through this chunk's Gram (two calls made the
+    // compiler merge their results with copies that wait for the loads)
+    if (c0 + CH < a.L || a.Lt > 0) {
+      const bool more = c0 + CH < a.L;
+      const int from = more ? c0 + CH : a.L, to = more ? a.L : a.L + a.Lt;
+      fetch_chunk<PRE>(Yw, a, ga.k, ga.woff, map, off, ga.aligned, from, to, pre);
+    }
     for (int st = ga.kq; st < CH / 16; st += KS) {
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
